@@ -1,0 +1,174 @@
+/*
+ * pdfpic -- particle-in-cell Monte Carlo step for the joint PDF of velocity
+ * and a passive scalar, for AMD Instinct MI355X (gfx950).
+ *
+ * Method: Bakosi, Franzese & Boybeyi, "Joint PDF modelling of turbulent flow
+ * and dispersion in an urban street canyon".  Particles carry position,
+ * velocity and scalar; one step advances them by the explicit Euler-Maruyama
+ * scheme (section 2.4) of
+ *   eq. (5)  position: dX = U dt + (2 nu)^(1/2) dW
+ *   eq. (6)  velocity: the generalized Langevin model, with the drift tensor
+ *            G and C0 either from the simplified Langevin model, eq. (19),
+ *            or from the elliptic-relaxation tensor, eqs. (12)-(13)
+ *   eq. (7)  scalar:   IECM relaxation toward <phi|V> over the time scale of
+ *            eq. (11)
+ * tracks them through an unstructured triangular grid with wall (resolved
+ * no-slip, free-slip, wall-function eqs. (20)-(26)) and periodic conditions,
+ * applies the street-level source (section 3), and estimates per-element
+ * statistics from the particles (sections 2.1 and 3).
+ *
+ * Memory: the caller owns all device memory.  pdf_query_sizes() gives the
+ * size of one device arena; the caller allocates it (e.g. a torch uint8
+ * tensor) and hands it to pdf_init_mesh().  The library never allocates
+ * device memory.  Host input arrays are copied during the call.
+ *
+ * Streams: every call enqueues on the HIP stream given to pdf_create() and
+ * returns without waiting, except pdf_sync(), the host-copy variants of
+ * pdf_estimate_statistics()/pdf_get_state(), and pdf_destroy().
+ *
+ * Errors: every entry point returns a pdf_status.  Failures found on the
+ * device (a particle the walk cannot place, a non-finite value, a full
+ * element segment) are recorded in a device error word; the step that raised
+ * one completes, later steps do nothing, and pdf_sync() returns the code.
+ * pdf_error_string() describes the last error.
+ */
+#ifndef PDFPIC_H
+#define PDFPIC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t pdf_status;
+#define PDF_OK 0
+#define PDF_E_ARG -1       /* invalid argument                                   */
+#define PDF_E_MESH -2      /* degenerate or inconsistent mesh                    */
+#define PDF_E_SIZE -3      /* arena too small                                    */
+#define PDF_E_HIP -4       /* HIP runtime error                                  */
+#define PDF_E_LOST -5      /* tracking could not place a particle                */
+#define PDF_E_NAN -6       /* non-finite particle state                          */
+#define PDF_E_CAPACITY -7  /* an element segment overflowed its slack            */
+#define PDF_E_STATE -8     /* call out of order (e.g. step before seeding)       */
+
+/* edge kinds of the mesh arrays */
+#define PDF_EDGE_INTERIOR 0
+#define PDF_EDGE_NOSLIP 1      /* resolved no-slip wall: U -> -U                 */
+#define PDF_EDGE_SLIP 2        /* free-slip wall: specular                       */
+#define PDF_EDGE_WALLFN 3      /* wall-function wall, eqs. (20)-(21)             */
+#define PDF_EDGE_PERIODIC_XP 4 /* crossing adds +Lx to x                         */
+#define PDF_EDGE_PERIODIC_XM 5 /* crossing adds -Lx to x                         */
+#define PDF_EDGE_PERIODIC_YP 6 /* crossing adds +Ly to y                         */
+#define PDF_EDGE_PERIODIC_YM 7 /* crossing adds -Ly to y                         */
+
+/* statistics record per (ensemble, element): doubles in this order */
+#define PDF_ST_N 0      /* particle count                                        */
+#define PDF_ST_MEAN 1   /* 4: <u> <v> <w> <psi>                                  */
+#define PDF_ST_M2 5     /* 10: central 2nd moments, index pairs a<=b of (u,v,w,psi) */
+#define PDF_ST_BINN 15  /* 8: particles per velocity bin b = [u'>0]+2[v'>0]+4[w'>0] */
+#define PDF_ST_BINM 23  /* 8: <phi|V> per bin, the element mean for an empty bin */
+#define PDF_ST_M3 31    /* 20: central 3rd moments, a<=b<=c (moments == 4 only)  */
+#define PDF_ST_M4 51    /* 35: central 4th moments, a<=b<=c<=d                   */
+#define PDF_NSTAT_2 31  /* record length with moments == 2 (histogram follows)   */
+#define PDF_NSTAT_4 86  /* record length with moments == 4 (histogram follows)   */
+
+/* per-vertex frozen Eulerian fields, doubles, in this order (20 per vertex) */
+#define PDF_NFIELD 20   /* U V dUdx dUdy dVdx dVdy lapU lapV dPdx dPdy
+                           R11 R22 R33 R12 eps wp11 wp12 wp21 wp22 wp33 */
+
+typedef struct pdf_params {
+  int32_t f32_state;  /* 1: particle state in float, 0: double                  */
+  int32_t model;      /* 0: SLM, eq. (19); 1: G and C0 from wp, eqs. (12)-(13)   */
+  int32_t moments;    /* highest central moment order estimated: 2 or 4          */
+  int32_t hist_bins;  /* scalar histogram bins on [0,1] per element: 0 or 32     */
+  int32_t mix;        /* 1: IECM mixing on                                       */
+  int32_t psi_init;   /* initial scalar: 0 zero; 1 one where x < 0.25            */
+  int32_t flags;      /* sub-steps: 1 velocity, 2 position+tracking, 4 IECM,
+                         8 source (15 = the full step)                           */
+  int32_t reserved;
+  double dt, nu, C0;  /* time step, kinematic viscosity, SLM constant           */
+  double CT, Cs, Ct;  /* Table 2 constants used by eqs. (8) and (11)            */
+  double Cmu, kappa, Ewall, yp; /* wall functions: C_mu, Karman constant, E,
+                                   distance of the stripped wall y_p            */
+  double Lx, Ly;      /* periodic lengths                                        */
+  double slack;       /* segment capacity = ceil(slack * initial count) + 32,
+                         slack >= 1 (2 leaves room for density fluctuations)     */
+} pdf_params;
+
+typedef struct pdf_mesh {
+  int32_t nvert, nelem;
+  const double* vtx;     /* host, nvert x 2                                       */
+  const int32_t* tri;    /* host, nelem x 3 vertex ids, counter-clockwise        */
+  const int32_t* nbr;    /* host, nelem x 3: element across edge k=(v_k,v_k+1),
+                            the periodic partner for periodic edges, -1 on walls */
+  const int32_t* ekind;  /* host, nelem x 3: PDF_EDGE_*                          */
+  const double* fields;  /* host, nvert x PDF_NFIELD                             */
+} pdf_mesh;
+
+typedef struct pdf_sizes {
+  /* in */
+  int32_t nvert, nelem, nens, reserved;
+  int64_t nparticles;    /* total particles over all ensembles                   */
+  /* out */
+  int64_t arena_bytes;   /* device bytes the caller must provide                  */
+  int64_t slots;         /* particle slots per state buffer                       */
+} pdf_sizes;
+
+typedef struct pdf_ctx pdf_ctx;
+
+/* Create a context.  hip_stream: a hipStream_t (NULL: the null stream).
+   *out receives the context; nothing is allocated on the device. */
+pdf_status pdf_create(const pdf_params* p, void* hip_stream, pdf_ctx** out);
+
+/* Fill s->arena_bytes and s->slots from the sizes in s. */
+pdf_status pdf_query_sizes(const pdf_ctx* ctx, pdf_sizes* s);
+
+/* Copy the mesh and frozen fields to the device arena (caller-owned device
+   memory of arena_bytes, 256-byte aligned) and precompute the per-vertex
+   drift/diffusion coefficients and the wall-function alpha per wall edge.
+   PDF_E_MESH if an element is degenerate or clockwise. */
+pdf_status pdf_init_mesh(pdf_ctx* ctx, const pdf_mesh* m, void* arena, int64_t arena_bytes);
+
+/* Seed nens ensembles.  counts: host, nens x nelem particles per element;
+   seeds: host, nens Philox keys; source: host, nens x 3 (x0, y0, r0; r0 = 0
+   for no source).  Particles are placed uniformly in their element with the
+   local mean velocity plus Gaussian fluctuations of the local Reynolds stress;
+   particle ids run element-major from 0 within each ensemble.  Resets the
+   step counter.  PDF_E_SIZE if the layout does not fit the arena. */
+pdf_status pdf_seed_particles(pdf_ctx* ctx, int32_t nens, const int64_t* counts,
+                              const uint64_t* seeds, const double* source);
+
+/* Enqueue nsteps time steps of every ensemble (asynchronous). */
+pdf_status pdf_step(pdf_ctx* ctx, int32_t nsteps);
+
+/* Estimate the statistics of the current state into out: nens x nelem x
+   nstat doubles (nstat = PDF_NSTAT_2 or PDF_NSTAT_4, plus hist_bins).
+   out_on_host: 1 -> out is host memory and the call waits; 0 -> device. */
+pdf_status pdf_estimate_statistics(pdf_ctx* ctx, double* out, int32_t out_on_host);
+
+/* Record length of the statistics. */
+int32_t pdf_nstat(const pdf_ctx* ctx);
+
+/* Wait for the stream; return the first device error since seeding. */
+pdf_status pdf_sync(pdf_ctx* ctx);
+
+/* Copy the state of ensemble ens in particle-id order into caller device
+   memory: xyuvwpsi (6 x n doubles: x, y, u, v, w, psi) and elem (n int32),
+   n = pdf_count(ctx, ens).  Asynchronous. */
+pdf_status pdf_get_state(pdf_ctx* ctx, int32_t ens, double* xyuvwpsi, int32_t* elem);
+
+/* Number of particles of an ensemble; steps completed since seeding. */
+int64_t pdf_count(const pdf_ctx* ctx, int32_t ens);
+int64_t pdf_steps_done(pdf_ctx* ctx);
+
+/* Text of the last error. */
+const char* pdf_error_string(const pdf_ctx* ctx);
+
+/* Release the context (waits for its stream). */
+void pdf_destroy(pdf_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

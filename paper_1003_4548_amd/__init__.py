@@ -1,0 +1,243 @@
+"""Python binding of the pdfpic C ABI (``include/pdfpic.h``).
+
+Argument marshalling only: every step of the particle method runs in the HIP
+kernels of ``libpdfpic.so``.  PyTorch supplies the device arena and the HIP
+stream.  Importing this module does not need a GPU; creating a
+:class:`Simulation` does, and it raises if the library was not built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpdfpic.so")
+
+PDF_OK = 0
+STATUS = {0: "PDF_OK", -1: "PDF_E_ARG", -2: "PDF_E_MESH", -3: "PDF_E_SIZE", -4: "PDF_E_HIP",
+          -5: "PDF_E_LOST", -6: "PDF_E_NAN", -7: "PDF_E_CAPACITY", -8: "PDF_E_STATE"}
+
+ST_N, ST_MEAN, ST_M2, ST_BINN, ST_BINM, ST_M3, ST_M4 = 0, 1, 5, 15, 23, 31, 51
+NSTAT_2, NSTAT_4 = 31, 86
+NFIELD = 20
+
+# exported entry points (the declarations of include/pdfpic.h)
+ENTRY_POINTS = ("pdf_create", "pdf_query_sizes", "pdf_init_mesh", "pdf_seed_particles", "pdf_step",
+                "pdf_estimate_statistics", "pdf_nstat", "pdf_sync", "pdf_get_state", "pdf_count",
+                "pdf_steps_done", "pdf_error_string", "pdf_destroy")
+
+
+class PdfError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class PdfParams(ctypes.Structure):
+    _fields_ = [("f32_state", ctypes.c_int32), ("model", ctypes.c_int32), ("moments", ctypes.c_int32),
+                ("hist_bins", ctypes.c_int32), ("mix", ctypes.c_int32), ("psi_init", ctypes.c_int32),
+                ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("dt", ctypes.c_double), ("nu", ctypes.c_double), ("C0", ctypes.c_double),
+                ("CT", ctypes.c_double), ("Cs", ctypes.c_double), ("Ct", ctypes.c_double),
+                ("Cmu", ctypes.c_double), ("kappa", ctypes.c_double), ("Ewall", ctypes.c_double),
+                ("yp", ctypes.c_double), ("Lx", ctypes.c_double), ("Ly", ctypes.c_double),
+                ("slack", ctypes.c_double)]
+
+
+class PdfMesh(ctypes.Structure):
+    _fields_ = [("nvert", ctypes.c_int32), ("nelem", ctypes.c_int32), ("vtx", ctypes.c_void_p),
+                ("tri", ctypes.c_void_p), ("nbr", ctypes.c_void_p), ("ekind", ctypes.c_void_p),
+                ("fields", ctypes.c_void_p)]
+
+
+class PdfSizes(ctypes.Structure):
+    _fields_ = [("nvert", ctypes.c_int32), ("nelem", ctypes.c_int32), ("nens", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("nparticles", ctypes.c_int64),
+                ("arena_bytes", ctypes.c_int64), ("slots", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def library_path() -> str:
+    return LIB_PATH
+
+
+def load_library():
+    """Load libpdfpic.so; raise if it was not built (there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, d = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    P = ctypes.POINTER
+    L.pdf_create.restype = i32
+    L.pdf_create.argtypes = [P(PdfParams), vp, P(vp)]
+    L.pdf_query_sizes.restype = i32
+    L.pdf_query_sizes.argtypes = [vp, P(PdfSizes)]
+    L.pdf_init_mesh.restype = i32
+    L.pdf_init_mesh.argtypes = [vp, P(PdfMesh), vp, i64]
+    L.pdf_seed_particles.restype = i32
+    L.pdf_seed_particles.argtypes = [vp, i32, vp, vp, vp]
+    L.pdf_step.restype = i32
+    L.pdf_step.argtypes = [vp, i32]
+    L.pdf_estimate_statistics.restype = i32
+    L.pdf_estimate_statistics.argtypes = [vp, vp, i32]
+    L.pdf_nstat.restype = i32
+    L.pdf_nstat.argtypes = [vp]
+    L.pdf_sync.restype = i32
+    L.pdf_sync.argtypes = [vp]
+    L.pdf_get_state.restype = i32
+    L.pdf_get_state.argtypes = [vp, i32, vp, vp]
+    L.pdf_count.restype = i64
+    L.pdf_count.argtypes = [vp, i32]
+    L.pdf_steps_done.restype = i64
+    L.pdf_steps_done.argtypes = [vp]
+    L.pdf_error_string.restype = ctypes.c_char_p
+    L.pdf_error_string.argtypes = [vp]
+    L.pdf_destroy.restype = None
+    L.pdf_destroy.argtypes = [vp]
+    _lib = L
+    return L
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+class Simulation:
+    """One set of ensembles on one mesh, advanced by the HIP library.
+
+    mesh arrays are host numpy arrays in the layout of ``include/pdfpic.h``;
+    ``counts`` is a list (one per ensemble) of per-element particle counts.
+    """
+
+    def __init__(self, *, vtx, tri, nbr, ekind, fields, counts: Sequence[np.ndarray],
+                 seeds: Sequence[int], sources: Sequence[Sequence[float]], precision: str = "f32",
+                 model: int = 1, moments: int = 2, hist_bins: int = 0, mix: bool = True,
+                 psi_init: int = 0, flags: int = 15, dt: float = 1e-3, nu: float = 0.0,
+                 C0: float = 2.1, CT: float = 6.0, Cs: float = 0.02, Ct: float = 0.7,
+                 Cmu: float = 0.09, kappa: float = 0.41, Ewall: float = 8.5, yp: float = 0.0,
+                 Lx: float = 1.0, Ly: float = 1.0, slack: float = 2.0, device: str = "cuda:0",
+                 stream=None):
+        import torch
+
+        self.torch = torch
+        L = load_library()
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.params = PdfParams(f32_state=1 if precision == "f32" else 0, model=int(model), moments=int(moments),
+                                hist_bins=int(hist_bins), mix=1 if mix else 0, psi_init=int(psi_init),
+                                flags=int(flags), reserved=0, dt=dt, nu=nu, C0=C0, CT=CT, Cs=Cs, Ct=Ct,
+                                Cmu=Cmu, kappa=kappa, Ewall=Ewall, yp=yp, Lx=Lx, Ly=Ly, slack=slack)
+        self.ctx = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            self._check(L.pdf_create(ctypes.byref(self.params), ctypes.c_void_p(self.stream.cuda_stream),
+                                     ctypes.byref(self.ctx)), "pdf_create")
+        self._host = dict(vtx=np.ascontiguousarray(vtx, np.float64), tri=np.ascontiguousarray(tri, np.int32),
+                          nbr=np.ascontiguousarray(nbr, np.int32), ekind=np.ascontiguousarray(ekind, np.int32),
+                          fields=np.ascontiguousarray(fields, np.float64))
+        self.nvert = int(self._host["vtx"].shape[0])
+        self.nelem = int(self._host["tri"].shape[0])
+        self.nens = len(counts)
+        cnt = np.ascontiguousarray(np.stack([np.asarray(c, np.int64) for c in counts]), np.int64)
+        self.counts = cnt
+        sz = PdfSizes(nvert=self.nvert, nelem=self.nelem, nens=self.nens, reserved=0,
+                      nparticles=int(cnt.sum()), arena_bytes=0, slots=0)
+        self._check(L.pdf_query_sizes(self.ctx, ctypes.byref(sz)), "pdf_query_sizes")
+        self.arena_bytes = int(sz.arena_bytes)
+        self.slots = int(sz.slots)
+        self.arena = torch.empty(self.arena_bytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.arena.data_ptr()
+        self._arena_ptr = (base + 255) // 256 * 256
+        h = self._host
+        mesh = PdfMesh(nvert=self.nvert, nelem=self.nelem, vtx=_ptr(h["vtx"]).value, tri=_ptr(h["tri"]).value,
+                       nbr=_ptr(h["nbr"]).value, ekind=_ptr(h["ekind"]).value, fields=_ptr(h["fields"]).value)
+        with torch.cuda.device(self.device):
+            self._check(L.pdf_init_mesh(self.ctx, ctypes.byref(mesh), ctypes.c_void_p(self._arena_ptr),
+                                        self.arena_bytes), "pdf_init_mesh")
+            self._seeds = np.ascontiguousarray(np.asarray(seeds, np.uint64))
+            self._src = np.ascontiguousarray(np.asarray(sources, np.float64).reshape(self.nens, 3))
+            self._check(L.pdf_seed_particles(self.ctx, self.nens, _ptr(cnt), _ptr(self._seeds), _ptr(self._src)),
+                        "pdf_seed_particles")
+        self.nstat = int(L.pdf_nstat(self.ctx))
+
+    @classmethod
+    def from_workload(cls, wl, device: str = "cuda:0", ensembles=None, **kw):
+        """Build from a workload description (mesh, fields, ensembles, model)."""
+        m = wl.mesh
+        ens = wl.ensembles if ensembles is None else ensembles
+        c = wl.constants
+        args = dict(vtx=m.vtx, tri=m.tri, nbr=m.nbr, ekind=m.ekind, fields=wl.fields,
+                    counts=[e.counts for e in ens], seeds=[e.seed for e in ens],
+                    sources=[(e.x0[0], e.x0[1], e.r0) for e in ens], precision=wl.precision,
+                    model=wl.model, moments=wl.moments, hist_bins=wl.hist_bins, mix=wl.mix,
+                    psi_init=wl.psi_init, flags=getattr(wl, "flags", 15), dt=wl.dt, nu=wl.nu, C0=wl.C0,
+                    CT=c["CT"], Cs=c["Cs"], Ct=c["Ct"], Cmu=c["Cmu"], kappa=c["kappa"], Ewall=c["Ewall"],
+                    yp=wl.yp, Lx=m.Lx, Ly=m.Ly, device=device)
+        args.update(kw)
+        return cls(**args)
+
+    # -- helpers -----------------------------------------------------------------
+    def _check(self, status: int, what: str) -> None:
+        if status != PDF_OK:
+            msg = ""
+            if self.ctx:
+                raw = load_library().pdf_error_string(self.ctx)
+                msg = raw.decode() if raw else ""
+            raise PdfError(int(status), f"{what}: {msg}")
+
+    def close(self) -> None:
+        if getattr(self, "ctx", None) and self.ctx.value:
+            load_library().pdf_destroy(self.ctx)
+            self.ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- the C ABI, call for call -------------------------------------------------
+    def step(self, n: int = 1) -> None:
+        self._check(load_library().pdf_step(self.ctx, int(n)), "pdf_step")
+
+    def sync(self) -> None:
+        self._check(load_library().pdf_sync(self.ctx), "pdf_sync")
+
+    def steps_done(self) -> int:
+        return int(load_library().pdf_steps_done(self.ctx))
+
+    def count(self, ens: int = 0) -> int:
+        return int(load_library().pdf_count(self.ctx, int(ens)))
+
+    def statistics_device(self):
+        """Statistics of the current state as a device tensor (nens, nelem, nstat)."""
+        out = self.torch.empty((self.nens, self.nelem, self.nstat), dtype=self.torch.float64, device=self.device)
+        self._check(load_library().pdf_estimate_statistics(self.ctx, ctypes.c_void_p(out.data_ptr()), 0),
+                    "pdf_estimate_statistics")
+        return out
+
+    def statistics(self) -> np.ndarray:
+        out = np.zeros((self.nens, self.nelem, self.nstat))
+        self._check(load_library().pdf_estimate_statistics(self.ctx, _ptr(out), 1), "pdf_estimate_statistics")
+        return out
+
+    def state_device(self, ens: int = 0):
+        n = self.count(ens)
+        vals = self.torch.empty((6, n), dtype=self.torch.float64, device=self.device)
+        elem = self.torch.empty((n,), dtype=self.torch.int32, device=self.device)
+        self._check(load_library().pdf_get_state(self.ctx, int(ens), ctypes.c_void_p(vals.data_ptr()),
+                                                 ctypes.c_void_p(elem.data_ptr())), "pdf_get_state")
+        return vals, elem
+
+    def state(self, ens: int = 0) -> dict:
+        vals, elem = self.state_device(ens)
+        self.stream.synchronize()
+        v = vals.cpu().numpy()
+        return dict(x=v[0], y=v[1], u=v[2], v=v[3], w=v[4], psi=v[5], elem=elem.cpu().numpy())

@@ -1,0 +1,201 @@
+"""Parity of the HIP library (through its C ABI) with the CPU oracle.
+
+Bar:
+* particle position, velocity and element index: bit-exact over the whole run
+  (they do not depend on the statistics, and both sides perform the same IEEE
+  operations in the same order);
+* scalar and statistics: within 1e-5 of the oracle, scale-aware
+  (|a - b| <= 1e-5 max(|b|, s), s the element's standard deviation to the
+  moment's order), because sums over an element's particles are added in a
+  different order on the two sides;
+* counts and histograms: exact.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1003_4548_amd as P
+    P.load_library()
+    return P
+
+
+def _label(wl, extra=""):
+    print(f"[case] {wl.name} n={wl.n_total} ens={wl.nens} {wl.precision} {extra}", flush=True)
+
+
+def assert_state_parity(g, o, psi_exact=False, what=""):
+    for k in ("x", "y", "u", "v", "w", "elem"):
+        if not np.array_equal(g[k], o[k]):
+            bad = np.nonzero(g[k] != o[k])[0]
+            raise AssertionError(f"{what}: {k} differs at {bad.size} particles, first id {bad[0]}: "
+                                 f"gpu {g[k][bad[0]]!r} oracle {o[k][bad[0]]!r}")
+    if psi_exact:
+        np.testing.assert_array_equal(g["psi"], o["psi"])
+    else:
+        np.testing.assert_allclose(g["psi"], o["psi"], rtol=TOL, atol=1e-6, err_msg=what)
+
+
+def assert_stats_parity(sg, so, moments, hist_bins, what=""):
+    """Scale-aware comparison of statistics records (nelem x nstat)."""
+    np.testing.assert_array_equal(sg[:, O.ST_N], so[:, O.ST_N], err_msg=what)
+    m2 = so[:, O.ST_M2:O.ST_M2 + 10]
+    diag = m2[:, [0, 4, 7, 9]]                              # uu vv ww psipsi
+    sig = np.sqrt(np.maximum(diag, 0.0))
+    tiny = 1e-30
+
+    def close(a, b, scale, name):
+        err = np.abs(a - b)
+        lim = TOL * np.maximum(np.abs(b), np.maximum(scale, tiny))
+        bad = err > lim
+        if bad.any():
+            i = np.argwhere(bad)[0]
+            raise AssertionError(f"{what}: {name} differs at {tuple(i)}: gpu {a[tuple(i)]!r} "
+                                 f"oracle {b[tuple(i)]!r} (scale {np.broadcast_to(scale, a.shape)[tuple(i)]!r})")
+
+    close(sg[:, O.ST_MEAN:O.ST_MEAN + 4], so[:, O.ST_MEAN:O.ST_MEAN + 4], sig, "means")
+    pairs = [(a, b) for a in range(4) for b in range(a, 4)]
+    sc2 = np.stack([sig[:, a] * sig[:, b] for a, b in pairs], axis=1)
+    close(sg[:, O.ST_M2:O.ST_M2 + 10], m2, sc2, "second moments")
+    np.testing.assert_array_equal(sg[:, O.ST_BINN:O.ST_BINN + 8], so[:, O.ST_BINN:O.ST_BINN + 8], err_msg=what)
+    close(sg[:, O.ST_BINM:O.ST_BINM + 8], so[:, O.ST_BINM:O.ST_BINM + 8], sig[:, 3:4], "bin means")
+    off = O.NSTAT_2
+    if moments >= 4:
+        trip = [(a, b, c) for a in range(4) for b in range(a, 4) for c in range(b, 4)]
+        quad = [(a, b, c, d) for a in range(4) for b in range(a, 4) for c in range(b, 4) for d in range(c, 4)]
+        sc3 = np.stack([sig[:, a] * sig[:, b] * sig[:, c] for a, b, c in trip], axis=1)
+        sc4 = np.stack([sig[:, a] * sig[:, b] * sig[:, c] * sig[:, d] for a, b, c, d in quad], axis=1)
+        close(sg[:, O.ST_M3:O.ST_M3 + 20], so[:, O.ST_M3:O.ST_M3 + 20], sc3, "third moments")
+        close(sg[:, O.ST_M4:O.ST_M4 + 35], so[:, O.ST_M4:O.ST_M4 + 35], sc4, "fourth moments")
+        off = O.NSTAT_4
+    if hist_bins:
+        np.testing.assert_array_equal(sg[:, off:off + hist_bins], so[:, off:off + hist_bins], err_msg=what)
+
+
+CASES = {
+    "config1_f64": lambda: W.config1(),
+    "tiny_canyon_glm_f32": lambda: W.tiny_canyon(precision="f32", steps=40),
+    "tiny_canyon_glm_f64": lambda: W.tiny_canyon(precision="f64", steps=20),
+    "small_canyon_wallfn_m4_hist": lambda: W.small_canyon(target=600, ppe=30, wallfn=True, moments=4,
+                                                          hist_bins=32, steps=30),
+    "tiny_canyon_3_ensembles": lambda: W.tiny_canyon(precision="f32", nens=3, steps=20),
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_seeding_bit_exact(gpu, case):
+    wl = CASES[case]()
+    _label(wl, "seeding")
+    sim = gpu.Simulation.from_workload(wl)
+    sim.sync()
+    orc = O.Oracle(wl)
+    for en in range(wl.nens):
+        assert_state_parity(sim.state(en), orc.state(en), psi_exact=True, what=f"{case} seed ens {en}")
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_trajectory_parity(gpu, case):
+    wl = CASES[case]()
+    _label(wl, "trajectory")
+    sim = gpu.Simulation.from_workload(wl)
+    orc = O.Oracle(wl)
+    done = 0
+    checkpoints = sorted({1, 2, max(1, wl.steps // 4), wl.steps})
+    for cp in checkpoints:
+        sim.step(cp - done)
+        orc.step(cp - done)
+        done = cp
+        sim.sync()
+        assert sim.steps_done() == done
+        for en in range(wl.nens):
+            assert_state_parity(sim.state(en), orc.state(en), what=f"{case} step {done} ens {en}")
+    sg = sim.statistics()
+    for en in range(wl.nens):
+        assert_stats_parity(sg[en], orc.stats(en), wl.moments, wl.hist_bins, what=f"{case} ens {en}")
+
+
+@pytest.mark.parametrize("case", ["config1_f64", "tiny_canyon_glm_f32", "small_canyon_wallfn_m4_hist"])
+def test_statistics_on_gpu_state(gpu, case):
+    """Estimation alone: the oracle's statistics of the GPU's own state."""
+    wl = CASES[case]()
+    _label(wl, "stats on gpu state")
+    sim = gpu.Simulation.from_workload(wl)
+    sim.step(7)
+    sim.sync()
+    orc = O.Oracle(wl)
+    g = sim.state()
+    orc.set_state(g)
+    assert_stats_parity(sim.statistics()[0], orc.stats(), wl.moments, wl.hist_bins, what=case)
+
+
+@pytest.mark.parametrize("case", ["config1_f64", "tiny_canyon_glm_f32"])
+def test_one_step_from_gpu_state(gpu, case):
+    """The scalar after one step from the GPU's own state (IECM with the GPU's
+    statistics order) and the full state, step by step."""
+    wl = CASES[case]()
+    _label(wl, "per-step")
+    sim = gpu.Simulation.from_workload(wl)
+    orc = O.Oracle(wl)
+    for n in range(5):
+        g0 = sim.state()
+        orc.set_state(g0)
+        orc.step_index = n
+        orc.step(1)
+        sim.step(1)
+        sim.sync()
+        assert_state_parity(sim.state(), orc.state(), what=f"{case} step {n}")
+
+
+@pytest.mark.parametrize("flags", [4, 1, 2, 8 | 2])
+def test_substeps(gpu, flags):
+    wl = W.tiny_canyon(precision="f32", steps=3)
+    wl.flags = flags
+    _label(wl, f"flags={flags}")
+    sim = gpu.Simulation.from_workload(wl)
+    orc = O.Oracle(wl)
+    sim.step(3)
+    orc.step(3)
+    sim.sync()
+    assert_state_parity(sim.state(), orc.state(), what=f"flags {flags}")
+
+
+def test_counts_and_invariants_config1(gpu):
+    wl = W.config1()
+    _label(wl, "invariants")
+    sim = gpu.Simulation.from_workload(wl)
+    psi0 = sim.state()["psi"].sum()
+    sim.step(100)
+    sim.sync()
+    st = sim.statistics()[0]
+    assert st[:, O.ST_N].sum() == 40000
+    s = sim.state()
+    assert s["psi"].min() >= 0 and s["psi"].max() <= 1
+    assert abs(s["psi"].sum() - psi0) < 40000 * 1e-13
+
+
+def test_config2_full_size_parity(gpu):
+    """The 1M-particle canyon in the launch configuration the benchmark times."""
+    wl = W.config2(steps=3)
+    _label(wl, "full size")
+    sim = gpu.Simulation.from_workload(wl)
+    orc = O.Oracle(wl)
+    sim.step(3)
+    orc.step(3)
+    sim.sync()
+    assert_state_parity(sim.state(), orc.state(), what="config2")
+    g = sim.state()
+    orc.set_state(g)
+    assert_stats_parity(sim.statistics()[0], orc.stats(), wl.moments, wl.hist_bins, what="config2 stats")
