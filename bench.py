@@ -1,0 +1,215 @@
+"""Throughput of the particle-in-cell joint PDF step on one MI355X.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload canyon1m|canyon10m|square40k]
+
+One step = one pass of the whole hot path over every particle: statistics of
+each element (means, Reynolds stresses, scalar moments, velocity-binned
+<phi|V>), IECM, Langevin velocity, position, tracking with wall/periodic
+conditions, source, re-binning into element segments.  Inputs are resident in
+HBM before the timed region.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, GB/s
+
+WORKLOADS = {
+    "canyon1m": ("config2", "street canyon, 9912-element Delaunay mesh, 1M particles, GLM, FP32 state"),
+    "canyon10m": ("config3", "wall-function canyon, 48618-element mesh, 10M particles, SLM, 4th moments + histograms"),
+    "square40k": ("config1", "unit square 20x20x2, 40k particles, SLM, FP64"),
+}
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_1003_4548_amd", "csrc")
+    for fn in sorted(os.listdir(d)):
+        if fn.endswith((".hip", ".hpp")):
+            with open(os.path.join(d, fn), "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes(wl) -> dict:
+    """Bytes one step must move at minimum in this design.
+
+    Per particle: read x y u v w psi id, write the same (7 words of state
+    type each way).  Per element cell: the statistics record written, the
+    cell's start/capacity/count/rate words, its mesh record and an even share
+    of the vertex coefficient table.
+    """
+    ts = 4 if wl.precision == "f32" else 8
+    per_particle = 2 * (6 * ts + 4)
+    nstat = (86 if wl.moments >= 4 else 31) + wl.hist_bins
+    ne, nv = wl.mesh.nelem, wl.mesh.nvert
+    ncell = ne * wl.nens
+    per_cell = nstat * 8 + 4 * 4 + ts
+    per_mesh = ne * (3 * 4 * 3 + 8 + 3 * 8) + nv * (2 * 8 + 16 * ts)
+    n = wl.n_total
+    total = n * per_particle + ncell * per_cell + per_mesh
+    return dict(per_particle=per_particle, per_cell=per_cell, per_step=total, particles=n)
+
+
+def read_traffic(workload: str, src_hash: str):
+    """HBM bytes per step from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source."""
+    fn = os.path.join(ROOT, "profiles", f"hbm_traffic_k_step_{workload}.txt")
+    if not os.path.exists(fn):
+        return None
+    vals = {}
+    for line in open(fn):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_hash") != src_hash:
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(wl_fn, seconds: float = 15.0) -> dict:
+    """The oracle on the host cores, on a bounded sample of the same workload:
+    the full particle set, as many whole steps as fit in about `seconds`."""
+    import oracle as O
+    threads = min(16, os.cpu_count() or 1)
+    wl = wl_fn()
+    orc = O.Oracle(wl, threads=threads)
+    orc.step(1)                       # warm caches; the first step is not timed
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        orc.step(1)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= seconds or steps >= 50:
+            break
+    n = wl.n_total
+    return {"value": n * steps / el, "unit": "particle-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"{wl.name}: all {n} particles, {steps} steps after one untimed step, {el:.1f} s"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="canyon1m", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--secondary", default="canyon10m", help="second workload reported in the same line ('' for none)")
+    ap.add_argument("--secondary-steps", type=int, default=100)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy (counter calibration under rocprofv3)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs on one GPU only; the batched-ensemble and mesh-partition "
+              "designs for several GPUs are described in DESIGN.md but not launched", file=sys.stderr)
+        return 2
+
+    import torch
+    import workloads as W
+    from paper_1003_4548_amd import Simulation
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        return 1
+    src_hash = kernel_source_hash()
+
+    def run(name, steps, warmup):
+        cfg_fn = getattr(W, WORKLOADS[name][0])
+        wl = cfg_fn(steps=steps)
+        sim = Simulation.from_workload(wl, device="cuda:0")
+        print(f"[bench] {name}: {wl.n_total} particles, {wl.mesh.nelem} elements, warmup {warmup}", file=sys.stderr, flush=True)
+        sim.step(warmup)
+        sim.sync()
+        stream = sim.stream
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(stream)
+        sim.step(steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        sim.sync()
+        assert sim.steps_done() == warmup + steps
+        wall = t1 - t0
+        kern_ms = e0.elapsed_time(e1) / steps
+        ab = algorithmic_bytes(wl)
+        achieved = ab["per_step"] / (kern_ms * 1e-3) / 1e9
+        traffic = read_traffic(name, src_hash)
+        res = {
+            "value": wl.n_total * steps / wall,
+            "ms_per_step": 1e3 * wall / steps,
+            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                         "kernel": "k_step", "kernel_ms": round(kern_ms, 5),
+                         "algorithmic_bytes_per_step": ab["per_step"],
+                         "algorithmic_bytes_per_particle": ab["per_particle"]},
+            "config": {"workload": WORKLOADS[name][1], "preset": name, "particles": wl.n_total,
+                       "elements": wl.mesh.nelem, "vertices": wl.mesh.nvert, "ensembles": wl.nens,
+                       "state_dtype": wl.precision, "statistics_dtype": "f64", "model": wl.describe()["model"],
+                       "moments": wl.moments, "hist_bins": wl.hist_bins, "dt": wl.dt,
+                       "kernel_source_hash": src_hash},
+            "wl_fn": (cfg_fn, steps),
+        }
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+        return res
+
+    main_res = run(args.workload, args.steps, args.warmup)
+    out = {
+        "metric": "particle-steps/s",
+        "value": round(main_res["value"], 1),
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(main_res["ms_per_step"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if main_res["config"]["state_dtype"] == "f32" else "f64",
+        "data": "synthetic",
+        "config": main_res["config"],
+        "roofline": main_res["roofline"],
+    }
+    if args.secondary and args.secondary != args.workload:
+        sec = run(args.secondary, args.secondary_steps, max(5, args.warmup // 2))
+        out["secondary"] = {"value": round(sec["value"], 1), "unit": "particle-steps/s",
+                            "steps": args.secondary_steps, "ms_per_step": round(sec["ms_per_step"], 5),
+                            "config": sec["config"], "roofline": sec["roofline"]}
+    if args.calibrate_copy:
+        nbytes = 1 << 30
+        a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda:0").fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = nbytes
+        del a, b
+    if not args.no_cpu_baseline:
+        cfg_fn, _ = main_res["wl_fn"]
+        out["cpu_baseline"] = cpu_baseline(lambda: cfg_fn(steps=1), args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

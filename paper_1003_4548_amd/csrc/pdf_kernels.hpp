@@ -10,12 +10,12 @@
 //              kinds (i32), 1/(2 area) (f64), wall-function alpha per edge.
 //   vertices   16 drift/diffusion coefficients per vertex (T), row-major.
 //
-// One wavefront (64 lanes) owns one cell per step.  It reads the segment,
-// estimates the cell's statistics with lane-strided FP64 accumulators and
-// cross-lane butterflies (no atomics), uses them for IECM, advances every
-// particle, tracks it through the mesh, and appends it to the segment of its
-// new cell in the other buffer.  Appends are counted per wavefront: lanes with
-// the same destination share one atomic add on that cell's counter.
+// One wavefront (64 lanes) owns one cell per step.  It reads the segment once
+// into LDS, estimates the cell's statistics with lane-strided FP64
+// accumulators and DPP row reductions (no atomics), uses them for IECM,
+// advances every particle, tracks it through the mesh, writes the particles
+// that stay back to its own segment in order, and appends the ones that move
+// to their new cell's segment with one atomic per particle.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -44,40 +44,53 @@ constexpr int WAVES_PER_BLOCK = BLOCK / WAVE;
 // Control block in device memory.
 struct Ctl {
   uint32_t step;      // Philox step word of the next step
-  uint32_t parity;    // buffer holding the current state
+  uint32_t parity;    // particle buffer holding the current state
+  uint32_t crot;      // counter set holding the current counts (0..2)
   int32_t error;      // OR of ERR_* raised since seeding
   int32_t halt;       // set at the end of a step that raised an error
-  uint32_t done;      // workgroups finished in the running launch
+  uint32_t spare;
   uint32_t ovf;       // particles written to the overflow area
+  uint32_t lost;
   int64_t steps_done; // steps completed since seeding
-  uint32_t lost;      // particles the walk could not place
-  uint32_t pad[9];
+  uint32_t pad[6];
 };
 
-struct MeshDev {
-  const double* vtx;
-  const int32_t* tri;
-  const int32_t* nbr;
-  const int32_t* ekind;
-  const double* inv2a;
-  const double* alpha;
-  int32_t ne;
-  int32_t nv;
-  double Lx, Ly;
+// Element record for tracking: vertex coordinates and, per edge k
+// (v_k -> v_k+1), code = kind | (neighbour + 1) << 4.  64 bytes, one
+// vector-load group per walk step.
+struct alignas(64) ERec {
+  double x[3];
+  double y[3];
+  int32_t code[3];
+  int32_t pad;
 };
+static_assert(sizeof(ERec) == 64, "element record must be 64 bytes");
 
 template <typename T> struct StateDev {
   T* x; T* y; T* u; T* v; T* w; T* psi;
   uint32_t* id;
 };
 
+// A cell's particles sit in two runs of its segment: the ones that stayed in
+// the element, written by the cell's own wavefront from the bottom
+// (count ns), and the ones that arrived from other elements, appended from the
+// top with an atomic counter (count nm).  Counter sets rotate over three
+// buffers: the current counts (read only), the next counts (being written),
+// and the set two steps back, cleared for the step after.
 template <typename T> struct StepArgs {
-  MeshDev mesh;
+  const ERec* erec;       // ne
+  const int32_t* tri;     // ne x 3
+  const double* inv2a;    // ne
+  const double* alpha;    // ne x 3
+  double Lx, Ly;
+  int32_t ne;
+  int32_t ncell;
   const T* coef;          // nv x 16
   const T* rate;          // ncell
   const int32_t* start;   // ncell
   const int32_t* cap;     // ncell
-  int32_t* cnt[2];        // ncell each
+  int32_t* ns[3];         // ncell each
+  int32_t* nm[3];         // ncell each
   StateDev<T> buf[2];
   StateDev<T> ovf;        // overflow area
   int32_t* ovf_cell;
@@ -86,7 +99,6 @@ template <typename T> struct StepArgs {
   const uint64_t* seed;   // nens
   const double* src;      // nens x 3
   Ctl* ctl;
-  int32_t ncell;
   int32_t nstat;
   int32_t flags;
   int32_t mix;
@@ -101,17 +113,71 @@ __device__ __forceinline__ int xcd_block(int b, int G) {
   return (x < r) ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
-  return v;
-}
-
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (WAVE - 1); }
 
 __device__ __forceinline__ uint64_t lanemask_lt() {
   const int l = lane_id();
   return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+template <int CTRL> __device__ __forceinline__ double dpp_f64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffll), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
+}
+
+// Sum over the 64 lanes, returned wave-uniform.  Rows of 16 lanes are reduced
+// with DPP (quad swaps, half-row and row mirrors: every lane of a row ends with
+// the same row sum), then the four row sums are combined in a fixed order.
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_f64<0x141>(v);  // row_half_mirror
+  v += dpp_f64<0x140>(v);  // row_mirror
+  const double r0 = readlane_f64(v, 0), r1 = readlane_f64(v, 16);
+  const double r2 = readlane_f64(v, 32), r3 = readlane_f64(v, 48);
+  return (r0 + r1) + (r2 + r3);
+}
+
+// Sums of K per-lane values, delivered transposed: lane q (q < K) receives
+// the wave sum of value q, other lanes 0.  Quads are reduced with DPP, the 16
+// quad sums of each value go through LDS (row stride 17 doubles against bank
+// conflicts), and lane q adds its 16 quad sums in order.  The order of every
+// addition is fixed, so the result does not depend on timing.
+constexpr int RED_STRIDE = 17;
+
+template <int K>
+__device__ __forceinline__ double wave_sums_to_lanes(const double (&vals)[K], double* red) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    double v = vals[q];
+    v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
+    v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
+    if ((lane & 3) == 0) red[q * RED_STRIDE + (lane >> 2)] = v;
+  }
+  double s = 0.0;
+  if (lane < K) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) s += red[lane * RED_STRIDE + r];
+  }
+  return s;
+}
+
+template <typename T> __device__ __forceinline__ T pick3(const T* a, int k) {
+  return k == 0 ? a[0] : (k == 1 ? a[1] : a[2]);
+}
+
+__device__ __forceinline__ int slot_of(int j, int start, int ns, int nm, int capc) {
+  return j < ns ? start + j : start + capc - nm + (j - ns);
 }
 
 // ---------------------------------------------------------------------------
@@ -120,64 +186,66 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
 // whose endpoints the line start->target separates; if rounding leaves none,
 // the edge the target is most outside of.  Walls mirror the rest of the path
 // about the wall line and reflect the velocity; periodic edges shift the path
-// by one period into the partner element.
+// by one period into the partner element.  R holds the record of element e.
 
 template <typename T>
-__device__ int walk(const MeshDev& M, int e, double Sx, double Sy, T& tx, T& ty, T& u, T& v, T& w) {
+__device__ int walk(const StepArgs<T>& a, ERec R, int e, double Sx, double Sy, T& tx, T& ty, T& u, T& v,
+                    T& w) {
 #pragma unroll 1
   for (int it = 0; it < 64; ++it) {
     const double Tx = (double)tx, Ty = (double)ty;
-    const int i0 = M.tri[3 * e], i1 = M.tri[3 * e + 1], i2 = M.tri[3 * e + 2];
-    double px[3], py[3];
-    px[0] = M.vtx[2 * i0]; py[0] = M.vtx[2 * i0 + 1];
-    px[1] = M.vtx[2 * i1]; py[1] = M.vtx[2 * i1 + 1];
-    px[2] = M.vtx[2 * i2]; py[2] = M.vtx[2 * i2 + 1];
-    double o[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const int k1 = k == 2 ? 0 : k + 1;
-      o[k] = orient_edge(px[k], py[k], px[k1], py[k1], Tx, Ty);
-    }
-    if (o[0] >= 0.0 && o[1] >= 0.0 && o[2] >= 0.0) return e;
+    const double o0 = orient_edge(R.x[0], R.y[0], R.x[1], R.y[1], Tx, Ty);
+    const double o1 = orient_edge(R.x[1], R.y[1], R.x[2], R.y[2], Tx, Ty);
+    const double o2 = orient_edge(R.x[2], R.y[2], R.x[0], R.y[0], Tx, Ty);
+    if (o0 >= 0.0 && o1 >= 0.0 && o2 >= 0.0) return e;
     int ex = -1;
+    {
+      const double o[3] = {o0, o1, o2};
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const int k1 = k == 2 ? 0 : k + 1;
-      if (ex < 0 && o[k] < 0.0) {
-        const double sa = orient2d(Sx, Sy, Tx, Ty, px[k], py[k]);
-        const double sb = orient2d(Sx, Sy, Tx, Ty, px[k1], py[k1]);
-        if ((sa <= 0.0 && sb >= 0.0) || (sa >= 0.0 && sb <= 0.0)) ex = k;
+      for (int k = 0; k < 3; ++k) {
+        const int k1 = k == 2 ? 0 : k + 1;
+        if (ex < 0 && o[k] < 0.0) {
+          const double sa = orient2d(Sx, Sy, Tx, Ty, R.x[k], R.y[k]);
+          const double sb = orient2d(Sx, Sy, Tx, Ty, R.x[k1], R.y[k1]);
+          if ((sa <= 0.0 && sb >= 0.0) || (sa >= 0.0 && sb <= 0.0)) ex = k;
+        }
+      }
+      if (ex < 0) {
+        ex = 0;
+        if (o1 < o0) ex = 1;
+        if (o2 < (ex == 0 ? o0 : o1)) ex = 2;
       }
     }
-    if (ex < 0) {
-      ex = 0;
-      if (o[1] < o[ex]) ex = 1;
-      if (o[2] < o[ex]) ex = 2;
-    }
-    const int kind = M.ekind[3 * e + ex];
+    const int code = pick3(R.code, ex);
+    const int kind = code & 15;
+    const int nb = (code >> 4) - 1;
     if (kind == EDGE_INTERIOR) {
-      e = M.nbr[3 * e + ex];
+      e = nb;
+      R = a.erec[e];
       continue;
     }
     if (kind >= EDGE_PXP) {
       double sx = 0.0, sy = 0.0;
-      if (kind == EDGE_PXP) sx = M.Lx;
-      if (kind == EDGE_PXM) sx = -M.Lx;
-      if (kind == EDGE_PYP) sy = M.Ly;
-      if (kind == EDGE_PYM) sy = -M.Ly;
+      if (kind == EDGE_PXP) sx = a.Lx;
+      if (kind == EDGE_PXM) sx = -a.Lx;
+      if (kind == EDGE_PYP) sy = a.Ly;
+      if (kind == EDGE_PYM) sy = -a.Ly;
       Sx = Sx + sx;
       Sy = Sy + sy;
       tx = tx + (T)sx;
       ty = ty + (T)sy;
-      e = M.nbr[3 * e + ex];
+      e = nb;
+      R = a.erec[e];
       continue;
     }
     const int ex1 = ex == 2 ? 0 : ex + 1;
-    const double ax = px[ex], ay = py[ex];
-    const double gx = px[ex1] - ax, gy = py[ex1] - ay;
+    const double ax = pick3(R.x, ex), ay = pick3(R.y, ex);
+    const double bx = pick3(R.x, ex1), by = pick3(R.y, ex1);
+    const double gx = bx - ax, gy = by - ay;
     const double len = sqrt(gx * gx + gy * gy);
     const double nx = gy / len, ny = -gx / len;  // outward unit normal
-    const double oS = orient_edge(ax, ay, px[ex1], py[ex1], Sx, Sy), oT = o[ex];
+    const double oS = orient_edge(ax, ay, bx, by, Sx, Sy);
+    const double oT = ex == 0 ? o0 : (ex == 1 ? o1 : o2);
     const double den = oS - oT;
     const double tpar = den > 0.0 ? oS / den : 0.0;
     const double Ix = Sx + tpar * (Tx - Sx), Iy = Sy + tpar * (Ty - Sy);
@@ -186,7 +254,7 @@ __device__ int walk(const MeshDev& M, int e, double Sx, double Sy, T& tx, T& ty,
     ty = (T)(Ty - (2.0 * d) * ny);
 #pragma unroll 1
     for (int j = 0; j < 8; ++j) {
-      if (!(orient_edge(ax, ay, px[ex1], py[ex1], (double)tx, (double)ty) < 0.0)) break;
+      if (!(orient_edge(ax, ay, bx, by, (double)tx, (double)ty) < 0.0)) break;
       if (nx != 0.0) tx = next_toward(tx, -nx);
       if (ny != 0.0) ty = next_toward(ty, -ny);
     }
@@ -204,7 +272,7 @@ __device__ int walk(const MeshDev& M, int e, double Sx, double Sy, T& tx, T& ty,
       const T tX = -nyT, tY = nxT;
       const T Vi = -(u * nxT + v * nyT);
       const T Ui = u * tX + v * tY;
-      const T al = (T)M.alpha[3 * e + ex];
+      const T al = (T)a.alpha[3 * e + ex];
       const T Ur = Ui + al * Vi;
       const T Vr = -Vi;
       u = Ur * tX + Vr * (-nxT);
@@ -215,10 +283,19 @@ __device__ int walk(const MeshDev& M, int e, double Sx, double Sy, T& tx, T& ty,
 }
 
 // ---------------------------------------------------------------------------
-// the fused step: statistics of the cell, then IECM, velocity, position,
-// tracking, source and append.  ADVANCE = false only estimates statistics.
+// the fused step.  One wavefront per cell:
+//   A  read the cell's particles once from HBM into an LDS tile (the first
+//      TILE of them; a larger cell re-reads the rest from L2) and sum the
+//      velocity and scalar: the means;
+//   B  central moments, velocity-bin counts and scalar sums, histogram: the
+//      statistics record of the cell;
+//   C  IECM with those statistics, velocity, position, tracking, source;
+//      stayers are written back in order without atomics, movers are
+//      appended to their new cell.
+// ADVANCE = false stops after B.
 
 template <int MOM> struct MomCount { static constexpr int M3 = 0, M4 = 0; };
+template <> struct MomCount<4> { static constexpr int M3 = 20, M4 = 35; };
 
 // position of (x, y), x <= y, in the lexicographic list of index pairs of (u, v, w, psi)
 __host__ __device__ constexpr int pair_index(int x, int y) { return x * 4 - (x * (x - 1)) / 2 + (y - x); }
@@ -226,172 +303,246 @@ __host__ __device__ constexpr int pair_index(int x, int y) { return x * 4 - (x *
 // position of (x, y, z), x <= y <= z, in the lexicographic list of index triples
 __host__ __device__ constexpr int triple_index(int x, int y, int z) {
   int it = 0;
-  for (int a = 0; a < 4; ++a)
-    for (int b = a; b < 4; ++b)
-      for (int c = b; c < 4; ++c)
-        if (a < x || (a == x && (b < y || (b == y && c < z)))) ++it;
+  for (int p = 0; p < 4; ++p)
+    for (int q = p; q < 4; ++q)
+      for (int r = q; r < 4; ++r)
+        if (p < x || (p == x && (q < y || (q == y && r < z)))) ++it;
   return it;
 }
-template <> struct MomCount<4> { static constexpr int M3 = 20, M4 = 35; };
+
+constexpr int TILE = 256;  // particles of a cell staged in LDS
+constexpr int RED_MAX = 20; // values reduced together
+
+template <typename T> struct Tile {
+  T x[TILE], y[TILE], u[TILE], v[TILE], w[TILE], psi[TILE];
+  uint32_t id[TILE];
+};
 
 template <typename T, int MOM, int HIST, bool ADVANCE>
 __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a) {
+  __shared__ Tile<T> tiles[WAVES_PER_BLOCK];
+  __shared__ double red_lds[WAVES_PER_BLOCK][RED_MAX * RED_STRIDE];
   __shared__ int hist_lds[WAVES_PER_BLOCK][HIST > 0 ? HIST : 1];
   Ctl* ctl = a.ctl;
   if (ADVANCE && ctl->halt) return;
   const uint32_t step = ctl->step;
   const uint32_t par = ctl->parity;
+  const uint32_t rot = ctl->crot;
   const int lane = lane_id();
-  const int wid = threadIdx.x / WAVE;
+  const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
   const int cell = xcd_block(blockIdx.x, gridDim.x) * WAVES_PER_BLOCK + wid;
-  const StateDev<T> src = a.buf[par];
-  const StateDev<T> dst = a.buf[par ^ 1u];
-  int32_t* cnt_src = a.cnt[par];
-  int32_t* cnt_dst = a.cnt[par ^ 1u];
+  const int rc = (int)rot, rn = (int)(rot == 2 ? 0 : rot + 1), rz = (int)(rot == 0 ? 2 : rot - 1);
 
   if (cell < a.ncell) {
-    const int ne = a.mesh.ne;
+    const StateDev<T> src = a.buf[par];
+    const StateDev<T> dst = a.buf[par ^ 1u];
+    Tile<T>& L = tiles[wid];
+    const int ne = a.ne;
     const int ens = cell / ne;
     const int e = cell - ens * ne;
     const int start = a.start[cell];
-    int n = cnt_src[cell];
     const int capc = a.cap[cell];
-    if (n > capc) n = capc;
-
-    // pass 1: means
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    for (int j = lane; j < n; j += WAVE) {
-      s0 += (double)src.u[start + j];
-      s1 += (double)src.v[start + j];
-      s2 += (double)src.w[start + j];
-      s3 += (double)src.psi[start + j];
-    }
+    // counts are clamped to the segment so that even the step after an
+    // overflow (whose results are void) reads inside the segment
+    const int ns = min(a.ns[rc][cell], capc);
+    const int nm = min(a.nm[rc][cell], capc - ns);
+    const int n = ns + nm;
     const double dn = (double)n;
-    double mean[4];
-    mean[0] = n > 0 ? wave_sum(s0) / dn : 0.0;
-    mean[1] = n > 0 ? wave_sum(s1) / dn : 0.0;
-    mean[2] = n > 0 ? wave_sum(s2) / dn : 0.0;
-    mean[3] = n > 0 ? wave_sum(s3) / dn : 0.0;
 
-    // pass 2: central moments, velocity bins, histogram
-    constexpr int NM3 = MomCount<MOM>::M3, NM4 = MomCount<MOM>::M4;
-    double m2[10], m3[NM3 > 0 ? NM3 : 1], m4[NM4 > 0 ? NM4 : 1];
-    double bn[8], bs[8];
+    // ---- A: load, stage, means ----
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    {
+      // the staged part: all TILE/WAVE loads in flight together
+      T tx_[TILE / WAVE], ty_[TILE / WAVE], tu_[TILE / WAVE], tv_[TILE / WAVE], tw_[TILE / WAVE], tp_[TILE / WAVE];
+      uint32_t ti_[TILE / WAVE];
 #pragma unroll
-    for (int q = 0; q < 10; ++q) m2[q] = 0.0;
+      for (int c = 0; c < TILE / WAVE; ++c) {
+        const int j = c * WAVE + lane;
+        if (j < n) {
+          const int s = slot_of(j, start, ns, nm, capc);
+          tx_[c] = src.x[s]; ty_[c] = src.y[s]; tu_[c] = src.u[s]; tv_[c] = src.v[s]; tw_[c] = src.w[s];
+          tp_[c] = src.psi[s]; ti_[c] = src.id[s];
+        }
+      }
 #pragma unroll
-    for (int q = 0; q < (NM3 > 0 ? NM3 : 1); ++q) m3[q] = 0.0;
+      for (int c = 0; c < TILE / WAVE; ++c) {
+        const int j = c * WAVE + lane;
+        if (j < n) {
+          L.x[j] = tx_[c]; L.y[j] = ty_[c]; L.u[j] = tu_[c]; L.v[j] = tv_[c]; L.w[j] = tw_[c]; L.psi[j] = tp_[c];
+          L.id[j] = ti_[c];
+          s0 += (double)tu_[c];
+          s1 += (double)tv_[c];
+          s2 += (double)tw_[c];
+          s3 += (double)tp_[c];
+        }
+      }
+    }
+    for (int base = TILE; base < n; base += WAVE) {
+      const int j = base + lane;
+      if (j < n) {
+        const int s = slot_of(j, start, ns, nm, capc);
+        const T u = src.u[s], v = src.v[s], w = src.w[s], p = src.psi[s];
+        s0 += (double)u;
+        s1 += (double)v;
+        s2 += (double)w;
+        s3 += (double)p;
+      }
+    }
+    double* red = red_lds[wid];
+    const double inv_n = n > 0 ? 1.0 / dn : 0.0;
+    double mean[4];
+    {
+      const double sums[4] = {s0, s1, s2, s3};
+      const double mean_l = wave_sums_to_lanes<4>(sums, red) * inv_n;
 #pragma unroll
-    for (int q = 0; q < (NM4 > 0 ? NM4 : 1); ++q) m4[q] = 0.0;
+      for (int q = 0; q < 4; ++q) mean[q] = readlane_f64(mean_l, q);
+    }
+
+    auto load4 = [&](int j, double* val) {
+      if (j < TILE) {
+        val[0] = (double)L.u[j]; val[1] = (double)L.v[j]; val[2] = (double)L.w[j]; val[3] = (double)L.psi[j];
+      } else {
+        const int s = slot_of(j, start, ns, nm, capc);
+        val[0] = (double)src.u[s]; val[1] = (double)src.v[s]; val[2] = (double)src.w[s]; val[3] = (double)src.psi[s];
+      }
+    };
+
+    // ---- B: second moments, bins, histogram ----
+    double acc[18];  // 10 second moments, 8 per-bin scalar sums
 #pragma unroll
-    for (int q = 0; q < 8; ++q) { bn[q] = 0.0; bs[q] = 0.0; }
+    for (int q = 0; q < 18; ++q) acc[q] = 0.0;
+    int bcount[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) bcount[q] = 0;
     if (HIST > 0) {
       for (int h = lane; h < HIST; h += WAVE) hist_lds[wid][h] = 0;
     }
-    for (int j = lane; j < n; j += WAVE) {
-      double val[4];
-      val[0] = (double)src.u[start + j];
-      val[1] = (double)src.v[start + j];
-      val[2] = (double)src.w[start + j];
-      val[3] = (double)src.psi[start + j];
-      double d[4];
+    for (int base = 0; base < n; base += WAVE) {
+      const int j = base + lane;
+      const bool act = j < n;
+      int bin = -1;
+      if (act) {
+        double val[4];
+        load4(j, val);
+        double d[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) d[q] = val[q] - mean[q];
-      double p2[10];
-      {
-        int idx = 0;
+        for (int q = 0; q < 4; ++q) d[q] = val[q] - mean[q];
 #pragma unroll
         for (int x = 0; x < 4; ++x)
 #pragma unroll
-          for (int y = x; y < 4; ++y) { p2[idx] = d[x] * d[y]; m2[idx] += p2[idx]; ++idx; }
+          for (int y = x; y < 4; ++y) acc[pair_index(x, y)] += d[x] * d[y];
+        bin = (val[0] > mean[0] ? 1 : 0) + (val[1] > mean[1] ? 2 : 0) + (val[2] > mean[2] ? 4 : 0);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc[10 + q] += (bin == q) ? val[3] : 0.0;
+        if (HIST > 0) {
+          const double hpos = floor(val[3] * (double)HIST);
+          const int hb = hpos < 0.0 ? 0 : (hpos >= (double)HIST ? HIST - 1 : (int)hpos);
+          atomicAdd(&hist_lds[wid][hb], 1);
+        }
       }
-      if constexpr (MOM >= 4) {
-        double p3[20];
-        int i3 = 0;
 #pragma unroll
-        for (int x = 0; x < 4; ++x)
-#pragma unroll
-          for (int y = x; y < 4; ++y)
-#pragma unroll
-            for (int z = y; z < 4; ++z) {
-              p3[i3] = p2[pair_index(x, y)] * d[z];
-              m3[i3] += p3[i3];
-              ++i3;
-            }
-        int i4 = 0;
-#pragma unroll
-        for (int x = 0; x < 4; ++x)
-#pragma unroll
-          for (int y = x; y < 4; ++y)
-#pragma unroll
-            for (int z = y; z < 4; ++z)
-#pragma unroll
-              for (int g = z; g < 4; ++g) {
-                m4[i4] += p3[triple_index(x, y, z)] * d[g];
-                ++i4;
-              }
-      }
-      const int bin = (val[0] > mean[0] ? 1 : 0) + (val[1] > mean[1] ? 2 : 0) + (val[2] > mean[2] ? 4 : 0);
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        bn[q] += (bin == q) ? 1.0 : 0.0;
-        bs[q] += (bin == q) ? val[3] : 0.0;
-      }
-      if (HIST > 0) {
-        const double hpos = floor(val[3] * (double)HIST);
-        const int hb = hpos < 0.0 ? 0 : (hpos >= (double)HIST ? HIST - 1 : (int)hpos);
-        atomicAdd(&hist_lds[wid][hb], 1);
-      }
+      for (int q = 0; q < 8; ++q) bcount[q] += (int)__popcll(__ballot(bin == q));
     }
+    const double sumB = wave_sums_to_lanes<18>(acc, red);
+    // lane q < 10: second moment q; lane 10 + b: scalar sum of bin b
+    double cnt_l = 0.0;
 #pragma unroll
-    for (int q = 0; q < 10; ++q) m2[q] = wave_sum(m2[q]);
-    if constexpr (MOM >= 4) {
-#pragma unroll
-      for (int q = 0; q < (NM3 > 0 ? NM3 : 1); ++q) m3[q] = wave_sum(m3[q]);
-#pragma unroll
-      for (int q = 0; q < (NM4 > 0 ? NM4 : 1); ++q) m4[q] = wave_sum(m4[q]);
-    }
+    for (int q = 0; q < 8; ++q) cnt_l = (lane == 10 + q) ? (double)bcount[q] : cnt_l;
+    const double bm_l = cnt_l > 0.0 ? sumB / cnt_l : mean[3];
     double bm[8];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      bn[q] = wave_sum(bn[q]);
-      bs[q] = wave_sum(bs[q]);
-      bm[q] = bn[q] > 0.0 ? bs[q] / bn[q] : mean[3];
-    }
+    for (int q = 0; q < 8; ++q) bm[q] = readlane_f64(bm_l, 10 + q);
     double* rec = a.stats + (size_t)cell * a.nstat;
-    if (lane == 0) {
-      if (n > 0) {
-        rec[ST_N] = dn;
+    {
+      // one store per lane: lanes 0-9 second moments, 10-17 bin means,
+      // 18-25 bin counts, 26 count, 27-30 means
+      int idx = -1;
+      double val = 0.0;
+      if (lane < 10) { idx = ST_M2 + lane; val = sumB * inv_n; }
+      else if (lane < 18) { idx = ST_BINM + (lane - 10); val = bm_l; }
+      else if (lane < 26) {
+        idx = ST_BINN + (lane - 18);
+        double c = 0.0;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) rec[ST_MEAN + q] = mean[q];
+        for (int q = 0; q < 8; ++q) c = (lane == 18 + q) ? (double)bcount[q] : c;
+        val = c;
+      } else if (lane == 26) { idx = ST_N; val = dn; }
+      else if (lane < 31) {
+        idx = ST_MEAN + (lane - 27);
+        double mq = mean[0];
 #pragma unroll
-        for (int q = 0; q < 10; ++q) rec[ST_M2 + q] = m2[q] / dn;
+        for (int q = 1; q < 4; ++q) mq = (lane == 27 + q) ? mean[q] : mq;
+        val = mq;
+      }
+      if (n == 0) val = 0.0;
+      if (idx >= 0) rec[idx] = val;
+    }
+    if constexpr (MOM >= 4) {
+      // third-order moments
+      double m3[20];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) { rec[ST_BINN + q] = bn[q]; rec[ST_BINM + q] = bm[q]; }
-        if constexpr (MOM >= 4) {
+      for (int q = 0; q < 20; ++q) m3[q] = 0.0;
+      for (int base = 0; base < n; base += WAVE) {
+        const int j = base + lane;
+        if (j < n) {
+          double val[4], d[4];
+          load4(j, val);
 #pragma unroll
-          for (int q = 0; q < (NM3 > 0 ? NM3 : 1); ++q) rec[ST_M3 + q] = m3[q] / dn;
+          for (int q = 0; q < 4; ++q) d[q] = val[q] - mean[q];
+          int i3 = 0;
 #pragma unroll
-          for (int q = 0; q < (NM4 > 0 ? NM4 : 1); ++q) rec[ST_M4 + q] = m4[q] / dn;
+          for (int x = 0; x < 4; ++x)
+#pragma unroll
+            for (int y = x; y < 4; ++y)
+#pragma unroll
+              for (int z = y; z < 4; ++z) { m3[i3] += (d[x] * d[y]) * d[z]; ++i3; }
         }
-      } else {
-        for (int q = 0; q < (MOM >= 4 ? NSTAT4 : NSTAT2); ++q) rec[q] = 0.0;
+      }
+      const double s3l = wave_sums_to_lanes<20>(m3, red);
+      if (lane < 20) rec[ST_M3 + lane] = s3l * inv_n;
+      // fourth-order moments, in two groups to bound the accumulator count
+#pragma unroll
+      for (int grp = 0; grp < 2; ++grp) {
+        constexpr int G0 = 18;
+        const int lo = grp == 0 ? 0 : G0, hi = grp == 0 ? G0 : 35;
+        double m4[G0];
+#pragma unroll
+        for (int q = 0; q < G0; ++q) m4[q] = 0.0;
+        for (int base = 0; base < n; base += WAVE) {
+          const int j = base + lane;
+          if (j < n) {
+            double val[4], d[4];
+            load4(j, val);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) d[q] = val[q] - mean[q];
+            int i4 = 0;
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+#pragma unroll
+              for (int y = x; y < 4; ++y)
+#pragma unroll
+                for (int z = y; z < 4; ++z)
+#pragma unroll
+                  for (int g = z; g < 4; ++g) {
+                    if (i4 >= lo && i4 < hi) m4[i4 - lo] += ((d[x] * d[y]) * d[z]) * d[g];
+                    ++i4;
+                  }
+          }
+        }
+        const double s4l = wave_sums_to_lanes<G0>(m4, red);
+        if (lane < hi - lo) rec[ST_M4 + lo + lane] = s4l * inv_n;
       }
     }
     if (HIST > 0) {
-      __builtin_amdgcn_wave_barrier();
       const int off = MOM >= 4 ? NSTAT4 : NSTAT2;
       for (int h = lane; h < HIST; h += WAVE) rec[off + h] = (double)hist_lds[wid][h];
     }
 
     if (ADVANCE) {
-      // ---- per-cell constants (wave-uniform) ----
-      const MeshDev& M = a.mesh;
-      const int v0 = M.tri[3 * e], v1 = M.tri[3 * e + 1], v2 = M.tri[3 * e + 2];
-      const double ax = M.vtx[2 * v0], ay = M.vtx[2 * v0 + 1];
-      const double bx = M.vtx[2 * v1], by = M.vtx[2 * v1 + 1];
-      const double cx = M.vtx[2 * v2], cy = M.vtx[2 * v2 + 1];
-      const double ia = M.inv2a[e];
+      // ---- C: advance ----
+      const ERec R0 = a.erec[e];
+      const int v0 = a.tri[3 * e], v1 = a.tri[3 * e + 1], v2 = a.tri[3 * e + 2];
+      const double ia = a.inv2a[e];
       const T* q0 = a.coef + (size_t)v0 * NCOEF;
       const T* q1 = a.coef + (size_t)v1 * NCOEF;
       const T* q2 = a.coef + (size_t)v2 * NCOEF;
@@ -401,28 +552,32 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a) {
       const double sx0 = a.src[3 * ens], sy0 = a.src[3 * ens + 1], sr0 = a.src[3 * ens + 2];
       const bool do_mix = a.mix && (a.flags & FLAG_MIX);
       int err = 0;
+      int stay_count = 0;
       for (int base = 0; base < n; base += WAVE) {
         const int j = base + lane;
         const bool act = j < n;
-        int tgt = -1;
+        int e2 = -1;
         T xn = 0, yn = 0, un = 0, vn = 0, wn = 0, psi = 0;
         uint32_t id = 0;
         if (act) {
-          const int s = start + j;
-          const T x = src.x[s], y = src.y[s], u = src.u[s], v = src.v[s], w = src.w[s];
-          psi = src.psi[s];
-          id = src.id[s];
+          T x, y, u, v, w;
+          if (j < TILE) {
+            x = L.x[j]; y = L.y[j]; u = L.u[j]; v = L.v[j]; w = L.w[j]; psi = L.psi[j]; id = L.id[j];
+          } else {
+            const int s = slot_of(j, start, ns, nm, capc);
+            x = src.x[s]; y = src.y[s]; u = src.u[s]; v = src.v[s]; w = src.w[s]; psi = src.psi[s]; id = src.id[s];
+          }
           uint32_t rw[8];
-          philox_words(id, step, (uint32_t)ens, k0, k1, rw, 2);
+          philox_words<2>(id, step, (uint32_t)ens, k0, k1, rw);
           T xi0, xi1, xi2, xi3, xi4, xi5;
           box_muller<T>(rw[0], rw[1], &xi0, &xi1);
           box_muller<T>(rw[2], rw[3], &xi2, &xi3);
           box_muller<T>(rw[4], rw[5], &xi4, &xi5);
           (void)xi5;
           const double X = (double)x, Y = (double)y;
-          const T l0 = (T)(orient_edge(bx, by, cx, cy, X, Y) * ia);
-          const T l1 = (T)(orient_edge(cx, cy, ax, ay, X, Y) * ia);
-          const T l2 = (T)(orient_edge(ax, ay, bx, by, X, Y) * ia);
+          const T l0 = (T)(orient_edge(R0.x[1], R0.y[1], R0.x[2], R0.y[2], X, Y) * ia);
+          const T l1 = (T)(orient_edge(R0.x[2], R0.y[2], R0.x[0], R0.y[0], X, Y) * ia);
+          const T l2 = (T)(orient_edge(R0.x[0], R0.y[0], R0.x[1], R0.y[1], X, Y) * ia);
           T f[NCOEF];
 #pragma unroll
           for (int q = 0; q < NCOEF; ++q) f[q] = (l0 * q0[q] + l1 * q1[q]) + l2 * q2[q];
@@ -447,9 +602,9 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a) {
           if (!(a.flags & FLAG_VEL)) { un = u; vn = v; wn = w; }
           xn = (x + u * a.dt) + a.s2nu * dW1;
           yn = (y + v * a.dt) + a.s2nu * dW2;
-          int e2 = e;
+          e2 = e;
           if (a.flags & FLAG_POS) {
-            e2 = walk<T>(M, e, X, Y, xn, yn, un, vn, wn);
+            e2 = walk<T>(a, R0, e, X, Y, xn, yn, un, vn, wn);
           } else {
             xn = x; yn = y;
           }
@@ -462,62 +617,65 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a) {
             }
             if (!(isfinite(un) && isfinite(vn) && isfinite(wn) && isfinite(psi) && isfinite(xn) && isfinite(yn)))
               err |= ERR_NAN;
-            tgt = ens * ne + e2;
           }
         }
-        // append to the destination cells, one atomic per distinct cell
-        uint64_t pending = __ballot(tgt >= 0);
-        while (pending) {
-          const int leader = __ffsll((unsigned long long)pending) - 1;
-          const int t = __shfl(tgt, leader, WAVE);
-          const uint64_t mask = __ballot(tgt == t) & pending;
-          int basei = 0;
-          if (lane == leader) basei = atomicAdd(&cnt_dst[t], (int)__popcll(mask));
-          basei = __shfl(basei, leader, WAVE);
-          if ((mask >> lane) & 1ull) {
-            const int rank = basei + (int)__popcll(mask & lanemask_lt());
-            if (rank < a.cap[t]) {
-              const int s = a.start[t] + rank;
-              dst.x[s] = xn; dst.y[s] = yn; dst.u[s] = un; dst.v[s] = vn; dst.w[s] = wn;
-              dst.psi[s] = psi; dst.id[s] = id;
+        // stayers: own segment, bottom run, in lane order, no atomics
+        const bool stay = act && e2 == e;
+        const uint64_t smask = __ballot(stay);
+        if (stay) {
+          const int s = start + stay_count + (int)__popcll(smask & lanemask_lt());
+          dst.x[s] = xn; dst.y[s] = yn; dst.u[s] = un; dst.v[s] = vn; dst.w[s] = wn; dst.psi[s] = psi;
+          dst.id[s] = id;
+        }
+        stay_count += (int)__popcll(smask);
+        // movers: top run of the new cell's segment
+        if (act && e2 >= 0 && e2 != e) {
+          const int t = ens * ne + e2;
+          const int k = atomicAdd(&a.nm[rn][t], 1);
+          const int capt = a.cap[t];
+          const int limit = capt - (a.ns[rc][t] + a.nm[rc][t]);
+          if (k < limit) {
+            const int s = a.start[t] + capt - 1 - k;
+            dst.x[s] = xn; dst.y[s] = yn; dst.u[s] = un; dst.v[s] = vn; dst.w[s] = wn; dst.psi[s] = psi;
+            dst.id[s] = id;
+          } else {
+            err |= ERR_CAPACITY;
+            const uint32_t kk = atomicAdd(&ctl->ovf, 1u);
+            if (kk < a.ovf_cap) {
+              a.ovf.x[kk] = xn; a.ovf.y[kk] = yn; a.ovf.u[kk] = un; a.ovf.v[kk] = vn; a.ovf.w[kk] = wn;
+              a.ovf.psi[kk] = psi; a.ovf.id[kk] = id;
+              a.ovf_cell[kk] = t;
             } else {
-              err |= ERR_CAPACITY;
-              const uint32_t k = atomicAdd(&ctl->ovf, 1u);
-              if (k < a.ovf_cap) {
-                a.ovf.x[k] = xn; a.ovf.y[k] = yn; a.ovf.u[k] = un; a.ovf.v[k] = vn; a.ovf.w[k] = wn;
-                a.ovf.psi[k] = psi; a.ovf.id[k] = id;
-                a.ovf_cell[k] = t;
-              } else {
-                err |= ERR_OVERFLOW_FULL;
-              }
+              err |= ERR_OVERFLOW_FULL;
             }
           }
-          pending &= ~mask;
         }
       }
-      if (lane == 0) cnt_src[cell] = 0;
-      // wave-level OR of the error bits, one atomic per wave
-      int werr = err;
+      if (lane == 0) {
+        a.ns[rn][cell] = stay_count;
+        a.ns[rz][cell] = 0;
+        a.nm[rz][cell] = 0;
+      }
+      int werr = 0;
 #pragma unroll
-      for (int off = 32; off > 0; off >>= 1) werr |= __shfl_xor(werr, off, WAVE);
+      for (int bit = 0; bit < 4; ++bit)
+        if (__ballot((err >> bit) & 1)) werr |= 1 << bit;
       if (lane == 0 && werr) atomicOr(&ctl->error, werr);
     }
   }
-  if (ADVANCE) {
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      __threadfence();
-      const uint32_t prev = atomicAdd(&ctl->done, 1u);
-      if (prev == gridDim.x - 1) {
-        // last workgroup of the step
-        __threadfence();
-        ctl->done = 0;
-        ctl->step = step + 1;
-        ctl->parity = par ^ 1u;
-        ctl->steps_done = ctl->steps_done + 1;
-        if (atomicAdd(&ctl->error, 0) != 0) ctl->halt = 1;
-      }
-    }
+}
+
+// End of a step: advance the step counter, swap the particle buffers, rotate
+// the counter sets, and stop further steps once an error was raised.  A
+// separate one-thread launch: the kernel boundary orders it after every
+// workgroup of the step without any device-wide fence in the step itself.
+__global__ void k_step_end(Ctl* ctl) {
+  if (threadIdx.x == 0 && blockIdx.x == 0 && !ctl->halt) {
+    ctl->step = ctl->step + 1;
+    ctl->parity = ctl->parity ^ 1u;
+    ctl->crot = ctl->crot == 2 ? 0 : ctl->crot + 1;
+    ctl->steps_done = ctl->steps_done + 1;
+    if (ctl->error != 0) ctl->halt = 1;
   }
 }
 
@@ -638,28 +796,42 @@ __global__ void k_alpha(const double* vtx, const int32_t* tri, const int32_t* ek
   alpha[i] = 2.0 * uhat * uhat * Up * fabs(Up) / (v2 * Ue * Ue);
 }
 
+// Per-element tracking records.
+__global__ void k_erec(const double* vtx, const int32_t* tri, const int32_t* nbr, const int32_t* ekind,
+                       ERec* erec, int ne) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ne) return;
+  ERec r;
+  for (int k = 0; k < 3; ++k) {
+    const int v = tri[3 * e + k];
+    r.x[k] = vtx[2 * v];
+    r.y[k] = vtx[2 * v + 1];
+    r.code[k] = ekind[3 * e + k] | ((nbr[3 * e + k] + 1) << 4);
+  }
+  r.pad = 0;
+  erec[e] = r;
+}
+
 // Initial particles: uniform in the element, velocity = local mean plus the
 // Cholesky factor of the local Reynolds stress times normals, scalar by rule.
 template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_seed(MeshDev M, const double* fields, StateDev<T> st,
-                                                const int32_t* start, const int32_t* count,
-                                                const int32_t* idoff, const uint64_t* seeds, int ncell,
-                                                int psi_init) {
+__global__ __launch_bounds__(BLOCK) void k_seed(const ERec* erec, const int32_t* tri, const double* inv2a,
+                                                const double* fields, StateDev<T> st, const int32_t* start,
+                                                const int32_t* count, const int32_t* idoff,
+                                                const uint64_t* seeds, int ne, int ncell, int psi_init) {
   const int lane = lane_id();
-  const int cell = blockIdx.x * WAVES_PER_BLOCK + threadIdx.x / WAVE;
+  const int cell = blockIdx.x * WAVES_PER_BLOCK + (int)(threadIdx.x / WAVE);
   if (cell >= ncell) return;
-  const int ne = M.ne;
   const int ens = cell / ne, e = cell - ens * ne;
-  const int v0 = M.tri[3 * e], v1 = M.tri[3 * e + 1], v2 = M.tri[3 * e + 2];
-  const double ax = M.vtx[2 * v0], ay = M.vtx[2 * v0 + 1];
-  const double bx = M.vtx[2 * v1] - ax, by = M.vtx[2 * v1 + 1] - ay;
-  const double cx = M.vtx[2 * v2] - ax, cy = M.vtx[2 * v2 + 1] - ay;
-  const double gx = ((M.vtx[2 * v0] + M.vtx[2 * v1]) + M.vtx[2 * v2]) / 3.0;
-  const double gy = ((M.vtx[2 * v0 + 1] + M.vtx[2 * v1 + 1]) + M.vtx[2 * v2 + 1]) / 3.0;
-  const double Ax = M.vtx[2 * v0], Ay = M.vtx[2 * v0 + 1];
-  const double Bx = M.vtx[2 * v1], By = M.vtx[2 * v1 + 1];
-  const double Cx = M.vtx[2 * v2], Cy = M.vtx[2 * v2 + 1];
-  const double ia = M.inv2a[e];
+  const ERec R = erec[e];
+  const int v0 = tri[3 * e], v1 = tri[3 * e + 1], v2 = tri[3 * e + 2];
+  const double Ax = R.x[0], Ay = R.y[0], Bx = R.x[1], By = R.y[1], Cx = R.x[2], Cy = R.y[2];
+  const double ax = Ax, ay = Ay;
+  const double bx = Bx - ax, by = By - ay;
+  const double cx = Cx - ax, cy = Cy - ay;
+  const double gx = ((Ax + Bx) + Cx) / 3.0;
+  const double gy = ((Ay + By) + Cy) / 3.0;
+  const double ia = inv2a[e];
   const double* f0 = fields + (size_t)v0 * NFIELD;
   const double* f1 = fields + (size_t)v1 * NFIELD;
   const double* f2 = fields + (size_t)v2 * NFIELD;
@@ -669,7 +841,7 @@ __global__ __launch_bounds__(BLOCK) void k_seed(MeshDev M, const double* fields,
   for (int j = lane; j < n; j += WAVE) {
     const uint32_t id = (uint32_t)(id0 + j);
     uint32_t r[8];
-    philox_words(id, SEED_STEP, (uint32_t)ens, k0, k1, r, 2);
+    philox_words<2>(id, SEED_STEP, (uint32_t)ens, k0, k1, r);
     double s1 = uniform01<double>(r[0]), s2 = uniform01<double>(r[1]);
     if (s1 + s2 > 1.0) {
       s1 = 1.0 - s1;
@@ -715,22 +887,27 @@ __global__ __launch_bounds__(BLOCK) void k_seed(MeshDev M, const double* fields,
 }
 
 // State of one ensemble in particle-id order (doubles) plus element index.
+struct CounterSets {
+  int32_t* ns[3];
+  int32_t* nm[3];
+};
+
 template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_gather(StateDev<T> b0, StateDev<T> b1, const int32_t* cnt0,
-                                                  const int32_t* cnt1, const int32_t* start,
-                                                  const int32_t* cap, const Ctl* ctl, int ens, int ne,
-                                                  int64_t n, double* out, int32_t* elem) {
+__global__ __launch_bounds__(BLOCK) void k_gather(StateDev<T> b0, StateDev<T> b1, CounterSets cs,
+                                                  const int32_t* start, const int32_t* cap, const Ctl* ctl,
+                                                  int ens, int ne, int64_t n, double* out, int32_t* elem) {
   const int lane = lane_id();
-  const int e = blockIdx.x * WAVES_PER_BLOCK + threadIdx.x / WAVE;
+  const int e = blockIdx.x * WAVES_PER_BLOCK + (int)(threadIdx.x / WAVE);
   if (e >= ne) return;
-  const uint32_t par = ctl->parity;
+  const uint32_t par = ctl->parity, rot = ctl->crot;
   const StateDev<T> st = par ? b1 : b0;
   const int cell = ens * ne + e;
-  int c = (par ? cnt1 : cnt0)[cell];
-  if (c > cap[cell]) c = cap[cell];
-  const int s0 = start[cell];
+  const int capc = cap[cell], s0 = start[cell];
+  const int ns = min(cs.ns[rot][cell], capc);
+  const int nm = min(cs.nm[rot][cell], capc - ns);
+  const int c = ns + nm;
   for (int j = lane; j < c; j += WAVE) {
-    const int s = s0 + j;
+    const int s = slot_of(j, s0, ns, nm, capc);
     const int64_t id = st.id[s];
     if (id < 0 || id >= n) continue;
     out[id] = (double)st.x[s];
@@ -745,8 +922,8 @@ __global__ __launch_bounds__(BLOCK) void k_gather(StateDev<T> b0, StateDev<T> b1
 
 __global__ void k_reset_ctl(Ctl* ctl) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
-    ctl->step = 0; ctl->parity = 0; ctl->error = 0; ctl->halt = 0; ctl->done = 0; ctl->ovf = 0;
-    ctl->steps_done = 0; ctl->lost = 0;
+    ctl->step = 0; ctl->parity = 0; ctl->crot = 0; ctl->error = 0; ctl->halt = 0; ctl->spare = 0;
+    ctl->ovf = 0; ctl->lost = 0; ctl->steps_done = 0;
   }
 }
 

@@ -22,8 +22,8 @@ int64_t align_up(int64_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
 // Byte offsets of the arena sections.
 struct Layout {
-  int64_t vtx, tri, nbr, ekind, inv2a, alpha, fields, coef;
-  int64_t start, cap, cnt0, cnt1, rate, idoff, seed, src;
+  int64_t vtx, tri, nbr, ekind, inv2a, alpha, fields, coef, erec;
+  int64_t start, cap, ns[3], nm[3], rate, idoff, seed, src;
   int64_t buf0, buf1, ovf, ovf_cell, stats, ctl, flag;
   int64_t total;
   int64_t slots;
@@ -43,10 +43,13 @@ Layout make_layout(int32_t nv, int32_t ne, int32_t nens, int64_t slots, int32_t 
   L.alpha = take((int64_t)ne * 3 * 8);
   L.fields = take((int64_t)nv * NFIELD * 8);
   L.coef = take((int64_t)nv * NCOEF * tsize);
+  L.erec = take((int64_t)ne * (int64_t)sizeof(ERec));
   L.start = take(ncell * 4);
   L.cap = take(ncell * 4);
-  L.cnt0 = take(ncell * 4);
-  L.cnt1 = take(ncell * 4);
+  for (int r = 0; r < 3; ++r) {
+    L.ns[r] = take(ncell * 4);
+    L.nm[r] = take(ncell * 4);
+  }
   L.rate = take(ncell * tsize);
   L.idoff = take(ncell * 4);
   L.seed = take((int64_t)nens * 8);
@@ -130,22 +133,21 @@ template <typename T> StepArgs<T> step_args(pdf_ctx* c) {
   const Layout& L = c->L;
   char* a = c->arena;
   StepArgs<T> s{};
-  s.mesh.vtx = (const double*)(a + L.vtx);
-  s.mesh.tri = (const int32_t*)(a + L.tri);
-  s.mesh.nbr = (const int32_t*)(a + L.nbr);
-  s.mesh.ekind = (const int32_t*)(a + L.ekind);
-  s.mesh.inv2a = (const double*)(a + L.inv2a);
-  s.mesh.alpha = (const double*)(a + L.alpha);
-  s.mesh.ne = c->ne;
-  s.mesh.nv = c->nv;
-  s.mesh.Lx = c->p.Lx;
-  s.mesh.Ly = c->p.Ly;
+  s.erec = (const ERec*)(a + L.erec);
+  s.tri = (const int32_t*)(a + L.tri);
+  s.inv2a = (const double*)(a + L.inv2a);
+  s.alpha = (const double*)(a + L.alpha);
+  s.ne = c->ne;
+  s.Lx = c->p.Lx;
+  s.Ly = c->p.Ly;
   s.coef = (const T*)(a + L.coef);
   s.rate = (const T*)(a + L.rate);
   s.start = (const int32_t*)(a + L.start);
   s.cap = (const int32_t*)(a + L.cap);
-  s.cnt[0] = (int32_t*)(a + L.cnt0);
-  s.cnt[1] = (int32_t*)(a + L.cnt1);
+  for (int r = 0; r < 3; ++r) {
+    s.ns[r] = (int32_t*)(a + L.ns[r]);
+    s.nm[r] = (int32_t*)(a + L.nm[r]);
+  }
   s.buf[0] = state_at<T>(a, L.buf0, L.slots);
   s.buf[1] = state_at<T>(a, L.buf1, L.slots);
   s.ovf = state_at<T>(a, L.ovf, L.ovf_cap);
@@ -232,7 +234,7 @@ pdf_status pdf_init_mesh(pdf_ctx* c, const pdf_mesh* m, void* arena, int64_t are
   c->arena_bytes = arena_bytes;
   // the mesh part of the layout does not depend on the ensembles
   Layout L = make_layout(c->nv, c->ne, 1, 1, nstat_of(c->p), tsize_of(c->p));
-  if (L.coef + (int64_t)c->nv * NCOEF * tsize_of(c->p) > arena_bytes) return fail(c, PDF_E_SIZE, "arena too small for the mesh");
+  if (L.erec + (int64_t)c->ne * (int64_t)sizeof(ERec) > arena_bytes) return fail(c, PDF_E_SIZE, "arena too small for the mesh");
   c->L = L;
   hipStream_t st = c->stream;
   pdf_status r;
@@ -246,6 +248,9 @@ pdf_status pdf_init_mesh(pdf_ctx* c, const pdf_mesh* m, void* arena, int64_t are
   const int tb = 256;
   hipLaunchKernelGGL(k_inv2a, dim3((c->ne + tb - 1) / tb), dim3(tb), 0, st, (const double*)(c->arena + L.vtx),
                      (const int32_t*)(c->arena + L.tri), (double*)(c->arena + L.inv2a), flag, c->ne);
+  hipLaunchKernelGGL(k_erec, dim3((c->ne + tb - 1) / tb), dim3(tb), 0, st, (const double*)(c->arena + L.vtx),
+                     (const int32_t*)(c->arena + L.tri), (const int32_t*)(c->arena + L.nbr),
+                     (const int32_t*)(c->arena + L.ekind), (ERec*)(c->arena + L.erec), c->ne);
   hipLaunchKernelGGL(k_alpha, dim3((3 * c->ne + tb - 1) / tb), dim3(tb), 0, st, (const double*)(c->arena + L.vtx),
                      (const int32_t*)(c->arena + L.tri), (const int32_t*)(c->arena + L.ekind),
                      (const double*)(c->arena + L.fields), (double*)(c->arena + L.alpha), c->ne, c->p.Cmu,
@@ -319,8 +324,11 @@ pdf_status pdf_seed_particles(pdf_ctx* c, int32_t nens, const int64_t* counts, c
   pdf_status r;
   if ((r = hip_check(c, hipMemcpyAsync(a + L.start, c->h_start.data(), ncell * 4, hipMemcpyHostToDevice, st), "copy start"))) return r;
   if ((r = hip_check(c, hipMemcpyAsync(a + L.cap, c->h_cap.data(), ncell * 4, hipMemcpyHostToDevice, st), "copy cap"))) return r;
-  if ((r = hip_check(c, hipMemcpyAsync(a + L.cnt0, c->h_cnt.data(), ncell * 4, hipMemcpyHostToDevice, st), "copy cnt"))) return r;
-  if ((r = hip_check(c, hipMemcpyAsync(a + L.cnt1, c->h_zero.data(), ncell * 4, hipMemcpyHostToDevice, st), "copy cnt1"))) return r;
+  if ((r = hip_check(c, hipMemcpyAsync(a + L.ns[0], c->h_cnt.data(), ncell * 4, hipMemcpyHostToDevice, st), "copy counts"))) return r;
+  for (int rr = 0; rr < 3; ++rr) {
+    if (rr > 0 && (r = hip_check(c, hipMemcpyAsync(a + L.ns[rr], c->h_zero.data(), ncell * 4, hipMemcpyHostToDevice, st), "clear counts"))) return r;
+    if ((r = hip_check(c, hipMemcpyAsync(a + L.nm[rr], c->h_zero.data(), ncell * 4, hipMemcpyHostToDevice, st), "clear counts"))) return r;
+  }
   if ((r = hip_check(c, hipMemcpyAsync(a + L.idoff, c->h_idoff.data(), ncell * 4, hipMemcpyHostToDevice, st), "copy idoff"))) return r;
   if ((r = hip_check(c, hipMemcpyAsync(a + L.seed, c->h_seed.data(), nens * 8, hipMemcpyHostToDevice, st), "copy seeds"))) return r;
   if ((r = hip_check(c, hipMemcpyAsync(a + L.src, c->h_src.data(), nens * 3 * 8, hipMemcpyHostToDevice, st), "copy src"))) return r;
@@ -329,20 +337,20 @@ pdf_status pdf_seed_particles(pdf_ctx* c, int32_t nens, const int64_t* counts, c
   const int cb = (int)((ncell + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK);
   if (c->p.f32_state) {
     StepArgs<float> s = step_args<float>(c);
-    hipLaunchKernelGGL(k_rate<float>, dim3((unsigned)((ncell + tb - 1) / tb)), dim3(tb), 0, st, s.mesh.vtx, s.mesh.tri,
+    hipLaunchKernelGGL(k_rate<float>, dim3((unsigned)((ncell + tb - 1) / tb)), dim3(tb), 0, st, (const double*)(a + L.vtx), s.tri,
                        (const double*)(a + L.fields), s.src, (float*)(a + L.rate), c->ne, (int)ncell, c->p.dt,
                        c->p.nu, c->p.CT, c->p.Cs, c->p.Ct);
-    hipLaunchKernelGGL(k_seed<float>, dim3(cb), dim3(BLOCK), 0, st, s.mesh, (const double*)(a + L.fields), s.buf[0],
-                       s.start, (const int32_t*)s.cnt[0], (const int32_t*)(a + L.idoff), s.seed, (int)ncell,
-                       c->p.psi_init);
+    hipLaunchKernelGGL(k_seed<float>, dim3(cb), dim3(BLOCK), 0, st, s.erec, s.tri, s.inv2a,
+                       (const double*)(a + L.fields), s.buf[0], s.start, (const int32_t*)s.ns[0],
+                       (const int32_t*)(a + L.idoff), s.seed, c->ne, (int)ncell, c->p.psi_init);
   } else {
     StepArgs<double> s = step_args<double>(c);
-    hipLaunchKernelGGL(k_rate<double>, dim3((unsigned)((ncell + tb - 1) / tb)), dim3(tb), 0, st, s.mesh.vtx, s.mesh.tri,
+    hipLaunchKernelGGL(k_rate<double>, dim3((unsigned)((ncell + tb - 1) / tb)), dim3(tb), 0, st, (const double*)(a + L.vtx), s.tri,
                        (const double*)(a + L.fields), s.src, (double*)(a + L.rate), c->ne, (int)ncell, c->p.dt,
                        c->p.nu, c->p.CT, c->p.Cs, c->p.Ct);
-    hipLaunchKernelGGL(k_seed<double>, dim3(cb), dim3(BLOCK), 0, st, s.mesh, (const double*)(a + L.fields), s.buf[0],
-                       s.start, (const int32_t*)s.cnt[0], (const int32_t*)(a + L.idoff), s.seed, (int)ncell,
-                       c->p.psi_init);
+    hipLaunchKernelGGL(k_seed<double>, dim3(cb), dim3(BLOCK), 0, st, s.erec, s.tri, s.inv2a,
+                       (const double*)(a + L.fields), s.buf[0], s.start, (const int32_t*)s.ns[0],
+                       (const int32_t*)(a + L.idoff), s.seed, c->ne, (int)ncell, c->p.psi_init);
   }
   if ((r = hip_check(c, hipGetLastError(), "seed kernels"))) return r;
   // the host vectors stay alive in the context until the copies complete
@@ -356,9 +364,11 @@ pdf_status pdf_seed_particles(pdf_ctx* c, int32_t nens, const int64_t* counts, c
 pdf_status pdf_step(pdf_ctx* c, int32_t nsteps) {
   if (!c || nsteps < 0) return fail(c, PDF_E_ARG, "pdf_step: bad argument");
   if (!c->seeded) return fail(c, PDF_E_STATE, "pdf_step before pdf_seed_particles");
+  Ctl* ctl = (Ctl*)(c->arena + c->L.ctl);
   for (int32_t i = 0; i < nsteps; ++i) {
     pdf_status r = c->p.f32_state ? dispatch_step<float, true>(c) : dispatch_step<double, true>(c);
     if (r) return r;
+    hipLaunchKernelGGL(k_step_end, dim3(1), dim3(64), 0, c->stream, ctl);
   }
   return PDF_OK;
 }
@@ -401,16 +411,19 @@ pdf_status pdf_get_state(pdf_ctx* c, int32_t ens, double* xyuvwpsi, int32_t* ele
   char* a = c->arena;
   const Layout& L = c->L;
   const int blocks = (c->ne + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
+  CounterSets cs;
+  for (int r = 0; r < 3; ++r) {
+    cs.ns[r] = (int32_t*)(a + L.ns[r]);
+    cs.nm[r] = (int32_t*)(a + L.nm[r]);
+  }
   if (c->p.f32_state)
     hipLaunchKernelGGL(k_gather<float>, dim3(blocks), dim3(BLOCK), 0, c->stream, state_at<float>(a, L.buf0, L.slots),
-                       state_at<float>(a, L.buf1, L.slots), (const int32_t*)(a + L.cnt0), (const int32_t*)(a + L.cnt1),
-                       (const int32_t*)(a + L.start), (const int32_t*)(a + L.cap), (const Ctl*)(a + L.ctl), ens, c->ne,
-                       n, xyuvwpsi, elem);
+                       state_at<float>(a, L.buf1, L.slots), cs, (const int32_t*)(a + L.start),
+                       (const int32_t*)(a + L.cap), (const Ctl*)(a + L.ctl), ens, c->ne, n, xyuvwpsi, elem);
   else
     hipLaunchKernelGGL(k_gather<double>, dim3(blocks), dim3(BLOCK), 0, c->stream, state_at<double>(a, L.buf0, L.slots),
-                       state_at<double>(a, L.buf1, L.slots), (const int32_t*)(a + L.cnt0), (const int32_t*)(a + L.cnt1),
-                       (const int32_t*)(a + L.start), (const int32_t*)(a + L.cap), (const Ctl*)(a + L.ctl), ens, c->ne,
-                       n, xyuvwpsi, elem);
+                       state_at<double>(a, L.buf1, L.slots), cs, (const int32_t*)(a + L.start),
+                       (const int32_t*)(a + L.cap), (const Ctl*)(a + L.ctl), ens, c->ne, n, xyuvwpsi, elem);
   return hip_check(c, hipGetLastError(), "gather launch");
 }
 

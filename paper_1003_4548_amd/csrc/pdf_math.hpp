@@ -13,8 +13,6 @@ namespace pdf {
 // Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11).  The key words are
 // wave-uniform (one seed per ensemble), so the key schedule stays scalar.
 
-struct U8 { uint32_t r[8]; };
-
 __device__ __forceinline__ void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32_t& c2, uint32_t& c3,
                                               uint32_t k0, uint32_t k1) {
 #pragma unroll
@@ -34,9 +32,11 @@ __device__ __forceinline__ void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32
 }
 
 // words 0..3 from counter block 0, 4..7 from block 1: counter (id, step, b, ens)
+template <int NBLOCKS>
 __device__ __forceinline__ void philox_words(uint32_t id, uint32_t step, uint32_t ens, uint32_t k0,
-                                             uint32_t k1, uint32_t* w, int nblocks) {
-  for (int b = 0; b < nblocks; ++b) {
+                                             uint32_t k1, uint32_t* w) {
+#pragma unroll
+  for (int b = 0; b < NBLOCKS; ++b) {
     uint32_t c0 = id, c1 = step, c2 = (uint32_t)b, c3 = ens;
     philox4x32_10(c0, c1, c2, c3, k0, k1);
     w[4 * b + 0] = c0; w[4 * b + 1] = c1; w[4 * b + 2] = c2; w[4 * b + 3] = c3;
