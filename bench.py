@@ -25,6 +25,8 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, GB/s
 
 WORKLOADS = {
     "canyon1m": ("config2", "street canyon, 9912-element Delaunay mesh, 1M particles, GLM, FP32 state"),
+    "batched64": ("config4", "64 independent canyon runs on the 9912-element mesh, 12.2M particles in total "
+                             "(10k-1M per run, log-uniform), distinct seeds and sources"),
     "canyon10m": ("config3", "wall-function canyon, 48618-element mesh, 10M particles, SLM, 4th moments + histograms"),
     "square40k": ("config1", "unit square 20x20x2, 40k particles, SLM, FP64"),
 }
@@ -108,8 +110,12 @@ def main() -> int:
     ap.add_argument("--workload", default="canyon1m", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--secondary", default="canyon10m", help="second workload reported in the same line ('' for none)")
+    ap.add_argument("--secondary", default="canyon10m,batched64",
+                    help="further workloads reported in the same line, comma separated ('' for none)")
     ap.add_argument("--secondary-steps", type=int, default=100)
+    ap.add_argument("--no-graph", action="store_true", help="launch steps one by one instead of graph replays")
+    ap.add_argument("--autotune-steps", type=int, default=5,
+                    help="steps per candidate launch shape before warmup (0: no tuning)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -129,25 +135,32 @@ def main() -> int:
         return 1
     src_hash = kernel_source_hash()
 
+    autotune_steps = args.autotune_steps
+
     def run(name, steps, warmup):
         cfg_fn = getattr(W, WORKLOADS[name][0])
         wl = cfg_fn(steps=steps)
         sim = Simulation.from_workload(wl, device="cuda:0")
         print(f"[bench] {name}: {wl.n_total} particles, {wl.mesh.nelem} elements, warmup {warmup}", file=sys.stderr, flush=True)
+        shape = sim.autotune(steps_per_trial=autotune_steps) if autotune_steps > 0 else (64, 0)
+        print(f"[bench] {name}: launch shape group={shape[0]} persistent={shape[1]}", file=sys.stderr, flush=True)
+        tuned = sim.steps_done()
         sim.step(warmup)
         sim.sync()
         stream = sim.stream
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
+        step_fn = sim.step if args.no_graph else sim.step_graph
         t0 = time.perf_counter()
         e0.record(stream)
-        sim.step(steps)
+        step_fn(steps)
         e1.record(stream)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         sim.sync()
-        assert sim.steps_done() == warmup + steps
+        assert sim.steps_done() == tuned + warmup + steps
+        repacks = sim.repacks()
         wall = t1 - t0
         kern_ms = e0.elapsed_time(e1) / steps
         ab = algorithmic_bytes(wl)
@@ -165,6 +178,10 @@ def main() -> int:
                        "elements": wl.mesh.nelem, "vertices": wl.mesh.nvert, "ensembles": wl.nens,
                        "state_dtype": wl.precision, "statistics_dtype": "f64", "model": wl.describe()["model"],
                        "moments": wl.moments, "hist_bins": wl.hist_bins, "dt": wl.dt,
+                       "launch": {"lanes_per_cell": shape[0], "persistent": bool(shape[1]),
+                                  "autotune_steps_per_candidate": autotune_steps,
+                                  "hip_graph": not args.no_graph},
+                       "segment_repacks": repacks,
                        "kernel_source_hash": src_hash},
             "wl_fn": (cfg_fn, steps),
         }
@@ -190,11 +207,11 @@ def main() -> int:
         "config": main_res["config"],
         "roofline": main_res["roofline"],
     }
-    if args.secondary and args.secondary != args.workload:
-        sec = run(args.secondary, args.secondary_steps, max(5, args.warmup // 2))
-        out["secondary"] = {"value": round(sec["value"], 1), "unit": "particle-steps/s",
-                            "steps": args.secondary_steps, "ms_per_step": round(sec["ms_per_step"], 5),
-                            "config": sec["config"], "roofline": sec["roofline"]}
+    for name in [w for w in args.secondary.split(",") if w and w != args.workload]:
+        sec = run(name, args.secondary_steps, max(5, args.warmup // 2))
+        out.setdefault("secondary", {})[name] = {
+            "value": round(sec["value"], 1), "unit": "particle-steps/s", "steps": args.secondary_steps,
+            "ms_per_step": round(sec["ms_per_step"], 5), "config": sec["config"], "roofline": sec["roofline"]}
     if args.calibrate_copy:
         nbytes = 1 << 30
         a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda:0").fill_(1.0)

@@ -49,7 +49,7 @@ typedef int32_t pdf_status;
 #define PDF_E_HIP -4       /* HIP runtime error                                  */
 #define PDF_E_LOST -5      /* tracking could not place a particle                */
 #define PDF_E_NAN -6       /* non-finite particle state                          */
-#define PDF_E_CAPACITY -7  /* an element segment overflowed its slack            */
+#define PDF_E_CAPACITY -7  /* an element segment overflowed between repacks       */
 #define PDF_E_STATE -8     /* call out of order (e.g. step before seeding)       */
 
 /* edge kinds of the mesh arrays */
@@ -81,7 +81,9 @@ typedef struct pdf_params {
   int32_t f32_state;  /* 1: particle state in float, 0: double                  */
   int32_t model;      /* 0: SLM, eq. (19); 1: G and C0 from wp, eqs. (12)-(13)   */
   int32_t moments;    /* highest central moment order estimated: 2 or 4          */
-  int32_t hist_bins;  /* scalar histogram bins on [0,1] per element: 0 or 32     */
+  int32_t hist_bins;  /* scalar histogram bins on [0,1] per element: 0 or 32;
+                         supported (moments, hist_bins): float state (2, 0) and
+                         (4, 32), double state (2, 0)                            */
   int32_t mix;        /* 1: IECM mixing on                                       */
   int32_t psi_init;   /* initial scalar: 0 zero; 1 one where x < 0.25            */
   int32_t flags;      /* sub-steps: 1 velocity, 2 position+tracking, 4 IECM,
@@ -139,8 +141,46 @@ pdf_status pdf_init_mesh(pdf_ctx* ctx, const pdf_mesh* m, void* arena, int64_t a
 pdf_status pdf_seed_particles(pdf_ctx* ctx, int32_t nens, const int64_t* counts,
                               const uint64_t* seeds, const double* source);
 
-/* Enqueue nsteps time steps of every ensemble (asynchronous). */
+/* Enqueue nsteps time steps of every ensemble (asynchronous).  After a
+   device error the remaining steps do nothing and pdf_sync reports it. */
 pdf_status pdf_step(pdf_ctx* ctx, int32_t nsteps);
+
+/* As pdf_step, but replays a HIP graph of six consecutive steps (built on
+   first use for the current launch shape, from kernel nodes only); the
+   leading and trailing steps that do not fill a graph are launched
+   directly.  Results are identical to pdf_step. */
+pdf_status pdf_step_graph(pdf_ctx* ctx, int32_t nsteps);
+
+/* Choose the launch shape of the step by timing: lanes per element cell
+   (64, 32 or 16; a wavefront then serves 1, 2 or 4 cells) and a one-item-
+   per-wavefront grid or a persistent grid pulling work from a counter.
+   Runs 1 + steps_per_trial real steps per candidate (the simulation advances
+   by them; particle trajectories do not depend on the shape).  The choice is
+   kept in the context and returned in *group, *persist (either may be NULL).
+   Synchronizes the stream. */
+pdf_status pdf_autotune(pdf_ctx* ctx, int32_t steps_per_trial, int32_t* group, int32_t* persist);
+
+/* Set the launch shape directly (group 16, 32 or 64; persist 0 or 1).  The
+   double state supports group 64 only. */
+pdf_status pdf_set_launch(pdf_ctx* ctx, int32_t group, int32_t persist);
+
+/* Re-sort by element (the particle-in-cell bookkeeping of section 2.4).
+   Each element cell owns a segment of the particle buffers, sized at seeding
+   from its initial count: ceil(slack n0) + 32 slots.  Particles stay in
+   their cell's segment or are appended to their new cell's segment, so the
+   statistics of a cell read one contiguous range (two runs).  When the
+   density drifts, a step flags every segment whose free room falls under
+   half its count (or under 16), and every sixth step (the end of the
+   six-step cycle of pdf_step_graph; pdf_step checks at the same step counts)
+   a device-side repack gives each cell max(initial, floor(max(2, slack) n)
+   + 32) slots (floor(slack n) + 32 if that would not fit), copies the
+   particles and continues; no host synchronisation is involved.  Particle
+   trajectories do not depend on the layout.  pdf_query_sizes reserves
+   ceil(slack N / 4) slots beyond the seeding layout for the growth.
+   pdf_repack enqueues a repack now (asynchronous); pdf_repack_count waits
+   for the stream and returns the repacks done since seeding (-1 on error). */
+pdf_status pdf_repack(pdf_ctx* ctx);
+int64_t pdf_repack_count(pdf_ctx* ctx);
 
 /* Estimate the statistics of the current state into out: nens x nelem x
    nstat doubles (nstat = PDF_NSTAT_2 or PDF_NSTAT_4, plus hist_bins).
@@ -158,7 +198,7 @@ pdf_status pdf_sync(pdf_ctx* ctx);
    n = pdf_count(ctx, ens).  Asynchronous. */
 pdf_status pdf_get_state(pdf_ctx* ctx, int32_t ens, double* xyuvwpsi, int32_t* elem);
 
-/* Number of particles of an ensemble; steps completed since seeding. */
+/* Number of particles of an ensemble; steps enqueued since seeding. */
 int64_t pdf_count(const pdf_ctx* ctx, int32_t ens);
 int64_t pdf_steps_done(pdf_ctx* ctx);
 

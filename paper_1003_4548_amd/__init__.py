@@ -26,8 +26,9 @@ NFIELD = 20
 
 # exported entry points (the declarations of include/pdfpic.h)
 ENTRY_POINTS = ("pdf_create", "pdf_query_sizes", "pdf_init_mesh", "pdf_seed_particles", "pdf_step",
-                "pdf_estimate_statistics", "pdf_nstat", "pdf_sync", "pdf_get_state", "pdf_count",
-                "pdf_steps_done", "pdf_error_string", "pdf_destroy")
+                "pdf_step_graph", "pdf_autotune", "pdf_set_launch", "pdf_repack", "pdf_repack_count",
+                "pdf_estimate_statistics", "pdf_nstat", "pdf_sync",
+                "pdf_get_state", "pdf_count", "pdf_steps_done", "pdf_error_string", "pdf_destroy")
 
 
 class PdfError(RuntimeError):
@@ -86,6 +87,16 @@ def load_library():
     L.pdf_seed_particles.argtypes = [vp, i32, vp, vp, vp]
     L.pdf_step.restype = i32
     L.pdf_step.argtypes = [vp, i32]
+    L.pdf_step_graph.restype = i32
+    L.pdf_step_graph.argtypes = [vp, i32]
+    L.pdf_autotune.restype = i32
+    L.pdf_autotune.argtypes = [vp, i32, P(i32), P(i32)]
+    L.pdf_set_launch.restype = i32
+    L.pdf_set_launch.argtypes = [vp, i32, i32]
+    L.pdf_repack.restype = i32
+    L.pdf_repack.argtypes = [vp]
+    L.pdf_repack_count.restype = i64
+    L.pdf_repack_count.argtypes = [vp]
     L.pdf_estimate_statistics.restype = i32
     L.pdf_estimate_statistics.argtypes = [vp, vp, i32]
     L.pdf_nstat.restype = i32
@@ -206,6 +217,31 @@ class Simulation:
     # -- the C ABI, call for call -------------------------------------------------
     def step(self, n: int = 1) -> None:
         self._check(load_library().pdf_step(self.ctx, int(n)), "pdf_step")
+
+    def step_graph(self, n: int = 1) -> None:
+        """As step(), replaying a HIP graph of six steps."""
+        self._check(load_library().pdf_step_graph(self.ctx, int(n)), "pdf_step_graph")
+
+    def autotune(self, steps_per_trial: int = 5):
+        """Pick the launch shape by timing real steps; returns (group, persist)."""
+        g, pe = ctypes.c_int32(), ctypes.c_int32()
+        self._check(load_library().pdf_autotune(self.ctx, int(steps_per_trial), ctypes.byref(g), ctypes.byref(pe)),
+                    "pdf_autotune")
+        return int(g.value), int(pe.value)
+
+    def set_launch(self, group: int, persist: int = 0) -> None:
+        self._check(load_library().pdf_set_launch(self.ctx, int(group), int(persist)), "pdf_set_launch")
+
+    def repack(self) -> None:
+        """Re-lay out the element segments from the current counts now."""
+        self._check(load_library().pdf_repack(self.ctx), "pdf_repack")
+
+    def repacks(self) -> int:
+        """Repacks done since seeding (waits for the stream)."""
+        n = int(load_library().pdf_repack_count(self.ctx))
+        if n < 0:
+            raise PdfError(-4, "pdf_repack_count failed")
+        return n
 
     def sync(self) -> None:
         self._check(load_library().pdf_sync(self.ctx), "pdf_sync")

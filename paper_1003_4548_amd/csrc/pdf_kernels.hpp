@@ -43,16 +43,33 @@ constexpr int WAVES_PER_BLOCK = BLOCK / WAVE;
 
 // Control block in device memory.
 struct Ctl {
-  uint32_t step;      // Philox step word of the next step
-  uint32_t parity;    // particle buffer holding the current state
-  uint32_t crot;      // counter set holding the current counts (0..2)
-  int32_t error;      // OR of ERR_* raised since seeding
-  int32_t halt;       // set at the end of a step that raised an error
-  uint32_t spare;
-  uint32_t ovf;       // particles written to the overflow area
-  uint32_t lost;
-  int64_t steps_done; // steps completed since seeding
-  uint32_t pad[6];
+  uint32_t step_base;  // Philox step word of the first step of the running pdf_step call
+  int32_t error;       // OR of ERR_* raised since seeding
+  uint32_t ovf;        // particles written to the overflow area
+  uint32_t next[2];    // work counters of the persistent scheduler, by step parity
+  uint32_t repack;     // set by a step that found a segment near its capacity
+  uint32_t active;     // the repack in progress (copied from repack by the planner)
+  uint32_t flip;       // XOR applied to the step parity to select the particle buffer
+  uint32_t repacks;    // repacks done since seeding
+  uint32_t pad[7];
+};
+static_assert(sizeof(Ctl) == 64, "control block is 64 bytes");
+
+// A segment needs a repack when its free room is under half its count (or
+// under 16 slots): arrivals in one step stay well below that.
+__device__ __forceinline__ bool repack_due(int n, int cap) {
+  const int room = cap - n;
+  return 2 * room < max(32, n);
+}
+
+// Per-launch step indices, passed by value: the Philox step word is
+// step_base + step_off; parity selects the particle buffer holding the
+// current state; rot the counter set holding its counts.
+struct StepIndex {
+  uint32_t step_off;
+  uint32_t parity;
+  uint32_t rot;
+  uint32_t pad;
 };
 
 // Element record for tracking: vertex coordinates and, per edge k
@@ -72,11 +89,11 @@ template <typename T> struct StateDev {
 };
 
 // A cell's particles sit in two runs of its segment: the ones that stayed in
-// the element, written by the cell's own wavefront from the bottom
-// (count ns), and the ones that arrived from other elements, appended from the
-// top with an atomic counter (count nm).  Counter sets rotate over three
-// buffers: the current counts (read only), the next counts (being written),
-// and the set two steps back, cleared for the step after.
+// the element, written by the cell's own lane group from the bottom (count
+// ns), and the ones that arrived from other elements, appended from the top
+// with an atomic counter (count nm).  Counter sets rotate over three buffers:
+// the current counts (read only), the next counts (being written), and the
+// set two steps back, cleared for the step after.
 template <typename T> struct StepArgs {
   const ERec* erec;       // ne
   const int32_t* tri;     // ne x 3
@@ -85,6 +102,7 @@ template <typename T> struct StepArgs {
   double Lx, Ly;
   int32_t ne;
   int32_t ncell;
+  const int32_t* order;   // ncell: processing order of the cells
   const T* coef;          // nv x 16
   const T* rate;          // ncell
   const int32_t* start;   // ncell
@@ -102,10 +120,11 @@ template <typename T> struct StepArgs {
   int32_t nstat;
   int32_t flags;
   int32_t mix;
+  int32_t nitems;         // work items (wavefronts' worth of cells)
   T dt, sdt, nu2, s2nu;
 };
 
-// Logical block index that gives each XCD a contiguous range of cells:
+// Logical block index that gives each XCD a contiguous range of work:
 // hardware dispatches consecutive workgroups round-robin over the 8 XCDs.
 __device__ __forceinline__ int xcd_block(int b, int G) {
   const int NX = 8;
@@ -127,6 +146,13 @@ template <int CTRL> __device__ __forceinline__ double dpp_f64(double v) {
   return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
 }
 
+__device__ __forceinline__ double shfl_xor_f64(double v, int m) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __shfl_xor((int)(unsigned)(b & 0xffffffffll), m, WAVE);
+  const int hi = __shfl_xor((int)(b >> 32), m, WAVE);
+  return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
+}
+
 __device__ __forceinline__ double readlane_f64(double v, int l) {
   const long long b = __double_as_longlong(v);
   const int lo = __builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffll), l);
@@ -134,42 +160,22 @@ __device__ __forceinline__ double readlane_f64(double v, int l) {
   return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
 }
 
-// Sum over the 64 lanes, returned wave-uniform.  Rows of 16 lanes are reduced
-// with DPP (quad swaps, half-row and row mirrors: every lane of a row ends with
-// the same row sum), then the four row sums are combined in a fixed order.
-__device__ __forceinline__ double wave_sum(double v) {
-  v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
-  v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
-  v += dpp_f64<0x141>(v);  // row_half_mirror
-  v += dpp_f64<0x140>(v);  // row_mirror
-  const double r0 = readlane_f64(v, 0), r1 = readlane_f64(v, 16);
-  const double r2 = readlane_f64(v, 32), r3 = readlane_f64(v, 48);
-  return (r0 + r1) + (r2 + r3);
+// Sum over a group of G consecutive lanes, returned to every lane of the
+// group.  A butterfly in a fixed order: quad swaps, half-row and row mirrors
+// (DPP), then lane swaps across rows; every lane of a group gets the same bits.
+template <int G> __device__ __forceinline__ double group_sum(double v) {
+  v += dpp_f64<0xB1>(v);                      // quad_perm [1,0,3,2]
+  v += dpp_f64<0x4E>(v);                      // quad_perm [2,3,0,1]
+  if constexpr (G >= 8) v += dpp_f64<0x141>(v);   // row_half_mirror
+  if constexpr (G >= 16) v += dpp_f64<0x140>(v);  // row_mirror
+  if constexpr (G >= 32) v += shfl_xor_f64(v, 16);
+  if constexpr (G >= 64) v += shfl_xor_f64(v, 32);
+  return v;
 }
 
-// Sums of K per-lane values, delivered transposed: lane q (q < K) receives
-// the wave sum of value q, other lanes 0.  Quads are reduced with DPP, the 16
-// quad sums of each value go through LDS (row stride 17 doubles against bank
-// conflicts), and lane q adds its 16 quad sums in order.  The order of every
-// addition is fixed, so the result does not depend on timing.
-constexpr int RED_STRIDE = 17;
-
-template <int K>
-__device__ __forceinline__ double wave_sums_to_lanes(const double (&vals)[K], double* red) {
-  const int lane = lane_id();
-#pragma unroll
-  for (int q = 0; q < K; ++q) {
-    double v = vals[q];
-    v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
-    v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
-    if ((lane & 3) == 0) red[q * RED_STRIDE + (lane >> 2)] = v;
-  }
-  double s = 0.0;
-  if (lane < K) {
-#pragma unroll
-    for (int r = 0; r < 16; ++r) s += red[lane * RED_STRIDE + r];
-  }
-  return s;
+template <int G> __device__ __forceinline__ uint64_t group_mask(int grp) {
+  if constexpr (G == 64) return ~0ull;
+  else return ((1ull << G) - 1ull) << (grp * G);
 }
 
 template <typename T> __device__ __forceinline__ T pick3(const T* a, int k) {
@@ -283,16 +289,19 @@ __device__ int walk(const StepArgs<T>& a, ERec R, int e, double Sx, double Sy, T
 }
 
 // ---------------------------------------------------------------------------
-// the fused step.  One wavefront per cell:
+// the fused step.  A group of G consecutive lanes owns one cell (64/G cells
+// per wavefront, taken from a list ordered so that the cells of a wavefront
+// have similar particle counts):
 //   A  read the cell's particles once from HBM into an LDS tile (the first
-//      TILE of them; a larger cell re-reads the rest from L2) and sum the
+//      4G of them; a larger cell re-reads the rest from L2) and sum the
 //      velocity and scalar: the means;
-//   B  central moments, velocity-bin counts and scalar sums, histogram: the
+//   B  central moments, velocity-bin scalar sums and counts, histogram: the
 //      statistics record of the cell;
 //   C  IECM with those statistics, velocity, position, tracking, source;
-//      stayers are written back in order without atomics, movers are
-//      appended to their new cell.
-// ADVANCE = false stops after B.
+//      stayers are written back in order without atomics, movers take one
+//      atomic slot at the top of their new cell's segment.
+// ADVANCE = false stops after B.  PERSIST: a grid sized to the machine pulls
+// wavefront work items from a counter instead of one item per wavefront.
 
 template <int MOM> struct MomCount { static constexpr int M3 = 0, M4 = 0; };
 template <> struct MomCount<4> { static constexpr int M3 = 20, M4 = 35; };
@@ -300,64 +309,85 @@ template <> struct MomCount<4> { static constexpr int M3 = 20, M4 = 35; };
 // position of (x, y), x <= y, in the lexicographic list of index pairs of (u, v, w, psi)
 __host__ __device__ constexpr int pair_index(int x, int y) { return x * 4 - (x * (x - 1)) / 2 + (y - x); }
 
-// position of (x, y, z), x <= y <= z, in the lexicographic list of index triples
-__host__ __device__ constexpr int triple_index(int x, int y, int z) {
-  int it = 0;
-  for (int p = 0; p < 4; ++p)
-    for (int q = p; q < 4; ++q)
-      for (int r = q; r < 4; ++r)
-        if (p < x || (p == x && (q < y || (q == y && r < z)))) ++it;
-  return it;
-}
-
-constexpr int TILE = 256;  // particles of a cell staged in LDS
-constexpr int RED_MAX = 20; // values reduced together
-
-template <typename T> struct Tile {
-  T x[TILE], y[TILE], u[TILE], v[TILE], w[TILE], psi[TILE];
-  uint32_t id[TILE];
+template <typename T, int TILEN> struct Tile {
+  T x[TILEN], y[TILEN], u[TILEN], v[TILEN], w[TILEN], psi[TILEN];
+  uint32_t id[TILEN];
 };
 
-template <typename T, int MOM, int HIST, bool ADVANCE>
-__global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a) {
-  __shared__ Tile<T> tiles[WAVES_PER_BLOCK];
-  __shared__ double red_lds[WAVES_PER_BLOCK][RED_MAX * RED_STRIDE];
-  __shared__ int hist_lds[WAVES_PER_BLOCK][HIST > 0 ? HIST : 1];
+// Group-uniform values v[0..K) written to rec[0..K) by the lanes of the group:
+// lane li writes entries li, li + G, ...
+template <int G, int K>
+__device__ __forceinline__ void group_store(double* rec, const double (&v)[K], int li, bool ok) {
+#pragma unroll
+  for (int r = 0; r < (K + G - 1) / G; ++r) {
+    double val = 0.0;
+#pragma unroll
+    for (int q = r * G; q < (r + 1) * G && q < K; ++q) val = (li == q - r * G) ? v[q] : val;
+    const int idx = r * G + li;
+    if (ok && idx < K) rec[idx] = val;
+  }
+}
+
+template <typename T, int MOM, int HIST, int G, bool ADVANCE, bool PERSIST>
+__global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
+  constexpr int GPW = WAVE / G;             // cells per wavefront
+  constexpr int TILEN = 4 * G;              // particles per cell staged in LDS
+  constexpr int CPB = WAVES_PER_BLOCK * GPW;
+  __shared__ Tile<T, TILEN> tiles[CPB];
+  __shared__ int hist_lds[HIST > 0 ? CPB : 1][HIST > 0 ? HIST : 1];
   Ctl* ctl = a.ctl;
-  if (ADVANCE && ctl->halt) return;
-  const uint32_t step = ctl->step;
-  const uint32_t par = ctl->parity;
-  const uint32_t rot = ctl->crot;
+  // after an error the state is void: later steps do nothing
+  if (ADVANCE && ctl->error != 0) return;
+  const uint32_t step = ctl->step_base + si.step_off;
+  const uint32_t par = si.parity;
+  const uint32_t bpar = par ^ (ctl->flip & 1u);
+  const int rc = (int)si.rot, rn = rc == 2 ? 0 : rc + 1, rz = rc == 0 ? 2 : rc - 1;
   const int lane = lane_id();
   const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
-  const int cell = xcd_block(blockIdx.x, gridDim.x) * WAVES_PER_BLOCK + wid;
-  const int rc = (int)rot, rn = (int)(rot == 2 ? 0 : rot + 1), rz = (int)(rot == 0 ? 2 : rot - 1);
+  const int grp = lane / G;
+  const int li = lane - grp * G;
+  const int slot_id = wid * GPW + grp;
+  const uint64_t gmask = group_mask<G>(grp);
+  if (ADVANCE && blockIdx.x == 0 && threadIdx.x == 0) ctl->next[par ^ 1u] = 0;
+  const StateDev<T> src = a.buf[bpar];
+  const StateDev<T> dst = a.buf[bpar ^ 1u];
+  Tile<T, TILEN>& L = tiles[slot_id];
 
-  if (cell < a.ncell) {
-    const StateDev<T> src = a.buf[par];
-    const StateDev<T> dst = a.buf[par ^ 1u];
-    Tile<T>& L = tiles[wid];
+  int item = PERSIST ? 0 : xcd_block(blockIdx.x, gridDim.x) * WAVES_PER_BLOCK + wid;
+  for (;;) {
+    if (PERSIST) {
+      int it = 0;
+      if (lane == 0) it = (int)atomicAdd(&ctl->next[par], 1u);
+      item = __builtin_amdgcn_readfirstlane(it);
+    }
+    if (item >= a.nitems) break;
+    const int idx = item * GPW + grp;
+    const int cell_l = idx < a.ncell ? a.order[idx] : -1;
+    const int cell = (G == WAVE) ? __builtin_amdgcn_readfirstlane(cell_l) : cell_l;
+    const bool has = cell >= 0;
     const int ne = a.ne;
-    const int ens = cell / ne;
-    const int e = cell - ens * ne;
-    const int start = a.start[cell];
-    const int capc = a.cap[cell];
-    // counts are clamped to the segment so that even the step after an
-    // overflow (whose results are void) reads inside the segment
-    const int ns = min(a.ns[rc][cell], capc);
-    const int nm = min(a.nm[rc][cell], capc - ns);
+    const int ens = has ? cell / ne : 0;
+    const int e = has ? cell - ens * ne : 0;
+    int start = 0, capc = 0, ns = 0, nm = 0;
+    if (has) {
+      start = a.start[cell];
+      capc = a.cap[cell];
+      // counts are clamped to the segment so that reads stay inside it
+      ns = min(a.ns[rc][cell], capc);
+      nm = min(a.nm[rc][cell], capc - ns);
+      if (ADVANCE && li == 0 && repack_due(ns + nm, capc)) ctl->repack = 1u;
+    }
     const int n = ns + nm;
     const double dn = (double)n;
 
     // ---- A: load, stage, means ----
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
     {
-      // the staged part: all TILE/WAVE loads in flight together
-      T tx_[TILE / WAVE], ty_[TILE / WAVE], tu_[TILE / WAVE], tv_[TILE / WAVE], tw_[TILE / WAVE], tp_[TILE / WAVE];
-      uint32_t ti_[TILE / WAVE];
+      T tx_[TILEN / G], ty_[TILEN / G], tu_[TILEN / G], tv_[TILEN / G], tw_[TILEN / G], tp_[TILEN / G];
+      uint32_t ti_[TILEN / G];
 #pragma unroll
-      for (int c = 0; c < TILE / WAVE; ++c) {
-        const int j = c * WAVE + lane;
+      for (int c = 0; c < TILEN / G; ++c) {
+        const int j = c * G + li;
         if (j < n) {
           const int s = slot_of(j, start, ns, nm, capc);
           tx_[c] = src.x[s]; ty_[c] = src.y[s]; tu_[c] = src.u[s]; tv_[c] = src.v[s]; tw_[c] = src.w[s];
@@ -365,8 +395,8 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a) {
         }
       }
 #pragma unroll
-      for (int c = 0; c < TILE / WAVE; ++c) {
-        const int j = c * WAVE + lane;
+      for (int c = 0; c < TILEN / G; ++c) {
+        const int j = c * G + li;
         if (j < n) {
           L.x[j] = tx_[c]; L.y[j] = ty_[c]; L.u[j] = tu_[c]; L.v[j] = tv_[c]; L.w[j] = tw_[c]; L.psi[j] = tp_[c];
           L.id[j] = ti_[c];
@@ -377,29 +407,25 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a) {
         }
       }
     }
-    for (int base = TILE; base < n; base += WAVE) {
-      const int j = base + lane;
+    for (int base = TILEN; __ballot(base < n) != 0; base += G) {
+      const int j = base + li;
       if (j < n) {
         const int s = slot_of(j, start, ns, nm, capc);
-        const T u = src.u[s], v = src.v[s], w = src.w[s], p = src.psi[s];
-        s0 += (double)u;
-        s1 += (double)v;
-        s2 += (double)w;
-        s3 += (double)p;
+        s0 += (double)src.u[s];
+        s1 += (double)src.v[s];
+        s2 += (double)src.w[s];
+        s3 += (double)src.psi[s];
       }
     }
-    double* red = red_lds[wid];
     const double inv_n = n > 0 ? 1.0 / dn : 0.0;
     double mean[4];
-    {
-      const double sums[4] = {s0, s1, s2, s3};
-      const double mean_l = wave_sums_to_lanes<4>(sums, red) * inv_n;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) mean[q] = readlane_f64(mean_l, q);
-    }
+    mean[0] = group_sum<G>(s0) * inv_n;
+    mean[1] = group_sum<G>(s1) * inv_n;
+    mean[2] = group_sum<G>(s2) * inv_n;
+    mean[3] = group_sum<G>(s3) * inv_n;
 
     auto load4 = [&](int j, double* val) {
-      if (j < TILE) {
+      if (j < TILEN) {
         val[0] = (double)L.u[j]; val[1] = (double)L.v[j]; val[2] = (double)L.w[j]; val[3] = (double)L.psi[j];
       } else {
         const int s = slot_of(j, start, ns, nm, capc);
@@ -415,10 +441,10 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a) {
 #pragma unroll
     for (int q = 0; q < 8; ++q) bcount[q] = 0;
     if (HIST > 0) {
-      for (int h = lane; h < HIST; h += WAVE) hist_lds[wid][h] = 0;
+      for (int h = li; h < HIST; h += G) hist_lds[slot_id][h] = 0;
     }
-    for (int base = 0; base < n; base += WAVE) {
-      const int j = base + lane;
+    for (int base = 0; __ballot(base < n) != 0; base += G) {
+      const int j = base + li;
       const bool act = j < n;
       int bin = -1;
       if (act) {
@@ -437,53 +463,43 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a) {
         if (HIST > 0) {
           const double hpos = floor(val[3] * (double)HIST);
           const int hb = hpos < 0.0 ? 0 : (hpos >= (double)HIST ? HIST - 1 : (int)hpos);
-          atomicAdd(&hist_lds[wid][hb], 1);
+          atomicAdd(&hist_lds[slot_id][hb], 1);
         }
       }
 #pragma unroll
-      for (int q = 0; q < 8; ++q) bcount[q] += (int)__popcll(__ballot(bin == q));
+      for (int q = 0; q < 8; ++q) bcount[q] += (int)__popcll(__ballot(bin == q) & gmask);
     }
-    const double sumB = wave_sums_to_lanes<18>(acc, red);
-    // lane q < 10: second moment q; lane 10 + b: scalar sum of bin b
-    double cnt_l = 0.0;
 #pragma unroll
-    for (int q = 0; q < 8; ++q) cnt_l = (lane == 10 + q) ? (double)bcount[q] : cnt_l;
-    const double bm_l = cnt_l > 0.0 ? sumB / cnt_l : mean[3];
+    for (int q = 0; q < 18; ++q) acc[q] = group_sum<G>(acc[q]);
     double bm[8];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) bm[q] = readlane_f64(bm_l, 10 + q);
-    double* rec = a.stats + (size_t)cell * a.nstat;
+    for (int q = 0; q < 8; ++q) bm[q] = bcount[q] > 0 ? acc[10 + q] / (double)bcount[q] : mean[3];
+    double* rec = a.stats + (size_t)(has ? cell : 0) * a.nstat;
     {
-      // one store per lane: lanes 0-9 second moments, 10-17 bin means,
-      // 18-25 bin counts, 26 count, 27-30 means
-      int idx = -1;
-      double val = 0.0;
-      if (lane < 10) { idx = ST_M2 + lane; val = sumB * inv_n; }
-      else if (lane < 18) { idx = ST_BINM + (lane - 10); val = bm_l; }
-      else if (lane < 26) {
-        idx = ST_BINN + (lane - 18);
-        double c = 0.0;
+      double r2[NSTAT2];
+      r2[ST_N] = dn;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) c = (lane == 18 + q) ? (double)bcount[q] : c;
-        val = c;
-      } else if (lane == 26) { idx = ST_N; val = dn; }
-      else if (lane < 31) {
-        idx = ST_MEAN + (lane - 27);
-        double mq = mean[0];
+      for (int q = 0; q < 4; ++q) r2[ST_MEAN + q] = mean[q];
 #pragma unroll
-        for (int q = 1; q < 4; ++q) mq = (lane == 27 + q) ? mean[q] : mq;
-        val = mq;
+      for (int q = 0; q < 10; ++q) r2[ST_M2 + q] = acc[q] * inv_n;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        r2[ST_BINN + q] = (double)bcount[q];
+        r2[ST_BINM + q] = bm[q];
       }
-      if (n == 0) val = 0.0;
-      if (idx >= 0) rec[idx] = val;
+      if (n == 0) {
+#pragma unroll
+        for (int q = 0; q < NSTAT2; ++q) r2[q] = 0.0;
+      }
+      group_store<G, NSTAT2>(rec, r2, li, has);
     }
     if constexpr (MOM >= 4) {
       // third-order moments
       double m3[20];
 #pragma unroll
       for (int q = 0; q < 20; ++q) m3[q] = 0.0;
-      for (int base = 0; base < n; base += WAVE) {
-        const int j = base + lane;
+      for (int base = 0; __ballot(base < n) != 0; base += G) {
+        const int j = base + li;
         if (j < n) {
           double val[4], d[4];
           load4(j, val);
@@ -498,18 +514,19 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a) {
               for (int z = y; z < 4; ++z) { m3[i3] += (d[x] * d[y]) * d[z]; ++i3; }
         }
       }
-      const double s3l = wave_sums_to_lanes<20>(m3, red);
-      if (lane < 20) rec[ST_M3 + lane] = s3l * inv_n;
+#pragma unroll
+      for (int q = 0; q < 20; ++q) m3[q] = group_sum<G>(m3[q]) * inv_n;
+      group_store<G, 20>(rec + ST_M3, m3, li, has);
       // fourth-order moments, in two groups to bound the accumulator count
 #pragma unroll
-      for (int grp = 0; grp < 2; ++grp) {
-        constexpr int G0 = 18;
-        const int lo = grp == 0 ? 0 : G0, hi = grp == 0 ? G0 : 35;
-        double m4[G0];
+      for (int part = 0; part < 2; ++part) {
+        constexpr int P0 = 18;
+        const int lo = part == 0 ? 0 : P0, hi = part == 0 ? P0 : 35;
+        double m4[P0];
 #pragma unroll
-        for (int q = 0; q < G0; ++q) m4[q] = 0.0;
-        for (int base = 0; base < n; base += WAVE) {
-          const int j = base + lane;
+        for (int q = 0; q < P0; ++q) m4[q] = 0.0;
+        for (int base = 0; __ballot(base < n) != 0; base += G) {
+          const int j = base + li;
           if (j < n) {
             double val[4], d[4];
             load4(j, val);
@@ -529,39 +546,48 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a) {
                   }
           }
         }
-        const double s4l = wave_sums_to_lanes<G0>(m4, red);
-        if (lane < hi - lo) rec[ST_M4 + lo + lane] = s4l * inv_n;
+#pragma unroll
+        for (int q = 0; q < P0; ++q) m4[q] = group_sum<G>(m4[q]) * inv_n;
+        if (part == 0) {
+          group_store<G, P0>(rec + ST_M4, m4, li, has);
+        } else {
+          double m4b[35 - P0];
+#pragma unroll
+          for (int q = 0; q < 35 - P0; ++q) m4b[q] = m4[q];
+          group_store<G, 35 - P0>(rec + ST_M4 + P0, m4b, li, has);
+        }
       }
     }
     if (HIST > 0) {
       const int off = MOM >= 4 ? NSTAT4 : NSTAT2;
-      for (int h = lane; h < HIST; h += WAVE) rec[off + h] = (double)hist_lds[wid][h];
+      for (int h = li; h < HIST; h += G)
+        if (has) rec[off + h] = (double)hist_lds[slot_id][h];
     }
 
     if (ADVANCE) {
       // ---- C: advance ----
-      const ERec R0 = a.erec[e];
+      ERec R0 = a.erec[e];
       const int v0 = a.tri[3 * e], v1 = a.tri[3 * e + 1], v2 = a.tri[3 * e + 2];
       const double ia = a.inv2a[e];
       const T* q0 = a.coef + (size_t)v0 * NCOEF;
       const T* q1 = a.coef + (size_t)v1 * NCOEF;
       const T* q2 = a.coef + (size_t)v2 * NCOEF;
-      const T rate = a.rate[cell];
+      const T rate = has ? a.rate[cell] : (T)0;
       const uint64_t seed = a.seed[ens];
       const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
       const double sx0 = a.src[3 * ens], sy0 = a.src[3 * ens + 1], sr0 = a.src[3 * ens + 2];
       const bool do_mix = a.mix && (a.flags & FLAG_MIX);
       int err = 0;
       int stay_count = 0;
-      for (int base = 0; base < n; base += WAVE) {
-        const int j = base + lane;
+      for (int base = 0; __ballot(base < n) != 0; base += G) {
+        const int j = base + li;
         const bool act = j < n;
         int e2 = -1;
         T xn = 0, yn = 0, un = 0, vn = 0, wn = 0, psi = 0;
         uint32_t id = 0;
         if (act) {
           T x, y, u, v, w;
-          if (j < TILE) {
+          if (j < TILEN) {
             x = L.x[j]; y = L.y[j]; u = L.u[j]; v = L.v[j]; w = L.w[j]; psi = L.psi[j]; id = L.id[j];
           } else {
             const int s = slot_of(j, start, ns, nm, capc);
@@ -621,7 +647,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a) {
         }
         // stayers: own segment, bottom run, in lane order, no atomics
         const bool stay = act && e2 == e;
-        const uint64_t smask = __ballot(stay);
+        const uint64_t smask = __ballot(stay) & gmask;
         if (stay) {
           const int s = start + stay_count + (int)__popcll(smask & lanemask_lt());
           dst.x[s] = xn; dst.y[s] = yn; dst.u[s] = un; dst.v[s] = vn; dst.w[s] = wn; dst.psi[s] = psi;
@@ -651,7 +677,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a) {
           }
         }
       }
-      if (lane == 0) {
+      if (has && li == 0) {
         a.ns[rn][cell] = stay_count;
         a.ns[rz][cell] = 0;
         a.nm[rz][cell] = 0;
@@ -662,21 +688,13 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a) {
         if (__ballot((err >> bit) & 1)) werr |= 1 << bit;
       if (lane == 0 && werr) atomicOr(&ctl->error, werr);
     }
+    if (!PERSIST) break;
   }
 }
 
-// End of a step: advance the step counter, swap the particle buffers, rotate
-// the counter sets, and stop further steps once an error was raised.  A
-// separate one-thread launch: the kernel boundary orders it after every
-// workgroup of the step without any device-wide fence in the step itself.
-__global__ void k_step_end(Ctl* ctl) {
-  if (threadIdx.x == 0 && blockIdx.x == 0 && !ctl->halt) {
-    ctl->step = ctl->step + 1;
-    ctl->parity = ctl->parity ^ 1u;
-    ctl->crot = ctl->crot == 2 ? 0 : ctl->crot + 1;
-    ctl->steps_done = ctl->steps_done + 1;
-    if (ctl->error != 0) ctl->halt = 1;
-  }
+// Adds the steps of one call to the Philox step base (after the call's steps).
+__global__ void k_advance_base(Ctl* ctl, uint32_t nsteps) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) ctl->step_base = ctl->step_base + nsteps;
 }
 
 // ---------------------------------------------------------------------------
@@ -895,16 +913,16 @@ struct CounterSets {
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_gather(StateDev<T> b0, StateDev<T> b1, CounterSets cs,
                                                   const int32_t* start, const int32_t* cap, const Ctl* ctl,
-                                                  int ens, int ne, int64_t n, double* out, int32_t* elem) {
+                                                  StepIndex si, int ens, int ne, int64_t n, double* out,
+                                                  int32_t* elem) {
   const int lane = lane_id();
   const int e = blockIdx.x * WAVES_PER_BLOCK + (int)(threadIdx.x / WAVE);
   if (e >= ne) return;
-  const uint32_t par = ctl->parity, rot = ctl->crot;
-  const StateDev<T> st = par ? b1 : b0;
+  const StateDev<T> st = (si.parity ^ (ctl->flip & 1u)) ? b1 : b0;
   const int cell = ens * ne + e;
   const int capc = cap[cell], s0 = start[cell];
-  const int ns = min(cs.ns[rot][cell], capc);
-  const int nm = min(cs.nm[rot][cell], capc - ns);
+  const int ns = min(cs.ns[si.rot][cell], capc);
+  const int nm = min(cs.nm[si.rot][cell], capc - ns);
   const int c = ns + nm;
   for (int j = lane; j < c; j += WAVE) {
     const int s = slot_of(j, s0, ns, nm, capc);
@@ -922,9 +940,159 @@ __global__ __launch_bounds__(BLOCK) void k_gather(StateDev<T> b0, StateDev<T> b1
 
 __global__ void k_reset_ctl(Ctl* ctl) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
-    ctl->step = 0; ctl->parity = 0; ctl->crot = 0; ctl->error = 0; ctl->halt = 0; ctl->spare = 0;
-    ctl->ovf = 0; ctl->lost = 0; ctl->steps_done = 0;
+    ctl->step_base = 0; ctl->error = 0; ctl->ovf = 0; ctl->next[0] = 0; ctl->next[1] = 0;
+    ctl->repack = 0; ctl->active = 0; ctl->flip = 0; ctl->repacks = 0;
   }
+}
+
+// ---------------------------------------------------------------------------
+// repack: new segment layout from the current counts
+//
+// Segments are sized at seeding from the initial counts.  When the particle
+// density drifts, a step flags the segments that run short of room
+// (repack_due) and, at the next check, the planner gives every cell
+// capacity max(initial, floor(grow n) + pad) (or floor(slack n) + pad if that
+// does not fit the slots), the mover copies each cell's particles, in their
+// logical order, into the other buffer at the new offsets, and the buffer
+// parity flips.  Without the flag both kernels return at once.
+
+struct RepackPlan {
+  const int32_t* cap;     // ncell: current capacities
+  const int32_t* cap0;    // ncell: capacities at seeding
+  const int32_t* ns;      // ncell: current counter set
+  const int32_t* nm;
+  int32_t* nstart;        // ncell: new offsets (out)
+  int32_t* ncap;          // ncell: new capacities (out)
+  Ctl* ctl;
+  int32_t ncell;
+  int32_t pad;
+  int64_t slots;
+  double grow, slack;
+};
+
+constexpr int PLAN_THREADS = 1024;
+
+__device__ __forceinline__ int64_t plan_cap(const RepackPlan& p, int c, bool fallback) {
+  const int capc = p.cap[c];
+  const int ns = min(p.ns[c], capc);
+  const int nm = min(p.nm[c], capc - ns);
+  const double n = (double)(ns + nm);
+  if (fallback) return (int64_t)floor(p.slack * n) + p.pad;
+  return max((int64_t)p.cap0[c], (int64_t)floor(p.grow * n) + p.pad);
+}
+
+// One block: capacities, then an exclusive scan over the cells.
+__global__ __launch_bounds__(PLAN_THREADS) void k_repack_plan(RepackPlan p) {
+  __shared__ int64_t wsum[PLAN_THREADS / WAVE];
+  __shared__ int64_t total_s;
+  Ctl* ctl = p.ctl;
+  if (ctl->repack == 0u || ctl->error != 0) {
+    if (threadIdx.x == 0) ctl->active = 0u;
+    return;
+  }
+  const int t = threadIdx.x;
+  const int lane = lane_id(), wv = t / WAVE;
+  const int per = (p.ncell + PLAN_THREADS - 1) / PLAN_THREADS;
+  const int c0 = min(p.ncell, t * per), c1 = min(p.ncell, c0 + per);
+  bool fallback = false;
+  int64_t excl = 0;
+  for (int pass = 0; pass < 2; ++pass) {
+    int64_t mine = 0;
+    for (int c = c0; c < c1; ++c) mine += plan_cap(p, c, fallback);
+    // block exclusive scan of the per-thread sums
+    int64_t incl = mine;
+    for (int off = 1; off < WAVE; off <<= 1) {
+      const int64_t o = __shfl_up(incl, off, WAVE);
+      if (lane >= off) incl += o;
+    }
+    if (lane == WAVE - 1) wsum[wv] = incl;
+    __syncthreads();
+    if (t == 0) {
+      int64_t acc = 0;
+      for (int w = 0; w < PLAN_THREADS / WAVE; ++w) {
+        const int64_t v = wsum[w];
+        wsum[w] = acc;
+        acc += v;
+      }
+      total_s = acc;
+    }
+    __syncthreads();
+    excl = wsum[wv] + incl - mine;
+    const int64_t total = total_s;
+    __syncthreads();
+    if (total <= p.slots) break;
+    if (fallback) {
+      // cannot happen while the particle count is conserved
+      if (t == 0) {
+        atomicOr(&ctl->error, ERR_CAPACITY);
+        ctl->active = 0u;
+        ctl->repack = 0u;
+      }
+      return;
+    }
+    fallback = true;
+  }
+  int64_t o = excl;
+  for (int c = c0; c < c1; ++c) {
+    const int64_t cp = plan_cap(p, c, fallback);
+    p.nstart[c] = (int32_t)o;
+    p.ncap[c] = (int32_t)cp;
+    o += cp;
+  }
+  if (t == 0) {
+    ctl->active = 1u;
+    ctl->repack = 0u;
+    ctl->flip = ctl->flip ^ 1u;
+    ctl->repacks = ctl->repacks + 1u;
+  }
+}
+
+template <typename T> struct RepackMove {
+  StateDev<T> buf[2];
+  int32_t* start;
+  int32_t* cap;
+  int32_t* ns;            // current counter set
+  int32_t* nm;
+  const int32_t* nstart;
+  const int32_t* ncap;
+  const Ctl* ctl;
+  int32_t ncell;
+};
+
+// One wavefront per cell: copy the particles to the new segment (all in the
+// bottom run) and install the new offsets, capacity and counts.
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_repack_move(RepackMove<T> m, StepIndex si) {
+  if (m.ctl->active == 0u) return;
+  const int cell = blockIdx.x * WAVES_PER_BLOCK + (int)(threadIdx.x / WAVE);
+  if (cell >= m.ncell) return;
+  const int lane = lane_id();
+  // the planner has flipped the parity: the current state is in the other buffer
+  const uint32_t bnew = si.parity ^ (m.ctl->flip & 1u);
+  const StateDev<T> src = m.buf[bnew ^ 1u];
+  const StateDev<T> dst = m.buf[bnew];
+  const int capc = m.cap[cell], s0 = m.start[cell];
+  const int ns = min(m.ns[cell], capc);
+  const int nm = min(m.nm[cell], capc - ns);
+  const int n = ns + nm;
+  const int d0 = m.nstart[cell];
+  for (int j = lane; j < n; j += WAVE) {
+    const int s = slot_of(j, s0, ns, nm, capc);
+    const int d = d0 + j;
+    dst.x[d] = src.x[s]; dst.y[d] = src.y[s]; dst.u[d] = src.u[s]; dst.v[d] = src.v[s]; dst.w[d] = src.w[s];
+    dst.psi[d] = src.psi[s]; dst.id[d] = src.id[s];
+  }
+  if (lane == 0) {
+    m.start[cell] = d0;
+    m.cap[cell] = m.ncap[cell];
+    m.ns[cell] = n;
+    m.nm[cell] = 0;
+  }
+}
+
+// Host-requested repack: raise the flag for the next planner.
+__global__ void k_request_repack(Ctl* ctl) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) ctl->repack = 1u;
 }
 
 __global__ void k_fill_i32(int32_t* p, int32_t v, int64_t n) {

@@ -23,7 +23,7 @@ int64_t align_up(int64_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 // Byte offsets of the arena sections.
 struct Layout {
   int64_t vtx, tri, nbr, ekind, inv2a, alpha, fields, coef, erec;
-  int64_t start, cap, ns[3], nm[3], rate, idoff, seed, src;
+  int64_t start, cap, cap0, nstart, ncap, ns[3], nm[3], rate, idoff, order, seed, src;
   int64_t buf0, buf1, ovf, ovf_cell, stats, ctl, flag;
   int64_t total;
   int64_t slots;
@@ -46,12 +46,16 @@ Layout make_layout(int32_t nv, int32_t ne, int32_t nens, int64_t slots, int32_t 
   L.erec = take((int64_t)ne * (int64_t)sizeof(ERec));
   L.start = take(ncell * 4);
   L.cap = take(ncell * 4);
+  L.cap0 = take(ncell * 4);
+  L.nstart = take(ncell * 4);
+  L.ncap = take(ncell * 4);
   for (int r = 0; r < 3; ++r) {
     L.ns[r] = take(ncell * 4);
     L.nm[r] = take(ncell * 4);
   }
   L.rate = take(ncell * tsize);
   L.idoff = take(ncell * 4);
+  L.order = take(ncell * 4);
   L.seed = take((int64_t)nens * 8);
   L.src = take((int64_t)nens * 3 * 8);
   const int64_t per_buf = align_up(slots * tsize) * 6 + align_up(slots * 4);
@@ -98,7 +102,18 @@ struct pdf_ctx {
   bool seeded = false;
   int64_t slots = 0;
   Layout L{};
-  std::vector<int32_t> h_start, h_cap, h_cnt, h_idoff, h_zero;
+  std::vector<int32_t> h_start, h_cap, h_cnt, h_idoff, h_zero, h_order;
+  // host-side step state: the launch arguments of the next step
+  int64_t steps_done = 0;
+  uint32_t parity = 0, rot = 0;
+  // launch configuration (set by pdf_autotune; defaults below)
+  int32_t group = 64;     // lanes per cell
+  int32_t persist = 0;    // persistent scheduler
+  int32_t persist_blocks = 0;
+  // replayable graph of GRAPH_STEPS steps (built for one launch shape)
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  int32_t graph_group = 0, graph_persist = -1;
   std::vector<uint64_t> h_seed;
   std::vector<double> h_src;
   std::vector<int64_t> ens_count;
@@ -125,15 +140,25 @@ pdf_status hip_check(pdf_ctx* c, hipError_t e, const char* what) {
   return fail(c, PDF_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-int64_t slots_bound(int64_t nparticles, int64_t ncell, double slack) {
-  return (int64_t)std::ceil(slack * (double)nparticles) + (int64_t)(SEG_PAD + 1) * ncell;
+// Slots beyond the seeding layout, kept for segments that grow at a repack.
+int64_t growth_reserve(int64_t nparticles, double slack) {
+  return (int64_t)std::ceil(0.25 * slack * (double)nparticles);
 }
+
+int64_t slots_bound(int64_t nparticles, int64_t ncell, double slack) {
+  return (int64_t)std::ceil(slack * (double)nparticles) + (int64_t)(SEG_PAD + 1) * ncell +
+         growth_reserve(nparticles, slack);
+}
+
+// Capacity factor of segments that a repack grows (at least 2 counts).
+double grow_factor(const pdf_params& p) { return std::max(2.0, p.slack); }
 
 template <typename T> StepArgs<T> step_args(pdf_ctx* c) {
   const Layout& L = c->L;
   char* a = c->arena;
   StepArgs<T> s{};
   s.erec = (const ERec*)(a + L.erec);
+  s.order = (const int32_t*)(a + L.order);
   s.tri = (const int32_t*)(a + L.tri);
   s.inv2a = (const double*)(a + L.inv2a);
   s.alpha = (const double*)(a + L.alpha);
@@ -168,22 +193,224 @@ template <typename T> StepArgs<T> step_args(pdf_ctx* c) {
   return s;
 }
 
-template <typename T, int MOM, int HIST, bool ADV> void launch_step(pdf_ctx* c, const StepArgs<T>& s) {
-  const int ncell = s.ncell;
-  const int blocks = (ncell + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
-  hipLaunchKernelGGL((k_step<T, MOM, HIST, ADV>), dim3(blocks), dim3(BLOCK), 0, c->stream, s);
+template <typename T, int MOM, int HIST, int G, bool ADV, bool PERSIST>
+void launch_step(pdf_ctx* c, StepArgs<T> s, StepIndex si) {
+  constexpr int GPW = WAVE / G;
+  s.nitems = (s.ncell + GPW - 1) / GPW;
+  int blocks = (s.nitems + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
+  if (PERSIST) {
+    int per_cu = 0;
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step<T, MOM, HIST, G, ADV, PERSIST>, BLOCK, 0);
+    int cus = 0;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device);
+    const int cap_blocks = std::max(1, per_cu) * std::max(1, cus);
+    blocks = std::min(blocks, cap_blocks);
+    c->persist_blocks = blocks;
+  }
+  hipLaunchKernelGGL((k_step<T, MOM, HIST, G, ADV, PERSIST>), dim3(blocks), dim3(BLOCK), 0, c->stream, s, si);
 }
 
-template <typename T, bool ADV> pdf_status dispatch_step(pdf_ctx* c) {
-  StepArgs<T> s = step_args<T>(c);
-  const int mom = c->p.moments >= 4 ? 4 : 2;
-  const int hist = c->p.hist_bins;
-  if (mom == 2 && hist == 0) launch_step<T, 2, 0, ADV>(c, s);
-  else if (mom == 2 && hist == 32) launch_step<T, 2, 32, ADV>(c, s);
-  else if (mom == 4 && hist == 0) launch_step<T, 4, 0, ADV>(c, s);
-  else if (mom == 4 && hist == 32) launch_step<T, 4, 32, ADV>(c, s);
-  else return fail(c, PDF_E_ARG, "unsupported moments/hist_bins combination");
+template <typename T, int MOM, int HIST, bool ADV>
+void launch_group(pdf_ctx* c, const StepArgs<T>& s, StepIndex si) {
+  const bool P = ADV && c->persist;
+  switch (c->group) {
+    case 16: P ? launch_step<T, MOM, HIST, 16, ADV, true>(c, s, si) : launch_step<T, MOM, HIST, 16, ADV, false>(c, s, si); break;
+    case 32: P ? launch_step<T, MOM, HIST, 32, ADV, true>(c, s, si) : launch_step<T, MOM, HIST, 32, ADV, false>(c, s, si); break;
+    default: P ? launch_step<T, MOM, HIST, 64, ADV, true>(c, s, si) : launch_step<T, MOM, HIST, 64, ADV, false>(c, s, si); break;
+  }
+}
+
+// The float state supports (moments, histogram) = (2, 0) and (4, 32); the
+// double state (2, 0).
+bool supported(const pdf_params& p) {
+  if (p.f32_state) return (p.moments == 2 && p.hist_bins == 0) || (p.moments == 4 && p.hist_bins == 32);
+  return p.moments == 2 && p.hist_bins == 0;
+}
+
+template <bool ADV> pdf_status dispatch_step(pdf_ctx* c, StepIndex si) {
+  if (c->p.f32_state) {
+    StepArgs<float> s = step_args<float>(c);
+    if (c->p.moments == 2) launch_group<float, 2, 0, ADV>(c, s, si);
+    else launch_group<float, 4, 32, ADV>(c, s, si);
+  } else {
+    StepArgs<double> s = step_args<double>(c);
+    launch_group<double, 2, 0, ADV>(c, s, si);
+  }
   return hip_check(c, hipGetLastError(), "step launch");
+}
+
+RepackPlan repack_plan_args(pdf_ctx* c, uint32_t rot) {
+  const Layout& L = c->L;
+  char* a = c->arena;
+  RepackPlan p{};
+  p.cap = (const int32_t*)(a + L.cap);
+  p.cap0 = (const int32_t*)(a + L.cap0);
+  p.ns = (const int32_t*)(a + L.ns[rot]);
+  p.nm = (const int32_t*)(a + L.nm[rot]);
+  p.nstart = (int32_t*)(a + L.nstart);
+  p.ncap = (int32_t*)(a + L.ncap);
+  p.ctl = (Ctl*)(a + L.ctl);
+  p.ncell = c->ne * c->nens;
+  p.pad = SEG_PAD;
+  p.slots = L.slots;
+  p.grow = grow_factor(c->p);
+  p.slack = c->p.slack;
+  return p;
+}
+
+template <typename T> RepackMove<T> repack_move_args(pdf_ctx* c, uint32_t rot) {
+  const Layout& L = c->L;
+  char* a = c->arena;
+  RepackMove<T> m{};
+  m.buf[0] = state_at<T>(a, L.buf0, L.slots);
+  m.buf[1] = state_at<T>(a, L.buf1, L.slots);
+  m.start = (int32_t*)(a + L.start);
+  m.cap = (int32_t*)(a + L.cap);
+  m.ns = (int32_t*)(a + L.ns[rot]);
+  m.nm = (int32_t*)(a + L.nm[rot]);
+  m.nstart = (const int32_t*)(a + L.nstart);
+  m.ncap = (const int32_t*)(a + L.ncap);
+  m.ctl = (const Ctl*)(a + L.ctl);
+  m.ncell = c->ne * c->nens;
+  return m;
+}
+
+int repack_move_blocks(const pdf_ctx* c) { return (c->ne * c->nens + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK; }
+
+// The planner and the mover at a step boundary; both return at once unless a
+// repack was requested.
+pdf_status enqueue_repack(pdf_ctx* c) {
+  const StepIndex si{0, c->parity, c->rot, 0};
+  hipLaunchKernelGGL(k_repack_plan, dim3(1), dim3(PLAN_THREADS), 0, c->stream, repack_plan_args(c, c->rot));
+  if (c->p.f32_state)
+    hipLaunchKernelGGL(k_repack_move<float>, dim3(repack_move_blocks(c)), dim3(BLOCK), 0, c->stream,
+                       repack_move_args<float>(c, c->rot), si);
+  else
+    hipLaunchKernelGGL(k_repack_move<double>, dim3(repack_move_blocks(c)), dim3(BLOCK), 0, c->stream,
+                       repack_move_args<double>(c, c->rot), si);
+  return hip_check(c, hipGetLastError(), "repack launch");
+}
+
+// One step's kernel, its grid and its arguments, for graph construction.
+struct StepLaunch {
+  const void* func = nullptr;
+  int blocks = 0;
+};
+
+template <typename T, int MOM, int HIST, int G, bool PERSIST>
+StepLaunch step_launch_of(pdf_ctx* c, StepArgs<T>& s) {
+  constexpr int GPW = WAVE / G;
+  s.nitems = (s.ncell + GPW - 1) / GPW;
+  int blocks = (s.nitems + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
+  if (PERSIST) {
+    int per_cu = 0, cus = 0;
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step<T, MOM, HIST, G, true, PERSIST>, BLOCK, 0);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device);
+    blocks = std::min(blocks, std::max(1, per_cu) * std::max(1, cus));
+  }
+  StepLaunch l;
+  l.func = reinterpret_cast<const void*>(&k_step<T, MOM, HIST, G, true, PERSIST>);
+  l.blocks = blocks;
+  return l;
+}
+
+template <typename T, int MOM, int HIST>
+StepLaunch step_launch_group(pdf_ctx* c, StepArgs<T>& s) {
+  const bool P = c->persist;
+  switch (c->group) {
+    case 16: return P ? step_launch_of<T, MOM, HIST, 16, true>(c, s) : step_launch_of<T, MOM, HIST, 16, false>(c, s);
+    case 32: return P ? step_launch_of<T, MOM, HIST, 32, true>(c, s) : step_launch_of<T, MOM, HIST, 32, false>(c, s);
+    default: return P ? step_launch_of<T, MOM, HIST, 64, true>(c, s) : step_launch_of<T, MOM, HIST, 64, false>(c, s);
+  }
+}
+
+constexpr int GRAPH_STEPS = 6;  // parity repeats every 2 steps, the counter sets every 3
+
+// Builds a graph of GRAPH_STEPS consecutive steps (plus the step-base update)
+// for the current launch shape.  Nodes are added explicitly, so no stream
+// capture is involved and nothing but kernel nodes is recorded.
+template <typename T> pdf_status build_graph_t(pdf_ctx* c) {
+  // the runtime copies kernel arguments into each node when it is added
+  StepArgs<T> args_store = step_args<T>(c);
+  StepLaunch l;
+  if (c->p.moments == 2) l = step_launch_group<T, 2, 0>(c, args_store);
+  else l = step_launch_group<T, 4, 32>(c, args_store);
+  pdf_status r;
+  hipGraph_t g = nullptr;
+  if ((r = hip_check(c, hipGraphCreate(&g, 0), "graph create"))) return r;
+  hipGraphNode_t prev = nullptr;
+  StepIndex sis[GRAPH_STEPS];
+  void* params[GRAPH_STEPS][2];
+  for (int i = 0; i < GRAPH_STEPS; ++i) {
+    sis[i] = StepIndex{(uint32_t)i, (uint32_t)(i % 2), (uint32_t)(i % 3), 0};
+    params[i][0] = &args_store;
+    params[i][1] = &sis[i];
+    hipKernelNodeParams kp{};
+    kp.func = const_cast<void*>(l.func);
+    kp.gridDim = dim3(l.blocks);
+    kp.blockDim = dim3(BLOCK);
+    kp.sharedMemBytes = 0;
+    kp.kernelParams = params[i];
+    kp.extra = nullptr;
+    hipGraphNode_t node;
+    if ((r = hip_check(c, hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &kp), "graph node"))) return r;
+    prev = node;
+  }
+  Ctl* ctl = (Ctl*)(c->arena + c->L.ctl);
+  uint32_t nst = GRAPH_STEPS;
+  void* bparams[2] = {&ctl, &nst};
+  hipKernelNodeParams kb{};
+  kb.func = reinterpret_cast<void*>(&k_advance_base);
+  kb.gridDim = dim3(1);
+  kb.blockDim = dim3(64);
+  kb.kernelParams = bparams;
+  hipGraphNode_t bnode;
+  if ((r = hip_check(c, hipGraphAddKernelNode(&bnode, g, &prev, 1, &kb), "graph node"))) return r;
+  // capacity check at the end of the cycle (parity 0, counter set 0)
+  RepackPlan plan = repack_plan_args(c, 0);
+  void* pparams[1] = {&plan};
+  hipKernelNodeParams kpl{};
+  kpl.func = reinterpret_cast<void*>(&k_repack_plan);
+  kpl.gridDim = dim3(1);
+  kpl.blockDim = dim3(PLAN_THREADS);
+  kpl.kernelParams = pparams;
+  hipGraphNode_t pnode;
+  if ((r = hip_check(c, hipGraphAddKernelNode(&pnode, g, &bnode, 1, &kpl), "graph node"))) return r;
+  RepackMove<T> mv = repack_move_args<T>(c, 0);
+  StepIndex si0{0, 0, 0, 0};
+  void* mparams[2] = {&mv, &si0};
+  hipKernelNodeParams kmv{};
+  kmv.func = reinterpret_cast<void*>(&k_repack_move<T>);
+  kmv.gridDim = dim3(repack_move_blocks(c));
+  kmv.blockDim = dim3(BLOCK);
+  kmv.kernelParams = mparams;
+  hipGraphNode_t mnode;
+  if ((r = hip_check(c, hipGraphAddKernelNode(&mnode, g, &pnode, 1, &kmv), "graph node"))) return r;
+  hipGraphExec_t ex = nullptr;
+  if ((r = hip_check(c, hipGraphInstantiate(&ex, g, nullptr, nullptr, 0), "graph instantiate"))) return r;
+  if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  c->graph = g;
+  c->graph_exec = ex;
+  c->graph_group = c->group;
+  c->graph_persist = c->persist;
+  return PDF_OK;
+}
+
+pdf_status enqueue_steps(pdf_ctx* c, int32_t nsteps) {
+  Ctl* ctl = (Ctl*)(c->arena + c->L.ctl);
+  for (int32_t i = 0; i < nsteps; ++i) {
+    StepIndex si{(uint32_t)i, c->parity, c->rot, 0};
+    pdf_status r = dispatch_step<true>(c, si);
+    if (r) return r;
+    c->parity ^= 1u;
+    c->rot = c->rot == 2 ? 0 : c->rot + 1;
+    // the capacity check runs every GRAPH_STEPS steps, where the graph runs it
+    if ((c->steps_done + i + 1) % GRAPH_STEPS == 0 && (r = enqueue_repack(c))) return r;
+  }
+  hipLaunchKernelGGL(k_advance_base, dim3(1), dim3(64), 0, c->stream, ctl, (uint32_t)nsteps);
+  c->steps_done += nsteps;
+  return hip_check(c, hipGetLastError(), "step base launch");
 }
 
 }  // namespace
@@ -195,6 +422,7 @@ pdf_status pdf_create(const pdf_params* p, void* hip_stream, pdf_ctx** out) {
   if (!(p->moments == 2 || p->moments == 4)) return PDF_E_ARG;
   if (!(p->hist_bins == 0 || p->hist_bins == 32)) return PDF_E_ARG;
   if (!(p->dt > 0.0) || p->nu < 0.0 || !(p->slack >= 1.0)) return PDF_E_ARG;
+  if (!supported(*p)) return PDF_E_ARG;
   pdf_ctx* c = new pdf_ctx();
   c->p = *p;
   c->stream = (hipStream_t)hip_stream;
@@ -309,7 +537,17 @@ pdf_status pdf_seed_particles(pdf_ctx* c, int32_t nens, const int64_t* counts, c
     c->h_cap[cell] = (int32_t)capc;
     slot += capc;
   }
-  const int64_t slots = slot;
+  // processing order: within windows of 256 consecutive cells (neighbouring
+  // elements), cells by decreasing particle count, so that the cells sharing
+  // a wavefront have similar counts
+  c->h_order.resize(ncell);
+  for (int64_t i = 0; i < ncell; ++i) c->h_order[i] = (int32_t)i;
+  for (int64_t w0 = 0; w0 < ncell; w0 += 256) {
+    const int64_t w1 = std::min<int64_t>(ncell, w0 + 256);
+    std::stable_sort(c->h_order.begin() + w0, c->h_order.begin() + w1,
+                     [&](int32_t x, int32_t y) { return c->h_cnt[x] > c->h_cnt[y]; });
+  }
+  const int64_t slots = slot + growth_reserve(total, slack);
   const Layout L = make_layout(c->nv, c->ne, nens, slots, nstat_of(c->p), tsize_of(c->p));
   if (L.total > c->arena_bytes)
     return fail(c, PDF_E_SIZE, "arena too small for the particle layout (query with slack >= 2)");
@@ -324,12 +562,14 @@ pdf_status pdf_seed_particles(pdf_ctx* c, int32_t nens, const int64_t* counts, c
   pdf_status r;
   if ((r = hip_check(c, hipMemcpyAsync(a + L.start, c->h_start.data(), ncell * 4, hipMemcpyHostToDevice, st), "copy start"))) return r;
   if ((r = hip_check(c, hipMemcpyAsync(a + L.cap, c->h_cap.data(), ncell * 4, hipMemcpyHostToDevice, st), "copy cap"))) return r;
+  if ((r = hip_check(c, hipMemcpyAsync(a + L.cap0, c->h_cap.data(), ncell * 4, hipMemcpyHostToDevice, st), "copy cap"))) return r;
   if ((r = hip_check(c, hipMemcpyAsync(a + L.ns[0], c->h_cnt.data(), ncell * 4, hipMemcpyHostToDevice, st), "copy counts"))) return r;
   for (int rr = 0; rr < 3; ++rr) {
     if (rr > 0 && (r = hip_check(c, hipMemcpyAsync(a + L.ns[rr], c->h_zero.data(), ncell * 4, hipMemcpyHostToDevice, st), "clear counts"))) return r;
     if ((r = hip_check(c, hipMemcpyAsync(a + L.nm[rr], c->h_zero.data(), ncell * 4, hipMemcpyHostToDevice, st), "clear counts"))) return r;
   }
   if ((r = hip_check(c, hipMemcpyAsync(a + L.idoff, c->h_idoff.data(), ncell * 4, hipMemcpyHostToDevice, st), "copy idoff"))) return r;
+  if ((r = hip_check(c, hipMemcpyAsync(a + L.order, c->h_order.data(), ncell * 4, hipMemcpyHostToDevice, st), "copy order"))) return r;
   if ((r = hip_check(c, hipMemcpyAsync(a + L.seed, c->h_seed.data(), nens * 8, hipMemcpyHostToDevice, st), "copy seeds"))) return r;
   if ((r = hip_check(c, hipMemcpyAsync(a + L.src, c->h_src.data(), nens * 3 * 8, hipMemcpyHostToDevice, st), "copy src"))) return r;
   hipLaunchKernelGGL(k_reset_ctl, dim3(1), dim3(64), 0, st, (Ctl*)(a + L.ctl));
@@ -356,6 +596,10 @@ pdf_status pdf_seed_particles(pdf_ctx* c, int32_t nens, const int64_t* counts, c
   // the host vectors stay alive in the context until the copies complete
   if ((r = hip_check(c, hipStreamSynchronize(st), "sync seed"))) return r;
   c->seeded = true;
+  c->graph_group = 0;  // a graph built for an earlier layout is stale
+  c->steps_done = 0;
+  c->parity = 0;
+  c->rot = 0;
   c->last = PDF_OK;
   c->err.clear();
   return PDF_OK;
@@ -364,13 +608,97 @@ pdf_status pdf_seed_particles(pdf_ctx* c, int32_t nens, const int64_t* counts, c
 pdf_status pdf_step(pdf_ctx* c, int32_t nsteps) {
   if (!c || nsteps < 0) return fail(c, PDF_E_ARG, "pdf_step: bad argument");
   if (!c->seeded) return fail(c, PDF_E_STATE, "pdf_step before pdf_seed_particles");
-  Ctl* ctl = (Ctl*)(c->arena + c->L.ctl);
-  for (int32_t i = 0; i < nsteps; ++i) {
-    pdf_status r = c->p.f32_state ? dispatch_step<float, true>(c) : dispatch_step<double, true>(c);
-    if (r) return r;
-    hipLaunchKernelGGL(k_step_end, dim3(1), dim3(64), 0, c->stream, ctl);
+  if (nsteps == 0) return PDF_OK;
+  return enqueue_steps(c, nsteps);
+}
+
+pdf_status pdf_step_graph(pdf_ctx* c, int32_t nsteps) {
+  if (!c || nsteps < 0) return fail(c, PDF_E_ARG, "pdf_step_graph: bad argument");
+  if (!c->seeded) return fail(c, PDF_E_STATE, "pdf_step_graph before pdf_seed_particles");
+  pdf_status r;
+  // align to the start of a parity / counter-set cycle with ordinary launches
+  int32_t lead = (int32_t)((GRAPH_STEPS - c->steps_done % GRAPH_STEPS) % GRAPH_STEPS);
+  lead = std::min(lead, nsteps);
+  if (lead > 0 && (r = enqueue_steps(c, lead))) return r;
+  int32_t left = nsteps - lead;
+  if (left >= GRAPH_STEPS) {
+    if (!c->graph_exec || c->graph_group != c->group || c->graph_persist != c->persist) {
+      r = c->p.f32_state ? build_graph_t<float>(c) : build_graph_t<double>(c);
+      if (r) return r;
+    }
+    while (left >= GRAPH_STEPS) {
+      if ((r = hip_check(c, hipGraphLaunch(c->graph_exec, c->stream), "graph launch"))) return r;
+      c->steps_done += GRAPH_STEPS;
+      left -= GRAPH_STEPS;
+    }
   }
+  if (left > 0 && (r = enqueue_steps(c, left))) return r;
   return PDF_OK;
+}
+
+pdf_status pdf_autotune(pdf_ctx* c, int32_t steps_per_trial, int32_t* group, int32_t* persist) {
+  if (!c || steps_per_trial <= 0) return fail(c, PDF_E_ARG, "pdf_autotune: bad argument");
+  if (!c->seeded) return fail(c, PDF_E_STATE, "pdf_autotune before pdf_seed_particles");
+  const int groups[3] = {64, 32, 16};
+  float best = 1e30f;
+  int bg = c->group, bp = c->persist;
+  hipEvent_t e0, e1;
+  pdf_status r;
+  if ((r = hip_check(c, hipEventCreate(&e0), "event"))) return r;
+  if ((r = hip_check(c, hipEventCreate(&e1), "event"))) return r;
+  for (int gi = 0; gi < 3; ++gi) {
+    for (int pe = 0; pe < 2; ++pe) {
+      if (!c->p.f32_state && groups[gi] != 64) continue;
+      c->group = groups[gi];
+      c->persist = pe;
+      // one untimed step with this shape, then the timed trial
+      if ((r = enqueue_steps(c, 1))) return r;
+      (void)hipEventRecord(e0, c->stream);
+      if ((r = enqueue_steps(c, steps_per_trial))) return r;
+      (void)hipEventRecord(e1, c->stream);
+      if ((r = hip_check(c, hipEventSynchronize(e1), "autotune sync"))) return r;
+      float ms = 0.0f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (ms < best) {
+        best = ms;
+        bg = groups[gi];
+        bp = pe;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c->group = bg;
+  c->persist = bp;
+  if (group) *group = bg;
+  if (persist) *persist = bp;
+  return PDF_OK;
+}
+
+pdf_status pdf_set_launch(pdf_ctx* c, int32_t group, int32_t persist) {
+  if (!c || !(group == 16 || group == 32 || group == 64) || persist < 0 || persist > 1)
+    return fail(c, PDF_E_ARG, "pdf_set_launch: group must be 16, 32 or 64, persist 0 or 1");
+  if (!c->p.f32_state && group != 64) return fail(c, PDF_E_ARG, "pdf_set_launch: double state runs with group 64");
+  c->group = group;
+  c->persist = persist;
+  return PDF_OK;
+}
+
+pdf_status pdf_repack(pdf_ctx* c) {
+  if (!c) return PDF_E_ARG;
+  if (!c->seeded) return fail(c, PDF_E_STATE, "pdf_repack before pdf_seed_particles");
+  hipLaunchKernelGGL(k_request_repack, dim3(1), dim3(64), 0, c->stream, (Ctl*)(c->arena + c->L.ctl));
+  pdf_status r = hip_check(c, hipGetLastError(), "repack request");
+  if (r) return r;
+  return enqueue_repack(c);
+}
+
+int64_t pdf_repack_count(pdf_ctx* c) {
+  if (!c || !c->seeded) return -1;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return -1;
+  Ctl h{};
+  if (hipMemcpy(&h, c->arena + c->L.ctl, sizeof(Ctl), hipMemcpyDeviceToHost) != hipSuccess) return -1;
+  return (int64_t)h.repacks;
 }
 
 int32_t pdf_nstat(const pdf_ctx* c) { return c ? nstat_of(c->p) : 0; }
@@ -378,7 +706,7 @@ int32_t pdf_nstat(const pdf_ctx* c) { return c ? nstat_of(c->p) : 0; }
 pdf_status pdf_estimate_statistics(pdf_ctx* c, double* out, int32_t out_on_host) {
   if (!c || !out) return fail(c, PDF_E_ARG, "pdf_estimate_statistics: null output");
   if (!c->seeded) return fail(c, PDF_E_STATE, "statistics before seeding");
-  pdf_status r = c->p.f32_state ? dispatch_step<float, false>(c) : dispatch_step<double, false>(c);
+  pdf_status r = dispatch_step<false>(c, StepIndex{0, c->parity, c->rot, 0});
   if (r) return r;
   const size_t bytes = (size_t)c->nens * c->ne * nstat_of(c->p) * 8;
   if ((r = hip_check(c, hipMemcpyAsync(out, c->arena + c->L.stats, bytes,
@@ -398,8 +726,27 @@ pdf_status pdf_sync(pdf_ctx* c) {
   if ((r = hip_check(c, hipMemcpy(&h, c->arena + c->L.ctl, sizeof(Ctl), hipMemcpyDeviceToHost), "read control"))) return r;
   if (h.error & ERR_LOST) return fail(c, PDF_E_LOST, "tracking could not place a particle");
   if (h.error & ERR_NAN) return fail(c, PDF_E_NAN, "non-finite particle state");
-  if (h.error & (ERR_CAPACITY | ERR_OVERFLOW_FULL))
-    return fail(c, PDF_E_CAPACITY, "an element segment overflowed its capacity");
+  if (h.error & (ERR_CAPACITY | ERR_OVERFLOW_FULL)) {
+    // name the first overflowing cell: its capacity and counter sets
+    std::string msg = "an element segment overflowed its capacity";
+    int32_t cell = -1;
+    if (h.ovf > 0 && hipMemcpy(&cell, c->arena + c->L.ovf_cell, 4, hipMemcpyDeviceToHost) == hipSuccess &&
+        cell >= 0 && cell < c->ne * c->nens) {
+      int32_t v[6] = {0, 0, 0, 0, 0, 0};
+      int32_t capd = 0;
+      (void)hipMemcpy(&capd, c->arena + c->L.cap + 4 * (int64_t)cell, 4, hipMemcpyDeviceToHost);
+      for (int rr = 0; rr < 3; ++rr) {
+        (void)hipMemcpy(&v[rr], c->arena + c->L.ns[rr] + 4 * (int64_t)cell, 4, hipMemcpyDeviceToHost);
+        (void)hipMemcpy(&v[3 + rr], c->arena + c->L.nm[rr] + 4 * (int64_t)cell, 4, hipMemcpyDeviceToHost);
+      }
+      msg += " (" + std::to_string(h.ovf) + " particles; first cell " + std::to_string(cell) + ", capacity " +
+             std::to_string(capd) + ", initial count " + std::to_string(c->h_cnt[cell]) +
+             ", counter sets ns " + std::to_string(v[0]) + "/" + std::to_string(v[1]) + "/" + std::to_string(v[2]) +
+             " nm " + std::to_string(v[3]) + "/" + std::to_string(v[4]) + "/" + std::to_string(v[5]) +
+             ", current set " + std::to_string(c->rot) + ", repacks " + std::to_string(h.repacks) + ")";
+    }
+    return fail(c, PDF_E_CAPACITY, msg);
+  }
   return PDF_OK;
 }
 
@@ -419,11 +766,13 @@ pdf_status pdf_get_state(pdf_ctx* c, int32_t ens, double* xyuvwpsi, int32_t* ele
   if (c->p.f32_state)
     hipLaunchKernelGGL(k_gather<float>, dim3(blocks), dim3(BLOCK), 0, c->stream, state_at<float>(a, L.buf0, L.slots),
                        state_at<float>(a, L.buf1, L.slots), cs, (const int32_t*)(a + L.start),
-                       (const int32_t*)(a + L.cap), (const Ctl*)(a + L.ctl), ens, c->ne, n, xyuvwpsi, elem);
+                       (const int32_t*)(a + L.cap), (const Ctl*)(a + L.ctl), StepIndex{0, c->parity, c->rot, 0}, ens, c->ne, n, xyuvwpsi,
+                       elem);
   else
     hipLaunchKernelGGL(k_gather<double>, dim3(blocks), dim3(BLOCK), 0, c->stream, state_at<double>(a, L.buf0, L.slots),
                        state_at<double>(a, L.buf1, L.slots), cs, (const int32_t*)(a + L.start),
-                       (const int32_t*)(a + L.cap), (const Ctl*)(a + L.ctl), ens, c->ne, n, xyuvwpsi, elem);
+                       (const int32_t*)(a + L.cap), (const Ctl*)(a + L.ctl), StepIndex{0, c->parity, c->rot, 0}, ens, c->ne, n, xyuvwpsi,
+                       elem);
   return hip_check(c, hipGetLastError(), "gather launch");
 }
 
@@ -434,16 +783,15 @@ int64_t pdf_count(const pdf_ctx* c, int32_t ens) {
 
 int64_t pdf_steps_done(pdf_ctx* c) {
   if (!c || !c->seeded) return -1;
-  Ctl h{};
-  if (hipStreamSynchronize(c->stream) != hipSuccess) return -1;
-  if (hipMemcpy(&h, c->arena + c->L.ctl, sizeof(Ctl), hipMemcpyDeviceToHost) != hipSuccess) return -1;
-  return h.steps_done;
+  return c->steps_done;
 }
 
 const char* pdf_error_string(const pdf_ctx* c) { return c ? c->err.c_str() : "null context"; }
 
 void pdf_destroy(pdf_ctx* c) {
   if (!c) return;
+  if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
   if (c->stream || c->seeded) (void)hipStreamSynchronize(c->stream);
   delete c;
 }

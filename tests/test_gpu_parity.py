@@ -192,10 +192,107 @@ def test_config2_full_size_parity(gpu):
     _label(wl, "full size")
     sim = gpu.Simulation.from_workload(wl)
     orc = O.Oracle(wl)
+    shape = sim.autotune(steps_per_trial=1)     # the benchmark tunes the same way
+    print(f"[case] tuned shape {shape}", flush=True)
     sim.step(3)
-    orc.step(3)
+    orc.step(sim.steps_done())
     sim.sync()
     assert_state_parity(sim.state(), orc.state(), what="config2")
     g = sim.state()
     orc.set_state(g)
     assert_stats_parity(sim.statistics()[0], orc.stats(), wl.moments, wl.hist_bins, what="config2 stats")
+
+
+SHAPES = [(64, 0), (64, 1), (32, 0), (32, 1), (16, 0), (16, 1)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("case", ["tiny_canyon_glm_f32", "small_canyon_wallfn_m4_hist", "tiny_canyon_3_ensembles"])
+def test_launch_shapes_give_the_same_trajectories(gpu, case, shape):
+    """Lanes per cell and the persistent scheduler change how work is laid out,
+    never the particle trajectories; statistics stay within the tolerance."""
+    wl = CASES[case]()
+    wl.steps = 6
+    _label(wl, f"shape={shape}")
+    sim = gpu.Simulation.from_workload(wl)
+    sim.set_launch(*shape)
+    orc = O.Oracle(wl)
+    sim.step(wl.steps)
+    orc.step(wl.steps)
+    sim.sync()
+    sg = sim.statistics()
+    for en in range(wl.nens):
+        assert_state_parity(sim.state(en), orc.state(en), what=f"{case} {shape} ens {en}")
+        assert_stats_parity(sg[en], orc.stats(en), wl.moments, wl.hist_bins, what=f"{case} {shape} ens {en}")
+
+
+def test_autotune_keeps_parity(gpu):
+    wl = W.tiny_canyon(precision="f32", steps=4)
+    _label(wl, "autotune")
+    sim = gpu.Simulation.from_workload(wl)
+    shape = sim.autotune(steps_per_trial=2)
+    assert shape[0] in (16, 32, 64) and shape[1] in (0, 1)
+    done = sim.steps_done()
+    assert done == 6 * 3
+    orc = O.Oracle(wl)
+    orc.step(done)
+    sim.sync()
+    assert_state_parity(sim.state(), orc.state(), what="after autotune")
+
+
+@pytest.mark.parametrize("shape", [(64, 0), (32, 1)])
+def test_graph_replay_matches_eager(gpu, shape):
+    """Six-step graph replays, with eager work and synchronisation between
+    them, against a run launched step by step."""
+    wl = W.tiny_canyon(precision="f32", steps=0)
+    _label(wl, f"graph {shape}")
+    eager = gpu.Simulation.from_workload(wl)
+    graph = gpu.Simulation.from_workload(wl)
+    eager.set_launch(*shape)
+    graph.set_launch(*shape)
+    orc = O.Oracle(wl)
+    for rep, n in enumerate([6, 6, 7, 12, 5]):
+        graph.step_graph(n)
+        eager.step(n)
+        orc.step(n)
+        graph.sync()
+        eager.sync()
+        assert graph.steps_done() == eager.steps_done() == orc.step_index
+        g, e = graph.state(), eager.state()
+        assert_state_parity(g, orc.state(), what=f"graph replay {rep}")
+        assert_state_parity(e, orc.state(), what=f"eager {rep}")
+        np.testing.assert_allclose(g["psi"], e["psi"], rtol=1e-6, atol=1e-7)
+        _ = graph.statistics()          # eager work between replays
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_repack_keeps_parity(gpu, graph):
+    """Segments sized with no slack run short of room within a few steps, so
+    the device-side repack runs repeatedly (plus one requested from the host
+    at an odd step count); trajectories stay bit-exact and the statistics
+    within tolerance."""
+    wl = W.small_canyon(target=600, ppe=30, wallfn=True, moments=4, hist_bins=32, steps=0)
+    _label(wl, f"repack graph={graph}")
+    sim = gpu.Simulation.from_workload(wl, slack=1.0)
+    orc = O.Oracle(wl)
+    run = sim.step_graph if graph else sim.step
+    for n in (7, 12, 17):
+        run(n)
+        orc.step(n)
+        sim.sync()
+        assert_state_parity(sim.state(), orc.state(), what=f"repack graph={graph} step {orc.step_index}")
+        if n == 7:
+            sim.repack()
+    assert sim.repacks() >= 2
+    sim.sync()
+    assert_stats_parity(sim.statistics()[0], orc.stats(), wl.moments, wl.hist_bins, what="after repacks")
+
+
+def test_repack_is_idle_with_room(gpu):
+    """With the default slack a short run needs no repack."""
+    wl = W.tiny_canyon(precision="f32", steps=12)
+    _label(wl, "no repack")
+    sim = gpu.Simulation.from_workload(wl)
+    sim.step(12)
+    sim.sync()
+    assert sim.repacks() == 0

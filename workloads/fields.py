@@ -65,13 +65,27 @@ def uniform_fields(nvert: int, U=(1.0, 0.0), k: float = 1.0, eps: float = 1.0) -
 # canyon
 
 
-def _velocity_functions(U0=1.0, delta=0.1, A=20.0, sq=0.6, xl=0.5, xr=1.5):
+def _velocity_functions(U0=1.0, delta=0.1, A=20.0, sq=0.6, xl=0.5, xr=1.5, ys=0.0, yr=1.0,
+                        slip_floor=0.0):
+    """Channel profile above y = yr plus a clockwise vortex in xl < x < xr.
+
+    With slip_floor = 0 both parts vanish to second order on the walls (no
+    slip); with slip_floor > 0 (wall functions) the stream function vanishes
+    to first order on the walls: no flow through them, a finite tangential
+    velocity along them."""
     x, y = sp.symbols("x y", real=True)
-    s = y - 1
-    S_ch = s - delta * sp.tanh(s / delta)          # dS/dy = tanh^2(s/delta), 0 for y < 1
-    X = (x - xl) * (xr - x)
-    q = y ** 2 * sp.exp(-(y / sq) ** 2)
-    Psi_v = -A * X ** 2 * q
+    s = y - yr
+    if slip_floor > 0.0:
+        S_ch = slip_floor * s + (1.0 - slip_floor) * (s - delta * sp.tanh(s / delta))
+        X = (x - xl) * (xr - x)
+        yy = y - ys
+        q = yy * sp.exp(-(yy / sq) ** 2)
+        Psi_v = -A * 0.25 * X * q
+    else:
+        S_ch = s - delta * sp.tanh(s / delta)          # dS/dy = tanh^2(s/delta), 0 for y < yr
+        X = (x - xl) * (xr - x)
+        q = y ** 2 * sp.exp(-(y / sq) ** 2)
+        Psi_v = -A * X ** 2 * q
     out = {}
     for name, psi in (("ch", U0 * S_ch), ("v", Psi_v)):
         U = sp.diff(psi, y)
@@ -82,14 +96,15 @@ def _velocity_functions(U0=1.0, delta=0.1, A=20.0, sq=0.6, xl=0.5, xr=1.5):
     return out
 
 
-def _mean_velocity(xy, geo_full):
-    fn = _velocity_functions(xl=geo_full["x_l"], xr=geo_full["x_r"])
+def _mean_velocity(xy, g):
+    fn = _velocity_functions(xl=g["x_l"], xr=g["x_r"], ys=g["y_street"], yr=g["y_roof"],
+                             slip_floor=g.get("slip_floor", 0.0))
     x, y = xy[:, 0], xy[:, 1]
     res = np.zeros((len(x), 8))
     ch = np.array([np.broadcast_to(v, x.shape) for v in fn["ch"](x, y)]).T
-    res += np.where((y >= 1.0)[:, None], ch, 0.0)
+    res += np.where((y >= g["y_roof"])[:, None], ch, 0.0)
     v = np.array([np.broadcast_to(v, x.shape) for v in fn["v"](x, y)]).T
-    inside = (x >= geo_full["x_l"]) & (x <= geo_full["x_r"])
+    inside = (x >= g["x_l"]) & (x <= g["x_r"])
     res += np.where(inside[:, None], v, 0.0)
     return res
 
@@ -129,14 +144,19 @@ def _stresses(x, y, dUdy, g, k0=0.002, k1=0.02, sk=0.25):
 
 def canyon_fields(mesh, nu: float = 1.0 / 12000.0, with_stats: bool = False):
     """Synthetic frozen fields for a street-canyon mesh (full or stripped)."""
-    g = dict(Lx=2.0, x_l=0.5, x_r=1.5)
+    g = dict(Lx=2.0, x_l=0.5, x_r=1.5, y_street=0.0, y_roof=1.0)
+    geo = getattr(mesh, "geometry", None)
+    flow = dict(g)
+    if geo is not None and geo.wallfn:
+        # mean flow built on the stripped walls: no flow through them
+        flow.update(x_l=geo.x_l, x_r=geo.x_r, y_street=geo.y_street, y_roof=geo.y_roof, slip_floor=0.3)
     xy = mesh.vtx
     x, y = xy[:, 0], xy[:, 1]
-    mv = _mean_velocity(xy, g)
+    mv = _mean_velocity(xy, flow)
     U, V, dUdx, dUdy, dVdx, dVdy, lapU, lapV = mv.T
 
     def stress_at(px, py):
-        m = _mean_velocity(np.stack([px, py], axis=1), g)
+        m = _mean_velocity(np.stack([px, py], axis=1), flow)
         return _stresses(px, py, m[:, 3], g)
 
     R11, R22, R33, R12, eps, k = _stresses(x, y, dUdy, g)
