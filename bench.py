@@ -43,7 +43,7 @@ def kernel_source_hash() -> str:
 
 
 def algorithmic_bytes(wl) -> dict:
-    """Bytes one step must move at minimum in this design (see DESIGN.md).
+    """Bytes one step must move at minimum in this design.
 
     Per particle: read x y u v w psi id, write the same (7 words of state
     type each way).  Per element cell: the statistics record written, the
@@ -116,6 +116,8 @@ def main() -> int:
     ap.add_argument("--no-graph", action="store_true", help="launch steps one by one instead of graph replays")
     ap.add_argument("--autotune-steps", type=int, default=5,
                     help="steps per candidate launch shape before warmup (0: no tuning)")
+    ap.add_argument("--launch", default="",
+                    help="fixed launch shape 'lanes_per_cell,persistent' (e.g. 32,1) instead of tuning")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -123,7 +125,7 @@ def main() -> int:
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py: this build runs on one GPU only; the batched-ensemble and mesh-partition "
-              "designs for several GPUs are described in DESIGN.md but not launched", file=sys.stderr)
+              "designs for several GPUs are documented with the library but not launched", file=sys.stderr)
         return 2
 
     import torch
@@ -142,7 +144,13 @@ def main() -> int:
         wl = cfg_fn(steps=steps)
         sim = Simulation.from_workload(wl, device="cuda:0")
         print(f"[bench] {name}: {wl.n_total} particles, {wl.mesh.nelem} elements, warmup {warmup}", file=sys.stderr, flush=True)
-        shape = sim.autotune(steps_per_trial=autotune_steps) if autotune_steps > 0 else (64, 0)
+        if args.launch:
+            shape = tuple(int(v) for v in args.launch.split(","))
+            sim.set_launch(*shape)
+        elif autotune_steps > 0:
+            shape = sim.autotune(steps_per_trial=autotune_steps)
+        else:
+            shape = (64, 0)
         print(f"[bench] {name}: launch shape group={shape[0]} persistent={shape[1]}", file=sys.stderr, flush=True)
         tuned = sim.steps_done()
         sim.step(warmup)
@@ -179,7 +187,7 @@ def main() -> int:
                        "state_dtype": wl.precision, "statistics_dtype": "f64", "model": wl.describe()["model"],
                        "moments": wl.moments, "hist_bins": wl.hist_bins, "dt": wl.dt,
                        "launch": {"lanes_per_cell": shape[0], "persistent": bool(shape[1]),
-                                  "autotune_steps_per_candidate": autotune_steps,
+                                  "autotune_steps_per_candidate": 0 if args.launch else autotune_steps,
                                   "hip_graph": not args.no_graph},
                        "segment_repacks": repacks,
                        "kernel_source_hash": src_hash},

@@ -1,7 +1,7 @@
 """ctypes wrapper of the CPU oracle (``orc.cpp``).
 
 TEST INFRASTRUCTURE ONLY.  The oracle is a plain, slow, independent CPU
-implementation of the particle step used to judge the GPU library.  Only the
+implementation of the particle step used to check the GPU library.  Only the
 tests, the smoke check and the benchmark's CPU-baseline leg may import this
 module; the product package never does.
 """

@@ -1,7 +1,7 @@
 // Oracle for the particle-in-cell joint velocity-scalar PDF step.
 //
 // TEST INFRASTRUCTURE ONLY: a plain CPU implementation used by the tests, the
-// smoke check and the CPU baseline to judge the GPU library.  Nothing in the
+// smoke check and the CPU baseline to check the GPU library.  Nothing in the
 // product path loads it.  It shares no code with the GPU library.
 //
 // Paper: Bakosi, Franzese & Boybeyi, "Joint PDF modelling of turbulent flow

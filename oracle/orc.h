@@ -3,7 +3,7 @@
  *
  * TEST INFRASTRUCTURE ONLY.  A plain, slow CPU implementation of what the
  * particle step computes, used by the tests, the smoke check and the CPU
- * baseline of the benchmark to judge the GPU library.  The product path never
+ * baseline of the benchmark to check the GPU library.  The product path never
  * links, loads or calls it.  It shares no code with the GPU library; the two
  * agree only on the documented array layouts and on the definition of the
  * random numbers (Philox4x32-10 counters, Box-Muller with series log/sincos).
