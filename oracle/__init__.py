@@ -80,6 +80,7 @@ def lib():
         L.orc_get_step.argtypes = [vp]
         L.orc_set_step.argtypes = [vp, i64]
         L.orc_set_threads.argtypes = [i32]
+        L.orc_set_cond_means.argtypes = [vp, i32, vp]
         L.orc_philox4x32_10.argtypes = [vp, vp, vp]
         L.orc_normals.argtypes = [u64, u32, u32, u32, i32, vp]
         L.orc_normals_batch.argtypes = [u64, i64, u32, u32, i32, vp]
@@ -176,6 +177,15 @@ class Oracle:
         a = {k: np.ascontiguousarray(st[k], np.float64) for k in ("x", "y", "u", "v", "w", "psi")}
         a["elem"] = np.ascontiguousarray(st["elem"], np.int32)
         lib().orc_set_state(self.ctx, ens, *(_ptr(a[k]) for k in ("x", "y", "u", "v", "w", "psi", "elem")))
+
+    def set_cond_means(self, cm, ens: int = 0) -> None:
+        """IECM toward the given conditional means (nelem x 8) instead of the
+        binned estimate, until called with None."""
+        if cm is None:
+            lib().orc_set_cond_means(self.ctx, ens, None)
+            return
+        a = np.ascontiguousarray(cm, np.float64).reshape(self.wl.mesh.nelem, 8)
+        lib().orc_set_cond_means(self.ctx, ens, _ptr(a))
 
     def coefficients(self) -> np.ndarray:
         out = np.zeros((self.wl.mesh.nvert, 16))

@@ -200,6 +200,7 @@ template <typename T> struct Ens {
   std::vector<T> x, y, u, v, w, psi;
   std::vector<int32_t> elem;
   std::vector<double> rate;  // IECM relaxation factor per element, min(dt/t_m, 1)
+  std::vector<double> cm;    // conditional means from elsewhere (nelem x 8), empty: binned
 };
 
 }  // namespace
@@ -656,7 +657,7 @@ template <typename T> int advance(orc_ctx* c, Ens<T>& en, uint32_t ens_index, ui
       const double* s = &st[(size_t)e * ns];
       int bin = ((double)u > s[ORC_ST_MEAN] ? 1 : 0) + ((double)v > s[ORC_ST_MEAN + 1] ? 2 : 0) +
                 ((double)w > s[ORC_ST_MEAN + 2] ? 4 : 0);
-      T m = (T)s[ORC_ST_BINM + bin];
+      T m = en.cm.empty() ? (T)s[ORC_ST_BINM + bin] : (T)en.cm[(size_t)e * 8 + bin];
       T r = (T)en.rate[e];
       psi = psi - r * (psi - m);
     }
@@ -817,6 +818,15 @@ int32_t orc_set_state(orc_ctx* c, int32_t ens, const double* x, const double* y,
   if (c->p.f32_state) set_state_t<float>(c->ensF[ens], x, y, u, v, w, psi, elem);
   else set_state_t<double>(c->ensD[ens], x, y, u, v, w, psi, elem);
   return 0;
+}
+
+void orc_set_cond_means(orc_ctx* c, int32_t ens, const double* cm) {
+  std::vector<double>& dst = c->p.f32_state ? c->ensF[ens].cm : c->ensD[ens].cm;
+  if (!cm) {
+    dst.clear();
+    return;
+  }
+  dst.assign(cm, cm + (size_t)c->ne * 8);
 }
 
 int64_t orc_get_step(const orc_ctx* c) { return c->step; }

@@ -82,6 +82,11 @@ int32_t orc_get_state(const orc_ctx* c, int32_t ens, double* x, double* y, doubl
 /* Replace the state of one ensemble (values are rounded to the state type). */
 int32_t orc_set_state(orc_ctx* c, int32_t ens, const double* x, const double* y, const double* u,
                       const double* v, const double* w, const double* psi, const int32_t* elem);
+/* Conditional means <phi|V> used by the IECM step in place of the binned
+   estimate of the state (nelem x 8, by velocity bin), until cleared with
+   cm = NULL: lets a test feed the step the values another estimator (the
+   learned one) produced. */
+void orc_set_cond_means(orc_ctx* c, int32_t ens, const double* cm);
 int64_t orc_get_step(const orc_ctx* c);
 void orc_set_step(orc_ctx* c, int64_t step);
 void orc_set_threads(int32_t n);

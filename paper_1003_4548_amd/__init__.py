@@ -28,6 +28,8 @@ NFIELD = 20
 ENTRY_POINTS = ("pdf_create", "pdf_query_sizes", "pdf_init_mesh", "pdf_seed_particles", "pdf_step",
                 "pdf_step_graph", "pdf_autotune", "pdf_set_launch", "pdf_repack", "pdf_repack_count",
                 "pdf_estimate_statistics", "pdf_nstat", "pdf_sync",
+                "pdf_mlp_work_floats", "pdf_mlp_dataset", "pdf_mlp_forward", "pdf_mlp_grad", "pdf_mlp_train",
+                "pdf_mlp_norm", "pdf_mlp_round", "pdf_mlp_infer", "pdf_mlp_attach",
                 "pdf_get_state", "pdf_count", "pdf_steps_done", "pdf_error_string", "pdf_destroy")
 
 
@@ -93,6 +95,25 @@ def load_library():
     L.pdf_autotune.argtypes = [vp, i32, P(i32), P(i32)]
     L.pdf_set_launch.restype = i32
     L.pdf_set_launch.argtypes = [vp, i32, i32]
+    u32, u64, f32 = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_float
+    L.pdf_mlp_work_floats.restype = i64
+    L.pdf_mlp_work_floats.argtypes = [i32]
+    L.pdf_mlp_dataset.restype = i32
+    L.pdf_mlp_dataset.argtypes = [vp, i32, u64, u32, vp]
+    L.pdf_mlp_forward.restype = i32
+    L.pdf_mlp_forward.argtypes = [vp, i64, i32, vp, vp, vp, vp]
+    L.pdf_mlp_grad.restype = i32
+    L.pdf_mlp_grad.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
+    L.pdf_mlp_train.restype = i32
+    L.pdf_mlp_train.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, i32, i32, f32, u64, i64, vp]
+    L.pdf_mlp_norm.restype = i32
+    L.pdf_mlp_norm.argtypes = [vp, i64, vp, vp]
+    L.pdf_mlp_round.restype = i32
+    L.pdf_mlp_round.argtypes = [vp, vp, vp]
+    L.pdf_mlp_infer.restype = i32
+    L.pdf_mlp_infer.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp]
+    L.pdf_mlp_attach.restype = i32
+    L.pdf_mlp_attach.argtypes = [vp, vp, vp, vp, vp]
     L.pdf_repack.restype = i32
     L.pdf_repack.argtypes = [vp]
     L.pdf_repack_count.restype = i64

@@ -116,6 +116,7 @@ template <typename T> struct StepArgs {
   double* stats;          // ncell x nstat
   const uint64_t* seed;   // nens
   const double* src;      // nens x 3
+  const double* cmean;    // ncell x 8 conditional means for IECM from elsewhere, or null
   Ctl* ctl;
   int32_t nstat;
   int32_t flags;
@@ -474,6 +475,14 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
     double bm[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) bm[q] = bcount[q] > 0 ? acc[10 + q] / (double)bcount[q] : mean[3];
+    double cm[8];
+    if (ADVANCE && a.cmean != nullptr && has) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) cm[q] = a.cmean[(size_t)cell * 8 + q];
+    } else {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) cm[q] = bm[q];
+    }
     double* rec = a.stats + (size_t)(has ? cell : 0) * a.nstat;
     {
       double r2[NSTAT2];
@@ -610,9 +619,9 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
           if (do_mix) {
             const int bin = ((double)u > mean[0] ? 1 : 0) + ((double)v > mean[1] ? 2 : 0) +
                             ((double)w > mean[2] ? 4 : 0);
-            double mb = bm[0];
+            double mb = cm[0];
 #pragma unroll
-            for (int q = 1; q < 8; ++q) mb = (bin == q) ? bm[q] : mb;
+            for (int q = 1; q < 8; ++q) mb = (bin == q) ? cm[q] : mb;
             const T m = (T)mb;
             psi = psi - rate * (psi - m);
           }

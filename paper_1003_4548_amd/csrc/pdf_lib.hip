@@ -9,6 +9,8 @@
 #include <vector>
 
 #include "pdf_kernels.hpp"
+#include "pdf_mlp.hpp"
+#include "pdfmlp.h"
 #include "pdfpic.h"
 
 using namespace pdf;
@@ -114,6 +116,11 @@ struct pdf_ctx {
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   int32_t graph_group = 0, graph_persist = -1;
+  // learned conditional means in the step (null: binned means)
+  const uint16_t* mlp_w = nullptr;
+  const float* mlp_norm = nullptr;
+  double* mlp_cm = nullptr;
+  uint32_t* mlp_served = nullptr;
   std::vector<uint64_t> h_seed;
   std::vector<double> h_src;
   std::vector<int64_t> ens_count;
@@ -230,13 +237,34 @@ bool supported(const pdf_params& p) {
 template <bool ADV> pdf_status dispatch_step(pdf_ctx* c, StepIndex si) {
   if (c->p.f32_state) {
     StepArgs<float> s = step_args<float>(c);
+    if (ADV) s.cmean = c->mlp_w ? c->mlp_cm : nullptr;
     if (c->p.moments == 2) launch_group<float, 2, 0, ADV>(c, s, si);
     else launch_group<float, 4, 32, ADV>(c, s, si);
   } else {
     StepArgs<double> s = step_args<double>(c);
+    if (ADV) s.cmean = c->mlp_w ? c->mlp_cm : nullptr;
     launch_group<double, 2, 0, ADV>(c, s, si);
   }
   return hip_check(c, hipGetLastError(), "step launch");
+}
+
+// The learned conditional means of the current state: its statistics, then
+// the network over every cell.
+pdf_status enqueue_mlp_means(pdf_ctx* c, StepIndex si) {
+  pdf_status r = dispatch_step<false>(c, si);
+  if (r) return r;
+  mlp::InferArgs ia{};
+  ia.stats = (const double*)(c->arena + c->L.stats);
+  ia.nstat = nstat_of(c->p);
+  ia.ncell = c->ne * c->nens;
+  ia.w = c->mlp_w;
+  ia.norm = c->mlp_norm;
+  ia.cm = c->mlp_cm;
+  ia.served = c->mlp_served;
+  const int tiles = (ia.ncell + mlp::TILE - 1) / mlp::TILE;
+  hipLaunchKernelGGL(mlp::k_mlp_infer, dim3((tiles + mlp::MLP_WAVES - 1) / mlp::MLP_WAVES), dim3(64 * mlp::MLP_WAVES),
+                     0, c->stream, ia);
+  return hip_check(c, hipGetLastError(), "inference launch");
 }
 
 RepackPlan repack_plan_args(pdf_ctx* c, uint32_t rot) {
@@ -401,8 +429,9 @@ pdf_status enqueue_steps(pdf_ctx* c, int32_t nsteps) {
   Ctl* ctl = (Ctl*)(c->arena + c->L.ctl);
   for (int32_t i = 0; i < nsteps; ++i) {
     StepIndex si{(uint32_t)i, c->parity, c->rot, 0};
-    pdf_status r = dispatch_step<true>(c, si);
-    if (r) return r;
+    pdf_status r;
+    if (c->mlp_w && (r = enqueue_mlp_means(c, si))) return r;
+    if ((r = dispatch_step<true>(c, si))) return r;
     c->parity ^= 1u;
     c->rot = c->rot == 2 ? 0 : c->rot + 1;
     // the capacity check runs every GRAPH_STEPS steps, where the graph runs it
@@ -616,6 +645,8 @@ pdf_status pdf_step_graph(pdf_ctx* c, int32_t nsteps) {
   if (!c || nsteps < 0) return fail(c, PDF_E_ARG, "pdf_step_graph: bad argument");
   if (!c->seeded) return fail(c, PDF_E_STATE, "pdf_step_graph before pdf_seed_particles");
   pdf_status r;
+  // with the learned conditional means every step is launched directly
+  if (c->mlp_w) return enqueue_steps(c, nsteps);
   // align to the start of a parity / counter-set cycle with ordinary launches
   int32_t lead = (int32_t)((GRAPH_STEPS - c->steps_done % GRAPH_STEPS) % GRAPH_STEPS);
   lead = std::min(lead, nsteps);
@@ -794,6 +825,174 @@ void pdf_destroy(pdf_ctx* c) {
   if (c->graph) (void)hipGraphDestroy(c->graph);
   if (c->stream || c->seeded) (void)hipStreamSynchronize(c->stream);
   delete c;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// learned conditional means
+
+namespace {
+
+int mlp_blocks(int64_t tiles) { return (int)((tiles + mlp::MLP_WAVES - 1) / mlp::MLP_WAVES); }
+
+pdf_status mlp_hip(hipError_t e) { return e == hipSuccess ? PDF_OK : PDF_E_HIP; }
+
+// One gradient pass over a batch, then the reduction (and, with update, the
+// Adam step numbered t).
+pdf_status mlp_grad_step(const float* rows, int64_t nrows, int32_t batch, int32_t draw, uint64_t seed, uint32_t t,
+                         const float* norm, uint16_t* w, float* work, float* grad, float* loss, int update,
+                         float* master, float* am, float* av, float lr, hipStream_t st) {
+  const int ntiles = (batch + mlp::TILE - 1) / mlp::TILE;
+  mlp::GradArgs g{};
+  g.rows = rows;
+  g.nrows = nrows;
+  g.batch = batch;
+  g.draw = draw;
+  g.k0 = (uint32_t)seed;
+  g.k1 = (uint32_t)(seed >> 32);
+  g.iter = t;
+  g.norm = norm;
+  g.w = w;
+  g.partial = work;
+  g.loss_partial = work + (size_t)ntiles * mlp::NPARAM;
+  hipLaunchKernelGGL(mlp::k_mlp_grad, dim3(mlp_blocks(ntiles)), dim3(64 * mlp::MLP_WAVES), 0, st, g);
+  mlp::AdamArgs a{};
+  a.partial = g.partial;
+  a.loss_partial = g.loss_partial;
+  a.ntiles = ntiles;
+  a.inv_batch = 1.0f / (float)batch;
+  a.loss_out = loss;
+  a.grad_out = grad;
+  a.update = update;
+  a.master = master;
+  a.m = am;
+  a.v = av;
+  a.w = w;
+  a.lr = lr;
+  a.b1 = 0.9f;
+  a.b2 = 0.999f;
+  a.eps = 1e-8f;
+  a.bc1 = (float)(1.0 - std::pow(0.9, (double)t));
+  a.bc2 = (float)(1.0 - std::pow(0.999, (double)t));
+  hipLaunchKernelGGL(mlp::k_mlp_adam, dim3((mlp::NPARAM + 255) / 256), dim3(256), 0, st, a);
+  return mlp_hip(hipGetLastError());
+}
+
+template <typename T> void launch_dataset(pdf_ctx* c, int32_t target, uint64_t key, uint32_t draw, float* rows) {
+  const Layout& L = c->L;
+  char* a = c->arena;
+  mlp::DatasetArgs<T> d{};
+  d.buf[0] = state_at<T>(a, L.buf0, L.slots);
+  d.buf[1] = state_at<T>(a, L.buf1, L.slots);
+  d.ctl = (const Ctl*)(a + L.ctl);
+  d.parity = c->parity;
+  d.start = (const int32_t*)(a + L.start);
+  d.cap = (const int32_t*)(a + L.cap);
+  d.ns = (const int32_t*)(a + L.ns[c->rot]);
+  d.nm = (const int32_t*)(a + L.nm[c->rot]);
+  d.ne = c->ne;
+  d.ncell = c->ne * c->nens;
+  d.target = target;
+  d.k0 = (uint32_t)key;
+  d.k1 = (uint32_t)(key >> 32);
+  d.draw = draw;
+  d.rows = rows;
+  hipLaunchKernelGGL(mlp::k_mlp_dataset<T>, dim3((d.ncell + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK), dim3(BLOCK), 0,
+                     c->stream, d);
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t pdf_mlp_work_floats(int32_t batch) {
+  if (batch <= 0) return 0;
+  const int64_t tiles = (batch + mlp::TILE - 1) / mlp::TILE;
+  return tiles * (mlp::NPARAM + 1);
+}
+
+pdf_status pdf_mlp_dataset(pdf_ctx* c, int32_t target, uint64_t key, uint32_t draw, float* rows) {
+  if (!c || !rows || target <= 0) return fail(c, PDF_E_ARG, "pdf_mlp_dataset: bad argument");
+  if (!c->seeded) return fail(c, PDF_E_STATE, "pdf_mlp_dataset before pdf_seed_particles");
+  if (c->p.f32_state) launch_dataset<float>(c, target, key, draw, rows);
+  else launch_dataset<double>(c, target, key, draw, rows);
+  return hip_check(c, hipGetLastError(), "dataset launch");
+}
+
+pdf_status pdf_mlp_forward(const float* rows, int64_t nrows, int32_t row_stride, const float* norm,
+                           const uint16_t* w, float* y, void* hip_stream) {
+  if (!rows || !norm || !w || !y || nrows < 0 || row_stride < mlp::NFEAT) return PDF_E_ARG;
+  if (nrows == 0) return PDF_OK;
+  mlp::ForwardArgs f{rows, nrows, row_stride, norm, w, y};
+  const int64_t tiles = (nrows + mlp::TILE - 1) / mlp::TILE;
+  if (tiles > (int64_t)1 << 30) return PDF_E_SIZE;
+  hipLaunchKernelGGL(mlp::k_mlp_forward, dim3(mlp_blocks(tiles)), dim3(64 * mlp::MLP_WAVES), 0,
+                     (hipStream_t)hip_stream, f);
+  return mlp_hip(hipGetLastError());
+}
+
+pdf_status pdf_mlp_grad(const float* rows, int32_t batch, const float* norm, const uint16_t* w, float* work,
+                        float* grad, float* loss, void* hip_stream) {
+  if (!rows || !norm || !w || !work || !grad || batch <= 0 || batch > PDF_MLP_MAX_BATCH) return PDF_E_ARG;
+  return mlp_grad_step(rows, batch, batch, 0, 0, 0, norm, const_cast<uint16_t*>(w), work, grad, loss, 0, nullptr,
+                       nullptr, nullptr, 0.0f, (hipStream_t)hip_stream);
+}
+
+pdf_status pdf_mlp_train(const float* rows, int64_t nrows, const float* norm, float* master, float* adam_m,
+                         float* adam_v, uint16_t* w, float* work, float* loss, int32_t iters, int32_t batch,
+                         float lr, uint64_t seed, int64_t t0, void* hip_stream) {
+  if (!rows || !norm || !master || !adam_m || !adam_v || !w || !work || nrows <= 0 || nrows > 0xFFFFFFFFll ||
+      iters < 0 || batch <= 0 || batch > PDF_MLP_MAX_BATCH || t0 < 0 || t0 + iters > 0xFFFFFFFFll || !(lr > 0.0f))
+    return PDF_E_ARG;
+  for (int32_t i = 0; i < iters; ++i) {
+    const uint32_t t = (uint32_t)(t0 + i + 1);
+    pdf_status r = mlp_grad_step(rows, nrows, batch, 1, seed, t, norm, w, work, nullptr, loss ? loss + i : nullptr, 1,
+                                 master, adam_m, adam_v, lr, (hipStream_t)hip_stream);
+    if (r) return r;
+  }
+  return PDF_OK;
+}
+
+pdf_status pdf_mlp_norm(const float* rows, int64_t nrows, float* norm, void* hip_stream) {
+  if (!rows || !norm || nrows < 0) return PDF_E_ARG;
+  hipLaunchKernelGGL(mlp::k_mlp_norm, dim3(mlp::NFEAT), dim3(256), 0, (hipStream_t)hip_stream, rows, nrows, norm);
+  return mlp_hip(hipGetLastError());
+}
+
+pdf_status pdf_mlp_round(const float* master, uint16_t* w, void* hip_stream) {
+  if (!master || !w) return PDF_E_ARG;
+  hipLaunchKernelGGL(mlp::k_mlp_to_bf16, dim3((mlp::NPARAM + 255) / 256), dim3(256), 0, (hipStream_t)hip_stream,
+                     master, w, (int)mlp::NPARAM);
+  return mlp_hip(hipGetLastError());
+}
+
+pdf_status pdf_mlp_infer(const double* stats, int32_t nstat, int32_t ncell, const uint16_t* w, const float* norm,
+                         double* cm, uint32_t* served, void* hip_stream) {
+  if (!stats || !w || !norm || !cm || ncell < 0 || nstat < NSTAT2) return PDF_E_ARG;
+  if (ncell == 0) return PDF_OK;
+  mlp::InferArgs ia{stats, nstat, ncell, w, norm, cm, served};
+  const int tiles = (ncell + mlp::TILE - 1) / mlp::TILE;
+  hipLaunchKernelGGL(mlp::k_mlp_infer, dim3(mlp_blocks(tiles)), dim3(64 * mlp::MLP_WAVES), 0, (hipStream_t)hip_stream,
+                     ia);
+  return mlp_hip(hipGetLastError());
+}
+
+pdf_status pdf_mlp_attach(pdf_ctx* c, const uint16_t* w, const float* norm, double* cm, uint32_t* served) {
+  if (!c) return PDF_E_ARG;
+  if (!w) {
+    c->mlp_w = nullptr;
+    c->mlp_norm = nullptr;
+    c->mlp_cm = nullptr;
+    c->mlp_served = nullptr;
+    return PDF_OK;
+  }
+  if (!norm || !cm) return fail(c, PDF_E_ARG, "pdf_mlp_attach: null normalisation or output");
+  c->mlp_w = w;
+  c->mlp_norm = norm;
+  c->mlp_cm = cm;
+  c->mlp_served = served;
+  return PDF_OK;
 }
 
 }  // extern "C"
