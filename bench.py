@@ -102,6 +102,114 @@ def cpu_baseline(wl_fn, seconds: float = 15.0) -> dict:
             "sample": f"{wl.name}: all {n} particles, {steps} steps after one untimed step, {el:.1f} s"}
 
 
+def learned_leg(torch, W, Simulation) -> dict:
+    """The learned conditional means on the 10k-element canyon with its street
+    source.  Training rows: 20-particle subsamples of runs at 500 particles per
+    element (seeds 1..4), taken every 100 steps from step 500 to 2000, eight
+    draws each, the rows with scalar spread kept.  Judged against a run at
+    4000 particles per element (seed 101) at the same steps, next to the
+    binned estimate of 20- and 500-particle subsamples.  Then used inside the
+    step of a 20-particle-per-element run on the 50k-element resolved-wall
+    mesh."""
+    from paper_1003_4548_amd import mlp as PM
+    t_start = time.perf_counter()
+    spin, every, snaps, draws = 500, 100, 16, 8
+
+    rows = []
+    for seed in (1, 2, 3, 4):
+        sim = Simulation.from_workload(W.config5(ppe=500, seed=seed), device="cuda:0")
+        sim.step_graph(spin)
+        for k in range(snaps):
+            if k:
+                sim.step_graph(every)
+            for d in range(draws):
+                r = PM.dataset(sim, target=20, key=1000 + seed, draw=draws * k + d)
+                rows.append(r[r[:, 40:48].sum(dim=1) > 0])
+        sim.sync()
+        sim.close()
+    rows = torch.cat(rows)
+    nrows = int(rows.shape[0])
+    print(f"[bench] learned: {nrows} training rows", file=sys.stderr, flush=True)
+    net = PM.ConditionalMeanNet(seed=0)
+    net.fit_norm(rows)
+    iters, batch = 6000, 2048
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(net.stream)
+    loss = net.train(rows, iters=iters, batch=batch, lr=2e-3, seed=7)
+    e1.record(net.stream)
+    torch.cuda.synchronize()
+    train_ms = e0.elapsed_time(e1)
+    loss = loss.cpu().numpy()
+    del rows
+    # judged against 4000 particles per element
+    sim = Simulation.from_workload(W.config5(ppe=4000, seed=101), device="cuda:0")
+    sim.step_graph(spin)
+    r20, r500 = [], []
+    for k in range(snaps):
+        if k:
+            sim.step_graph(every)
+        r20.append(PM.dataset(sim, target=20, key=5555, draw=k))
+        r500.append(PM.dataset(sim, target=500, key=6666, draw=k))
+    sim.sync()
+    sim.close()
+    r20 = torch.cat(r20)
+    r500 = torch.cat(r500)
+    rec = PM.records_from_rows(r20)
+    cm, _ = net.infer(rec)
+    domain = (r20[:, 0] > 0) & (r20[:, 31] > 1e-4)
+    took = (cm != rec[:, 23:31]).any(dim=1)
+    err = {"plain_20": PM.estimate_error(r20), "learned_20": PM.estimate_error(r20, cm),
+           "plain_500": PM.estimate_error(r500)}
+    served_frac = float((took & domain).sum()) / max(1, int(domain.sum()))
+    n_domain = int(domain.sum())
+    del r20, r500, rec, cm
+    torch.cuda.empty_cache()
+    # inside the step: 20 particles per element on the 50k-element resolved-wall canyon
+    wl = W.config5(ppe=20, seed=101, target=50000)
+    sim = Simulation.from_workload(wl, device="cuda:0")
+    sim.step_graph(spin)
+    steps = 200
+    sim.sync()
+    t0 = time.perf_counter()
+    sim.step_graph(steps)
+    sim.sync()
+    plain_s = time.perf_counter() - t0
+    lm = net.attach(sim)
+    sim.step(10)
+    sim.sync()
+    lm.served.zero_()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    sim.sync()
+    mlp_s = time.perf_counter() - t0
+    st = sim.statistics_device()[0]
+    in_domain = int(((st[:, 0] > 0) & (st[:, 14] > 1e-8)).sum())
+    inloop_served = int(lm.served.cpu()[0]) / (steps * max(1, in_domain))
+    lm.detach()
+    sim.close()
+    n, E = wl.n_total, wl.mesh.nelem
+    res = {
+        "error_metric": "population-weighted RMS of <phi|V> over (element, bin) against 4000 particles/element",
+        "error_plain_20ppe": round(err["plain_20"], 6), "error_learned_20ppe": round(err["learned_20"], 6),
+        "error_plain_500ppe": round(err["plain_500"], 6),
+        "learned_vs_plain20": round(err["learned_20"] / err["plain_20"], 4),
+        "learned_vs_plain500": round(err["learned_20"] / err["plain_500"], 4),
+        "elements_with_scalar_spread": n_domain,
+        "served_fraction_with_scalar_spread": round(served_frac, 4),
+        "train": {"rows": nrows, "iters": iters, "batch": batch, "ms": round(train_ms, 2),
+                  "loss_first": float(loss[:20].mean()), "loss_last": float(loss[-200:].mean())},
+        "in_step": {"workload": wl.name, "particles": n, "elements": E, "steps": steps,
+                    "value": round(n * steps / mlp_s, 1), "ms_per_step": round(1e3 * mlp_s / steps, 5),
+                    "plain_value": round(n * steps / plain_s, 1),
+                    "ppe500_equivalent_value": round(500 * E * steps / mlp_s, 1),
+                    "served_fraction_with_scalar_spread": round(inloop_served, 4)},
+        "seconds": round(time.perf_counter() - t_start, 1),
+    }
+    print(f"[bench] learned: {res}", file=sys.stderr, flush=True)
+    return res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -118,6 +226,8 @@ def main() -> int:
                     help="steps per candidate launch shape before warmup (0: no tuning)")
     ap.add_argument("--launch", default="",
                     help="fixed launch shape 'lanes_per_cell,persistent' (e.g. 32,1) instead of tuning")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned conditional-mean leg (training, error, in-step throughput)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -220,6 +330,8 @@ def main() -> int:
         out.setdefault("secondary", {})[name] = {
             "value": round(sec["value"], 1), "unit": "particle-steps/s", "steps": args.secondary_steps,
             "ms_per_step": round(sec["ms_per_step"], 5), "config": sec["config"], "roofline": sec["roofline"]}
+    if not args.no_learned:
+        out["learned_phi_given_v"] = learned_leg(torch, W, Simulation)
     if args.calibrate_copy:
         nbytes = 1 << 30
         a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda:0").fill_(1.0)

@@ -293,8 +293,9 @@ def dataset_rows(state, nelem: int, target: int, key: int, draw: int, ens: int =
 def plain_and_learned_error(rows, params, norm):
     """Population-weighted RMS error of the binned and of the learned estimate
     against the reference conditional means of dataset rows (the learned one
-    with its fallback).  Returns (plain, learned, fraction of the rows whose
-    subsample scalar varies that took the learned value)."""
+    with its fallback).  Returns (plain, learned, fraction of the rows in the
+    trained domain, subsample scalar spread above SIGMA_MIN, that took the
+    learned value)."""
     rows = np.asarray(rows, np.float64)
     feat = rows[:, :32]
     n = feat[:, 0] * 64.0
@@ -311,5 +312,5 @@ def plain_and_learned_error(rows, params, norm):
     den = wgt.sum()
     ep = np.sqrt((wgt * (plain - ref) ** 2).sum() / den)
     el = np.sqrt((wgt * (cm - ref) ** 2).sum() / den)
-    varies = (n > 0) & (feat[:, 31] > 0)
+    varies = (n > 0) & (feat[:, 31] > SIGMA_MIN)
     return float(ep), float(el), float(ok[varies].mean() if varies.any() else 0.0)

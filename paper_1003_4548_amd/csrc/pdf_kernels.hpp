@@ -315,19 +315,25 @@ template <typename T, int TILEN> struct Tile {
   uint32_t id[TILEN];
 };
 
-// Group-uniform values v[0..K) written to rec[0..K) by the lanes of the group:
-// lane li writes entries li, li + G, ...
-template <int G, int K>
-__device__ __forceinline__ void group_store(double* rec, const double (&v)[K], int li, bool ok) {
-#pragma unroll
-  for (int r = 0; r < (K + G - 1) / G; ++r) {
-    double val = 0.0;
-#pragma unroll
-    for (int q = r * G; q < (r + 1) * G && q < K; ++q) val = (li == q - r * G) ? v[q] : val;
-    const int idx = r * G + li;
-    if (ok && idx < K) rec[idx] = val;
-  }
+// LDS written by some lanes of a wavefront and read by others.  A wavefront's
+// LDS instructions execute in order, so a wavefront-scope fence (which keeps
+// the compiler from moving memory operations across it and adds no wait on
+// outstanding global memory) is enough.
+__device__ __forceinline__ void lds_sync_wave() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
 }
+
+// Per-cell constants of the advance, kept in LDS rather than in registers
+// across the particle loop: the element's vertices, the interpolation
+// coefficients of its three vertices, the velocity means that define the
+// bins and the conditional means IECM relaxes toward.
+template <typename T> struct CellConst {
+  T coef[3 * NCOEF];
+  double vx[3], vy[3];
+  double mean[3];
+  double cm[8];
+};
 
 template <typename T, int MOM, int HIST, int G, bool ADVANCE, bool PERSIST>
 __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
@@ -336,6 +342,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
   constexpr int CPB = WAVES_PER_BLOCK * GPW;
   __shared__ Tile<T, TILEN> tiles[CPB];
   __shared__ int hist_lds[HIST > 0 ? CPB : 1][HIST > 0 ? HIST : 1];
+  __shared__ CellConst<T> ccs[ADVANCE ? CPB : 1];
   Ctl* ctl = a.ctl;
   // after an error the state is void: later steps do nothing
   if (ADVANCE && ctl->error != 0) return;
@@ -484,64 +491,54 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
       for (int q = 0; q < 8; ++q) cm[q] = bm[q];
     }
     double* rec = a.stats + (size_t)(has ? cell : 0) * a.nstat;
-    {
-      double r2[NSTAT2];
-      r2[ST_N] = dn;
+    // the record is written by the group's first lane straight from the
+    // (group-uniform) accumulators
+    if (has && li == 0) {
+      const double z = n > 0 ? 1.0 : 0.0;
+      rec[ST_N] = dn;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) r2[ST_MEAN + q] = mean[q];
+      for (int q = 0; q < 4; ++q) rec[ST_MEAN + q] = mean[q] * z;
 #pragma unroll
-      for (int q = 0; q < 10; ++q) r2[ST_M2 + q] = acc[q] * inv_n;
+      for (int q = 0; q < 10; ++q) rec[ST_M2 + q] = acc[q] * inv_n;
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
-        r2[ST_BINN + q] = (double)bcount[q];
-        r2[ST_BINM + q] = bm[q];
+        rec[ST_BINN + q] = (double)bcount[q];
+        rec[ST_BINM + q] = bm[q] * z;
       }
-      if (n == 0) {
-#pragma unroll
-        for (int q = 0; q < NSTAT2; ++q) r2[q] = 0.0;
-      }
-      group_store<G, NSTAT2>(rec, r2, li, has);
     }
     if constexpr (MOM >= 4) {
-      // third-order moments
-      double m3[20];
-#pragma unroll
-      for (int q = 0; q < 20; ++q) m3[q] = 0.0;
-      for (int base = 0; __ballot(base < n) != 0; base += G) {
-        const int j = base + li;
-        if (j < n) {
-          double val[4], d[4];
-          load4(j, val);
-#pragma unroll
-          for (int q = 0; q < 4; ++q) d[q] = val[q] - mean[q];
-          int i3 = 0;
-#pragma unroll
-          for (int x = 0; x < 4; ++x)
-#pragma unroll
-            for (int y = x; y < 4; ++y)
-#pragma unroll
-              for (int z = y; z < 4; ++z) { m3[i3] += (d[x] * d[y]) * d[z]; ++i3; }
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < 20; ++q) m3[q] = group_sum<G>(m3[q]) * inv_n;
-      group_store<G, 20>(rec + ST_M3, m3, li, has);
-      // fourth-order moments, in two groups to bound the accumulator count
+      // third- and fourth-order central moments: the 20 + 35 index combinations
+      // in lexicographic order, each product built from the ten pairwise
+      // products d_x d_y and accumulated with a fused multiply-add; two passes
+      // over the particles bound the number of live accumulators
+      constexpr int NM = 55, SPLIT = 28;
 #pragma unroll
       for (int part = 0; part < 2; ++part) {
-        constexpr int P0 = 18;
-        const int lo = part == 0 ? 0 : P0, hi = part == 0 ? P0 : 35;
-        double m4[P0];
+        const int lo = part == 0 ? 0 : SPLIT, hi = part == 0 ? SPLIT : NM;
+        double acc3[NM - SPLIT > SPLIT ? NM - SPLIT : SPLIT];
 #pragma unroll
-        for (int q = 0; q < P0; ++q) m4[q] = 0.0;
+        for (int q = 0; q < (NM - SPLIT > SPLIT ? NM - SPLIT : SPLIT); ++q) acc3[q] = 0.0;
         for (int base = 0; __ballot(base < n) != 0; base += G) {
           const int j = base + li;
           if (j < n) {
-            double val[4], d[4];
+            double val[4], d[4], pr[10];
             load4(j, val);
 #pragma unroll
             for (int q = 0; q < 4; ++q) d[q] = val[q] - mean[q];
-            int i4 = 0;
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+#pragma unroll
+              for (int y = x; y < 4; ++y) pr[pair_index(x, y)] = d[x] * d[y];
+            int k = 0;
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+#pragma unroll
+              for (int y = x; y < 4; ++y)
+#pragma unroll
+                for (int z = y; z < 4; ++z) {
+                  if (k >= lo && k < hi) acc3[k - lo] = __builtin_fma(pr[pair_index(x, y)], d[z], acc3[k - lo]);
+                  ++k;
+                }
 #pragma unroll
             for (int x = 0; x < 4; ++x)
 #pragma unroll
@@ -550,52 +547,95 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
                 for (int z = y; z < 4; ++z)
 #pragma unroll
                   for (int g = z; g < 4; ++g) {
-                    if (i4 >= lo && i4 < hi) m4[i4 - lo] += ((d[x] * d[y]) * d[z]) * d[g];
-                    ++i4;
+                    if (k >= lo && k < hi)
+                      acc3[k - lo] = __builtin_fma(pr[pair_index(x, y)], pr[pair_index(z, g)], acc3[k - lo]);
+                    ++k;
                   }
           }
         }
+        // M3 (20 entries) and M4 (35) are contiguous in the record
 #pragma unroll
-        for (int q = 0; q < P0; ++q) m4[q] = group_sum<G>(m4[q]) * inv_n;
-        if (part == 0) {
-          group_store<G, P0>(rec + ST_M4, m4, li, has);
-        } else {
-          double m4b[35 - P0];
-#pragma unroll
-          for (int q = 0; q < 35 - P0; ++q) m4b[q] = m4[q];
-          group_store<G, 35 - P0>(rec + ST_M4 + P0, m4b, li, has);
+        for (int q = 0; q < (part == 0 ? SPLIT : NM - SPLIT); ++q) {
+          const double r = group_sum<G>(acc3[q]) * inv_n;
+          if (has && li == 0) rec[ST_M3 + lo + q] = r;
         }
       }
     }
     if (HIST > 0) {
       const int off = MOM >= 4 ? NSTAT4 : NSTAT2;
+      lds_sync_wave();
       for (int h = li; h < HIST; h += G)
         if (has) rec[off + h] = (double)hist_lds[slot_id][h];
     }
 
     if (ADVANCE) {
       // ---- C: advance ----
-      ERec R0 = a.erec[e];
-      const int v0 = a.tri[3 * e], v1 = a.tri[3 * e + 1], v2 = a.tri[3 * e + 2];
+      CellConst<T>& CC = ccs[ADVANCE ? slot_id : 0];
+      {
+        const int vtx[3] = {a.tri[3 * e], a.tri[3 * e + 1], a.tri[3 * e + 2]};
+        for (int q = li; q < 3 * NCOEF; q += G) {
+          const int k = q / NCOEF;
+          const int vk = k == 0 ? vtx[0] : (k == 1 ? vtx[1] : vtx[2]);
+          CC.coef[q] = a.coef[(size_t)vk * NCOEF + (q - k * NCOEF)];
+        }
+        if (li == 0) {
+          const ERec R = a.erec[e];
+#pragma unroll
+          for (int k = 0; k < 3; ++k) { CC.vx[k] = R.x[k]; CC.vy[k] = R.y[k]; }
+#pragma unroll
+          for (int q = 0; q < 3; ++q) CC.mean[q] = mean[q];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) CC.cm[q] = cm[q];
+        }
+        lds_sync_wave();
+      }
       const double ia = a.inv2a[e];
-      const T* q0 = a.coef + (size_t)v0 * NCOEF;
-      const T* q1 = a.coef + (size_t)v1 * NCOEF;
-      const T* q2 = a.coef + (size_t)v2 * NCOEF;
       const T rate = has ? a.rate[cell] : (T)0;
       const uint64_t seed = a.seed[ens];
       const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
-      const double sx0 = a.src[3 * ens], sy0 = a.src[3 * ens + 1], sr0 = a.src[3 * ens + 2];
       const bool do_mix = a.mix && (a.flags & FLAG_MIX);
       int err = 0;
       int stay_count = 0;
+
+      // Writes a particle that ended in element e2 of ensemble qens: its own
+      // cell's bottom run at index k, or the top run of the new cell.
+      auto put_mover = [&](int qens, int e2, T xn, T yn, T un, T vn, T wn, T psi, uint32_t id) {
+        const int t = qens * ne + e2;
+        const int k = atomicAdd(&a.nm[rn][t], 1);
+        const int capt = a.cap[t];
+        const int limit = capt - (a.ns[rc][t] + a.nm[rc][t]);
+        if (k < limit) {
+          const int s = a.start[t] + capt - 1 - k;
+          dst.x[s] = xn; dst.y[s] = yn; dst.u[s] = un; dst.v[s] = vn; dst.w[s] = wn; dst.psi[s] = psi;
+          dst.id[s] = id;
+        } else {
+          err |= ERR_CAPACITY;
+          const uint32_t kk = atomicAdd(&ctl->ovf, 1u);
+          if (kk < a.ovf_cap) {
+            a.ovf.x[kk] = xn; a.ovf.y[kk] = yn; a.ovf.u[kk] = un; a.ovf.v[kk] = vn; a.ovf.w[kk] = wn;
+            a.ovf.psi[kk] = psi; a.ovf.id[kk] = id;
+            a.ovf_cell[kk] = t;
+          } else {
+            err |= ERR_OVERFLOW_FULL;
+          }
+        }
+      };
+      // the source, section 3: a particle ending within r0 of x0 takes scalar 1
+      auto finish = [&](int qens, T xn, T yn, T& psi) {
+        const double qsr = a.src[3 * qens + 2];
+        if ((a.flags & FLAG_SRC) && qsr > 0.0) {
+          const double ddx = (double)xn - a.src[3 * qens], ddy = (double)yn - a.src[3 * qens + 1];
+          if (ddx * ddx + ddy * ddy <= qsr * qsr) psi = (T)1;
+        }
+      };
       for (int base = 0; __ballot(base < n) != 0; base += G) {
         const int j = base + li;
         const bool act = j < n;
-        int e2 = -1;
-        T xn = 0, yn = 0, un = 0, vn = 0, wn = 0, psi = 0;
+        bool moved = false;
+        T x = 0, y = 0, xn = 0, yn = 0, un = 0, vn = 0, wn = 0, psi = 0;
         uint32_t id = 0;
         if (act) {
-          T x, y, u, v, w;
+          T u, v, w;
           if (j < TILEN) {
             x = L.x[j]; y = L.y[j]; u = L.u[j]; v = L.v[j]; w = L.w[j]; psi = L.psi[j]; id = L.id[j];
           } else {
@@ -610,19 +650,17 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
           box_muller<T>(rw[4], rw[5], &xi4, &xi5);
           (void)xi5;
           const double X = (double)x, Y = (double)y;
-          const T l0 = (T)(orient_edge(R0.x[1], R0.y[1], R0.x[2], R0.y[2], X, Y) * ia);
-          const T l1 = (T)(orient_edge(R0.x[2], R0.y[2], R0.x[0], R0.y[0], X, Y) * ia);
-          const T l2 = (T)(orient_edge(R0.x[0], R0.y[0], R0.x[1], R0.y[1], X, Y) * ia);
+          const double ax = CC.vx[0], ay = CC.vy[0], bx = CC.vx[1], by = CC.vy[1], cx = CC.vx[2], cy = CC.vy[2];
+          const T l0 = (T)(orient_edge(bx, by, cx, cy, X, Y) * ia);
+          const T l1 = (T)(orient_edge(cx, cy, ax, ay, X, Y) * ia);
+          const T l2 = (T)(orient_edge(ax, ay, bx, by, X, Y) * ia);
           T f[NCOEF];
 #pragma unroll
-          for (int q = 0; q < NCOEF; ++q) f[q] = (l0 * q0[q] + l1 * q1[q]) + l2 * q2[q];
+          for (int q = 0; q < NCOEF; ++q) f[q] = (l0 * CC.coef[q] + l1 * CC.coef[NCOEF + q]) + l2 * CC.coef[2 * NCOEF + q];
           if (do_mix) {
-            const int bin = ((double)u > mean[0] ? 1 : 0) + ((double)v > mean[1] ? 2 : 0) +
-                            ((double)w > mean[2] ? 4 : 0);
-            double mb = cm[0];
-#pragma unroll
-            for (int q = 1; q < 8; ++q) mb = (bin == q) ? cm[q] : mb;
-            const T m = (T)mb;
+            const int bin = ((double)u > CC.mean[0] ? 1 : 0) + ((double)v > CC.mean[1] ? 2 : 0) +
+                            ((double)w > CC.mean[2] ? 4 : 0);
+            const T m = (T)CC.cm[bin];
             psi = psi - rate * (psi - m);
           }
           const T dW1 = a.sdt * xi0, dW2 = a.sdt * xi1;
@@ -635,27 +673,40 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
           vn = ((v + av * a.dt) + a.s2nu * (f[C_DVDX] * dW1 + f[C_DVDY] * dW2)) + sq * dWp2;
           wn = (w + (f[C_G33] * w) * a.dt) + sq * dWp3;
           if (!(a.flags & FLAG_VEL)) { un = u; vn = v; wn = w; }
-          xn = (x + u * a.dt) + a.s2nu * dW1;
-          yn = (y + v * a.dt) + a.s2nu * dW2;
-          e2 = e;
           if (a.flags & FLAG_POS) {
-            e2 = walk<T>(a, R0, e, X, Y, xn, yn, un, vn, wn);
+            xn = (x + u * a.dt) + a.s2nu * dW1;
+            yn = (y + v * a.dt) + a.s2nu * dW2;
+            // the walk's first test: is the end point still in the element?
+            const double Tx = (double)xn, Ty = (double)yn;
+            const double o0 = orient_edge(ax, ay, bx, by, Tx, Ty);
+            const double o1 = orient_edge(bx, by, cx, cy, Tx, Ty);
+            const double o2 = orient_edge(cx, cy, ax, ay, Tx, Ty);
+            if (!(o0 >= 0.0 && o1 >= 0.0 && o2 >= 0.0)) {
+              // it left: the rest of the walk, with walls and periodic edges
+              const int e2 = walk<T>(a, a.erec[e], e, X, Y, xn, yn, un, vn, wn);
+              if (e2 != e) {
+                moved = true;
+                if (e2 < 0) {
+                  err |= ERR_LOST;
+                } else {
+                  finish(ens, xn, yn, psi);
+                  if (!(isfinite(un) && isfinite(vn) && isfinite(wn) && isfinite(psi) && isfinite(xn) && isfinite(yn)))
+                    err |= ERR_NAN;
+                  put_mover(ens, e2, xn, yn, un, vn, wn, psi, id);
+                }
+              }
+            }
           } else {
             xn = x; yn = y;
           }
-          if (e2 < 0) {
-            err |= ERR_LOST;
-          } else {
-            if ((a.flags & FLAG_SRC) && sr0 > 0.0) {
-              const double ddx = (double)xn - sx0, ddy = (double)yn - sy0;
-              if (ddx * ddx + ddy * ddy <= sr0 * sr0) psi = (T)1;
-            }
+          if (!moved) {
+            finish(ens, xn, yn, psi);
             if (!(isfinite(un) && isfinite(vn) && isfinite(wn) && isfinite(psi) && isfinite(xn) && isfinite(yn)))
               err |= ERR_NAN;
           }
         }
         // stayers: own segment, bottom run, in lane order, no atomics
-        const bool stay = act && e2 == e;
+        const bool stay = act && !moved;
         const uint64_t smask = __ballot(stay) & gmask;
         if (stay) {
           const int s = start + stay_count + (int)__popcll(smask & lanemask_lt());
@@ -663,28 +714,6 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
           dst.id[s] = id;
         }
         stay_count += (int)__popcll(smask);
-        // movers: top run of the new cell's segment
-        if (act && e2 >= 0 && e2 != e) {
-          const int t = ens * ne + e2;
-          const int k = atomicAdd(&a.nm[rn][t], 1);
-          const int capt = a.cap[t];
-          const int limit = capt - (a.ns[rc][t] + a.nm[rc][t]);
-          if (k < limit) {
-            const int s = a.start[t] + capt - 1 - k;
-            dst.x[s] = xn; dst.y[s] = yn; dst.u[s] = un; dst.v[s] = vn; dst.w[s] = wn; dst.psi[s] = psi;
-            dst.id[s] = id;
-          } else {
-            err |= ERR_CAPACITY;
-            const uint32_t kk = atomicAdd(&ctl->ovf, 1u);
-            if (kk < a.ovf_cap) {
-              a.ovf.x[kk] = xn; a.ovf.y[kk] = yn; a.ovf.u[kk] = un; a.ovf.v[kk] = vn; a.ovf.w[kk] = wn;
-              a.ovf.psi[kk] = psi; a.ovf.id[kk] = id;
-              a.ovf_cell[kk] = t;
-            } else {
-              err |= ERR_OVERFLOW_FULL;
-            }
-          }
-        }
       }
       if (has && li == 0) {
         a.ns[rn][cell] = stay_count;

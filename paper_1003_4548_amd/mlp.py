@@ -161,3 +161,29 @@ def dataset(sim, target: int, key: int, draw: int):
     sim._check(load_library().pdf_mlp_dataset(sim.ctx, int(target), int(key), int(draw) & 0xFFFFFFFF, _vp(rows)),
                "pdf_mlp_dataset")
     return rows
+
+
+def records_from_rows(rows):
+    """Statistics records (nrows x 31 doubles) carried by dataset rows: the
+    subsample's count, means, second moments, bin counts and binned means."""
+    torch = rows.torch if hasattr(rows, "torch") else __import__("torch")
+    f = rows[:, :32].double()
+    rec = torch.zeros((rows.shape[0], 31), dtype=torch.float64, device=rows.device)
+    n = torch.round(f[:, 0] * 64.0)
+    rec[:, 0] = n
+    rec[:, 1:5] = f[:, 1:5]
+    rec[:, 5:15] = f[:, 5:15]
+    rec[:, 15:23] = torch.round(f[:, 15:23] * n[:, None])
+    rec[:, 23:31] = f[:, 23:31]
+    return rec
+
+
+def estimate_error(rows, cm=None) -> float:
+    """Population-weighted RMS difference between an estimate of the eight
+    conditional means (cm, nrows x 8; None: the subsample's binned means) and
+    the whole-population values carried by dataset rows."""
+    n = rows[:, 0] * 64.0
+    est = rows[:, 23:31].double() if cm is None else cm.double()
+    ref = rows[:, 48:56].double()
+    wgt = rows[:, 56:64].double() * (n > 0).double()[:, None]
+    return float((((est - ref) ** 2) * wgt).sum() / wgt.sum()) ** 0.5
