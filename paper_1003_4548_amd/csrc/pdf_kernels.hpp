@@ -122,6 +122,7 @@ template <typename T> struct StepArgs {
   int32_t flags;
   int32_t mix;
   int32_t nitems;         // work items (wavefronts' worth of cells)
+  int32_t pchunk;         // work items a persistent wavefront claims per atomic
   T dt, sdt, nu2, s2nu;
 };
 
@@ -206,7 +207,12 @@ __device__ int walk(const StepArgs<T>& a, ERec R, int e, double Sx, double Sy, T
     const double o2 = orient_edge(R.x[2], R.y[2], R.x[0], R.y[0], Tx, Ty);
     if (o0 >= 0.0 && o1 >= 0.0 && o2 >= 0.0) return e;
     int ex = -1;
-    {
+    const int nneg = (o0 < 0.0 ? 1 : 0) + (o1 < 0.0 ? 1 : 0) + (o2 < 0.0 ? 1 : 0);
+    if (nneg == 1) {
+      // one edge has the target outside: the separation test below either
+      // picks it or finds none, and then the most-outside edge is that one
+      ex = o0 < 0.0 ? 0 : (o1 < 0.0 ? 1 : 2);
+    } else {
       const double o[3] = {o0, o1, o2};
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
@@ -361,12 +367,20 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
   const StateDev<T> dst = a.buf[bpar ^ 1u];
   Tile<T, TILEN>& L = tiles[slot_id];
 
+  // persistent grid: a wavefront claims a.pchunk consecutive work items per
+  // atomic on the shared counter (one address: its atomics serialise in L2)
   int item = PERSIST ? 0 : xcd_block(blockIdx.x, gridDim.x) * WAVES_PER_BLOCK + wid;
+  int chunk_end = 0;
   for (;;) {
     if (PERSIST) {
-      int it = 0;
-      if (lane == 0) it = (int)atomicAdd(&ctl->next[par], 1u);
-      item = __builtin_amdgcn_readfirstlane(it);
+      if (item + 1 < chunk_end) {
+        ++item;
+      } else {
+        int it = 0;
+        if (lane == 0) it = (int)atomicAdd(&ctl->next[par], (uint32_t)a.pchunk);
+        item = __builtin_amdgcn_readfirstlane(it);
+        chunk_end = item + a.pchunk;
+      }
     }
     if (item >= a.nitems) break;
     const int idx = item * GPW + grp;

@@ -200,6 +200,13 @@ template <typename T> StepArgs<T> step_args(pdf_ctx* c) {
   return s;
 }
 
+// Work items per claim of a persistent wavefront: about a sixteenth of its
+// fair share, between 1 and 16.
+int persist_chunk(int nitems, int blocks) {
+  const int waves = std::max(1, blocks * WAVES_PER_BLOCK);
+  return std::max(1, std::min(16, nitems / (16 * waves)));
+}
+
 template <typename T, int MOM, int HIST, int G, bool ADV, bool PERSIST>
 void launch_step(pdf_ctx* c, StepArgs<T> s, StepIndex si) {
   constexpr int GPW = WAVE / G;
@@ -214,6 +221,7 @@ void launch_step(pdf_ctx* c, StepArgs<T> s, StepIndex si) {
     blocks = std::min(blocks, cap_blocks);
     c->persist_blocks = blocks;
   }
+  s.pchunk = persist_chunk(s.nitems, blocks);
   hipLaunchKernelGGL((k_step<T, MOM, HIST, G, ADV, PERSIST>), dim3(blocks), dim3(BLOCK), 0, c->stream, s, si);
 }
 
@@ -336,6 +344,7 @@ StepLaunch step_launch_of(pdf_ctx* c, StepArgs<T>& s) {
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device);
     blocks = std::min(blocks, std::max(1, per_cu) * std::max(1, cus));
   }
+  s.pchunk = persist_chunk(s.nitems, blocks);
   StepLaunch l;
   l.func = reinterpret_cast<const void*>(&k_step<T, MOM, HIST, G, true, PERSIST>);
   l.blocks = blocks;
