@@ -336,10 +336,20 @@ __device__ __forceinline__ void lds_sync_wave() {
 // bins and the conditional means IECM relaxes toward.
 template <typename T> struct CellConst {
   T coef[3 * NCOEF];
-  double vx[3], vy[3];
+  // edge k (vertex k -> k+1) from its lexicographically smaller endpoint:
+  // origin, direction and the sign that turns the result into the
+  // orientation against the element's own edge (orient_edge)
+  double ox[3], oy[3], dx[3], dy[3], sg[3];
   double mean[3];
   double cm[8];
 };
+
+// orient_edge of (px, py) against edge k of a cell, from its CellConst data;
+// the same operations in the same order, so the same bits.
+template <typename T>
+__device__ __forceinline__ double orient_cc(const CellConst<T>& C, int k, double px, double py) {
+  return ((C.dx[k] * (py - C.oy[k])) - (C.dy[k] * (px - C.ox[k]))) * C.sg[k];
+}
 
 template <typename T, int MOM, int HIST, int G, bool ADVANCE, bool PERSIST>
 __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
@@ -595,7 +605,16 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
         if (li == 0) {
           const ERec R = a.erec[e];
 #pragma unroll
-          for (int k = 0; k < 3; ++k) { CC.vx[k] = R.x[k]; CC.vy[k] = R.y[k]; }
+          for (int k = 0; k < 3; ++k) {
+            const int k1 = k == 2 ? 0 : k + 1;
+            const double ax = R.x[k], ay = R.y[k], bx = R.x[k1], by = R.y[k1];
+            const bool a_first = (ax < bx) || (ax == bx && ay < by);
+            CC.ox[k] = a_first ? ax : bx;
+            CC.oy[k] = a_first ? ay : by;
+            CC.dx[k] = a_first ? bx - ax : ax - bx;
+            CC.dy[k] = a_first ? by - ay : ay - by;
+            CC.sg[k] = a_first ? 1.0 : -1.0;
+          }
 #pragma unroll
           for (int q = 0; q < 3; ++q) CC.mean[q] = mean[q];
 #pragma unroll
@@ -664,10 +683,9 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
           box_muller<T>(rw[4], rw[5], &xi4, &xi5);
           (void)xi5;
           const double X = (double)x, Y = (double)y;
-          const double ax = CC.vx[0], ay = CC.vy[0], bx = CC.vx[1], by = CC.vy[1], cx = CC.vx[2], cy = CC.vy[2];
-          const T l0 = (T)(orient_edge(bx, by, cx, cy, X, Y) * ia);
-          const T l1 = (T)(orient_edge(cx, cy, ax, ay, X, Y) * ia);
-          const T l2 = (T)(orient_edge(ax, ay, bx, by, X, Y) * ia);
+          const T l0 = (T)(orient_cc(CC, 1, X, Y) * ia);
+          const T l1 = (T)(orient_cc(CC, 2, X, Y) * ia);
+          const T l2 = (T)(orient_cc(CC, 0, X, Y) * ia);
           T f[NCOEF];
 #pragma unroll
           for (int q = 0; q < NCOEF; ++q) f[q] = (l0 * CC.coef[q] + l1 * CC.coef[NCOEF + q]) + l2 * CC.coef[2 * NCOEF + q];
@@ -692,9 +710,9 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
             yn = (y + v * a.dt) + a.s2nu * dW2;
             // the walk's first test: is the end point still in the element?
             const double Tx = (double)xn, Ty = (double)yn;
-            const double o0 = orient_edge(ax, ay, bx, by, Tx, Ty);
-            const double o1 = orient_edge(bx, by, cx, cy, Tx, Ty);
-            const double o2 = orient_edge(cx, cy, ax, ay, Tx, Ty);
+            const double o0 = orient_cc(CC, 0, Tx, Ty);
+            const double o1 = orient_cc(CC, 1, Tx, Ty);
+            const double o2 = orient_cc(CC, 2, Tx, Ty);
             if (!(o0 >= 0.0 && o1 >= 0.0 && o2 >= 0.0)) {
               // it left: the rest of the walk, with walls and periodic edges
               const int e2 = walk<T>(a, a.erec[e], e, X, Y, xn, yn, un, vn, wn);
