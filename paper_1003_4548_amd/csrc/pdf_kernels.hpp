@@ -99,6 +99,7 @@ template <typename T> struct StepArgs {
   const int32_t* tri;     // ne x 3
   const double* inv2a;    // ne
   const double* alpha;    // ne x 3
+  const double* wnorm;    // ne x 3 x 2: outward unit normal of each element edge
   double Lx, Ly;
   int32_t ne;
   int32_t ncell;
@@ -196,15 +197,20 @@ __device__ __forceinline__ int slot_of(int j, int start, int ns, int nm, int cap
 // about the wall line and reflect the velocity; periodic edges shift the path
 // by one period into the partner element.  R holds the record of element e.
 
+// (f0, f1, f2): the target's orientations against the edges of element e,
+// known to the caller for the first iteration.
 template <typename T>
 __device__ int walk(const StepArgs<T>& a, ERec R, int e, double Sx, double Sy, T& tx, T& ty, T& u, T& v,
-                    T& w) {
+                    T& w, double f0, double f1, double f2) {
 #pragma unroll 1
   for (int it = 0; it < 64; ++it) {
     const double Tx = (double)tx, Ty = (double)ty;
-    const double o0 = orient_edge(R.x[0], R.y[0], R.x[1], R.y[1], Tx, Ty);
-    const double o1 = orient_edge(R.x[1], R.y[1], R.x[2], R.y[2], Tx, Ty);
-    const double o2 = orient_edge(R.x[2], R.y[2], R.x[0], R.y[0], Tx, Ty);
+    double o0 = f0, o1 = f1, o2 = f2;
+    if (it > 0) {
+      o0 = orient_edge(R.x[0], R.y[0], R.x[1], R.y[1], Tx, Ty);
+      o1 = orient_edge(R.x[1], R.y[1], R.x[2], R.y[2], Tx, Ty);
+      o2 = orient_edge(R.x[2], R.y[2], R.x[0], R.y[0], Tx, Ty);
+    }
     if (o0 >= 0.0 && o1 >= 0.0 && o2 >= 0.0) return e;
     int ex = -1;
     const int nneg = (o0 < 0.0 ? 1 : 0) + (o1 < 0.0 ? 1 : 0) + (o2 < 0.0 ? 1 : 0);
@@ -254,9 +260,8 @@ __device__ int walk(const StepArgs<T>& a, ERec R, int e, double Sx, double Sy, T
     const int ex1 = ex == 2 ? 0 : ex + 1;
     const double ax = pick3(R.x, ex), ay = pick3(R.y, ex);
     const double bx = pick3(R.x, ex1), by = pick3(R.y, ex1);
-    const double gx = bx - ax, gy = by - ay;
-    const double len = sqrt(gx * gx + gy * gy);
-    const double nx = gy / len, ny = -gx / len;  // outward unit normal
+    // outward unit normal (g_y, -g_x) / |g| of the edge g = b - a, precomputed
+    const double nx = a.wnorm[6 * e + 2 * ex], ny = a.wnorm[6 * e + 2 * ex + 1];
     const double oS = orient_edge(ax, ay, bx, by, Sx, Sy);
     const double oT = ex == 0 ? o0 : (ex == 1 ? o1 : o2);
     const double den = oS - oT;
@@ -715,7 +720,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
             const double o2 = orient_cc(CC, 2, Tx, Ty);
             if (!(o0 >= 0.0 && o1 >= 0.0 && o2 >= 0.0)) {
               // it left: the rest of the walk, with walls and periodic edges
-              const int e2 = walk<T>(a, a.erec[e], e, X, Y, xn, yn, un, vn, wn);
+              const int e2 = walk<T>(a, a.erec[e], e, X, Y, xn, yn, un, vn, wn, o0, o1, o2);
               if (e2 != e) {
                 moved = true;
                 if (e2 < 0) {
@@ -898,6 +903,18 @@ __global__ void k_erec(const double* vtx, const int32_t* tri, const int32_t* nbr
   }
   r.pad = 0;
   erec[e] = r;
+}
+
+// Outward unit normal of every element edge: g = v_k+1 - v_k, n = (g_y, -g_x) / |g|.
+__global__ void k_wnorm(const double* vtx, const int32_t* tri, double* wn, int ne) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 3 * ne) return;
+  const int e = i / 3, k = i - 3 * e, k1 = k == 2 ? 0 : k + 1;
+  const int va = tri[3 * e + k], vb = tri[3 * e + k1];
+  const double gx = vtx[2 * vb] - vtx[2 * va], gy = vtx[2 * vb + 1] - vtx[2 * va + 1];
+  const double len = sqrt(gx * gx + gy * gy);
+  wn[2 * i] = gy / len;
+  wn[2 * i + 1] = -gx / len;
 }
 
 // Initial particles: uniform in the element, velocity = local mean plus the

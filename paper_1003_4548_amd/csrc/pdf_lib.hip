@@ -24,7 +24,7 @@ int64_t align_up(int64_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
 // Byte offsets of the arena sections.
 struct Layout {
-  int64_t vtx, tri, nbr, ekind, inv2a, alpha, fields, coef, erec;
+  int64_t vtx, tri, nbr, ekind, inv2a, alpha, wnorm, fields, coef, erec;
   int64_t start, cap, cap0, nstart, ncap, ns[3], nm[3], rate, idoff, order, seed, src;
   int64_t buf0, buf1, ovf, ovf_cell, stats, ctl, flag;
   int64_t total;
@@ -43,6 +43,7 @@ Layout make_layout(int32_t nv, int32_t ne, int32_t nens, int64_t slots, int32_t 
   L.ekind = take((int64_t)ne * 3 * 4);
   L.inv2a = take((int64_t)ne * 8);
   L.alpha = take((int64_t)ne * 3 * 8);
+  L.wnorm = take((int64_t)ne * 6 * 8);
   L.fields = take((int64_t)nv * NFIELD * 8);
   L.coef = take((int64_t)nv * NCOEF * tsize);
   L.erec = take((int64_t)ne * (int64_t)sizeof(ERec));
@@ -169,6 +170,7 @@ template <typename T> StepArgs<T> step_args(pdf_ctx* c) {
   s.tri = (const int32_t*)(a + L.tri);
   s.inv2a = (const double*)(a + L.inv2a);
   s.alpha = (const double*)(a + L.alpha);
+  s.wnorm = (const double*)(a + L.wnorm);
   s.ne = c->ne;
   s.Lx = c->p.Lx;
   s.Ly = c->p.Ly;
@@ -514,6 +516,8 @@ pdf_status pdf_init_mesh(pdf_ctx* c, const pdf_mesh* m, void* arena, int64_t are
   const int tb = 256;
   hipLaunchKernelGGL(k_inv2a, dim3((c->ne + tb - 1) / tb), dim3(tb), 0, st, (const double*)(c->arena + L.vtx),
                      (const int32_t*)(c->arena + L.tri), (double*)(c->arena + L.inv2a), flag, c->ne);
+  hipLaunchKernelGGL(k_wnorm, dim3((3 * c->ne + tb - 1) / tb), dim3(tb), 0, st, (const double*)(c->arena + L.vtx),
+                     (const int32_t*)(c->arena + L.tri), (double*)(c->arena + L.wnorm), c->ne);
   hipLaunchKernelGGL(k_erec, dim3((c->ne + tb - 1) / tb), dim3(tb), 0, st, (const double*)(c->arena + L.vtx),
                      (const int32_t*)(c->arena + L.tri), (const int32_t*)(c->arena + L.nbr),
                      (const int32_t*)(c->arena + L.ekind), (ERec*)(c->arena + L.erec), c->ne);
