@@ -296,3 +296,86 @@ def test_repack_is_idle_with_room(gpu):
     sim.step(12)
     sim.sync()
     assert sim.repacks() == 0
+
+
+def test_config3_full_size_parity(gpu):
+    """The 10M-particle wall-function canyon (moments to 4th order, histograms)
+    at the benchmark's tuned launch shape: whole trajectories bit-exact, the
+    statistics of the GPU state against the oracle's."""
+    wl = W.config3(steps=2)
+    _label(wl, "full size")
+    sim = gpu.Simulation.from_workload(wl)
+    shape = sim.autotune(steps_per_trial=1)
+    print(f"[case] tuned shape {shape}", flush=True)
+    sim.step(2)
+    sim.sync()
+    orc = O.Oracle(wl)
+    orc.step(sim.steps_done())
+    g = sim.state()
+    assert_state_parity(g, orc.state(), what="config3")
+    orc.set_state(g)
+    assert_stats_parity(sim.statistics()[0], orc.stats(), wl.moments, wl.hist_bins, what="config3 stats")
+
+
+def test_config4_full_size_parity(gpu):
+    """64 batched ensembles of uneven size (12M particles) at the tuned shape:
+    every ensemble bit-exact, each one as if run alone."""
+    wl = W.config4(steps=2)
+    _label(wl, "full size")
+    sim = gpu.Simulation.from_workload(wl)
+    shape = sim.autotune(steps_per_trial=1)
+    print(f"[case] tuned shape {shape}", flush=True)
+    sim.step(2)
+    sim.sync()
+    orc = O.Oracle(wl)
+    orc.step(sim.steps_done())
+    sg = sim.statistics()
+    for en in range(wl.nens):
+        assert_state_parity(sim.state(en), orc.state(en), what=f"config4 ens {en}")
+    for en in (0, 17, 63):
+        orc_one = O.Oracle(wl, ensembles=[wl.ensembles[en]])
+        orc_one.set_state(sim.state(en))
+        assert_stats_parity(sg[en], orc_one.stats(), wl.moments, wl.hist_bins, what=f"config4 stats ens {en}")
+
+
+def test_empty_ensemble_and_empty_cells(gpu):
+    """An ensemble with no particles at all next to a normal one."""
+    wl = W.tiny_canyon(precision="f32", nens=2, steps=5)
+    wl.ensembles[1].counts = np.zeros_like(wl.ensembles[1].counts)
+    _label(wl, "empty ensemble")
+    sim = gpu.Simulation.from_workload(wl)
+    orc = O.Oracle(wl)
+    sim.step(5)
+    orc.step(5)
+    sim.sync()
+    assert sim.count(1) == 0
+    assert_state_parity(sim.state(0), orc.state(0), what="non-empty ensemble")
+    sg = sim.statistics()
+    assert not sg[1].any()
+    assert_stats_parity(sg[0], orc.stats(0), wl.moments, wl.hist_bins, what="non-empty ensemble")
+
+
+def test_host_rejects_bad_input(gpu):
+    """Argument and mesh errors come back as status codes, before any kernel
+    touches the data."""
+    wl = W.tiny_canyon(precision="f32", steps=1)
+    # clockwise element
+    tri = wl.mesh.tri.copy()
+    tri[0] = tri[0][::-1]
+    with pytest.raises(gpu.PdfError) as ex:
+        gpu.Simulation.from_workload(wl, tri=tri)
+    assert ex.value.code == -2
+    # a vertex id out of range
+    tri = wl.mesh.tri.copy()
+    tri[3, 1] = wl.mesh.nvert + 5
+    with pytest.raises(gpu.PdfError) as ex:
+        gpu.Simulation.from_workload(wl, tri=tri)
+    assert ex.value.code == -2
+    # unsupported statistics shape
+    with pytest.raises(gpu.PdfError) as ex:
+        gpu.Simulation.from_workload(wl, moments=3)
+    assert ex.value.code == -1
+    sim = gpu.Simulation.from_workload(wl)
+    with pytest.raises(gpu.PdfError) as ex:
+        sim.set_launch(48, 0)
+    assert ex.value.code == -1
