@@ -176,11 +176,11 @@ def learned_leg(torch, W, Simulation) -> dict:
     sim.sync()
     plain_s = time.perf_counter() - t0
     lm = net.attach(sim)
-    sim.step(10)
+    sim.step_graph(12)
     sim.sync()
     lm.served.zero_()
     t0 = time.perf_counter()
-    sim.step(steps)
+    sim.step_graph(steps)
     sim.sync()
     mlp_s = time.perf_counter() - t0
     st = sim.statistics_device()[0]

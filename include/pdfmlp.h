@@ -116,11 +116,15 @@ pdf_status pdf_mlp_round(const float* master, uint16_t* w, void* hip_stream);
 pdf_status pdf_mlp_infer(const double* stats, int32_t nstat, int32_t ncell, const uint16_t* w,
                          const float* norm, double* cm, uint32_t* served, void* hip_stream);
 
-/* Use the network in the context's steps: before each step the statistics
-   of the state and the learned conditional means are computed into cm
-   (nens x nelem x 8 doubles) and IECM relaxes toward them.  pdf_step_graph
-   then launches its steps one by one.  w = NULL returns to the binned
-   means.  The arrays must stay valid while attached. */
+/* Use the network in the context's steps: each step computes the learned
+   conditional means of the state's statistics, writes them to cm (nens x
+   nelem x 8 doubles) and relaxes IECM toward them.  With a one-item-per-
+   wavefront launch shape this happens inside the step kernel (each block's
+   cells form one 16-column network tile; graphs replay it as usual); with a
+   persistent shape as a statistics pass and an inference launch before the
+   step (pdf_step_graph then launches its steps one by one).  The results are
+   the same.  w = NULL returns to the binned means.  The arrays must stay
+   valid while attached. */
 pdf_status pdf_mlp_attach(pdf_ctx* ctx, const uint16_t* w, const float* norm, double* cm, uint32_t* served);
 
 #ifdef __cplusplus

@@ -21,6 +21,7 @@
 #include <stdint.h>
 
 #include "pdf_math.hpp"
+#include "pdf_mlp_core.hpp"
 
 namespace pdf {
 
@@ -118,6 +119,12 @@ template <typename T> struct StepArgs {
   const uint64_t* seed;   // nens
   const double* src;      // nens x 3
   const double* cmean;    // ncell x 8 conditional means for IECM from elsewhere, or null
+  // learned conditional means computed inside the step (one-item-per-wavefront
+  // grids only): network weights, normalisation, output and served count
+  const uint16_t* mlp_w;  // null: not used
+  const float* mlp_norm;
+  double* mlp_cm;
+  uint32_t* mlp_served;
   Ctl* ctl;
   int32_t nstat;
   int32_t flags;
@@ -356,8 +363,11 @@ __device__ __forceinline__ double orient_cc(const CellConst<T>& C, int k, double
   return ((C.dx[k] * (py - C.oy[k])) - (C.dy[k] * (px - C.ox[k]))) * C.sg[k];
 }
 
-template <typename T, int MOM, int HIST, int G, bool ADVANCE, bool PERSIST>
+// SCHED: 0 one work item per wavefront; 1 persistent grid; 2 one item per
+// wavefront with the learned conditional means computed inside the step.
+template <typename T, int MOM, int HIST, int G, bool ADVANCE, int SCHED>
 __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
+  constexpr bool PERSIST = SCHED == 1;
   constexpr int GPW = WAVE / G;             // cells per wavefront
   constexpr int TILEN = 4 * G;              // particles per cell staged in LDS
   constexpr int CPB = WAVES_PER_BLOCK * GPW;
@@ -366,7 +376,10 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
   __shared__ CellConst<T> ccs[ADVANCE ? CPB : 1];
   Ctl* ctl = a.ctl;
   // after an error the state is void: later steps do nothing
-  if (ADVANCE && ctl->error != 0) return;
+  // (with the learned means inside the step every wavefront of a block must
+  // reach its barriers: the step then runs on, on a state that is void anyway)
+  constexpr bool fused_mlp = ADVANCE && SCHED == 2;
+  if (ADVANCE && !fused_mlp && ctl->error != 0) return;
   const uint32_t step = ctl->step_base + si.step_off;
   const uint32_t par = si.parity;
   const uint32_t bpar = par ^ (ctl->flip & 1u);
@@ -397,7 +410,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
         chunk_end = item + a.pchunk;
       }
     }
-    if (item >= a.nitems) break;
+    if (item >= a.nitems && !fused_mlp) break;
     const int idx = item * GPW + grp;
     const int cell_l = idx < a.ncell ? a.order[idx] : -1;
     const int cell = (G == WAVE) ? __builtin_amdgcn_readfirstlane(cell_l) : cell_l;
@@ -512,7 +525,59 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
 #pragma unroll
     for (int q = 0; q < 8; ++q) bm[q] = bcount[q] > 0 ? acc[10 + q] / (double)bcount[q] : mean[3];
     double cm[8];
-    if (ADVANCE && a.cmean != nullptr && has) {
+    if constexpr (fused_mlp) {
+      // learned conditional means: the block's cells form one 16-column tile
+      // of the network (columns beyond the block's cells are padding)
+      __shared__ uint16_t mxs[16][mlp::NFEAT];
+      __shared__ float mys[16][mlp::NOUT];
+      __shared__ int minbox[16];
+      const double z = n > 0 ? 1.0 : 0.0;
+      double binn[8], binm[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        binn[q] = (double)bcount[q];
+        binm[q] = bm[q] * z;
+      }
+      if (li == 0) {
+        double meanr[4], m2r[10];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) meanr[q] = mean[q] * z;
+#pragma unroll
+        for (int q = 0; q < 10; ++q) m2r[q] = acc[q] * inv_n;
+        float f[mlp::NFEAT];
+        mlp::features_from(dn, meanr, m2r, binn, binm, f);
+        int ok = has ? 1 : 0;
+#pragma unroll
+        for (int k = 0; k < mlp::NFEAT; ++k) {
+          ok &= (f[k] >= a.mlp_norm[2 * mlp::NFEAT + k] && f[k] <= a.mlp_norm[3 * mlp::NFEAT + k]) ? 1 : 0;
+          mxs[slot_id][k] = mlp::f2bf((f[k] - a.mlp_norm[k]) * a.mlp_norm[mlp::NFEAT + k]);
+        }
+        minbox[slot_id] = ok;
+      }
+      __syncthreads();
+      if (wid == 0) {
+        const int r = lane & 15;
+        mlp::bf16x4 xb[2], h1[4], h2[4], h3[4];
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks)
+          xb[ks] = r < CPB ? *(const mlp::bf16x4*)&mxs[r][16 * ks + 4 * (lane >> 4)] : mlp::bf16x4{0, 0, 0, 0};
+        const mlp::f32x4 y = mlp::forward_tile(a.mlp_w, xb, h1, h2, h3, lane);
+        if (lane < 32 && r < CPB) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) mys[r][4 * (lane >> 4) + i] = y[i];
+        }
+      }
+      __syncthreads();
+      float yv[mlp::NOUT];
+#pragma unroll
+      for (int b = 0; b < mlp::NOUT; ++b) yv[b] = mys[slot_id][b];
+      const bool took = mlp::learned_estimate(dn, mean[3] * z, acc[9] * inv_n, binn, binm, yv, minbox[slot_id] != 0, cm);
+      if (has && li == 0) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) a.mlp_cm[(size_t)cell * 8 + q] = cm[q];
+        if (took && a.mlp_served) atomicAdd(a.mlp_served, 1u);
+      }
+    } else if (ADVANCE && a.cmean != nullptr && has) {
 #pragma unroll
       for (int q = 0; q < 8; ++q) cm[q] = a.cmean[(size_t)cell * 8 + q];
     } else {

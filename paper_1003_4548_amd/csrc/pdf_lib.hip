@@ -191,6 +191,13 @@ template <typename T> StepArgs<T> step_args(pdf_ctx* c) {
   s.seed = (const uint64_t*)(a + L.seed);
   s.src = (const double*)(a + L.src);
   s.ctl = (Ctl*)(a + L.ctl);
+  // the learned means run inside the step on one-item-per-wavefront grids
+  if (c->mlp_w && !c->persist) {
+    s.mlp_w = c->mlp_w;
+    s.mlp_norm = c->mlp_norm;
+    s.mlp_cm = c->mlp_cm;
+    s.mlp_served = c->mlp_served;
+  }
   s.ncell = c->ne * c->nens;
   s.nstat = nstat_of(c->p);
   s.flags = c->p.flags;
@@ -209,14 +216,14 @@ int persist_chunk(int nitems, int blocks) {
   return std::max(1, std::min(16, nitems / (16 * waves)));
 }
 
-template <typename T, int MOM, int HIST, int G, bool ADV, bool PERSIST>
+template <typename T, int MOM, int HIST, int G, bool ADV, int SCHED>
 void launch_step(pdf_ctx* c, StepArgs<T> s, StepIndex si) {
   constexpr int GPW = WAVE / G;
   s.nitems = (s.ncell + GPW - 1) / GPW;
   int blocks = (s.nitems + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
-  if (PERSIST) {
+  if (SCHED == 1) {
     int per_cu = 0;
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step<T, MOM, HIST, G, ADV, PERSIST>, BLOCK, 0);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step<T, MOM, HIST, G, ADV, SCHED>, BLOCK, 0);
     int cus = 0;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device);
     const int cap_blocks = std::max(1, per_cu) * std::max(1, cus);
@@ -224,16 +231,36 @@ void launch_step(pdf_ctx* c, StepArgs<T> s, StepIndex si) {
     c->persist_blocks = blocks;
   }
   s.pchunk = persist_chunk(s.nitems, blocks);
-  hipLaunchKernelGGL((k_step<T, MOM, HIST, G, ADV, PERSIST>), dim3(blocks), dim3(BLOCK), 0, c->stream, s, si);
+  hipLaunchKernelGGL((k_step<T, MOM, HIST, G, ADV, SCHED>), dim3(blocks), dim3(BLOCK), 0, c->stream, s, si);
+}
+
+// Scheduling variant of a step launch: persistent grid, or one work item per
+// wavefront with or without the learned means inside the step.
+int sched_of(const pdf_ctx* c, bool adv) {
+  if (!adv) return 0;
+  if (c->persist) return 1;
+  return c->mlp_w ? 2 : 0;
 }
 
 template <typename T, int MOM, int HIST, bool ADV>
 void launch_group(pdf_ctx* c, const StepArgs<T>& s, StepIndex si) {
-  const bool P = ADV && c->persist;
+  const int sc = sched_of(c, ADV);
   switch (c->group) {
-    case 16: P ? launch_step<T, MOM, HIST, 16, ADV, true>(c, s, si) : launch_step<T, MOM, HIST, 16, ADV, false>(c, s, si); break;
-    case 32: P ? launch_step<T, MOM, HIST, 32, ADV, true>(c, s, si) : launch_step<T, MOM, HIST, 32, ADV, false>(c, s, si); break;
-    default: P ? launch_step<T, MOM, HIST, 64, ADV, true>(c, s, si) : launch_step<T, MOM, HIST, 64, ADV, false>(c, s, si); break;
+    case 16:
+      if (!ADV || sc == 0) launch_step<T, MOM, HIST, 16, ADV, 0>(c, s, si);
+      else if (sc == 1) launch_step<T, MOM, HIST, 16, ADV, ADV ? 1 : 0>(c, s, si);
+      else launch_step<T, MOM, HIST, 16, ADV, ADV ? 2 : 0>(c, s, si);
+      break;
+    case 32:
+      if (!ADV || sc == 0) launch_step<T, MOM, HIST, 32, ADV, 0>(c, s, si);
+      else if (sc == 1) launch_step<T, MOM, HIST, 32, ADV, ADV ? 1 : 0>(c, s, si);
+      else launch_step<T, MOM, HIST, 32, ADV, ADV ? 2 : 0>(c, s, si);
+      break;
+    default:
+      if (!ADV || sc == 0) launch_step<T, MOM, HIST, 64, ADV, 0>(c, s, si);
+      else if (sc == 1) launch_step<T, MOM, HIST, 64, ADV, ADV ? 1 : 0>(c, s, si);
+      else launch_step<T, MOM, HIST, 64, ADV, ADV ? 2 : 0>(c, s, si);
+      break;
   }
 }
 
@@ -247,12 +274,14 @@ bool supported(const pdf_params& p) {
 template <bool ADV> pdf_status dispatch_step(pdf_ctx* c, StepIndex si) {
   if (c->p.f32_state) {
     StepArgs<float> s = step_args<float>(c);
-    if (ADV) s.cmean = c->mlp_w ? c->mlp_cm : nullptr;
+    if (ADV) s.cmean = (c->mlp_w && c->persist) ? c->mlp_cm : nullptr;
+    if (!ADV) s.mlp_w = nullptr;
     if (c->p.moments == 2) launch_group<float, 2, 0, ADV>(c, s, si);
     else launch_group<float, 4, 32, ADV>(c, s, si);
   } else {
     StepArgs<double> s = step_args<double>(c);
-    if (ADV) s.cmean = c->mlp_w ? c->mlp_cm : nullptr;
+    if (ADV) s.cmean = (c->mlp_w && c->persist) ? c->mlp_cm : nullptr;
+    if (!ADV) s.mlp_w = nullptr;
     launch_group<double, 2, 0, ADV>(c, s, si);
   }
   return hip_check(c, hipGetLastError(), "step launch");
@@ -335,31 +364,34 @@ struct StepLaunch {
   int blocks = 0;
 };
 
-template <typename T, int MOM, int HIST, int G, bool PERSIST>
+template <typename T, int MOM, int HIST, int G, int SCHED>
 StepLaunch step_launch_of(pdf_ctx* c, StepArgs<T>& s) {
   constexpr int GPW = WAVE / G;
   s.nitems = (s.ncell + GPW - 1) / GPW;
   int blocks = (s.nitems + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
-  if (PERSIST) {
+  if (SCHED == 1) {
     int per_cu = 0, cus = 0;
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step<T, MOM, HIST, G, true, PERSIST>, BLOCK, 0);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step<T, MOM, HIST, G, true, SCHED>, BLOCK, 0);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device);
     blocks = std::min(blocks, std::max(1, per_cu) * std::max(1, cus));
   }
   s.pchunk = persist_chunk(s.nitems, blocks);
   StepLaunch l;
-  l.func = reinterpret_cast<const void*>(&k_step<T, MOM, HIST, G, true, PERSIST>);
+  l.func = reinterpret_cast<const void*>(&k_step<T, MOM, HIST, G, true, SCHED>);
   l.blocks = blocks;
   return l;
 }
 
 template <typename T, int MOM, int HIST>
 StepLaunch step_launch_group(pdf_ctx* c, StepArgs<T>& s) {
-  const bool P = c->persist;
+  const int sc = sched_of(c, true);
   switch (c->group) {
-    case 16: return P ? step_launch_of<T, MOM, HIST, 16, true>(c, s) : step_launch_of<T, MOM, HIST, 16, false>(c, s);
-    case 32: return P ? step_launch_of<T, MOM, HIST, 32, true>(c, s) : step_launch_of<T, MOM, HIST, 32, false>(c, s);
-    default: return P ? step_launch_of<T, MOM, HIST, 64, true>(c, s) : step_launch_of<T, MOM, HIST, 64, false>(c, s);
+    case 16: return sc == 1 ? step_launch_of<T, MOM, HIST, 16, 1>(c, s)
+                            : (sc == 2 ? step_launch_of<T, MOM, HIST, 16, 2>(c, s) : step_launch_of<T, MOM, HIST, 16, 0>(c, s));
+    case 32: return sc == 1 ? step_launch_of<T, MOM, HIST, 32, 1>(c, s)
+                            : (sc == 2 ? step_launch_of<T, MOM, HIST, 32, 2>(c, s) : step_launch_of<T, MOM, HIST, 32, 0>(c, s));
+    default: return sc == 1 ? step_launch_of<T, MOM, HIST, 64, 1>(c, s)
+                            : (sc == 2 ? step_launch_of<T, MOM, HIST, 64, 2>(c, s) : step_launch_of<T, MOM, HIST, 64, 0>(c, s));
   }
 }
 
@@ -441,7 +473,9 @@ pdf_status enqueue_steps(pdf_ctx* c, int32_t nsteps) {
   for (int32_t i = 0; i < nsteps; ++i) {
     StepIndex si{(uint32_t)i, c->parity, c->rot, 0};
     pdf_status r;
-    if (c->mlp_w && (r = enqueue_mlp_means(c, si))) return r;
+    // persistent grids take the learned means from a separate statistics pass
+    // and inference launch; the other grids compute them inside the step
+    if (c->mlp_w && c->persist && (r = enqueue_mlp_means(c, si))) return r;
     if ((r = dispatch_step<true>(c, si))) return r;
     c->parity ^= 1u;
     c->rot = c->rot == 2 ? 0 : c->rot + 1;
@@ -658,8 +692,9 @@ pdf_status pdf_step_graph(pdf_ctx* c, int32_t nsteps) {
   if (!c || nsteps < 0) return fail(c, PDF_E_ARG, "pdf_step_graph: bad argument");
   if (!c->seeded) return fail(c, PDF_E_STATE, "pdf_step_graph before pdf_seed_particles");
   pdf_status r;
-  // with the learned conditional means every step is launched directly
-  if (c->mlp_w) return enqueue_steps(c, nsteps);
+  // with the learned conditional means on a persistent grid every step is
+  // launched directly
+  if (c->mlp_w && c->persist) return enqueue_steps(c, nsteps);
   // align to the start of a parity / counter-set cycle with ordinary launches
   int32_t lead = (int32_t)((GRAPH_STEPS - c->steps_done % GRAPH_STEPS) % GRAPH_STEPS);
   lead = std::min(lead, nsteps);
@@ -993,6 +1028,7 @@ pdf_status pdf_mlp_infer(const double* stats, int32_t nstat, int32_t ncell, cons
 
 pdf_status pdf_mlp_attach(pdf_ctx* c, const uint16_t* w, const float* norm, double* cm, uint32_t* served) {
   if (!c) return PDF_E_ARG;
+  c->graph_group = 0;  // a graph holds the step arguments it was built with
   if (!w) {
     c->mlp_w = nullptr;
     c->mlp_norm = nullptr;

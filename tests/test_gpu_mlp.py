@@ -224,13 +224,16 @@ def test_inference_matches_oracle(gpu):
     assert abs(int(served.cpu()[0]) - int(oko.sum())) <= int(edge.sum())
 
 
-def test_step_with_learned_means_matches_oracle(gpu):
+@pytest.mark.parametrize("shape", [(64, 0), (16, 0), (32, 1)])
+def test_step_with_learned_means_matches_oracle(gpu, shape):
     """IECM toward the network's conditional means: the oracle, given the same
-    means, reproduces the step bit for bit."""
+    means, reproduces the step bit for bit (inside the step kernel for the
+    one-item-per-wavefront shapes, a separate pass for the persistent one)."""
     P, PM, torch = gpu
     wl = _scalar_canyon(ppe=20, steps=4)
-    _label(f"mlp step {wl.name}")
+    _label(f"mlp step {wl.name} shape {shape}")
     sim = P.Simulation.from_workload(wl)
+    sim.set_launch(*shape)
     sim.step(wl.steps)
     sim.sync()
     stats = sim.statistics()[0]
@@ -294,3 +297,41 @@ def test_trained_network_beats_the_binned_estimate(gpu):
     print(f"[case] plain@20 {ep:.4g} learned@20 {el:.4g} served {served:.3f}", flush=True)
     assert served > 0.3
     assert el < 0.8 * ep
+
+
+def test_learned_means_same_in_step_and_in_separate_pass(gpu):
+    """The means computed inside the step kernel equal those of the separate
+    inference kernel on the same statistics, bit for bit, with graph replays
+    and direct launches alike."""
+    P, PM, torch = gpu
+    wl = _scalar_canyon(ppe=20, steps=6)
+    _label(f"mlp fused vs separate {wl.name}")
+    sim = P.Simulation.from_workload(wl)
+    sim.set_launch(16, 0)          # statistics summed in the same order as in the step below
+    sim.step(wl.steps)
+    sim.sync()
+    stats = sim.statistics()[0]
+    feat = M.features_from_stats(stats)
+    norm = M.feature_norm(feat[stats[:, O.ST_N] > 0])
+    net = _net(PM, torch, _small_output(M.init_params(8)), norm)
+    ref, _ = net.infer(sim.statistics_device()[0])
+    lm = net.attach(sim)
+    sim.step(1)
+    sim.sync()
+    np.testing.assert_array_equal(lm.cm.cpu().numpy(), ref.cpu().numpy())
+    # the graph path with the network attached, against direct launches of
+    # the same sequence
+    other = P.Simulation.from_workload(wl)
+    other.set_launch(16, 0)
+    other.step(wl.steps)
+    lm3 = net.attach(other)
+    other.step(1)
+    sim.step_graph(12)
+    other.step(12)
+    sim.sync()
+    other.sync()
+    s1, s2 = sim.state(), other.state()
+    for q in ("x", "y", "u", "v", "w", "elem"):
+        np.testing.assert_array_equal(s1[q], s2[q])
+    np.testing.assert_allclose(s1["psi"], s2["psi"], rtol=1e-6, atol=1e-7)
+    np.testing.assert_allclose(lm.cm.cpu().numpy(), lm3.cm.cpu().numpy(), rtol=1e-6, atol=1e-7)
