@@ -168,6 +168,10 @@ def learned_leg(torch, W, Simulation) -> dict:
     # inside the step: 20 particles per element on the 50k-element resolved-wall canyon
     wl = W.config5(ppe=20, seed=101, target=50000)
     sim = Simulation.from_workload(wl, device="cuda:0")
+    in_step_shape = sim.autotune(steps_per_trial=5)
+    if in_step_shape[1]:
+        in_step_shape = (in_step_shape[0], 0)      # the learned means run inside one-item-per-wavefront steps
+        sim.set_launch(*in_step_shape)
     sim.step_graph(spin)
     steps = 200
     sim.sync()
@@ -200,6 +204,7 @@ def learned_leg(torch, W, Simulation) -> dict:
         "train": {"rows": nrows, "iters": iters, "batch": batch, "ms": round(train_ms, 2),
                   "loss_first": float(loss[:20].mean()), "loss_last": float(loss[-200:].mean())},
         "in_step": {"workload": wl.name, "particles": n, "elements": E, "steps": steps,
+                    "lanes_per_cell": in_step_shape[0],
                     "value": round(n * steps / mlp_s, 1), "ms_per_step": round(1e3 * mlp_s / steps, 5),
                     "plain_value": round(n * steps / plain_s, 1),
                     "ppe500_equivalent_value": round(500 * E * steps / mlp_s, 1),

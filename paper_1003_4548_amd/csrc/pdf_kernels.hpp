@@ -555,16 +555,46 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
         minbox[slot_id] = ok;
       }
       __syncthreads();
+      // the 16-column tile: each wavefront computes output tile wid of a
+      // hidden layer (the B operand of k-step wid of the next layer) and
+      // leaves it in LDS; wavefront 0 computes the output layer
+      __shared__ mlp::bf16x4 hb[2][4][WAVE];
+      {
+        const int r = lane & 15;
+        mlp::f32x4 acc = mlp::zero4();
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+          const mlp::bf16x4 xb = r < CPB ? *(const mlp::bf16x4*)&mxs[r][16 * ks + 4 * (lane >> 4)] : mlp::bf16x4{0, 0, 0, 0};
+          acc = mlp::mfma16(mlp::load_w(a.mlp_w + mlp::OFF_W1, mlp::NFEAT, wid, ks, lane), xb, acc);
+        }
+        hb[0][wid][lane] = mlp::bias_relu_bf16(acc, a.mlp_w + mlp::OFF_B1, wid, lane);
+      }
+      __syncthreads();
+      {
+        mlp::f32x4 acc = mlp::zero4();
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks)
+          acc = mlp::mfma16(mlp::load_w(a.mlp_w + mlp::OFF_W2, mlp::NHID, wid, ks, lane), hb[0][ks][lane], acc);
+        hb[1][wid][lane] = mlp::bias_relu_bf16(acc, a.mlp_w + mlp::OFF_B2, wid, lane);
+      }
+      __syncthreads();
+      {
+        mlp::f32x4 acc = mlp::zero4();
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks)
+          acc = mlp::mfma16(mlp::load_w(a.mlp_w + mlp::OFF_W3, mlp::NHID, wid, ks, lane), hb[1][ks][lane], acc);
+        // hb[0] was last read before the previous barrier
+        hb[0][wid][lane] = mlp::bias_relu_bf16(acc, a.mlp_w + mlp::OFF_B3, wid, lane);
+      }
+      __syncthreads();
       if (wid == 0) {
         const int r = lane & 15;
-        mlp::bf16x4 xb[2], h1[4], h2[4], h3[4];
+        mlp::f32x4 y = mlp::zero4();
 #pragma unroll
-        for (int ks = 0; ks < 2; ++ks)
-          xb[ks] = r < CPB ? *(const mlp::bf16x4*)&mxs[r][16 * ks + 4 * (lane >> 4)] : mlp::bf16x4{0, 0, 0, 0};
-        const mlp::f32x4 y = mlp::forward_tile(a.mlp_w, xb, h1, h2, h3, lane);
+        for (int ks = 0; ks < 4; ++ks) y = mlp::mfma16(mlp::load_w4(a.mlp_w + mlp::OFF_W4, ks, lane), hb[0][ks][lane], y);
         if (lane < 32 && r < CPB) {
 #pragma unroll
-          for (int i = 0; i < 4; ++i) mys[r][4 * (lane >> 4) + i] = y[i];
+          for (int i = 0; i < 4; ++i) mys[r][4 * (lane >> 4) + i] = y[i] + mlp::bf2f(a.mlp_w[mlp::OFF_B4 + 4 * (lane >> 4) + i]);
         }
       }
       __syncthreads();
