@@ -62,21 +62,39 @@ def algorithmic_bytes(wl) -> dict:
     return dict(per_particle=per_particle, per_cell=per_cell, per_step=total, particles=n)
 
 
-def read_traffic(workload: str, src_hash: str):
-    """HBM bytes per step from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source."""
-    fn = os.path.join(ROOT, "profiles", f"hbm_traffic_k_step_{workload}.txt")
+def read_profile(kind: str, workload: str, src_hash: str) -> dict:
+    """Figures of a committed rocprofv3 summary ("key value" lines), if it was
+    taken on the current kernel source; {} otherwise."""
+    fn = os.path.join(ROOT, "profiles", f"{kind}_k_step_{workload}.txt")
     if not os.path.exists(fn):
-        return None
+        return {}
     vals = {}
     for line in open(fn):
-        if ":" in line and not line.startswith("#"):
-            k, v = line.split(":", 1)
-            vals[k.strip()] = v.strip()
-    if vals.get("kernel_source_hash") != src_hash:
-        return None
+        if line.startswith("#"):
+            continue
+        parts = line.replace(":", " ").split()
+        if len(parts) == 2:
+            vals[parts[0]] = parts[1]
+    return vals if vals.get("kernel_source_hash") == src_hash else {}
+
+
+def read_traffic(workload: str, src_hash: str):
+    """HBM bytes per step of the step kernel from the calibrated counters."""
     try:
-        return float(vals["hbm_bytes_per_launch"])
+        return float(read_profile("hbm_traffic", workload, src_hash)["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+# VALU issue peak: 256 CUs x 4 SIMDs x 2.4 GHz, one wavefront-instruction
+# (64 lanes on a 16-lane SIMD) every 4 cycles
+VALU_PEAK_WAVE_INSTS = 256 * 4 * 2.4e9 / 4
+
+
+def read_valu(workload: str, src_hash: str):
+    """VALU wavefront-instructions per step of the step kernel (SQ_INSTS_VALU)."""
+    try:
+        return float(read_profile("valu", workload, src_hash)["valu_wave_instructions_per_launch"])
     except (KeyError, ValueError):
         return None
 
@@ -254,6 +272,17 @@ def main() -> int:
 
     autotune_steps = args.autotune_steps
 
+    def valu_issue(name, kern_ms):
+        """The bound the step kernel actually sits at: VALU issue, from the
+        profiled instruction count over the live kernel time."""
+        n = read_valu(name, src_hash)
+        if n is None:
+            return None
+        rate = n / (kern_ms * 1e-3)
+        return {"bound": "alu", "achieved": round(rate / 1e9, 2), "peak": round(VALU_PEAK_WAVE_INSTS / 1e9, 2),
+                "unit": "G VALU wavefront-instructions/s", "frac": round(rate / VALU_PEAK_WAVE_INSTS, 4),
+                "valu_wave_instructions_per_step": n}
+
     def run(name, steps, warmup):
         cfg_fn = getattr(W, WORKLOADS[name][0])
         wl = cfg_fn(steps=steps)
@@ -296,7 +325,8 @@ def main() -> int:
                          "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                          "kernel": "k_step", "kernel_ms": round(kern_ms, 5),
                          "algorithmic_bytes_per_step": ab["per_step"],
-                         "algorithmic_bytes_per_particle": ab["per_particle"]},
+                         "algorithmic_bytes_per_particle": ab["per_particle"],
+                         "valu_issue": valu_issue(name, kern_ms)},
             "config": {"workload": WORKLOADS[name][1], "preset": name, "particles": wl.n_total,
                        "elements": wl.mesh.nelem, "vertices": wl.mesh.nvert, "ensembles": wl.nens,
                        "state_dtype": wl.precision, "statistics_dtype": "f64", "model": wl.describe()["model"],
