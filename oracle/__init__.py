@@ -40,11 +40,13 @@ def build(force: bool = True) -> str:
 class _Params(ctypes.Structure):
     _fields_ = [("f32_state", ctypes.c_int32), ("model", ctypes.c_int32), ("moments", ctypes.c_int32),
                 ("hist_bins", ctypes.c_int32), ("mix", ctypes.c_int32), ("psi_init", ctypes.c_int32),
-                ("flags", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("flags", ctypes.c_int32), ("omega", ctypes.c_int32),
                 ("dt", ctypes.c_double), ("nu", ctypes.c_double), ("C0", ctypes.c_double),
                 ("CT", ctypes.c_double), ("Cs", ctypes.c_double), ("Ct", ctypes.c_double),
                 ("Cmu", ctypes.c_double), ("kappa", ctypes.c_double), ("Ewall", ctypes.c_double),
-                ("yp", ctypes.c_double), ("Lx", ctypes.c_double), ("Ly", ctypes.c_double)]
+                ("yp", ctypes.c_double), ("Lx", ctypes.c_double), ("Ly", ctypes.c_double),
+                ("C3", ctypes.c_double), ("C4", ctypes.c_double), ("Cw1", ctypes.c_double),
+                ("Cw2", ctypes.c_double)]
 
 
 _lib = None
@@ -95,8 +97,15 @@ def lib():
         L.orc_coefficients.argtypes = [vp, vp]
         L.orc_mix_rate.argtypes = [vp, i32, vp]
         L.orc_wall_alpha.argtypes = [vp, vp]
+        L.orc_exp64.restype = d
+        L.orc_exp64.argtypes = [d]
+        L.orc_get_omega.restype = i32
+        L.orc_get_omega.argtypes = [vp, i32, vp]
+        L.orc_set_omega.restype = i32
+        L.orc_set_omega.argtypes = [vp, i32, vp]
+        L.orc_omega_fields.argtypes = [vp, vp, vp, vp]
         L.orc_walk.restype = i32
-        L.orc_walk.argtypes = [vp, i32, d, d, P(d), P(d), vp, P(i32)]
+        L.orc_walk.argtypes = [vp, i32, d, d, P(d), P(d), vp, P(i32), P(d)]
         _lib = L
     return _lib
 
@@ -111,7 +120,9 @@ def params_of(wl) -> _Params:
                    hist_bins=int(wl.hist_bins), mix=1 if wl.mix else 0, psi_init=int(wl.psi_init),
                    flags=int(getattr(wl, 'flags', 15)),
                    dt=wl.dt, nu=wl.nu, C0=wl.C0, CT=c["CT"], Cs=c["Cs"], Ct=c["Ct"], Cmu=c["Cmu"],
-                   kappa=c["kappa"], Ewall=c["Ewall"], yp=wl.yp, Lx=wl.mesh.Lx, Ly=wl.mesh.Ly)
+                   kappa=c["kappa"], Ewall=c["Ewall"], yp=wl.yp, Lx=wl.mesh.Lx, Ly=wl.mesh.Ly,
+                   omega=1 if getattr(wl, "omega", False) else 0, C3=c.get("C3", 5.0),
+                   C4=c.get("C4", 0.25), Cw1=c.get("Cw1", 0.5), Cw2=c.get("Cw2", 0.73))
 
 
 class Oracle:
@@ -178,6 +189,26 @@ class Oracle:
         a["elem"] = np.ascontiguousarray(st["elem"], np.int32)
         lib().orc_set_state(self.ctx, ens, *(_ptr(a[k]) for k in ("x", "y", "u", "v", "w", "psi", "elem")))
 
+    def omega(self, ens: int = 0) -> np.ndarray:
+        """Turbulent frequency per particle, id order."""
+        out = np.zeros(self.count(ens))
+        if lib().orc_get_omega(self.ctx, ens, _ptr(out)) != 0:
+            raise RuntimeError("the workload carries no turbulent frequency")
+        return out
+
+    def set_omega(self, om, ens: int = 0) -> None:
+        a = np.ascontiguousarray(om, np.float64)
+        if lib().orc_set_omega(self.ctx, ens, _ptr(a)) != 0:
+            raise RuntimeError("the workload carries no turbulent frequency")
+
+    def omega_fields(self):
+        """(<omega> at each centroid, S_omega per element, <omega> at each
+        wall-function edge midpoint (nelem x 3, 0 elsewhere))."""
+        ne = self.wl.mesh.nelem
+        om0, sw, omw = np.zeros(ne), np.zeros(ne), np.zeros((ne, 3))
+        lib().orc_omega_fields(self.ctx, _ptr(om0), _ptr(sw), _ptr(omw))
+        return om0, sw, omw
+
     def set_cond_means(self, cm, ens: int = 0) -> None:
         """IECM toward the given conditional means (nelem x 8) instead of the
         binned estimate, until called with None."""
@@ -202,13 +233,18 @@ class Oracle:
         lib().orc_wall_alpha(self.ctx, _ptr(out))
         return out
 
-    def walk(self, e: int, s, t, vel):
+    def walk(self, e: int, s, t, vel, om: Optional[float] = None):
+        """One walk (see orc_walk); with om given, also returns the frequency
+        after the wall conditions."""
         tx = ctypes.c_double(float(t[0]))
         ty = ctypes.c_double(float(t[1]))
         v = np.ascontiguousarray(vel, np.float64).copy()
         nref = ctypes.c_int32(0)
+        o = None if om is None else ctypes.c_double(float(om))
         r = lib().orc_walk(self.ctx, int(e), float(s[0]), float(s[1]), ctypes.byref(tx), ctypes.byref(ty),
-                           _ptr(v), ctypes.byref(nref))
+                           _ptr(v), ctypes.byref(nref), None if o is None else ctypes.byref(o))
+        if o is not None:
+            return r, (tx.value, ty.value), v, nref.value, o.value
         return r, (tx.value, ty.value), v, nref.value
 
 
@@ -234,6 +270,10 @@ def normals_batch(seed: int, n: int, step: int, ens: int, f32: bool) -> np.ndarr
     out = np.zeros((n, 8))
     lib().orc_normals_batch(seed, n, step, ens, 1 if f32 else 0, _ptr(out))
     return out
+
+
+def exp64(x: float) -> float:
+    return lib().orc_exp64(x)
 
 
 def log64(x: float) -> float:

@@ -201,6 +201,7 @@ template <typename T> struct Ens {
   std::vector<int32_t> elem;
   std::vector<double> rate;  // IECM relaxation factor per element, min(dt/t_m, 1)
   std::vector<double> cm;    // conditional means from elsewhere (nelem x 8), empty: binned
+  std::vector<T> om;         // turbulent frequency (when enabled)
 };
 
 }  // namespace
@@ -214,6 +215,9 @@ struct orc_ctx {
   std::vector<double> inv2a;   // 1 / (2 area) per element
   std::vector<double> coef;    // per-vertex coefficient table, double
   std::vector<double> alpha;   // wall-function alpha per element edge
+  std::vector<double> om0;     // frozen <omega> per element (centroid)
+  std::vector<double> somega;  // S_omega per element (centroid), eq. (10)
+  std::vector<double> omw;     // frozen <omega> at wall-function edge midpoints
   std::vector<Ens<float>> ensF;
   std::vector<Ens<double>> ensD;
   int64_t step = 0;
@@ -360,6 +364,57 @@ void build_alpha(orc_ctx* c) {
   }
 }
 
+// exp x = 2^k exp r with k = rint(x / ln 2) and r = x - k ln 2 (ln 2 split in
+// a high part with trailing zero bits and a low part, Cody & Waite), exp r
+// by its Taylor series through r^13 (|r| <= ln 2 / 2) in Horner form.
+double exp_series(double x) {
+  const double LN2_HI = 0x1.62e42fefa3800p-1, LN2_LO = 0x1.ef35793c76730p-45;
+  const double k = std::rint(x * 0x1.71547652b82fep0);
+  const double r = (x - k * LN2_HI) - k * LN2_LO;
+  double fact = 1.0;
+  for (int j = 2; j <= 13; ++j) fact = fact * (double)j;
+  double p = 1.0 / fact;                       // 1/13!
+  for (int j = 12; j >= 1; --j) {
+    fact = fact / (double)(j + 1);             // j!
+    p = p * r + 1.0 / fact;
+  }
+  p = p * r + 1.0;
+  return std::ldexp(p, (int)k);
+}
+
+// Turbulent frequency: per element the frozen <omega> at the centroid (eq. 8
+// solved) and S_omega = C_w2 - C_w1 P / eps (eq. 10) with the production
+// P = -<u_i u_j> d<U_i>/dx_j of the frozen fields at the centroid; per
+// wall-function edge the frozen <omega> at its midpoint (y_p), for eq. (27).
+void build_omega(orc_ctx* c) {
+  const orc_params& p = c->p;
+  c->om0.assign(c->ne, 0.0);
+  c->somega.assign(c->ne, 0.0);
+  c->omw.assign((size_t)c->ne * 3, 0.0);
+  for (int e = 0; e < c->ne; ++e) {
+    int v0 = c->tri[3 * e], v1 = c->tri[3 * e + 1], v2 = c->tri[3 * e + 2];
+    const double* f0 = &c->fields[(size_t)v0 * NF];
+    const double* f1 = &c->fields[(size_t)v1 * NF];
+    const double* f2 = &c->fields[(size_t)v2 * NF];
+    auto cen = [&](int j) { return ((f0[j] + f1[j]) + f2[j]) / 3.0; };
+    double k = 0.5 * ((cen(F_R11) + cen(F_R22)) + cen(F_R33));
+    double eps = cen(F_EPS);
+    double prod = -((cen(F_R11) * cen(F_DUDX) + cen(F_R12) * cen(F_DUDY)) +
+                    (cen(F_R12) * cen(F_DVDX) + cen(F_R22) * cen(F_DVDY)));
+    c->om0[e] = mean_omega(k, eps, p.nu, p.CT);
+    c->somega[e] = p.Cw2 - p.Cw1 * (prod / eps);
+    for (int q = 0; q < 3; ++q) {
+      if (c->ekind[3 * e + q] != ORC_EDGE_WALLFN) continue;
+      int a = c->tri[3 * e + q], b = c->tri[3 * e + (q + 1) % 3];
+      const double* fa = &c->fields[(size_t)a * NF];
+      const double* fb = &c->fields[(size_t)b * NF];
+      double kp = 0.5 * (((fa[F_R11] + fb[F_R11]) / 2.0 + (fa[F_R22] + fb[F_R22]) / 2.0) + (fa[F_R33] + fb[F_R33]) / 2.0);
+      double ep = (fa[F_EPS] + fb[F_EPS]) / 2.0;
+      c->omw[3 * e + q] = mean_omega(kp, ep, p.nu, p.CT);
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // particle tracking (section 2.4: the grid is used to track particles)
 //
@@ -376,7 +431,8 @@ template <typename T> T toward(T x, double dir) {
 }
 
 template <typename T>
-int walk(const orc_ctx* c, int e, double Sx, double Sy, T& tx, T& ty, T& u, T& v, T& w, int* nref) {
+int walk(const orc_ctx* c, int e, double Sx, double Sy, T& tx, T& ty, T& u, T& v, T& w, int* nref,
+         T* om = nullptr) {
   for (int it = 0; it < 64; ++it) {
     double Tx = (double)tx, Ty = (double)ty;
     double o[3];
@@ -454,6 +510,12 @@ int walk(const orc_ctx* c, int e, double Sx, double Sy, T& tx, T& ty, T& u, T& v
       T Vr = -Vi;
       u = Ur * tX + Vr * (-nxT);
       v = Ur * tY + Vr * (-nyT);
+      // turbulent frequency, eqs. (27)-(28): omega_R = omega_I exp(beta V_I / (y_p <omega>))
+      if (om) {
+        const double beta = -2.0 / ((((0.5 + 0.75 * c->p.C0) + c->p.C3) + c->p.Cw2) - c->p.Cw1);
+        const double arg = beta * (double)Vi / (c->p.yp * c->omw[3 * e + ex]);
+        *om = (T)((double)(*om) * exp_series(arg));
+      }
     }
     if (nref) ++(*nref);
   }
@@ -468,6 +530,7 @@ template <typename T> void seed_ensemble(orc_ctx* c, Ens<T>& en, uint32_t ens_in
   int64_t n = 0;
   for (int e = 0; e < c->ne; ++e) n += en.counts[e];
   en.x.assign(n, 0); en.y.assign(n, 0); en.u.assign(n, 0); en.v.assign(n, 0);
+  if (c->p.omega) en.om.assign(n, 0);
   en.w.assign(n, 0); en.psi.assign(n, 0); en.elem.assign(n, 0);
   uint32_t key[2] = {(uint32_t)en.seed, (uint32_t)(en.seed >> 32)};
   int64_t id = 0;
@@ -522,6 +585,7 @@ template <typename T> void seed_ensemble(orc_ctx* c, Ens<T>& en, uint32_t ens_in
       en.v[id] = (T)(V + (L21 * z0 + L22 * z1));
       en.w[id] = (T)(L33 * z2);
       en.psi[id] = (T)((c->p.psi_init == 1 && (double)tx < 0.25) ? 1.0 : 0.0);
+      if (c->p.omega) en.om[id] = (T)c->om0[e];
       en.elem[id] = e;
     }
   }
@@ -535,7 +599,7 @@ template <typename T> void seed_ensemble(orc_ctx* c, Ens<T>& en, uint32_t ens_in
 // element's particles in particle-id order.
 
 int nstat_of(const orc_params& p) {
-  return (p.moments >= 4 ? ORC_NSTAT_4 : ORC_NSTAT_2) + p.hist_bins;
+  return (p.moments >= 4 ? ORC_NSTAT_4 : ORC_NSTAT_2) + p.hist_bins + (p.omega ? 3 : 0);
 }
 
 template <typename T> void estimate(const orc_ctx* c, const Ens<T>& en, std::vector<double>& st) {
@@ -576,6 +640,18 @@ template <typename T> void estimate(const orc_ctx* c, const Ens<T>& en, std::vec
     }
     double mean[4];
     for (int q = 0; q < 4; ++q) mean[q] = sum[q] / (double)cnt;
+    // turbulent frequency: mean and variance; eps from <omega> by eq. (8)
+    double om_mean = 0.0, om_var = 0.0;
+    if (p.omega) {
+      double so = 0.0;
+      for (int64_t j = start[e]; j < start[e + 1]; ++j) so += (double)en.om[list[j]];
+      om_mean = so / (double)cnt;
+      for (int64_t j = start[e]; j < start[e + 1]; ++j) {
+        double d = (double)en.om[list[j]] - om_mean;
+        om_var += d * d;
+      }
+      om_var = om_var / (double)cnt;
+    }
     double m2[10] = {0}, m3[20] = {0}, m4[35] = {0};
     double binn[8] = {0}, bins[8] = {0};
     std::vector<double> hist(p.hist_bins, 0.0);
@@ -617,6 +693,13 @@ template <typename T> void estimate(const orc_ctx* c, const Ens<T>& en, std::vec
       off = ORC_NSTAT_4;
     }
     for (int h = 0; h < p.hist_bins; ++h) s[off + h] = hist[h];
+    if (p.omega) {
+      double* so = s + off + p.hist_bins;
+      double kh = 0.5 * ((s[ORC_ST_M2 + 0] + s[ORC_ST_M2 + 4]) + s[ORC_ST_M2 + 7]);
+      so[0] = om_mean;
+      so[1] = om_var;
+      so[2] = om_mean * (kh + (p.nu * (p.CT * p.CT)) * om_mean);
+    }
   }
 }
 
@@ -674,12 +757,25 @@ template <typename T> int advance(orc_ctx* c, Ens<T>& en, uint32_t ens_index, ui
     if (!(p.flags & 1)) {
       un = u; vn = v; wn = w;
     }
+    // turbulent frequency, eq. (9), with <omega> the element's estimate and the
+    // sixth normal; Euler-Maruyama, reflected at zero (part of sub-step 1)
+    T omn = p.omega ? en.om[i] : (T)0;
+    if (p.omega && (p.flags & 1)) {
+      const double* s = &st[(size_t)e * ns];
+      const T om = en.om[i];
+      const T mw = (T)s[ns - 3];
+      const T c3 = (T)p.C3, c34 = (T)(2.0 * p.C3 * p.C4), sw = (T)c->somega[e];
+      const T drift = (c3 * mw) * (om - mw) + (sw * mw) * om;
+      const T diff = std::sqrt((c34 * (mw * mw)) * om);
+      omn = (om - drift * dt) + diff * (sdt * xi[5]);
+      omn = std::fabs(omn);
+    }
     // position, eq. (5), with the velocity at the start of the step
     T xn = (x + u * dt) + s2nu * dW1;
     T yn = (y + v * dt) + s2nu * dW2;
     int e2 = e;
     if (p.flags & 2) {
-      e2 = walk<T>(c, e, (double)x, (double)y, xn, yn, un, vn, wn, nullptr);
+      e2 = walk<T>(c, e, (double)x, (double)y, xn, yn, un, vn, wn, nullptr, p.omega ? &omn : nullptr);
       if (e2 < 0) {
         lost += 1;
         continue;
@@ -693,6 +789,7 @@ template <typename T> int advance(orc_ctx* c, Ens<T>& en, uint32_t ens_index, ui
       if (dx * dx + dy * dy <= en.r0 * en.r0) psi = (T)1;
     }
     en.x[i] = xn; en.y[i] = yn; en.u[i] = un; en.v[i] = vn; en.w[i] = wn; en.psi[i] = psi;
+    if (p.omega) en.om[i] = omn;
     en.elem[i] = e2;
   }
   return lost ? -5 : 0;
@@ -727,6 +824,13 @@ void set_state_t(Ens<T>& en, const double* x, const double* y, const double* u,
   }
 }
 
+template <typename T> void get_om_t(const Ens<T>& en, double* om) {
+  for (size_t i = 0; i < en.om.size(); ++i) om[i] = (double)en.om[i];
+}
+template <typename T> void set_om_t(Ens<T>& en, const double* om) {
+  for (size_t i = 0; i < en.om.size(); ++i) en.om[i] = (T)om[i];
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -759,6 +863,7 @@ orc_ctx* orc_create(const orc_params* p, int32_t nvert, const double* vtx, int32
   }
   build_coefficients(c);
   build_alpha(c);
+  build_omega(c);
   return c;
 }
 
@@ -818,6 +923,30 @@ int32_t orc_set_state(orc_ctx* c, int32_t ens, const double* x, const double* y,
   if (c->p.f32_state) set_state_t<float>(c->ensF[ens], x, y, u, v, w, psi, elem);
   else set_state_t<double>(c->ensD[ens], x, y, u, v, w, psi, elem);
   return 0;
+}
+
+double orc_exp64(double x) { return exp_series(x); }
+
+int32_t orc_get_omega(const orc_ctx* c, int32_t ens, double* om) {
+  if (!c->p.omega) return -1;
+  if (c->p.f32_state) get_om_t<float>(c->ensF[ens], om);
+  else get_om_t<double>(c->ensD[ens], om);
+  return 0;
+}
+
+int32_t orc_set_omega(orc_ctx* c, int32_t ens, const double* om) {
+  if (!c->p.omega) return -1;
+  if (c->p.f32_state) set_om_t<float>(c->ensF[ens], om);
+  else set_om_t<double>(c->ensD[ens], om);
+  return 0;
+}
+
+void orc_omega_fields(const orc_ctx* c, double* om0, double* somega, double* omw) {
+  for (int e = 0; e < c->ne; ++e) {
+    om0[e] = c->om0[e];
+    somega[e] = c->somega[e];
+    for (int q = 0; q < 3; ++q) omw[3 * e + q] = c->omw[3 * e + q];
+  }
 }
 
 void orc_set_cond_means(orc_ctx* c, int32_t ens, const double* cm) {
@@ -883,17 +1012,21 @@ void orc_wall_alpha(const orc_ctx* c, double* out) {
 }
 
 int32_t orc_walk(const orc_ctx* c, int32_t e, double sx, double sy, double* tx, double* ty,
-                 double* vel, int32_t* n_reflect) {
+                 double* vel, int32_t* n_reflect, double* om) {
   int nref = 0;
   int r;
   if (c->p.f32_state) {
     float X = (float)*tx, Y = (float)*ty, u = (float)vel[0], v = (float)vel[1], w = (float)vel[2];
-    r = walk<float>(c, e, sx, sy, X, Y, u, v, w, &nref);
+    float o = om ? (float)*om : 0.0f;
+    r = walk<float>(c, e, sx, sy, X, Y, u, v, w, &nref, om ? &o : nullptr);
     *tx = X; *ty = Y; vel[0] = u; vel[1] = v; vel[2] = w;
+    if (om) *om = o;
   } else {
     double X = *tx, Y = *ty, u = vel[0], v = vel[1], w = vel[2];
-    r = walk<double>(c, e, sx, sy, X, Y, u, v, w, &nref);
+    double o = om ? *om : 0.0;
+    r = walk<double>(c, e, sx, sy, X, Y, u, v, w, &nref, om ? &o : nullptr);
     *tx = X; *ty = Y; vel[0] = u; vel[1] = v; vel[2] = w;
+    if (om) *om = o;
   }
   if (n_reflect) *n_reflect = nref;
   return r;

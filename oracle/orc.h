@@ -53,11 +53,12 @@ typedef struct orc_params {
   int32_t mix;         /* IECM on */
   int32_t psi_init;    /* 0 zero, 1 psi=1 for x<0.25 */
   int32_t flags;       /* sub-steps: 1 velocity, 2 position and tracking, 4 IECM, 8 source */
-  int32_t pad_;
+  int32_t omega;       /* 1: stochastic turbulent frequency per particle, eqs. (9)-(10), (27)-(28) */
   double dt, nu, C0;   /* time step, viscosity, SLM constant */
   double CT, Cs, Ct;   /* Table 2 */
   double Cmu, kappa, Ewall, yp;  /* wall functions */
   double Lx, Ly;       /* periodic lengths */
+  double C3, C4, Cw1, Cw2;  /* Table 2: turbulent frequency model */
 } orc_params;
 
 typedef struct orc_ctx orc_ctx;
@@ -82,6 +83,18 @@ int32_t orc_get_state(const orc_ctx* c, int32_t ens, double* x, double* y, doubl
 /* Replace the state of one ensemble (values are rounded to the state type). */
 int32_t orc_set_state(orc_ctx* c, int32_t ens, const double* x, const double* y, const double* u,
                       const double* v, const double* w, const double* psi, const int32_t* elem);
+/* The series exponential the wall condition on the turbulent frequency uses
+   (range reduction by ln 2, Taylor series through r^13). */
+double orc_exp64(double x);
+/* Turbulent frequency per particle of one ensemble, in id order; -1 when the
+   context carries none (omega = 0). */
+int32_t orc_get_omega(const orc_ctx* c, int32_t ens, double* om);
+int32_t orc_set_omega(orc_ctx* c, int32_t ens, const double* om);
+/* Per element: frozen <omega> at the centroid (eq. 8 solved) and S_omega
+   (eq. 10); per element edge: frozen <omega> at a wall-function edge's
+   midpoint (0 elsewhere). */
+void orc_omega_fields(const orc_ctx* c, double* om0, double* somega, double* omw);
+
 /* Conditional means <phi|V> used by the IECM step in place of the binned
    estimate of the state (nelem x 8, by velocity bin), until cleared with
    cm = NULL: lets a test feed the step the values another estimator (the
@@ -112,9 +125,10 @@ void orc_mix_rate(const orc_ctx* c, int32_t ens, double* out);
 void orc_wall_alpha(const orc_ctx* c, double* out);
 /* One straight-line walk from a point in element e to a target, with boundary
    handling.  (sx,sy): start, (tx,ty): target (rounded to the state type);
-   vel: 3 velocity components (in/out).  Returns the final element, or -1. */
+   vel: 3 velocity components (in/out); om: turbulent frequency (in/out, may
+   be NULL: no frequency condition).  Returns the final element, or -1. */
 int32_t orc_walk(const orc_ctx* c, int32_t e, double sx, double sy, double* tx, double* ty,
-                 double* vel, int32_t* n_reflect);
+                 double* vel, int32_t* n_reflect, double* om);
 
 #ifdef __cplusplus
 }

@@ -60,8 +60,10 @@ class Workload:
     flags: int = 15                 # sub-steps: 1 velocity, 2 position/tracking, 4 IECM, 8 source
     steps: int = 100
     yp: float = 0.0                 # wall-function distance of the stripped walls
+    omega: bool = False             # stochastic turbulent frequency per particle, eqs. (9)-(10)
     constants: dict = field(default_factory=lambda: dict(CT=6.0, Cs=0.02, Ct=0.7, Cmu=0.09,
-                                                         kappa=0.41, Ewall=8.5))
+                                                         kappa=0.41, Ewall=8.5, C3=5.0, C4=0.25,
+                                                         Cw1=0.5, Cw2=0.73))
 
     @property
     def n_total(self) -> int:
@@ -75,7 +77,8 @@ class Workload:
         return dict(workload=self.name, mesh=self.mesh.name, elements=self.mesh.nelem,
                     vertices=self.mesh.nvert, particles=self.n_total, ensembles=self.nens,
                     precision=self.precision, model=("SLM" if self.model == SLM else "GLM"),
-                    dt=self.dt, steps=self.steps, moments=self.moments, hist_bins=self.hist_bins)
+                    dt=self.dt, steps=self.steps, moments=self.moments, hist_bins=self.hist_bins,
+                    omega=self.omega)
 
 
 def apportion(areas: np.ndarray, n: int) -> np.ndarray:
@@ -164,7 +167,7 @@ def config5(ppe: int = 20, seed: int = 101, steps: int = 500, target: int = 1000
 
 def small_canyon(target: int = 2000, ppe: int = 40, seed: int = 7, wallfn: bool = False,
                  precision: str = "f32", moments: int = 2, hist_bins: int = 0, nens: int = 1,
-                 steps: int = 20) -> Workload:
+                 steps: int = 20, omega: bool = False) -> Workload:
     m, f = _canyon(target, wallfn)
     yp = 13.0 / 256.0 if wallfn else 0.0
     n = ppe * m.nelem
@@ -177,7 +180,7 @@ def small_canyon(target: int = 2000, ppe: int = 40, seed: int = 7, wallfn: bool 
     return Workload(name=f"small_canyon_{m.nelem}e", mesh=m, fields=f, ensembles=ens,
                     precision=precision, model=(SLM if wallfn else GLM), dt=1e-3,
                     nu=1.0 / 12000.0, C0=(3.5 if wallfn else 2.1), moments=moments,
-                    hist_bins=hist_bins, steps=steps, yp=yp)
+                    hist_bins=hist_bins, steps=steps, yp=yp, omega=omega)
 
 
 def tiny_canyon(**kw) -> Workload:
