@@ -12,6 +12,9 @@
  *            or from the elliptic-relaxation tensor, eqs. (12)-(13)
  *   eq. (7)  scalar:   IECM relaxation toward <phi|V> over the time scale of
  *            eq. (11)
+ *   eq. (9)  optionally, the stochastic turbulent frequency omega, with the
+ *            source term of eq. (10) and, at wall-function walls, the
+ *            reflection condition of the wall-function section
  * tracks them through an unstructured triangular grid with wall (resolved
  * no-slip, free-slip, wall-function eqs. (20)-(26)) and periodic conditions,
  * applies the street-level source (section 3), and estimates per-element
@@ -88,7 +91,15 @@ typedef struct pdf_params {
   int32_t psi_init;   /* initial scalar: 0 zero; 1 one where x < 0.25            */
   int32_t flags;      /* sub-steps: 1 velocity, 2 position+tracking, 4 IECM,
                          8 source (15 = the full step)                           */
-  int32_t reserved;
+  int32_t omega;      /* 1: particles carry the turbulent frequency of eq. (9):
+                         seeded at the element's frozen <omega> (eq. 8 solved
+                         at the centroid), advanced with the element's
+                         estimated <omega> and the sixth normal of the step,
+                         reflected at zero, rescaled at wall-function walls;
+                         the velocity keeps the frozen-field coefficients.
+                         The record gains <omega>, <omega'^2> and eps =
+                         <omega>(k + nu C_T^2 <omega>), k from the record's
+                         stresses.  0: off (no memory or work for it).      */
   double dt, nu, C0;  /* time step, kinematic viscosity, SLM constant           */
   double CT, Cs, Ct;  /* Table 2 constants used by eqs. (8) and (11)            */
   double Cmu, kappa, Ewall, yp; /* wall functions: C_mu, Karman constant, E,
@@ -96,6 +107,8 @@ typedef struct pdf_params {
   double Lx, Ly;      /* periodic lengths                                        */
   double slack;       /* segment capacity = ceil(slack * initial count) + 32,
                          slack >= 1 (2 leaves room for density fluctuations)     */
+  double C3, C4, Cw1, Cw2; /* Table 2, turbulent frequency (used when omega = 1;
+                         C3, C4 > 0 and 1/2 + 3/4 C0 + C3 + Cw2 - Cw1 > 0)     */
 } pdf_params;
 
 typedef struct pdf_mesh {
@@ -183,7 +196,9 @@ pdf_status pdf_repack(pdf_ctx* ctx);
 int64_t pdf_repack_count(pdf_ctx* ctx);
 
 /* Estimate the statistics of the current state into out: nens x nelem x
-   nstat doubles (nstat = PDF_NSTAT_2 or PDF_NSTAT_4, plus hist_bins).
+   nstat doubles (nstat = PDF_NSTAT_2 or PDF_NSTAT_4, plus hist_bins, plus 3
+   with the turbulent frequency: <omega>, <omega'^2>, eps, after the
+   histogram).
    out_on_host: 1 -> out is host memory and the call waits; 0 -> device. */
 pdf_status pdf_estimate_statistics(pdf_ctx* ctx, double* out, int32_t out_on_host);
 
@@ -197,6 +212,17 @@ pdf_status pdf_sync(pdf_ctx* ctx);
    memory: xyuvwpsi (6 x n doubles: x, y, u, v, w, psi) and elem (n int32),
    n = pdf_count(ctx, ens).  Asynchronous. */
 pdf_status pdf_get_state(pdf_ctx* ctx, int32_t ens, double* xyuvwpsi, int32_t* elem);
+
+/* As pdf_get_state, plus the turbulent frequency om (n doubles, device
+   memory).  PDF_E_STATE if the context carries none. */
+pdf_status pdf_get_omega(pdf_ctx* ctx, int32_t ens, double* xyuvwpsi, int32_t* elem, double* om);
+
+/* The frozen turbulent-frequency fields, into host memory (waits): om0 (nelem:
+   <omega> at each centroid, eq. 8), somega (nelem: S_omega of eq. 10 with the
+   production of the frozen fields at the centroid), omw (nelem x 3: <omega>
+   at the midpoint of each wall-function edge, 0 on other edges).  PDF_E_STATE
+   if the context carries no turbulent frequency. */
+pdf_status pdf_omega_fields(pdf_ctx* ctx, double* om0, double* somega, double* omw);
 
 /* Number of particles of an ensemble; steps enqueued since seeding. */
 int64_t pdf_count(const pdf_ctx* ctx, int32_t ens);

@@ -104,6 +104,8 @@ def lib():
         L.orc_set_omega.restype = i32
         L.orc_set_omega.argtypes = [vp, i32, vp]
         L.orc_omega_fields.argtypes = [vp, vp, vp, vp]
+        L.orc_wallfn_hits.restype = i64
+        L.orc_wallfn_hits.argtypes = [vp]
         L.orc_walk.restype = i32
         L.orc_walk.argtypes = [vp, i32, d, d, P(d), P(d), vp, P(i32), P(d)]
         _lib = L
@@ -208,6 +210,10 @@ class Oracle:
         om0, sw, omw = np.zeros(ne), np.zeros(ne), np.zeros((ne, 3))
         lib().orc_omega_fields(self.ctx, _ptr(om0), _ptr(sw), _ptr(omw))
         return om0, sw, omw
+
+    def wallfn_hits(self) -> int:
+        """Particle steps so far whose frequency a wall-function reflection changed."""
+        return int(lib().orc_wallfn_hits(self.ctx))
 
     def set_cond_means(self, cm, ens: int = 0) -> None:
         """IECM toward the given conditional means (nelem x 8) instead of the

@@ -218,6 +218,7 @@ struct orc_ctx {
   std::vector<double> om0;     // frozen <omega> per element (centroid)
   std::vector<double> somega;  // S_omega per element (centroid), eq. (10)
   std::vector<double> omw;     // frozen <omega> at wall-function edge midpoints
+  int64_t wf_hits = 0;         // particle steps whose frequency a wall condition changed
   std::vector<Ens<float>> ensF;
   std::vector<Ens<double>> ensD;
   int64_t step = 0;
@@ -719,7 +720,8 @@ template <typename T> int advance(orc_ctx* c, Ens<T>& en, uint32_t ens_index, ui
   const T s2nu = std::sqrt(nu2);
   const int64_t n = (int64_t)en.x.size();
   int lost = 0;
-#pragma omp parallel for schedule(static) reduction(+ : lost)
+  int64_t hits = 0;
+#pragma omp parallel for schedule(static) reduction(+ : lost, hits)
   for (int64_t i = 0; i < n; ++i) {
     int e = en.elem[i];
     T xi[8];
@@ -775,7 +777,9 @@ template <typename T> int advance(orc_ctx* c, Ens<T>& en, uint32_t ens_index, ui
     T yn = (y + v * dt) + s2nu * dW2;
     int e2 = e;
     if (p.flags & 2) {
+      const T om_before = omn;
       e2 = walk<T>(c, e, (double)x, (double)y, xn, yn, un, vn, wn, nullptr, p.omega ? &omn : nullptr);
+      if (omn != om_before) hits += 1;
       if (e2 < 0) {
         lost += 1;
         continue;
@@ -792,6 +796,7 @@ template <typename T> int advance(orc_ctx* c, Ens<T>& en, uint32_t ens_index, ui
     if (p.omega) en.om[i] = omn;
     en.elem[i] = e2;
   }
+  c->wf_hits += hits;
   return lost ? -5 : 0;
 }
 
@@ -926,6 +931,8 @@ int32_t orc_set_state(orc_ctx* c, int32_t ens, const double* x, const double* y,
 }
 
 double orc_exp64(double x) { return exp_series(x); }
+
+int64_t orc_wallfn_hits(const orc_ctx* c) { return c->wf_hits; }
 
 int32_t orc_get_omega(const orc_ctx* c, int32_t ens, double* om) {
   if (!c->p.omega) return -1;

@@ -94,6 +94,8 @@ int32_t orc_set_omega(orc_ctx* c, int32_t ens, const double* om);
    (eq. 10); per element edge: frozen <omega> at a wall-function edge's
    midpoint (0 elsewhere). */
 void orc_omega_fields(const orc_ctx* c, double* om0, double* somega, double* omw);
+/* Particle steps so far in which a wall-function reflection changed omega. */
+int64_t orc_wallfn_hits(const orc_ctx* c);
 
 /* Conditional means <phi|V> used by the IECM step in place of the binned
    estimate of the state (nelem x 8, by velocity bin), until cleared with

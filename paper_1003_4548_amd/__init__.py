@@ -30,7 +30,7 @@ ENTRY_POINTS = ("pdf_create", "pdf_query_sizes", "pdf_init_mesh", "pdf_seed_part
                 "pdf_estimate_statistics", "pdf_nstat", "pdf_sync",
                 "pdf_mlp_work_floats", "pdf_mlp_dataset", "pdf_mlp_forward", "pdf_mlp_grad", "pdf_mlp_train",
                 "pdf_mlp_norm", "pdf_mlp_round", "pdf_mlp_infer", "pdf_mlp_attach",
-                "pdf_get_state", "pdf_count", "pdf_steps_done", "pdf_error_string", "pdf_destroy")
+                "pdf_get_state", "pdf_get_omega", "pdf_omega_fields", "pdf_count", "pdf_steps_done", "pdf_error_string", "pdf_destroy")
 
 
 class PdfError(RuntimeError):
@@ -42,12 +42,13 @@ class PdfError(RuntimeError):
 class PdfParams(ctypes.Structure):
     _fields_ = [("f32_state", ctypes.c_int32), ("model", ctypes.c_int32), ("moments", ctypes.c_int32),
                 ("hist_bins", ctypes.c_int32), ("mix", ctypes.c_int32), ("psi_init", ctypes.c_int32),
-                ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("flags", ctypes.c_int32), ("omega", ctypes.c_int32),
                 ("dt", ctypes.c_double), ("nu", ctypes.c_double), ("C0", ctypes.c_double),
                 ("CT", ctypes.c_double), ("Cs", ctypes.c_double), ("Ct", ctypes.c_double),
                 ("Cmu", ctypes.c_double), ("kappa", ctypes.c_double), ("Ewall", ctypes.c_double),
                 ("yp", ctypes.c_double), ("Lx", ctypes.c_double), ("Ly", ctypes.c_double),
-                ("slack", ctypes.c_double)]
+                ("slack", ctypes.c_double), ("C3", ctypes.c_double), ("C4", ctypes.c_double),
+                ("Cw1", ctypes.c_double), ("Cw2", ctypes.c_double)]
 
 
 class PdfMesh(ctypes.Structure):
@@ -126,6 +127,10 @@ def load_library():
     L.pdf_sync.argtypes = [vp]
     L.pdf_get_state.restype = i32
     L.pdf_get_state.argtypes = [vp, i32, vp, vp]
+    L.pdf_get_omega.restype = i32
+    L.pdf_get_omega.argtypes = [vp, i32, vp, vp, vp]
+    L.pdf_omega_fields.restype = i32
+    L.pdf_omega_fields.argtypes = [vp, vp, vp, vp]
     L.pdf_count.restype = i64
     L.pdf_count.argtypes = [vp, i32]
     L.pdf_steps_done.restype = i64
@@ -155,8 +160,9 @@ class Simulation:
                  psi_init: int = 0, flags: int = 15, dt: float = 1e-3, nu: float = 0.0,
                  C0: float = 2.1, CT: float = 6.0, Cs: float = 0.02, Ct: float = 0.7,
                  Cmu: float = 0.09, kappa: float = 0.41, Ewall: float = 8.5, yp: float = 0.0,
-                 Lx: float = 1.0, Ly: float = 1.0, slack: float = 2.0, device: str = "cuda:0",
-                 stream=None):
+                 Lx: float = 1.0, Ly: float = 1.0, slack: float = 2.0, omega: bool = False,
+                 C3: float = 5.0, C4: float = 0.25, Cw1: float = 0.5, Cw2: float = 0.73,
+                 device: str = "cuda:0", stream=None):
         import torch
 
         self.torch = torch
@@ -165,8 +171,9 @@ class Simulation:
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.params = PdfParams(f32_state=1 if precision == "f32" else 0, model=int(model), moments=int(moments),
                                 hist_bins=int(hist_bins), mix=1 if mix else 0, psi_init=int(psi_init),
-                                flags=int(flags), reserved=0, dt=dt, nu=nu, C0=C0, CT=CT, Cs=Cs, Ct=Ct,
-                                Cmu=Cmu, kappa=kappa, Ewall=Ewall, yp=yp, Lx=Lx, Ly=Ly, slack=slack)
+                                flags=int(flags), omega=1 if omega else 0, dt=dt, nu=nu, C0=C0, CT=CT, Cs=Cs,
+                                Ct=Ct, Cmu=Cmu, kappa=kappa, Ewall=Ewall, yp=yp, Lx=Lx, Ly=Ly, slack=slack,
+                                C3=C3, C4=C4, Cw1=Cw1, Cw2=Cw2)
         self.ctx = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             self._check(L.pdf_create(ctypes.byref(self.params), ctypes.c_void_p(self.stream.cuda_stream),
@@ -211,7 +218,9 @@ class Simulation:
                     model=wl.model, moments=wl.moments, hist_bins=wl.hist_bins, mix=wl.mix,
                     psi_init=wl.psi_init, flags=getattr(wl, "flags", 15), dt=wl.dt, nu=wl.nu, C0=wl.C0,
                     CT=c["CT"], Cs=c["Cs"], Ct=c["Ct"], Cmu=c["Cmu"], kappa=c["kappa"], Ewall=c["Ewall"],
-                    yp=wl.yp, Lx=m.Lx, Ly=m.Ly, device=device)
+                    yp=wl.yp, Lx=m.Lx, Ly=m.Ly, omega=bool(getattr(wl, "omega", False)),
+                    C3=c.get("C3", 5.0), C4=c.get("C4", 0.25), Cw1=c.get("Cw1", 0.5), Cw2=c.get("Cw2", 0.73),
+                    device=device)
         args.update(kw)
         return cls(**args)
 
@@ -294,7 +303,27 @@ class Simulation:
         return vals, elem
 
     def state(self, ens: int = 0) -> dict:
-        vals, elem = self.state_device(ens)
+        """State in id order; with the turbulent frequency also "omega"."""
+        if self.params.omega:
+            n = self.count(ens)
+            vals = self.torch.empty((6, n), dtype=self.torch.float64, device=self.device)
+            elem = self.torch.empty((n,), dtype=self.torch.int32, device=self.device)
+            om = self.torch.empty((n,), dtype=self.torch.float64, device=self.device)
+            self._check(load_library().pdf_get_omega(self.ctx, int(ens), ctypes.c_void_p(vals.data_ptr()),
+                                                     ctypes.c_void_p(elem.data_ptr()),
+                                                     ctypes.c_void_p(om.data_ptr())), "pdf_get_omega")
+        else:
+            vals, elem = self.state_device(ens)
         self.stream.synchronize()
         v = vals.cpu().numpy()
-        return dict(x=v[0], y=v[1], u=v[2], v=v[3], w=v[4], psi=v[5], elem=elem.cpu().numpy())
+        out = dict(x=v[0], y=v[1], u=v[2], v=v[3], w=v[4], psi=v[5], elem=elem.cpu().numpy())
+        if self.params.omega:
+            out["omega"] = om.cpu().numpy()
+        return out
+
+    def omega_fields(self):
+        """(<omega> per centroid, S_omega per element, <omega> per wall-function
+        edge midpoint (nelem x 3))."""
+        om0, sw, omw = np.zeros(self.nelem), np.zeros(self.nelem), np.zeros((self.nelem, 3))
+        self._check(load_library().pdf_omega_fields(self.ctx, _ptr(om0), _ptr(sw), _ptr(omw)), "pdf_omega_fields")
+        return om0, sw, omw

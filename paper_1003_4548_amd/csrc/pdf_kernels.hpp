@@ -1,7 +1,8 @@
 // Kernels of the particle-in-cell joint velocity-scalar PDF step.
 //
 // Data layout in HBM (structure of arrays):
-//   particles  x y u v w psi (state type T) and id (u32), in two buffers.
+//   particles  x y u v w psi (state type T), id (u32) and, with the
+//              stochastic turbulent frequency, omega (T), in two buffers.
 //              Each (ensemble, element) pair -- a "cell" -- owns a segment of
 //              fixed capacity; its particles sit densely at the front.  A
 //              particle's element is implied by the segment that holds it.
@@ -87,6 +88,7 @@ static_assert(sizeof(ERec) == 64, "element record must be 64 bytes");
 template <typename T> struct StateDev {
   T* x; T* y; T* u; T* v; T* w; T* psi;
   uint32_t* id;
+  T* om;  // turbulent frequency, null when the state carries none
 };
 
 // A cell's particles sit in two runs of its segment: the ones that stayed in
@@ -125,6 +127,13 @@ template <typename T> struct StepArgs {
   const float* mlp_norm;
   double* mlp_cm;
   uint32_t* mlp_served;
+  // stochastic turbulent frequency, eqs. (9)-(10) and the wall condition:
+  // S_omega per element, frozen <omega> at the wall-function edges (ne x 3),
+  // beta, y_p, nu C_T^2 (for the dissipation estimate, eq. 8), C3, 2 C3 C4
+  const double* somega;
+  const double* omw;
+  double om_beta, om_yp, om_nuct2;
+  T om_c3, om_c34;
   Ctl* ctl;
   int32_t nstat;
   int32_t flags;
@@ -205,10 +214,11 @@ __device__ __forceinline__ int slot_of(int j, int start, int ns, int nm, int cap
 // by one period into the partner element.  R holds the record of element e.
 
 // (f0, f1, f2): the target's orientations against the edges of element e,
-// known to the caller for the first iteration.
-template <typename T>
+// known to the caller for the first iteration.  OMG: the particle carries a
+// turbulent frequency om, which a wall-function reflection rescales.
+template <typename T, bool OMG>
 __device__ int walk(const StepArgs<T>& a, ERec R, int e, double Sx, double Sy, T& tx, T& ty, T& u, T& v,
-                    T& w, double f0, double f1, double f2) {
+                    T& w, T& om, double f0, double f1, double f2) {
 #pragma unroll 1
   for (int it = 0; it < 64; ++it) {
     const double Tx = (double)tx, Ty = (double)ty;
@@ -302,6 +312,12 @@ __device__ int walk(const StepArgs<T>& a, ERec R, int e, double Sx, double Sy, T
       const T Vr = -Vi;
       u = Ur * tX + Vr * (-nxT);
       v = Ur * tY + Vr * (-nyT);
+      if constexpr (OMG) {
+        // omega_R = omega_I exp(beta V_I / (y_p <omega>)), <omega> frozen at the
+        // edge midpoint; V_I < 0 toward the wall, beta < 0: omega grows
+        const double arg = a.om_beta * (double)Vi / (a.om_yp * a.omw[3 * e + ex]);
+        om = (T)((double)om * series_exp(arg));
+      }
     }
   }
   return -1;
@@ -354,6 +370,7 @@ template <typename T> struct CellConst {
   double ox[3], oy[3], dx[3], dy[3], sg[3];
   double mean[3];
   double cm[8];
+  double om_mean, sw;  // turbulent frequency: the cell's <omega> and S_omega
 };
 
 // orient_edge of (px, py) against edge k of a cell, from its CellConst data;
@@ -365,8 +382,11 @@ __device__ __forceinline__ double orient_cc(const CellConst<T>& C, int k, double
 
 // SCHED: 0 one work item per wavefront; 1 persistent grid; 2 one item per
 // wavefront with the learned conditional means computed inside the step.
-template <typename T, int MOM, int HIST, int G, bool ADVANCE, int SCHED>
+// OMG: the particles carry the stochastic turbulent frequency of eq. (9); the
+// record gains its mean, variance and the dissipation estimate of eq. (8).
+template <typename T, int MOM, int HIST, int G, bool ADVANCE, int SCHED, bool OMG>
 __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
+  static_assert(!(OMG && SCHED == 2), "the turbulent frequency runs with the separate learned-means pass");
   constexpr bool PERSIST = SCHED == 1;
   constexpr int GPW = WAVE / G;             // cells per wavefront
   constexpr int TILEN = 4 * G;              // particles per cell staged in LDS
@@ -374,6 +394,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
   __shared__ Tile<T, TILEN> tiles[CPB];
   __shared__ int hist_lds[HIST > 0 ? CPB : 1][HIST > 0 ? HIST : 1];
   __shared__ CellConst<T> ccs[ADVANCE ? CPB : 1];
+  __shared__ T otile[OMG ? CPB : 1][OMG ? TILEN : 1];
   Ctl* ctl = a.ctl;
   // after an error the state is void: later steps do nothing
   // (with the learned means inside the step every wavefront of a block must
@@ -394,6 +415,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
   const StateDev<T> src = a.buf[bpar];
   const StateDev<T> dst = a.buf[bpar ^ 1u];
   Tile<T, TILEN>& L = tiles[slot_id];
+  T* LO = otile[OMG ? slot_id : 0];
 
   // persistent grid: a wavefront claims a.pchunk consecutive work items per
   // atomic on the shared counter (one address: its atomics serialise in L2)
@@ -431,9 +453,10 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
     const double dn = (double)n;
 
     // ---- A: load, stage, means ----
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0;
     {
       T tx_[TILEN / G], ty_[TILEN / G], tu_[TILEN / G], tv_[TILEN / G], tw_[TILEN / G], tp_[TILEN / G];
+      T to_[OMG ? TILEN / G : 1];
       uint32_t ti_[TILEN / G];
 #pragma unroll
       for (int c = 0; c < TILEN / G; ++c) {
@@ -442,6 +465,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
           const int s = slot_of(j, start, ns, nm, capc);
           tx_[c] = src.x[s]; ty_[c] = src.y[s]; tu_[c] = src.u[s]; tv_[c] = src.v[s]; tw_[c] = src.w[s];
           tp_[c] = src.psi[s]; ti_[c] = src.id[s];
+          if constexpr (OMG) to_[c] = src.om[s];
         }
       }
 #pragma unroll
@@ -454,6 +478,10 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
           s1 += (double)tv_[c];
           s2 += (double)tw_[c];
           s3 += (double)tp_[c];
+          if constexpr (OMG) {
+            LO[j] = to_[c];
+            s4 += (double)to_[c];
+          }
         }
       }
     }
@@ -465,6 +493,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
         s1 += (double)src.v[s];
         s2 += (double)src.w[s];
         s3 += (double)src.psi[s];
+        if constexpr (OMG) s4 += (double)src.om[s];
       }
     }
     const double inv_n = n > 0 ? 1.0 / dn : 0.0;
@@ -473,6 +502,8 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
     mean[1] = group_sum<G>(s1) * inv_n;
     mean[2] = group_sum<G>(s2) * inv_n;
     mean[3] = group_sum<G>(s3) * inv_n;
+    double om_mean = 0.0;
+    if constexpr (OMG) om_mean = group_sum<G>(s4) * inv_n;
 
     auto load4 = [&](int j, double* val) {
       if (j < TILEN) {
@@ -487,6 +518,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
     double acc[18];  // 10 second moments, 8 per-bin scalar sums
 #pragma unroll
     for (int q = 0; q < 18; ++q) acc[q] = 0.0;
+    double accw = 0.0;  // turbulent frequency: sum of squared fluctuations
     int bcount[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) bcount[q] = 0;
@@ -510,6 +542,10 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
         bin = (val[0] > mean[0] ? 1 : 0) + (val[1] > mean[1] ? 2 : 0) + (val[2] > mean[2] ? 4 : 0);
 #pragma unroll
         for (int q = 0; q < 8; ++q) acc[10 + q] += (bin == q) ? val[3] : 0.0;
+        if constexpr (OMG) {
+          const double dw = (double)(j < TILEN ? LO[j] : src.om[slot_of(j, start, ns, nm, capc)]) - om_mean;
+          accw += dw * dw;
+        }
         if (HIST > 0) {
           const double hpos = floor(val[3] * (double)HIST);
           const int hb = hpos < 0.0 ? 0 : (hpos >= (double)HIST ? HIST - 1 : (int)hpos);
@@ -521,6 +557,8 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
     }
 #pragma unroll
     for (int q = 0; q < 18; ++q) acc[q] = group_sum<G>(acc[q]);
+    double om_var = 0.0;
+    if constexpr (OMG) om_var = group_sum<G>(accw) * inv_n;
     double bm[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) bm[q] = bcount[q] > 0 ? acc[10 + q] / (double)bcount[q] : mean[3];
@@ -629,6 +667,15 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
         rec[ST_BINN + q] = (double)bcount[q];
         rec[ST_BINM + q] = bm[q] * z;
       }
+      if constexpr (OMG) {
+        // after the moments and the histogram: <omega>, its variance, and
+        // eps = <omega>(k + nu C_T^2 <omega>) with k from the estimated stresses
+        constexpr int OFF = (MOM >= 4 ? NSTAT4 : NSTAT2) + HIST;
+        const double kh = 0.5 * ((acc[0] * inv_n + acc[4] * inv_n) + acc[7] * inv_n);
+        rec[OFF] = om_mean;
+        rec[OFF + 1] = om_var;
+        rec[OFF + 2] = om_mean * (kh + a.om_nuct2 * om_mean);
+      }
     }
     if constexpr (MOM >= 4) {
       // third- and fourth-order central moments: the 20 + 35 index combinations
@@ -719,6 +766,10 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
           for (int q = 0; q < 3; ++q) CC.mean[q] = mean[q];
 #pragma unroll
           for (int q = 0; q < 8; ++q) CC.cm[q] = cm[q];
+          if constexpr (OMG) {
+            CC.om_mean = om_mean;
+            CC.sw = a.somega[e];
+          }
         }
         lds_sync_wave();
       }
@@ -732,7 +783,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
 
       // Writes a particle that ended in element e2 of ensemble qens: its own
       // cell's bottom run at index k, or the top run of the new cell.
-      auto put_mover = [&](int qens, int e2, T xn, T yn, T un, T vn, T wn, T psi, uint32_t id) {
+      auto put_mover = [&](int qens, int e2, T xn, T yn, T un, T vn, T wn, T psi, uint32_t id, T omv) {
         const int t = qens * ne + e2;
         const int k = atomicAdd(&a.nm[rn][t], 1);
         const int capt = a.cap[t];
@@ -741,12 +792,14 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
           const int s = a.start[t] + capt - 1 - k;
           dst.x[s] = xn; dst.y[s] = yn; dst.u[s] = un; dst.v[s] = vn; dst.w[s] = wn; dst.psi[s] = psi;
           dst.id[s] = id;
+          if constexpr (OMG) dst.om[s] = omv;
         } else {
           err |= ERR_CAPACITY;
           const uint32_t kk = atomicAdd(&ctl->ovf, 1u);
           if (kk < a.ovf_cap) {
             a.ovf.x[kk] = xn; a.ovf.y[kk] = yn; a.ovf.u[kk] = un; a.ovf.v[kk] = vn; a.ovf.w[kk] = wn;
             a.ovf.psi[kk] = psi; a.ovf.id[kk] = id;
+            if constexpr (OMG) a.ovf.om[kk] = omv;
             a.ovf_cell[kk] = t;
           } else {
             err |= ERR_OVERFLOW_FULL;
@@ -765,15 +818,17 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
         const int j = base + li;
         const bool act = j < n;
         bool moved = false;
-        T x = 0, y = 0, xn = 0, yn = 0, un = 0, vn = 0, wn = 0, psi = 0;
+        T x = 0, y = 0, xn = 0, yn = 0, un = 0, vn = 0, wn = 0, psi = 0, omn = 0;
         uint32_t id = 0;
         if (act) {
-          T u, v, w;
+          T u, v, w, om = 0;
           if (j < TILEN) {
             x = L.x[j]; y = L.y[j]; u = L.u[j]; v = L.v[j]; w = L.w[j]; psi = L.psi[j]; id = L.id[j];
+            if constexpr (OMG) om = LO[j];
           } else {
             const int s = slot_of(j, start, ns, nm, capc);
             x = src.x[s]; y = src.y[s]; u = src.u[s]; v = src.v[s]; w = src.w[s]; psi = src.psi[s]; id = src.id[s];
+            if constexpr (OMG) om = src.om[s];
           }
           uint32_t rw[8];
           philox_words<2>(id, step, (uint32_t)ens, k0, k1, rw);
@@ -781,7 +836,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
           box_muller<T>(rw[0], rw[1], &xi0, &xi1);
           box_muller<T>(rw[2], rw[3], &xi2, &xi3);
           box_muller<T>(rw[4], rw[5], &xi4, &xi5);
-          (void)xi5;
+          if constexpr (!OMG) (void)xi5;
           const double X = (double)x, Y = (double)y;
           const T l0 = (T)(orient_cc(CC, 1, X, Y) * ia);
           const T l1 = (T)(orient_cc(CC, 2, X, Y) * ia);
@@ -805,6 +860,18 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
           vn = ((v + av * a.dt) + a.s2nu * (f[C_DVDX] * dW1 + f[C_DVDY] * dW2)) + sq * dWp2;
           wn = (w + (f[C_G33] * w) * a.dt) + sq * dWp3;
           if (!(a.flags & FLAG_VEL)) { un = u; vn = v; wn = w; }
+          if constexpr (OMG) {
+            // turbulent frequency, eq. (9), with the cell's <omega> and the
+            // sixth normal; reflected at zero
+            omn = om;
+            if (a.flags & FLAG_VEL) {
+              const T mw = (T)CC.om_mean, sw = (T)CC.sw;
+              const T drift = (a.om_c3 * mw) * (om - mw) + (sw * mw) * om;
+              const T diff = sqrt_t((a.om_c34 * (mw * mw)) * om);
+              omn = (om - drift * a.dt) + diff * (a.sdt * xi5);
+              omn = fabs(omn);
+            }
+          }
           if (a.flags & FLAG_POS) {
             xn = (x + u * a.dt) + a.s2nu * dW1;
             yn = (y + v * a.dt) + a.s2nu * dW2;
@@ -815,16 +882,17 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
             const double o2 = orient_cc(CC, 2, Tx, Ty);
             if (!(o0 >= 0.0 && o1 >= 0.0 && o2 >= 0.0)) {
               // it left: the rest of the walk, with walls and periodic edges
-              const int e2 = walk<T>(a, a.erec[e], e, X, Y, xn, yn, un, vn, wn, o0, o1, o2);
+              const int e2 = walk<T, OMG>(a, a.erec[e], e, X, Y, xn, yn, un, vn, wn, omn, o0, o1, o2);
               if (e2 != e) {
                 moved = true;
                 if (e2 < 0) {
                   err |= ERR_LOST;
                 } else {
                   finish(ens, xn, yn, psi);
-                  if (!(isfinite(un) && isfinite(vn) && isfinite(wn) && isfinite(psi) && isfinite(xn) && isfinite(yn)))
+                  if (!(isfinite(un) && isfinite(vn) && isfinite(wn) && isfinite(psi) && isfinite(xn) && isfinite(yn)) ||
+                      (OMG && !isfinite(omn)))
                     err |= ERR_NAN;
-                  put_mover(ens, e2, xn, yn, un, vn, wn, psi, id);
+                  put_mover(ens, e2, xn, yn, un, vn, wn, psi, id, omn);
                 }
               }
             }
@@ -833,7 +901,8 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
           }
           if (!moved) {
             finish(ens, xn, yn, psi);
-            if (!(isfinite(un) && isfinite(vn) && isfinite(wn) && isfinite(psi) && isfinite(xn) && isfinite(yn)))
+            if (!(isfinite(un) && isfinite(vn) && isfinite(wn) && isfinite(psi) && isfinite(xn) && isfinite(yn)) ||
+                (OMG && !isfinite(omn)))
               err |= ERR_NAN;
           }
         }
@@ -844,6 +913,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
           const int s = start + stay_count + (int)__popcll(smask & lanemask_lt());
           dst.x[s] = xn; dst.y[s] = yn; dst.u[s] = un; dst.v[s] = vn; dst.w[s] = wn; dst.psi[s] = psi;
           dst.id[s] = id;
+          if constexpr (OMG) dst.om[s] = omn;
         }
         stay_count += (int)__popcll(smask);
       }
@@ -1013,12 +1083,14 @@ __global__ void k_wnorm(const double* vtx, const int32_t* tri, double* wn, int n
 }
 
 // Initial particles: uniform in the element, velocity = local mean plus the
-// Cholesky factor of the local Reynolds stress times normals, scalar by rule.
+// Cholesky factor of the local Reynolds stress times normals, scalar by rule,
+// turbulent frequency (if carried) the element's frozen <omega> (om0).
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_seed(const ERec* erec, const int32_t* tri, const double* inv2a,
                                                 const double* fields, StateDev<T> st, const int32_t* start,
                                                 const int32_t* count, const int32_t* idoff,
-                                                const uint64_t* seeds, int ne, int ncell, int psi_init) {
+                                                const uint64_t* seeds, int ne, int ncell, int psi_init,
+                                                const double* om0) {
   const int lane = lane_id();
   const int cell = blockIdx.x * WAVES_PER_BLOCK + (int)(threadIdx.x / WAVE);
   if (cell >= ncell) return;
@@ -1083,6 +1155,43 @@ __global__ __launch_bounds__(BLOCK) void k_seed(const ERec* erec, const int32_t*
     st.w[s] = (T)(L33 * z2);
     st.psi[s] = (T)((psi_init == 1 && X < 0.25) ? 1.0 : 0.0);
     st.id[s] = id;
+    if (st.om) st.om[s] = (T)om0[e];
+  }
+}
+
+// Turbulent frequency fields per element: the frozen <omega> at the centroid
+// (eq. 8 solved for its positive root) and S_omega = C_w2 - C_w1 P / eps
+// (eq. 10) with P = -<u_i u_j> d<U_i>/dx_j from the centroid values; per
+// wall-function edge the frozen <omega> at its midpoint (0 on other edges).
+__device__ __forceinline__ double frozen_omega(double k, double eps, double nu, double CT) {
+  return 2.0 * eps / (k + sqrt(k * k + 4.0 * nu * CT * CT * eps));
+}
+
+__global__ void k_omega_fields(const int32_t* tri, const int32_t* ekind, const double* fields, double* om0,
+                               double* somega, double* omw, int ne, double nu, double CT, double Cw1,
+                               double Cw2) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ne) return;
+  const double* f0 = fields + (size_t)tri[3 * e] * NFIELD;
+  const double* f1 = fields + (size_t)tri[3 * e + 1] * NFIELD;
+  const double* f2 = fields + (size_t)tri[3 * e + 2] * NFIELD;
+  double c[NFIELD];
+  for (int j = 0; j < NFIELD; ++j) c[j] = ((f0[j] + f1[j]) + f2[j]) / 3.0;
+  const double k = 0.5 * ((c[F_R11] + c[F_R22]) + c[F_R33]);
+  const double eps = c[F_EPS];
+  const double prod = -((c[F_R11] * c[F_DUDX] + c[F_R12] * c[F_DUDY]) + (c[F_R12] * c[F_DVDX] + c[F_R22] * c[F_DVDY]));
+  om0[e] = frozen_omega(k, eps, nu, CT);
+  somega[e] = Cw2 - Cw1 * (prod / eps);
+  for (int q = 0; q < 3; ++q) {
+    double w = 0.0;
+    if (ekind[3 * e + q] == EDGE_WALLFN) {
+      const double* fa = fields + (size_t)tri[3 * e + q] * NFIELD;
+      const double* fb = fields + (size_t)tri[3 * e + (q == 2 ? 0 : q + 1)] * NFIELD;
+      const double kp = 0.5 * (((fa[F_R11] + fb[F_R11]) / 2.0 + (fa[F_R22] + fb[F_R22]) / 2.0) +
+                               (fa[F_R33] + fb[F_R33]) / 2.0);
+      w = frozen_omega(kp, (fa[F_EPS] + fb[F_EPS]) / 2.0, nu, CT);
+    }
+    omw[3 * e + q] = w;
   }
 }
 
@@ -1096,7 +1205,7 @@ template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_gather(StateDev<T> b0, StateDev<T> b1, CounterSets cs,
                                                   const int32_t* start, const int32_t* cap, const Ctl* ctl,
                                                   StepIndex si, int ens, int ne, int64_t n, double* out,
-                                                  int32_t* elem) {
+                                                  int32_t* elem, double* om_out) {
   const int lane = lane_id();
   const int e = blockIdx.x * WAVES_PER_BLOCK + (int)(threadIdx.x / WAVE);
   if (e >= ne) return;
@@ -1117,6 +1226,7 @@ __global__ __launch_bounds__(BLOCK) void k_gather(StateDev<T> b0, StateDev<T> b1
     out[4 * n + id] = (double)st.w[s];
     out[5 * n + id] = (double)st.psi[s];
     elem[id] = e;
+    if (om_out) om_out[id] = (double)st.om[s];
   }
 }
 
@@ -1263,6 +1373,7 @@ __global__ __launch_bounds__(BLOCK) void k_repack_move(RepackMove<T> m, StepInde
     const int d = d0 + j;
     dst.x[d] = src.x[s]; dst.y[d] = src.y[s]; dst.u[d] = src.u[s]; dst.v[d] = src.v[s]; dst.w[d] = src.w[s];
     dst.psi[d] = src.psi[s]; dst.id[d] = src.id[s];
+    if (src.om) dst.om[d] = src.om[s];
   }
   if (lane == 0) {
     m.start[cell] = d0;

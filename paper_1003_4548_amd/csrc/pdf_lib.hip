@@ -24,15 +24,16 @@ int64_t align_up(int64_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
 // Byte offsets of the arena sections.
 struct Layout {
-  int64_t vtx, tri, nbr, ekind, inv2a, alpha, wnorm, fields, coef, erec;
+  int64_t vtx, tri, nbr, ekind, inv2a, alpha, wnorm, fields, coef, erec, om0, somega, omw;
   int64_t start, cap, cap0, nstart, ncap, ns[3], nm[3], rate, idoff, order, seed, src;
   int64_t buf0, buf1, ovf, ovf_cell, stats, ctl, flag;
   int64_t total;
   int64_t slots;
   int64_t ovf_cap;
+  bool omega;  // the particle buffers carry the turbulent frequency
 };
 
-Layout make_layout(int32_t nv, int32_t ne, int32_t nens, int64_t slots, int32_t nstat, int tsize) {
+Layout make_layout(int32_t nv, int32_t ne, int32_t nens, int64_t slots, int32_t nstat, int tsize, bool omega) {
   Layout L{};
   int64_t o = 0;
   auto take = [&](int64_t bytes) { int64_t r = o; o = align_up(o + bytes); return r; };
@@ -47,6 +48,9 @@ Layout make_layout(int32_t nv, int32_t ne, int32_t nens, int64_t slots, int32_t 
   L.fields = take((int64_t)nv * NFIELD * 8);
   L.coef = take((int64_t)nv * NCOEF * tsize);
   L.erec = take((int64_t)ne * (int64_t)sizeof(ERec));
+  L.om0 = take(omega ? (int64_t)ne * 8 : 0);
+  L.somega = take(omega ? (int64_t)ne * 8 : 0);
+  L.omw = take(omega ? (int64_t)ne * 3 * 8 : 0);
   L.start = take(ncell * 4);
   L.cap = take(ncell * 4);
   L.cap0 = take(ncell * 4);
@@ -61,21 +65,23 @@ Layout make_layout(int32_t nv, int32_t ne, int32_t nens, int64_t slots, int32_t 
   L.order = take(ncell * 4);
   L.seed = take((int64_t)nens * 8);
   L.src = take((int64_t)nens * 3 * 8);
-  const int64_t per_buf = align_up(slots * tsize) * 6 + align_up(slots * 4);
+  const int64_t per_buf = align_up(slots * tsize) * (omega ? 7 : 6) + align_up(slots * 4);
   L.buf0 = take(per_buf);
   L.buf1 = take(per_buf);
   L.ovf_cap = std::max<int64_t>(4096, slots / 64);
-  L.ovf = take(align_up(L.ovf_cap * tsize) * 6 + align_up(L.ovf_cap * 4));
+  L.ovf = take(align_up(L.ovf_cap * tsize) * (omega ? 7 : 6) + align_up(L.ovf_cap * 4));
   L.ovf_cell = take(L.ovf_cap * 4);
   L.stats = take(ncell * (int64_t)nstat * 8);
   L.ctl = take(sizeof(Ctl));
   L.flag = take(16);
   L.total = o;
   L.slots = slots;
+  L.omega = omega;
   return L;
 }
 
-template <typename T> StateDev<T> state_at(char* base, int64_t off, int64_t slots) {
+// x y u v w psi, id, then omega when carried
+template <typename T> StateDev<T> state_at(char* base, int64_t off, int64_t slots, bool omega) {
   StateDev<T> s;
   char* p = base + off;
   const int64_t fb = align_up(slots * (int64_t)sizeof(T));
@@ -86,6 +92,7 @@ template <typename T> StateDev<T> state_at(char* base, int64_t off, int64_t slot
   s.w = (T*)(p + 4 * fb);
   s.psi = (T*)(p + 5 * fb);
   s.id = (uint32_t*)(p + 6 * fb);
+  s.om = omega ? (T*)(p + 6 * fb + align_up(slots * 4)) : nullptr;
   return s;
 }
 
@@ -133,7 +140,14 @@ namespace {
 
 int tsize_of(const pdf_params& p) { return p.f32_state ? 4 : 8; }
 
-int nstat_of(const pdf_params& p) { return (p.moments >= 4 ? NSTAT4 : NSTAT2) + p.hist_bins; }
+int nstat_of(const pdf_params& p) {
+  return (p.moments >= 4 ? NSTAT4 : NSTAT2) + p.hist_bins + (p.omega ? 3 : 0);
+}
+
+// The learned conditional means run as a statistics pass and an inference
+// launch before each step on persistent grids and with the turbulent
+// frequency; otherwise inside the step.
+bool mlp_separate(const pdf_ctx* c) { return c->mlp_w && (c->persist || c->p.omega); }
 
 pdf_status fail(pdf_ctx* c, pdf_status s, const std::string& msg) {
   if (c) {
@@ -141,6 +155,11 @@ pdf_status fail(pdf_ctx* c, pdf_status s, const std::string& msg) {
     c->last = s;
   }
   return s;
+}
+
+// beta of the wall condition on the turbulent frequency (SLM wall functions)
+double omega_beta(const pdf_params& p) {
+  return -2.0 / ((((0.5 + 0.75 * p.C0) + p.C3) + p.Cw2) - p.Cw1);
 }
 
 pdf_status hip_check(pdf_ctx* c, hipError_t e, const char* what) {
@@ -182,9 +201,9 @@ template <typename T> StepArgs<T> step_args(pdf_ctx* c) {
     s.ns[r] = (int32_t*)(a + L.ns[r]);
     s.nm[r] = (int32_t*)(a + L.nm[r]);
   }
-  s.buf[0] = state_at<T>(a, L.buf0, L.slots);
-  s.buf[1] = state_at<T>(a, L.buf1, L.slots);
-  s.ovf = state_at<T>(a, L.ovf, L.ovf_cap);
+  s.buf[0] = state_at<T>(a, L.buf0, L.slots, L.omega);
+  s.buf[1] = state_at<T>(a, L.buf1, L.slots, L.omega);
+  s.ovf = state_at<T>(a, L.ovf, L.ovf_cap, L.omega);
   s.ovf_cell = (int32_t*)(a + L.ovf_cell);
   s.ovf_cap = (uint32_t)L.ovf_cap;
   s.stats = (double*)(a + L.stats);
@@ -192,7 +211,7 @@ template <typename T> StepArgs<T> step_args(pdf_ctx* c) {
   s.src = (const double*)(a + L.src);
   s.ctl = (Ctl*)(a + L.ctl);
   // the learned means run inside the step on one-item-per-wavefront grids
-  if (c->mlp_w && !c->persist) {
+  if (c->mlp_w && !mlp_separate(c)) {
     s.mlp_w = c->mlp_w;
     s.mlp_norm = c->mlp_norm;
     s.mlp_cm = c->mlp_cm;
@@ -206,6 +225,15 @@ template <typename T> StepArgs<T> step_args(pdf_ctx* c) {
   s.sdt = (T)std::sqrt((T)c->p.dt);
   s.nu2 = (T)(2.0 * c->p.nu);
   s.s2nu = (T)std::sqrt((T)(2.0 * c->p.nu));
+  if (c->p.omega) {
+    s.somega = (const double*)(a + L.somega);
+    s.omw = (const double*)(a + L.omw);
+    s.om_beta = omega_beta(c->p);
+    s.om_yp = c->p.yp;
+    s.om_nuct2 = c->p.nu * (c->p.CT * c->p.CT);
+    s.om_c3 = (T)c->p.C3;
+    s.om_c34 = (T)(2.0 * c->p.C3 * c->p.C4);
+  }
   return s;
 }
 
@@ -216,14 +244,14 @@ int persist_chunk(int nitems, int blocks) {
   return std::max(1, std::min(16, nitems / (16 * waves)));
 }
 
-template <typename T, int MOM, int HIST, int G, bool ADV, int SCHED>
+template <typename T, int MOM, int HIST, int G, bool ADV, int SCHED, bool OMG>
 void launch_step(pdf_ctx* c, StepArgs<T> s, StepIndex si) {
   constexpr int GPW = WAVE / G;
   s.nitems = (s.ncell + GPW - 1) / GPW;
   int blocks = (s.nitems + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
   if (SCHED == 1) {
     int per_cu = 0;
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step<T, MOM, HIST, G, ADV, SCHED>, BLOCK, 0);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step<T, MOM, HIST, G, ADV, SCHED, OMG>, BLOCK, 0);
     int cus = 0;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device);
     const int cap_blocks = std::max(1, per_cu) * std::max(1, cus);
@@ -231,7 +259,7 @@ void launch_step(pdf_ctx* c, StepArgs<T> s, StepIndex si) {
     c->persist_blocks = blocks;
   }
   s.pchunk = persist_chunk(s.nitems, blocks);
-  hipLaunchKernelGGL((k_step<T, MOM, HIST, G, ADV, SCHED>), dim3(blocks), dim3(BLOCK), 0, c->stream, s, si);
+  hipLaunchKernelGGL((k_step<T, MOM, HIST, G, ADV, SCHED, OMG>), dim3(blocks), dim3(BLOCK), 0, c->stream, s, si);
 }
 
 // Scheduling variant of a step launch: persistent grid, or one work item per
@@ -239,28 +267,23 @@ void launch_step(pdf_ctx* c, StepArgs<T> s, StepIndex si) {
 int sched_of(const pdf_ctx* c, bool adv) {
   if (!adv) return 0;
   if (c->persist) return 1;
-  return c->mlp_w ? 2 : 0;
+  return (c->mlp_w && !mlp_separate(c)) ? 2 : 0;
 }
 
-template <typename T, int MOM, int HIST, bool ADV>
+template <typename T, int MOM, int HIST, bool ADV, bool OMG, int G>
+void launch_shape(pdf_ctx* c, const StepArgs<T>& s, StepIndex si, int sc) {
+  if (!ADV || sc == 0) launch_step<T, MOM, HIST, G, ADV, 0, OMG>(c, s, si);
+  else if (sc == 1) launch_step<T, MOM, HIST, G, ADV, ADV ? 1 : 0, OMG>(c, s, si);
+  else if constexpr (!OMG) launch_step<T, MOM, HIST, G, ADV, ADV ? 2 : 0, OMG>(c, s, si);
+}
+
+template <typename T, int MOM, int HIST, bool ADV, bool OMG>
 void launch_group(pdf_ctx* c, const StepArgs<T>& s, StepIndex si) {
   const int sc = sched_of(c, ADV);
   switch (c->group) {
-    case 16:
-      if (!ADV || sc == 0) launch_step<T, MOM, HIST, 16, ADV, 0>(c, s, si);
-      else if (sc == 1) launch_step<T, MOM, HIST, 16, ADV, ADV ? 1 : 0>(c, s, si);
-      else launch_step<T, MOM, HIST, 16, ADV, ADV ? 2 : 0>(c, s, si);
-      break;
-    case 32:
-      if (!ADV || sc == 0) launch_step<T, MOM, HIST, 32, ADV, 0>(c, s, si);
-      else if (sc == 1) launch_step<T, MOM, HIST, 32, ADV, ADV ? 1 : 0>(c, s, si);
-      else launch_step<T, MOM, HIST, 32, ADV, ADV ? 2 : 0>(c, s, si);
-      break;
-    default:
-      if (!ADV || sc == 0) launch_step<T, MOM, HIST, 64, ADV, 0>(c, s, si);
-      else if (sc == 1) launch_step<T, MOM, HIST, 64, ADV, ADV ? 1 : 0>(c, s, si);
-      else launch_step<T, MOM, HIST, 64, ADV, ADV ? 2 : 0>(c, s, si);
-      break;
+    case 16: launch_shape<T, MOM, HIST, ADV, OMG, 16>(c, s, si, sc); break;
+    case 32: launch_shape<T, MOM, HIST, ADV, OMG, 32>(c, s, si, sc); break;
+    default: launch_shape<T, MOM, HIST, ADV, OMG, 64>(c, s, si, sc); break;
   }
 }
 
@@ -271,18 +294,24 @@ bool supported(const pdf_params& p) {
   return p.moments == 2 && p.hist_bins == 0;
 }
 
+template <typename T, int MOM, int HIST, bool ADV>
+void launch_omega(pdf_ctx* c, const StepArgs<T>& s, StepIndex si) {
+  if (c->p.omega) launch_group<T, MOM, HIST, ADV, true>(c, s, si);
+  else launch_group<T, MOM, HIST, ADV, false>(c, s, si);
+}
+
 template <bool ADV> pdf_status dispatch_step(pdf_ctx* c, StepIndex si) {
   if (c->p.f32_state) {
     StepArgs<float> s = step_args<float>(c);
-    if (ADV) s.cmean = (c->mlp_w && c->persist) ? c->mlp_cm : nullptr;
+    if (ADV) s.cmean = mlp_separate(c) ? c->mlp_cm : nullptr;
     if (!ADV) s.mlp_w = nullptr;
-    if (c->p.moments == 2) launch_group<float, 2, 0, ADV>(c, s, si);
-    else launch_group<float, 4, 32, ADV>(c, s, si);
+    if (c->p.moments == 2) launch_omega<float, 2, 0, ADV>(c, s, si);
+    else launch_omega<float, 4, 32, ADV>(c, s, si);
   } else {
     StepArgs<double> s = step_args<double>(c);
-    if (ADV) s.cmean = (c->mlp_w && c->persist) ? c->mlp_cm : nullptr;
+    if (ADV) s.cmean = mlp_separate(c) ? c->mlp_cm : nullptr;
     if (!ADV) s.mlp_w = nullptr;
-    launch_group<double, 2, 0, ADV>(c, s, si);
+    launch_omega<double, 2, 0, ADV>(c, s, si);
   }
   return hip_check(c, hipGetLastError(), "step launch");
 }
@@ -329,8 +358,8 @@ template <typename T> RepackMove<T> repack_move_args(pdf_ctx* c, uint32_t rot) {
   const Layout& L = c->L;
   char* a = c->arena;
   RepackMove<T> m{};
-  m.buf[0] = state_at<T>(a, L.buf0, L.slots);
-  m.buf[1] = state_at<T>(a, L.buf1, L.slots);
+  m.buf[0] = state_at<T>(a, L.buf0, L.slots, L.omega);
+  m.buf[1] = state_at<T>(a, L.buf1, L.slots, L.omega);
   m.start = (int32_t*)(a + L.start);
   m.cap = (int32_t*)(a + L.cap);
   m.ns = (int32_t*)(a + L.ns[rot]);
@@ -364,34 +393,40 @@ struct StepLaunch {
   int blocks = 0;
 };
 
-template <typename T, int MOM, int HIST, int G, int SCHED>
+template <typename T, int MOM, int HIST, int G, int SCHED, bool OMG>
 StepLaunch step_launch_of(pdf_ctx* c, StepArgs<T>& s) {
   constexpr int GPW = WAVE / G;
   s.nitems = (s.ncell + GPW - 1) / GPW;
   int blocks = (s.nitems + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
   if (SCHED == 1) {
     int per_cu = 0, cus = 0;
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step<T, MOM, HIST, G, true, SCHED>, BLOCK, 0);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step<T, MOM, HIST, G, true, SCHED, OMG>, BLOCK, 0);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device);
     blocks = std::min(blocks, std::max(1, per_cu) * std::max(1, cus));
   }
   s.pchunk = persist_chunk(s.nitems, blocks);
   StepLaunch l;
-  l.func = reinterpret_cast<const void*>(&k_step<T, MOM, HIST, G, true, SCHED>);
+  l.func = reinterpret_cast<const void*>(&k_step<T, MOM, HIST, G, true, SCHED, OMG>);
   l.blocks = blocks;
   return l;
 }
 
-template <typename T, int MOM, int HIST>
+template <typename T, int MOM, int HIST, bool OMG, int G>
+StepLaunch step_launch_shape(pdf_ctx* c, StepArgs<T>& s, int sc) {
+  if (sc == 1) return step_launch_of<T, MOM, HIST, G, 1, OMG>(c, s);
+  if constexpr (!OMG) {
+    if (sc == 2) return step_launch_of<T, MOM, HIST, G, 2, OMG>(c, s);
+  }
+  return step_launch_of<T, MOM, HIST, G, 0, OMG>(c, s);
+}
+
+template <typename T, int MOM, int HIST, bool OMG>
 StepLaunch step_launch_group(pdf_ctx* c, StepArgs<T>& s) {
   const int sc = sched_of(c, true);
   switch (c->group) {
-    case 16: return sc == 1 ? step_launch_of<T, MOM, HIST, 16, 1>(c, s)
-                            : (sc == 2 ? step_launch_of<T, MOM, HIST, 16, 2>(c, s) : step_launch_of<T, MOM, HIST, 16, 0>(c, s));
-    case 32: return sc == 1 ? step_launch_of<T, MOM, HIST, 32, 1>(c, s)
-                            : (sc == 2 ? step_launch_of<T, MOM, HIST, 32, 2>(c, s) : step_launch_of<T, MOM, HIST, 32, 0>(c, s));
-    default: return sc == 1 ? step_launch_of<T, MOM, HIST, 64, 1>(c, s)
-                            : (sc == 2 ? step_launch_of<T, MOM, HIST, 64, 2>(c, s) : step_launch_of<T, MOM, HIST, 64, 0>(c, s));
+    case 16: return step_launch_shape<T, MOM, HIST, OMG, 16>(c, s, sc);
+    case 32: return step_launch_shape<T, MOM, HIST, OMG, 32>(c, s, sc);
+    default: return step_launch_shape<T, MOM, HIST, OMG, 64>(c, s, sc);
   }
 }
 
@@ -404,8 +439,10 @@ template <typename T> pdf_status build_graph_t(pdf_ctx* c) {
   // the runtime copies kernel arguments into each node when it is added
   StepArgs<T> args_store = step_args<T>(c);
   StepLaunch l;
-  if (c->p.moments == 2) l = step_launch_group<T, 2, 0>(c, args_store);
-  else l = step_launch_group<T, 4, 32>(c, args_store);
+  if (c->p.moments == 2)
+    l = c->p.omega ? step_launch_group<T, 2, 0, true>(c, args_store) : step_launch_group<T, 2, 0, false>(c, args_store);
+  else
+    l = c->p.omega ? step_launch_group<T, 4, 32, true>(c, args_store) : step_launch_group<T, 4, 32, false>(c, args_store);
   pdf_status r;
   hipGraph_t g = nullptr;
   if ((r = hip_check(c, hipGraphCreate(&g, 0), "graph create"))) return r;
@@ -473,9 +510,10 @@ pdf_status enqueue_steps(pdf_ctx* c, int32_t nsteps) {
   for (int32_t i = 0; i < nsteps; ++i) {
     StepIndex si{(uint32_t)i, c->parity, c->rot, 0};
     pdf_status r;
-    // persistent grids take the learned means from a separate statistics pass
-    // and inference launch; the other grids compute them inside the step
-    if (c->mlp_w && c->persist && (r = enqueue_mlp_means(c, si))) return r;
+    // persistent grids (and steps with the turbulent frequency) take the
+    // learned means from a separate statistics pass and inference launch; the
+    // other grids compute them inside the step
+    if (mlp_separate(c) && (r = enqueue_mlp_means(c, si))) return r;
     if ((r = dispatch_step<true>(c, si))) return r;
     c->parity ^= 1u;
     c->rot = c->rot == 2 ? 0 : c->rot + 1;
@@ -496,6 +534,9 @@ pdf_status pdf_create(const pdf_params* p, void* hip_stream, pdf_ctx** out) {
   if (!(p->moments == 2 || p->moments == 4)) return PDF_E_ARG;
   if (!(p->hist_bins == 0 || p->hist_bins == 32)) return PDF_E_ARG;
   if (!(p->dt > 0.0) || p->nu < 0.0 || !(p->slack >= 1.0)) return PDF_E_ARG;
+  if (!(p->omega == 0 || p->omega == 1)) return PDF_E_ARG;
+  if (p->omega && (!(p->C3 > 0.0) || !(p->C4 > 0.0) || !(((((0.5 + 0.75 * p->C0) + p->C3) + p->Cw2) - p->Cw1) > 0.0)))
+    return PDF_E_ARG;
   if (!supported(*p)) return PDF_E_ARG;
   pdf_ctx* c = new pdf_ctx();
   c->p = *p;
@@ -513,7 +554,7 @@ pdf_status pdf_query_sizes(const pdf_ctx* c, pdf_sizes* s) {
   const int64_t ncell = (int64_t)s->nelem * s->nens;
   const int64_t slots = slots_bound(s->nparticles, ncell, c->p.slack);
   if (slots >= (int64_t)1 << 31) return PDF_E_SIZE;
-  const Layout L = make_layout(s->nvert, s->nelem, s->nens, slots, nstat_of(c->p), tsize_of(c->p));
+  const Layout L = make_layout(s->nvert, s->nelem, s->nens, slots, nstat_of(c->p), tsize_of(c->p), c->p.omega != 0);
   s->arena_bytes = L.total;
   s->slots = slots;
   return PDF_OK;
@@ -535,8 +576,8 @@ pdf_status pdf_init_mesh(pdf_ctx* c, const pdf_mesh* m, void* arena, int64_t are
   c->arena = (char*)arena;
   c->arena_bytes = arena_bytes;
   // the mesh part of the layout does not depend on the ensembles
-  Layout L = make_layout(c->nv, c->ne, 1, 1, nstat_of(c->p), tsize_of(c->p));
-  if (L.erec + (int64_t)c->ne * (int64_t)sizeof(ERec) > arena_bytes) return fail(c, PDF_E_SIZE, "arena too small for the mesh");
+  Layout L = make_layout(c->nv, c->ne, 1, 1, nstat_of(c->p), tsize_of(c->p), c->p.omega != 0);
+  if (L.start > arena_bytes) return fail(c, PDF_E_SIZE, "arena too small for the mesh");
   c->L = L;
   hipStream_t st = c->stream;
   pdf_status r;
@@ -567,6 +608,11 @@ pdf_status pdf_init_mesh(pdf_ctx* c, const pdf_mesh* m, void* arena, int64_t are
     hipLaunchKernelGGL(k_coefficients<double>, dim3((c->nv + tb - 1) / tb), dim3(tb), 0, st,
                        (const double*)(c->arena + L.fields), (double*)(c->arena + L.coef), c->nv, c->p.model,
                        c->p.C0, c->p.nu, c->p.CT);
+  if (c->p.omega)
+    hipLaunchKernelGGL(k_omega_fields, dim3((c->ne + tb - 1) / tb), dim3(tb), 0, st, (const int32_t*)(c->arena + L.tri),
+                       (const int32_t*)(c->arena + L.ekind), (const double*)(c->arena + L.fields),
+                       (double*)(c->arena + L.om0), (double*)(c->arena + L.somega), (double*)(c->arena + L.omw), c->ne,
+                       c->p.nu, c->p.CT, c->p.Cw1, c->p.Cw2);
   if ((r = hip_check(c, hipGetLastError(), "init kernels"))) return r;
   int32_t bad = 0;
   if ((r = hip_check(c, hipMemcpyAsync(&bad, flag, 4, hipMemcpyDeviceToHost, st), "read mesh flag"))) return r;
@@ -624,7 +670,7 @@ pdf_status pdf_seed_particles(pdf_ctx* c, int32_t nens, const int64_t* counts, c
                      [&](int32_t x, int32_t y) { return c->h_cnt[x] > c->h_cnt[y]; });
   }
   const int64_t slots = slot + growth_reserve(total, slack);
-  const Layout L = make_layout(c->nv, c->ne, nens, slots, nstat_of(c->p), tsize_of(c->p));
+  const Layout L = make_layout(c->nv, c->ne, nens, slots, nstat_of(c->p), tsize_of(c->p), c->p.omega != 0);
   if (L.total > c->arena_bytes)
     return fail(c, PDF_E_SIZE, "arena too small for the particle layout (query with slack >= 2)");
   c->L = L;
@@ -658,7 +704,8 @@ pdf_status pdf_seed_particles(pdf_ctx* c, int32_t nens, const int64_t* counts, c
                        c->p.nu, c->p.CT, c->p.Cs, c->p.Ct);
     hipLaunchKernelGGL(k_seed<float>, dim3(cb), dim3(BLOCK), 0, st, s.erec, s.tri, s.inv2a,
                        (const double*)(a + L.fields), s.buf[0], s.start, (const int32_t*)s.ns[0],
-                       (const int32_t*)(a + L.idoff), s.seed, c->ne, (int)ncell, c->p.psi_init);
+                       (const int32_t*)(a + L.idoff), s.seed, c->ne, (int)ncell, c->p.psi_init,
+                       (const double*)(a + L.om0));
   } else {
     StepArgs<double> s = step_args<double>(c);
     hipLaunchKernelGGL(k_rate<double>, dim3((unsigned)((ncell + tb - 1) / tb)), dim3(tb), 0, st, (const double*)(a + L.vtx), s.tri,
@@ -666,7 +713,8 @@ pdf_status pdf_seed_particles(pdf_ctx* c, int32_t nens, const int64_t* counts, c
                        c->p.nu, c->p.CT, c->p.Cs, c->p.Ct);
     hipLaunchKernelGGL(k_seed<double>, dim3(cb), dim3(BLOCK), 0, st, s.erec, s.tri, s.inv2a,
                        (const double*)(a + L.fields), s.buf[0], s.start, (const int32_t*)s.ns[0],
-                       (const int32_t*)(a + L.idoff), s.seed, c->ne, (int)ncell, c->p.psi_init);
+                       (const int32_t*)(a + L.idoff), s.seed, c->ne, (int)ncell, c->p.psi_init,
+                       (const double*)(a + L.om0));
   }
   if ((r = hip_check(c, hipGetLastError(), "seed kernels"))) return r;
   // the host vectors stay alive in the context until the copies complete
@@ -692,9 +740,9 @@ pdf_status pdf_step_graph(pdf_ctx* c, int32_t nsteps) {
   if (!c || nsteps < 0) return fail(c, PDF_E_ARG, "pdf_step_graph: bad argument");
   if (!c->seeded) return fail(c, PDF_E_STATE, "pdf_step_graph before pdf_seed_particles");
   pdf_status r;
-  // with the learned conditional means on a persistent grid every step is
+  // with the learned conditional means as a separate pass every step is
   // launched directly
-  if (c->mlp_w && c->persist) return enqueue_steps(c, nsteps);
+  if (mlp_separate(c)) return enqueue_steps(c, nsteps);
   // align to the start of a parity / counter-set cycle with ordinary launches
   int32_t lead = (int32_t)((GRAPH_STEPS - c->steps_done % GRAPH_STEPS) % GRAPH_STEPS);
   lead = std::min(lead, nsteps);
@@ -829,8 +877,9 @@ pdf_status pdf_sync(pdf_ctx* c) {
   return PDF_OK;
 }
 
-pdf_status pdf_get_state(pdf_ctx* c, int32_t ens, double* xyuvwpsi, int32_t* elem) {
-  if (!c || !xyuvwpsi || !elem) return fail(c, PDF_E_ARG, "pdf_get_state: null output");
+// State of one ensemble in id order; om (may be null) receives the turbulent
+// frequency.
+static pdf_status gather_state(pdf_ctx* c, int32_t ens, double* xyuvwpsi, int32_t* elem, double* om) {
   if (!c->seeded) return fail(c, PDF_E_STATE, "state before seeding");
   if (ens < 0 || ens >= c->nens) return fail(c, PDF_E_ARG, "ensemble out of range");
   const int64_t n = c->ens_count[ens];
@@ -843,16 +892,39 @@ pdf_status pdf_get_state(pdf_ctx* c, int32_t ens, double* xyuvwpsi, int32_t* ele
     cs.nm[r] = (int32_t*)(a + L.nm[r]);
   }
   if (c->p.f32_state)
-    hipLaunchKernelGGL(k_gather<float>, dim3(blocks), dim3(BLOCK), 0, c->stream, state_at<float>(a, L.buf0, L.slots),
-                       state_at<float>(a, L.buf1, L.slots), cs, (const int32_t*)(a + L.start),
+    hipLaunchKernelGGL(k_gather<float>, dim3(blocks), dim3(BLOCK), 0, c->stream, state_at<float>(a, L.buf0, L.slots, L.omega),
+                       state_at<float>(a, L.buf1, L.slots, L.omega), cs, (const int32_t*)(a + L.start),
                        (const int32_t*)(a + L.cap), (const Ctl*)(a + L.ctl), StepIndex{0, c->parity, c->rot, 0}, ens, c->ne, n, xyuvwpsi,
-                       elem);
+                       elem, om);
   else
-    hipLaunchKernelGGL(k_gather<double>, dim3(blocks), dim3(BLOCK), 0, c->stream, state_at<double>(a, L.buf0, L.slots),
-                       state_at<double>(a, L.buf1, L.slots), cs, (const int32_t*)(a + L.start),
+    hipLaunchKernelGGL(k_gather<double>, dim3(blocks), dim3(BLOCK), 0, c->stream, state_at<double>(a, L.buf0, L.slots, L.omega),
+                       state_at<double>(a, L.buf1, L.slots, L.omega), cs, (const int32_t*)(a + L.start),
                        (const int32_t*)(a + L.cap), (const Ctl*)(a + L.ctl), StepIndex{0, c->parity, c->rot, 0}, ens, c->ne, n, xyuvwpsi,
-                       elem);
+                       elem, om);
   return hip_check(c, hipGetLastError(), "gather launch");
+}
+
+pdf_status pdf_get_state(pdf_ctx* c, int32_t ens, double* xyuvwpsi, int32_t* elem) {
+  if (!c || !xyuvwpsi || !elem) return fail(c, PDF_E_ARG, "pdf_get_state: null output");
+  return gather_state(c, ens, xyuvwpsi, elem, nullptr);
+}
+
+pdf_status pdf_get_omega(pdf_ctx* c, int32_t ens, double* xyuvwpsi, int32_t* elem, double* om) {
+  if (!c || !xyuvwpsi || !elem || !om) return fail(c, PDF_E_ARG, "pdf_get_omega: null output");
+  if (!c->p.omega) return fail(c, PDF_E_STATE, "pdf_get_omega: the context carries no turbulent frequency");
+  return gather_state(c, ens, xyuvwpsi, elem, om);
+}
+
+pdf_status pdf_omega_fields(pdf_ctx* c, double* om0, double* somega, double* omw) {
+  if (!c || !om0 || !somega || !omw) return fail(c, PDF_E_ARG, "pdf_omega_fields: null output");
+  if (!c->mesh_ready) return fail(c, PDF_E_STATE, "pdf_omega_fields before pdf_init_mesh");
+  if (!c->p.omega) return fail(c, PDF_E_STATE, "pdf_omega_fields: the context carries no turbulent frequency");
+  pdf_status r;
+  const char* a = c->arena;
+  if ((r = hip_check(c, hipMemcpyAsync(om0, a + c->L.om0, (size_t)c->ne * 8, hipMemcpyDeviceToHost, c->stream), "copy om0"))) return r;
+  if ((r = hip_check(c, hipMemcpyAsync(somega, a + c->L.somega, (size_t)c->ne * 8, hipMemcpyDeviceToHost, c->stream), "copy somega"))) return r;
+  if ((r = hip_check(c, hipMemcpyAsync(omw, a + c->L.omw, (size_t)c->ne * 24, hipMemcpyDeviceToHost, c->stream), "copy omw"))) return r;
+  return hip_check(c, hipStreamSynchronize(c->stream), "sync omega fields");
 }
 
 int64_t pdf_count(const pdf_ctx* c, int32_t ens) {
@@ -931,8 +1003,8 @@ template <typename T> void launch_dataset(pdf_ctx* c, int32_t target, uint64_t k
   const Layout& L = c->L;
   char* a = c->arena;
   mlp::DatasetArgs<T> d{};
-  d.buf[0] = state_at<T>(a, L.buf0, L.slots);
-  d.buf[1] = state_at<T>(a, L.buf1, L.slots);
+  d.buf[0] = state_at<T>(a, L.buf0, L.slots, L.omega);
+  d.buf[1] = state_at<T>(a, L.buf1, L.slots, L.omega);
   d.ctl = (const Ctl*)(a + L.ctl);
   d.parity = c->parity;
   d.start = (const int32_t*)(a + L.start);

@@ -123,6 +123,21 @@ template <typename T> __device__ __forceinline__ void series_sincos2pi(T t, T* s
   *cs_out = co;
 }
 
+// exp x = 2^k exp r: k the nearest integer to x / ln 2, r = x - k ln 2 with
+// ln 2 split into a high part whose trailing bits are zero (so k times it is
+// exact) and a low part (Cody & Waite); exp r by its Taylor series through
+// r^13 (|r| <= ln 2 / 2, truncation below 2^-60) in Horner form; then the
+// exact scaling by 2^k.
+__device__ __forceinline__ double series_exp(double x) {
+  const double k = rint(x * 0x1.71547652b82fep0);
+  const double r = (x - k * 0x1.62e42fefa3800p-1) - k * 0x1.ef35793c76730p-45;
+  double p = inv_fact<double>(13);
+#pragma unroll
+  for (int j = 12; j >= 1; --j) p = p * r + inv_fact<double>(j);
+  p = p * r + 1.0;
+  return ldexp(p, (int)k);
+}
+
 // Box-Muller (Box & Muller 1958) on two words.
 template <typename T> __device__ __forceinline__ void box_muller(uint32_t r1, uint32_t r2, T* z0, T* z1) {
   const T u1 = uniform01<T>(r1), u2 = uniform01<T>(r2);
