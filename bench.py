@@ -28,6 +28,8 @@ WORKLOADS = {
     "batched64": ("config4", "64 independent canyon runs on the 9912-element mesh, 12.2M particles in total "
                              "(10k-1M per run, log-uniform), distinct seeds and sources"),
     "canyon10m": ("config3", "wall-function canyon, 48618-element mesh, 10M particles, SLM, 4th moments + histograms"),
+    "canyon10m_omega": ("config3w", "wall-function canyon, 48618-element mesh, 10M particles, SLM, 4th moments + "
+                                    "histograms, stochastic turbulent frequency per particle"),
     "square40k": ("config1", "unit square 20x20x2, 40k particles, SLM, FP64"),
 }
 
@@ -45,18 +47,19 @@ def kernel_source_hash() -> str:
 def algorithmic_bytes(wl) -> dict:
     """Bytes one step must move at minimum in this design.
 
-    Per particle: read x y u v w psi id, write the same (7 words of state
-    type each way).  Per element cell: the statistics record written, the
-    cell's start/capacity/count/rate words, its mesh record and an even share
-    of the vertex coefficient table.
+    Per particle: read x y u v w psi id (and omega when carried), write the
+    same.  Per element cell: the statistics record written, the cell's
+    start/capacity/count/rate words, its mesh record and an even share of the
+    vertex coefficient table.
     """
     ts = 4 if wl.precision == "f32" else 8
-    per_particle = 2 * (6 * ts + 4)
-    nstat = (86 if wl.moments >= 4 else 31) + wl.hist_bins
+    om = bool(getattr(wl, "omega", False))
+    per_particle = 2 * ((7 if om else 6) * ts + 4)
+    nstat = (86 if wl.moments >= 4 else 31) + wl.hist_bins + (3 if om else 0)
     ne, nv = wl.mesh.nelem, wl.mesh.nvert
     ncell = ne * wl.nens
     per_cell = nstat * 8 + 4 * 4 + ts
-    per_mesh = ne * (3 * 4 * 3 + 8 + 3 * 8) + nv * (2 * 8 + 16 * ts)
+    per_mesh = ne * (3 * 4 * 3 + 8 + 3 * 8 + (8 if om else 0)) + nv * (2 * 8 + 16 * ts)
     n = wl.n_total
     total = n * per_particle + ncell * per_cell + per_mesh
     return dict(per_particle=per_particle, per_cell=per_cell, per_step=total, particles=n)
@@ -113,7 +116,7 @@ def cpu_baseline(wl_fn, seconds: float = 15.0) -> dict:
         orc.step(1)
         steps += 1
         el = time.perf_counter() - t0
-        if el >= seconds or steps >= 50:
+        if el >= seconds or steps >= 2000:
             break
     n = wl.n_total
     return {"value": n * steps / el, "unit": "particle-steps/s", "cores": threads, "kind": "oracle",
@@ -241,7 +244,7 @@ def main() -> int:
     ap.add_argument("--workload", default="canyon1m", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--secondary", default="canyon10m,batched64",
+    ap.add_argument("--secondary", default="canyon10m,batched64,canyon10m_omega",
                     help="further workloads reported in the same line, comma separated ('' for none)")
     ap.add_argument("--secondary-steps", type=int, default=100)
     ap.add_argument("--no-graph", action="store_true", help="launch steps one by one instead of graph replays")
@@ -331,6 +334,7 @@ def main() -> int:
                        "elements": wl.mesh.nelem, "vertices": wl.mesh.nvert, "ensembles": wl.nens,
                        "state_dtype": wl.precision, "statistics_dtype": "f64", "model": wl.describe()["model"],
                        "moments": wl.moments, "hist_bins": wl.hist_bins, "dt": wl.dt,
+                       "turbulent_frequency": bool(getattr(wl, "omega", False)),
                        "launch": {"lanes_per_cell": shape[0], "persistent": bool(shape[1]),
                                   "autotune_steps_per_candidate": 0 if args.launch else autotune_steps,
                                   "hip_graph": not args.no_graph},

@@ -140,6 +140,15 @@ def config3(steps: int = 1000, n: int = 10_000_000, seed: int = 0, target: int =
                     moments=4, hist_bins=32, steps=steps, yp=yp)
 
 
+def config3w(steps: int = 1000, n: int = 10_000_000, seed: int = 0, target: int = 50000) -> Workload:
+    """The large wall-function canyon with the stochastic turbulent frequency
+    carried by every particle (eqs. 8-10 and the wall condition on omega)."""
+    wl = config3(steps=steps, n=n, seed=seed, target=target)
+    wl.omega = True
+    wl.name = wl.name + "_omega"
+    return wl
+
+
 def config4(steps: int = 100, nens: int = 64, target: int = 10000) -> Workload:
     """64 independent canyon runs of uneven size on the 10k-element mesh."""
     m, f = _canyon(target, False)
