@@ -24,6 +24,7 @@ CFLAGS = ["-O2", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fa
 
 NSTAT_2 = 31
 NSTAT_4 = 86
+AV_STEPS, AV_N, AV_MEAN, AV_M2, AV_HIST = 0, 1, 2, 6, 16
 ST_N, ST_MEAN, ST_M2, ST_BINN, ST_BINM, ST_M3, ST_M4 = 0, 1, 5, 15, 23, 31, 51
 
 
@@ -104,6 +105,14 @@ def lib():
         L.orc_set_omega.restype = i32
         L.orc_set_omega.argtypes = [vp, i32, vp]
         L.orc_omega_fields.argtypes = [vp, vp, vp, vp]
+        L.orc_navg.restype = i32
+        L.orc_navg.argtypes = [vp]
+        L.orc_average_start.argtypes = [vp]
+        L.orc_average_stop.argtypes = [vp]
+        L.orc_average.restype = i32
+        L.orc_average.argtypes = [vp, i32, vp]
+        L.orc_locate.restype = i32
+        L.orc_locate.argtypes = [vp, d, d]
         L.orc_wallfn_hits.restype = i64
         L.orc_wallfn_hits.argtypes = [vp]
         L.orc_walk.restype = i32
@@ -210,6 +219,23 @@ class Oracle:
         om0, sw, omw = np.zeros(ne), np.zeros(ne), np.zeros((ne, 3))
         lib().orc_omega_fields(self.ctx, _ptr(om0), _ptr(sw), _ptr(omw))
         return om0, sw, omw
+
+    def average_start(self) -> None:
+        """Average the statistics of every following step (restarts the average)."""
+        lib().orc_average_start(self.ctx)
+
+    def average_stop(self) -> None:
+        lib().orc_average_stop(self.ctx)
+
+    def average(self, ens: int = 0) -> np.ndarray:
+        """Time-averaged records (nelem x navg), layout of ORC_AV_*."""
+        L = lib()
+        out = np.zeros((self.wl.mesh.nelem, L.orc_navg(self.ctx)))
+        L.orc_average(self.ctx, ens, _ptr(out))
+        return out
+
+    def locate(self, x: float, y: float) -> int:
+        return int(lib().orc_locate(self.ctx, float(x), float(y)))
 
     def wallfn_hits(self) -> int:
         """Particle steps so far whose frequency a wall-function reflection changed."""

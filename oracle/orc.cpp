@@ -222,6 +222,10 @@ struct orc_ctx {
   std::vector<Ens<float>> ensF;
   std::vector<Ens<double>> ensD;
   int64_t step = 0;
+  // time averaging: the statistics record of every step since the start,
+  // per ensemble (kept whole; combined when asked for)
+  bool averaging = false;
+  std::vector<std::vector<std::vector<double>>> avg_rec;
 };
 
 namespace {
@@ -801,9 +805,11 @@ template <typename T> int advance(orc_ctx* c, Ens<T>& en, uint32_t ens_index, ui
 }
 
 template <typename T> int step_all(orc_ctx* c, std::vector<Ens<T>>& ens) {
+  if (c->averaging && c->avg_rec.size() < ens.size()) c->avg_rec.resize(ens.size());
   for (size_t k = 0; k < ens.size(); ++k) {
     std::vector<double> st;
     estimate<T>(c, ens[k], st);
+    if (c->averaging) c->avg_rec[k].push_back(st);
     int r = advance<T>(c, ens[k], (uint32_t)k, (uint32_t)c->step, st);
     if (r) return r;
   }
@@ -931,6 +937,81 @@ int32_t orc_set_state(orc_ctx* c, int32_t ens, const double* x, const double* y,
 }
 
 double orc_exp64(double x) { return exp_series(x); }
+
+int32_t orc_navg(const orc_ctx* c) {
+  return ORC_AV_HIST + c->p.hist_bins + (c->p.omega ? 2 : 0);
+}
+
+void orc_average_start(orc_ctx* c) {
+  c->averaging = true;
+  c->avg_rec.clear();
+}
+
+void orc_average_stop(orc_ctx* c) { c->averaging = false; }
+
+// Time-averaged statistics: the particles of an element over all averaged
+// steps taken as one pooled sample.  With n_t, m_t and C_t the count, means
+// and central second moments of step t, the pooled count is N = sum n_t, the
+// mean M = sum n_t m_t / N and the central moments
+// sum n_t (C_t + (m_t - M)(m_t - M)^T) / N (the law of total variance), two
+// passes over the stored records; histograms add up.
+int32_t orc_average(const orc_ctx* c, int32_t ens, double* out) {
+  const orc_params& p = c->p;
+  const int ns = nstat_of(p);
+  const int na = orc_navg(c);
+  const int hoff = p.moments >= 4 ? ORC_NSTAT_4 : ORC_NSTAT_2;
+  std::memset(out, 0, sizeof(double) * (size_t)na * c->ne);
+  if (ens < 0 || (size_t)ens >= c->avg_rec.size()) return 0;
+  const std::vector<std::vector<double>>& recs = c->avg_rec[ens];
+  const double T = (double)recs.size();
+  for (int e = 0; e < c->ne; ++e) {
+    double* o = out + (size_t)e * na;
+    o[ORC_AV_STEPS] = T;
+    double N = 0.0, sm[4] = {0, 0, 0, 0}, sw = 0.0;
+    for (const std::vector<double>& st : recs) {
+      const double* r = &st[(size_t)e * ns];
+      const double n = r[ORC_ST_N];
+      N += n;
+      for (int q = 0; q < 4; ++q) sm[q] += n * r[ORC_ST_MEAN + q];
+      if (p.omega) sw += n * r[ns - 3];
+      for (int h = 0; h < p.hist_bins; ++h) o[ORC_AV_HIST + h] += r[hoff + h];
+    }
+    o[ORC_AV_N] = N;
+    if (N == 0.0) continue;
+    double M[4];
+    for (int q = 0; q < 4; ++q) M[q] = sm[q] / N;
+    const double MW = sw / N;
+    double C[10] = {0}, CW = 0.0;
+    for (const std::vector<double>& st : recs) {
+      const double* r = &st[(size_t)e * ns];
+      const double n = r[ORC_ST_N];
+      if (n == 0.0) continue;
+      double d[4];
+      for (int q = 0; q < 4; ++q) d[q] = r[ORC_ST_MEAN + q] - M[q];
+      int idx = 0;
+      for (int a = 0; a < 4; ++a)
+        for (int b = a; b < 4; ++b, ++idx) C[idx] += n * (r[ORC_ST_M2 + idx] + d[a] * d[b]);
+      if (p.omega) {
+        const double dw = r[ns - 3] - MW;
+        CW += n * (r[ns - 2] + dw * dw);
+      }
+    }
+    for (int q = 0; q < 4; ++q) o[ORC_AV_MEAN + q] = M[q];
+    for (int t = 0; t < 10; ++t) o[ORC_AV_M2 + t] = C[t] / N;
+    if (p.omega) {
+      o[ORC_AV_HIST + p.hist_bins] = MW;
+      o[ORC_AV_HIST + p.hist_bins + 1] = CW / N;
+    }
+  }
+  return 0;
+}
+
+int32_t orc_locate(const orc_ctx* c, double x, double y) {
+  for (int e = 0; e < c->ne; ++e)
+    if (orient_edge(c, e, 0, x, y) >= 0.0 && orient_edge(c, e, 1, x, y) >= 0.0 && orient_edge(c, e, 2, x, y) >= 0.0)
+      return e;
+  return -1;
+}
 
 int64_t orc_wallfn_hits(const orc_ctx* c) { return c->wf_hits; }
 

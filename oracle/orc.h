@@ -45,6 +45,17 @@ enum {
   ORC_NSTAT_4 = 86
 };
 
+/* time-averaged record per element, doubles, in this order; with the
+   turbulent frequency two more after the histogram: pooled <omega> and
+   <omega'^2> */
+enum {
+  ORC_AV_STEPS = 0,    /* steps averaged                                    */
+  ORC_AV_N = 1,        /* pooled particle count (sum over the steps)        */
+  ORC_AV_MEAN = 2,     /* 4: pooled means of u, v, w, psi                   */
+  ORC_AV_M2 = 6,       /* 10: pooled central 2nd moments                    */
+  ORC_AV_HIST = 16     /* hist_bins: summed scalar histogram counts         */
+};
+
 typedef struct orc_params {
   int32_t f32_state;   /* 1: float particle state, 0: double */
   int32_t model;       /* 0 SLM (eq. 19), 1 GLM from wp (eqs. 12-13) */
@@ -94,6 +105,15 @@ int32_t orc_set_omega(orc_ctx* c, int32_t ens, const double* om);
    (eq. 10); per element edge: frozen <omega> at a wall-function edge's
    midpoint (0 elsewhere). */
 void orc_omega_fields(const orc_ctx* c, double* om0, double* somega, double* omw);
+/* Time averaging: from orc_average_start on, every step's statistics record
+   (of the state at the start of the step) joins the average; orc_average
+   writes the time-averaged records of one ensemble (nelem x orc_navg). */
+int32_t orc_navg(const orc_ctx* c);
+void orc_average_start(orc_ctx* c);
+void orc_average_stop(orc_ctx* c);
+int32_t orc_average(const orc_ctx* c, int32_t ens, double* out);
+/* Lowest-index element whose closed triangle contains (x, y), or -1. */
+int32_t orc_locate(const orc_ctx* c, double x, double y);
 /* Particle steps so far in which a wall-function reflection changed omega. */
 int64_t orc_wallfn_hits(const orc_ctx* c);
 
