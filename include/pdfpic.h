@@ -224,6 +224,45 @@ pdf_status pdf_get_omega(pdf_ctx* ctx, int32_t ens, double* xyuvwpsi, int32_t* e
    if the context carries no turbulent frequency. */
 pdf_status pdf_omega_fields(pdf_ctx* ctx, double* om0, double* somega, double* omw);
 
+/* Time averaging (the statistics the paper collects once the flow is
+   stationary).  pdf_average_attach clears acc (device memory, caller-owned:
+   nens x nelem x pdf_navg doubles) and from then on every step merges the
+   statistics record it computes (of the state at the start of the step) into
+   acc, on the stream, also inside graph replays; acc = NULL stops it.  acc
+   per cell then holds the statistics of the cell's particles over all merged
+   steps taken as one sample:
+     PDF_AV_STEPS  steps merged
+     PDF_AV_N      pooled particle count (sum of the per-step counts)
+     PDF_AV_MEAN   4: pooled <u> <v> <w> <psi>
+     PDF_AV_M2     10: pooled central second moments (PDF_ST_M2 pair order)
+     PDF_AV_HIST   hist_bins: summed scalar histogram counts
+     then, with the turbulent frequency, pooled <omega> and <omega'^2>.
+   Means and moments are combined pairwise per step (Chan, Golub & LeVeque),
+   so the result equals the law-of-total-variance pooling of the per-step
+   records up to rounding.  acc must stay valid while attached. */
+#define PDF_AV_STEPS 0
+#define PDF_AV_N 1
+#define PDF_AV_MEAN 2
+#define PDF_AV_M2 6
+#define PDF_AV_HIST 16
+int32_t pdf_navg(const pdf_ctx* ctx);
+pdf_status pdf_average_attach(pdf_ctx* ctx, double* acc);
+
+/* Point location: elem[i] = the lowest-index element whose closed triangle
+   contains point i (xy: n x 2 doubles), -1 if none.  Device memory in and
+   out, asynchronous.  Used to map sampling locations to elements. */
+pdf_status pdf_locate(pdf_ctx* ctx, const double* xy, int32_t n, int32_t* elem);
+
+/* Probe values of ensemble ens from a time average acc at the given elements
+   (device memory): out, nprobe x (4 + hist_bins) doubles per probe: steps
+   averaged, mean particle count per step, <psi>, <psi'^2>, then the scalar
+   CDF of eq. (29) at the upper edge of every histogram bin,
+   F((b + 1) / hist_bins) = fraction of the pooled particles with
+   psi < (b + 1) / hist_bins (the last bin includes psi = 1).  An element
+   index out of range yields NaN entries.  Asynchronous. */
+pdf_status pdf_average_probe(pdf_ctx* ctx, const double* acc, int32_t ens, const int32_t* elems, int32_t nprobe,
+                             double* out);
+
 /* Number of particles of an ensemble; steps enqueued since seeding. */
 int64_t pdf_count(const pdf_ctx* ctx, int32_t ens);
 int64_t pdf_steps_done(pdf_ctx* ctx);

@@ -30,7 +30,8 @@ ENTRY_POINTS = ("pdf_create", "pdf_query_sizes", "pdf_init_mesh", "pdf_seed_part
                 "pdf_estimate_statistics", "pdf_nstat", "pdf_sync",
                 "pdf_mlp_work_floats", "pdf_mlp_dataset", "pdf_mlp_forward", "pdf_mlp_grad", "pdf_mlp_train",
                 "pdf_mlp_norm", "pdf_mlp_round", "pdf_mlp_infer", "pdf_mlp_attach",
-                "pdf_get_state", "pdf_get_omega", "pdf_omega_fields", "pdf_count", "pdf_steps_done", "pdf_error_string", "pdf_destroy")
+                "pdf_get_state", "pdf_get_omega", "pdf_omega_fields", "pdf_navg", "pdf_average_attach",
+                "pdf_locate", "pdf_average_probe", "pdf_count", "pdf_steps_done", "pdf_error_string", "pdf_destroy")
 
 
 class PdfError(RuntimeError):
@@ -131,6 +132,14 @@ def load_library():
     L.pdf_get_omega.argtypes = [vp, i32, vp, vp, vp]
     L.pdf_omega_fields.restype = i32
     L.pdf_omega_fields.argtypes = [vp, vp, vp, vp]
+    L.pdf_navg.restype = i32
+    L.pdf_navg.argtypes = [vp]
+    L.pdf_average_attach.restype = i32
+    L.pdf_average_attach.argtypes = [vp, vp]
+    L.pdf_locate.restype = i32
+    L.pdf_locate.argtypes = [vp, vp, i32, vp]
+    L.pdf_average_probe.restype = i32
+    L.pdf_average_probe.argtypes = [vp, vp, i32, vp, i32, vp]
     L.pdf_count.restype = i64
     L.pdf_count.argtypes = [vp, i32]
     L.pdf_steps_done.restype = i64
@@ -320,6 +329,45 @@ class Simulation:
         if self.params.omega:
             out["omega"] = om.cpu().numpy()
         return out
+
+    # -- time averaging and probes ---------------------------------------------
+    def average_attach(self):
+        """Start (or restart) time averaging; returns the accumulator tensor
+        (nens, nelem, navg) that every following step merges into."""
+        navg = int(load_library().pdf_navg(self.ctx))
+        self._avg = self.torch.empty((self.nens, self.nelem, navg), dtype=self.torch.float64, device=self.device)
+        self._check(load_library().pdf_average_attach(self.ctx, ctypes.c_void_p(self._avg.data_ptr())),
+                    "pdf_average_attach")
+        return self._avg
+
+    def average_detach(self) -> None:
+        self._check(load_library().pdf_average_attach(self.ctx, None), "pdf_average_attach")
+
+    def average(self) -> np.ndarray:
+        """The time-averaged records so far (waits for the stream)."""
+        self.stream.synchronize()
+        return self._avg.cpu().numpy()
+
+    def locate(self, points) -> np.ndarray:
+        """Element containing each point (lowest index; -1 outside)."""
+        xy = self.torch.tensor(np.asarray(points, np.float64).reshape(-1, 2), device=self.device)
+        out = self.torch.empty((xy.shape[0],), dtype=self.torch.int32, device=self.device)
+        self._check(load_library().pdf_locate(self.ctx, ctypes.c_void_p(xy.data_ptr()), int(xy.shape[0]),
+                                              ctypes.c_void_p(out.data_ptr())), "pdf_locate")
+        self.stream.synchronize()
+        return out.cpu().numpy()
+
+    def probe(self, elems, ens: int = 0) -> np.ndarray:
+        """Probe rows (steps, count per step, <psi>, <psi'^2>, CDF at the bin
+        edges) of the current time average at the given elements."""
+        el = self.torch.tensor(np.asarray(elems, np.int32), device=self.device)
+        hist = int(self.params.hist_bins)
+        out = self.torch.empty((el.shape[0], 4 + hist), dtype=self.torch.float64, device=self.device)
+        self._check(load_library().pdf_average_probe(self.ctx, ctypes.c_void_p(self._avg.data_ptr()), int(ens),
+                                                     ctypes.c_void_p(el.data_ptr()), int(el.shape[0]),
+                                                     ctypes.c_void_p(out.data_ptr())), "pdf_average_probe")
+        self.stream.synchronize()
+        return out.cpu().numpy()
 
     def omega_fields(self):
         """(<omega> per centroid, S_omega per element, <omega> per wall-function

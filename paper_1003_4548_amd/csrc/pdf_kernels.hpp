@@ -1388,6 +1388,104 @@ __global__ void k_request_repack(Ctl* ctl) {
   if (threadIdx.x == 0 && blockIdx.x == 0) ctl->repack = 1u;
 }
 
+// ---------------------------------------------------------------------------
+// time averaging, point location, probes
+
+// Time-averaged record per cell (doubles): steps averaged, pooled particle
+// count, pooled means of u v w psi, pooled central second moments (pairs a<=b),
+// summed histogram, then (with the turbulent frequency) pooled <omega> and
+// <omega'^2>.
+enum { AV_STEPS = 0, AV_N = 1, AV_MEAN = 2, AV_M2 = 6, AV_HIST = 16 };
+
+// Merges each cell's statistics record of one step into its time average:
+// the pooled sample of all the cell's particles over the averaged steps.
+// Means and central moments are combined pairwise (Chan, Golub & LeVeque):
+// with counts na, nb and mean difference d, M' = M_a + d nb / n and
+// C' = (na C_a + nb C_b + d d^T na nb / n) / n.
+__global__ void k_average_merge(const double* stats, int nstat, int hoff, int hist, int omega, double* acc,
+                                int navg, int ncell) {
+  const int cell = blockIdx.x * blockDim.x + threadIdx.x;
+  if (cell >= ncell) return;
+  const double* r = stats + (size_t)cell * nstat;
+  double* A = acc + (size_t)cell * navg;
+  A[AV_STEPS] = A[AV_STEPS] + 1.0;
+  const double nb = r[ST_N];
+  if (!(nb > 0.0)) return;
+  const double na = A[AV_N], nn = na + nb;
+  const double fb = nb / nn, wab = na * fb;
+  double d[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) d[q] = r[ST_MEAN + q] - A[AV_MEAN + q];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) A[AV_MEAN + q] = A[AV_MEAN + q] + d[q] * fb;
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = x; y < 4; ++y) {
+      const int t = pair_index(x, y);
+      A[AV_M2 + t] = ((na * A[AV_M2 + t] + nb * r[ST_M2 + t]) + wab * (d[x] * d[y])) / nn;
+    }
+  for (int h = 0; h < hist; ++h) A[AV_HIST + h] = A[AV_HIST + h] + r[hoff + h];
+  if (omega) {
+    double* W = A + AV_HIST + hist;
+    const double dw = r[nstat - 3] - W[0];
+    W[0] = W[0] + dw * fb;
+    W[1] = ((na * W[1] + nb * r[nstat - 2]) + wab * (dw * dw)) / nn;
+  }
+  A[AV_N] = nn;
+}
+
+// Lowest-index element whose closed triangle contains each point (-1: none);
+// one block per point.
+__global__ __launch_bounds__(BLOCK) void k_locate(const ERec* erec, int ne, const double* xy, int npt,
+                                                  int32_t* out) {
+  __shared__ int best;
+  const int p = blockIdx.x;
+  if (p >= npt) return;
+  if (threadIdx.x == 0) best = 0x7fffffff;
+  __syncthreads();
+  const double px = xy[2 * p], py = xy[2 * p + 1];
+  for (int e = threadIdx.x; e < ne; e += BLOCK) {
+    const ERec R = erec[e];
+    if (orient_edge(R.x[0], R.y[0], R.x[1], R.y[1], px, py) >= 0.0 &&
+        orient_edge(R.x[1], R.y[1], R.x[2], R.y[2], px, py) >= 0.0 &&
+        orient_edge(R.x[2], R.y[2], R.x[0], R.y[0], px, py) >= 0.0) {
+      atomicMin(&best, e);
+      break;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) out[p] = best == 0x7fffffff ? -1 : best;
+}
+
+// Probe values from the time average of ensemble ens at the given elements,
+// 4 + hist doubles each: steps averaged, mean particle count per step, <psi>,
+// <psi'^2>, then the CDF of psi (eq. 29) at the upper edge of each histogram
+// bin, F((b + 1) / hist) = (particles with psi < (b + 1) / hist) / count, from
+// the summed histogram.  An element index out of range gives NaN.
+__global__ void k_probe(const double* acc, int navg, int ne, int ens, const int32_t* elems, int nprobe, int hist,
+                        double* out) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nprobe) return;
+  double* o = out + (size_t)p * (4 + hist);
+  const int e = elems[p];
+  if (e < 0 || e >= ne) {
+    for (int q = 0; q < 4 + hist; ++q) o[q] = __builtin_nan("");
+    return;
+  }
+  const double* A = acc + ((size_t)ens * ne + e) * navg;
+  const double T = A[AV_STEPS], N = A[AV_N];
+  o[0] = T;
+  o[1] = T > 0.0 ? N / T : 0.0;
+  o[2] = A[AV_MEAN + 3];
+  o[3] = A[AV_M2 + 9];
+  double cum = 0.0;
+  for (int b = 0; b < hist; ++b) {
+    cum = cum + A[AV_HIST + b];
+    o[4 + b] = N > 0.0 ? cum / N : 0.0;
+  }
+}
+
 __global__ void k_fill_i32(int32_t* p, int32_t v, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;

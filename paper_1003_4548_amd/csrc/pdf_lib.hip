@@ -129,6 +129,8 @@ struct pdf_ctx {
   const float* mlp_norm = nullptr;
   double* mlp_cm = nullptr;
   uint32_t* mlp_served = nullptr;
+  // time-averaged statistics (caller-owned, null: not averaging)
+  double* avg = nullptr;
   std::vector<uint64_t> h_seed;
   std::vector<double> h_src;
   std::vector<int64_t> ens_count;
@@ -143,6 +145,8 @@ int tsize_of(const pdf_params& p) { return p.f32_state ? 4 : 8; }
 int nstat_of(const pdf_params& p) {
   return (p.moments >= 4 ? NSTAT4 : NSTAT2) + p.hist_bins + (p.omega ? 3 : 0);
 }
+
+int navg_of(const pdf_params& p) { return AV_HIST + p.hist_bins + (p.omega ? 2 : 0); }
 
 // The learned conditional means run as a statistics pass and an inference
 // launch before each step on persistent grids and with the turbulent
@@ -335,6 +339,36 @@ pdf_status enqueue_mlp_means(pdf_ctx* c, StepIndex si) {
   return hip_check(c, hipGetLastError(), "inference launch");
 }
 
+// Arguments of the time-average merge of one step's statistics.
+struct MergeArgs {
+  const double* stats;
+  int nstat, hoff, hist, omega;
+  double* acc;
+  int navg, ncell;
+};
+
+MergeArgs merge_args(pdf_ctx* c) {
+  MergeArgs m{};
+  m.stats = (const double*)(c->arena + c->L.stats);
+  m.nstat = nstat_of(c->p);
+  m.hoff = c->p.moments >= 4 ? NSTAT4 : NSTAT2;
+  m.hist = c->p.hist_bins;
+  m.omega = c->p.omega;
+  m.acc = c->avg;
+  m.navg = navg_of(c->p);
+  m.ncell = c->ne * c->nens;
+  return m;
+}
+
+constexpr int MERGE_THREADS = 256;
+
+pdf_status enqueue_merge(pdf_ctx* c) {
+  const MergeArgs m = merge_args(c);
+  hipLaunchKernelGGL(k_average_merge, dim3((m.ncell + MERGE_THREADS - 1) / MERGE_THREADS), dim3(MERGE_THREADS), 0,
+                     c->stream, m.stats, m.nstat, m.hoff, m.hist, m.omega, m.acc, m.navg, m.ncell);
+  return hip_check(c, hipGetLastError(), "average launch");
+}
+
 RepackPlan repack_plan_args(pdf_ctx* c, uint32_t rot) {
   const Layout& L = c->L;
   char* a = c->arena;
@@ -449,6 +483,9 @@ template <typename T> pdf_status build_graph_t(pdf_ctx* c) {
   hipGraphNode_t prev = nullptr;
   StepIndex sis[GRAPH_STEPS];
   void* params[GRAPH_STEPS][2];
+  MergeArgs margs = merge_args(c);
+  void* mparams8[8] = {&margs.stats, &margs.nstat, &margs.hoff, &margs.hist, &margs.omega, &margs.acc, &margs.navg,
+                       &margs.ncell};
   for (int i = 0; i < GRAPH_STEPS; ++i) {
     sis[i] = StepIndex{(uint32_t)i, (uint32_t)(i % 2), (uint32_t)(i % 3), 0};
     params[i][0] = &args_store;
@@ -463,6 +500,16 @@ template <typename T> pdf_status build_graph_t(pdf_ctx* c) {
     hipGraphNode_t node;
     if ((r = hip_check(c, hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &kp), "graph node"))) return r;
     prev = node;
+    if (c->avg) {
+      hipKernelNodeParams km{};
+      km.func = reinterpret_cast<void*>(&k_average_merge);
+      km.gridDim = dim3((margs.ncell + MERGE_THREADS - 1) / MERGE_THREADS);
+      km.blockDim = dim3(MERGE_THREADS);
+      km.kernelParams = mparams8;
+      hipGraphNode_t mn;
+      if ((r = hip_check(c, hipGraphAddKernelNode(&mn, g, &prev, 1, &km), "graph node"))) return r;
+      prev = mn;
+    }
   }
   Ctl* ctl = (Ctl*)(c->arena + c->L.ctl);
   uint32_t nst = GRAPH_STEPS;
@@ -515,6 +562,8 @@ pdf_status enqueue_steps(pdf_ctx* c, int32_t nsteps) {
     // other grids compute them inside the step
     if (mlp_separate(c) && (r = enqueue_mlp_means(c, si))) return r;
     if ((r = dispatch_step<true>(c, si))) return r;
+    // the step's statistics (of the state it started from) join the time average
+    if (c->avg && (r = enqueue_merge(c))) return r;
     c->parity ^= 1u;
     c->rot = c->rot == 2 ? 0 : c->rot + 1;
     // the capacity check runs every GRAPH_STEPS steps, where the graph runs it
@@ -925,6 +974,38 @@ pdf_status pdf_omega_fields(pdf_ctx* c, double* om0, double* somega, double* omw
   if ((r = hip_check(c, hipMemcpyAsync(somega, a + c->L.somega, (size_t)c->ne * 8, hipMemcpyDeviceToHost, c->stream), "copy somega"))) return r;
   if ((r = hip_check(c, hipMemcpyAsync(omw, a + c->L.omw, (size_t)c->ne * 24, hipMemcpyDeviceToHost, c->stream), "copy omw"))) return r;
   return hip_check(c, hipStreamSynchronize(c->stream), "sync omega fields");
+}
+
+int32_t pdf_navg(const pdf_ctx* c) { return c ? navg_of(c->p) : 0; }
+
+pdf_status pdf_average_attach(pdf_ctx* c, double* acc) {
+  if (!c) return PDF_E_ARG;
+  if (!c->seeded) return fail(c, PDF_E_STATE, "pdf_average_attach before pdf_seed_particles");
+  c->avg = acc;
+  c->graph_group = 0;  // graphs carry the merge only when averaging
+  if (!acc) return PDF_OK;
+  const int64_t words = 2 * (int64_t)c->nens * c->ne * navg_of(c->p);
+  hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, c->stream, (int32_t*)acc, 0, words);
+  return hip_check(c, hipGetLastError(), "average clear");
+}
+
+pdf_status pdf_locate(pdf_ctx* c, const double* xy, int32_t n, int32_t* elem) {
+  if (!c || n < 0 || (n > 0 && (!xy || !elem))) return fail(c, PDF_E_ARG, "pdf_locate: bad argument");
+  if (!c->mesh_ready) return fail(c, PDF_E_STATE, "pdf_locate before pdf_init_mesh");
+  if (n == 0) return PDF_OK;
+  hipLaunchKernelGGL(k_locate, dim3(n), dim3(BLOCK), 0, c->stream, (const ERec*)(c->arena + c->L.erec), c->ne, xy, n, elem);
+  return hip_check(c, hipGetLastError(), "locate launch");
+}
+
+pdf_status pdf_average_probe(pdf_ctx* c, const double* acc, int32_t ens, const int32_t* elems, int32_t nprobe,
+                             double* out) {
+  if (!c || !acc || nprobe < 0 || (nprobe > 0 && (!elems || !out))) return fail(c, PDF_E_ARG, "pdf_average_probe: bad argument");
+  if (!c->seeded) return fail(c, PDF_E_STATE, "pdf_average_probe before pdf_seed_particles");
+  if (ens < 0 || ens >= c->nens) return fail(c, PDF_E_ARG, "ensemble out of range");
+  if (nprobe == 0) return PDF_OK;
+  hipLaunchKernelGGL(k_probe, dim3((nprobe + 63) / 64), dim3(64), 0, c->stream, acc, navg_of(c->p), c->ne, ens, elems,
+                     nprobe, c->p.hist_bins, out);
+  return hip_check(c, hipGetLastError(), "probe launch");
 }
 
 int64_t pdf_count(const pdf_ctx* c, int32_t ens) {
