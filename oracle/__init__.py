@@ -41,7 +41,8 @@ def build(force: bool = True) -> str:
 class _Params(ctypes.Structure):
     _fields_ = [("f32_state", ctypes.c_int32), ("model", ctypes.c_int32), ("moments", ctypes.c_int32),
                 ("hist_bins", ctypes.c_int32), ("mix", ctypes.c_int32), ("psi_init", ctypes.c_int32),
-                ("flags", ctypes.c_int32), ("omega", ctypes.c_int32),
+                ("flags", ctypes.c_int32), ("omega", ctypes.c_int32), ("vbins", ctypes.c_int32),
+                ("pad_", ctypes.c_int32),
                 ("dt", ctypes.c_double), ("nu", ctypes.c_double), ("C0", ctypes.c_double),
                 ("CT", ctypes.c_double), ("Cs", ctypes.c_double), ("Ct", ctypes.c_double),
                 ("Cmu", ctypes.c_double), ("kappa", ctypes.c_double), ("Ewall", ctypes.c_double),
@@ -132,7 +133,8 @@ def params_of(wl) -> _Params:
                    flags=int(getattr(wl, 'flags', 15)),
                    dt=wl.dt, nu=wl.nu, C0=wl.C0, CT=c["CT"], Cs=c["Cs"], Ct=c["Ct"], Cmu=c["Cmu"],
                    kappa=c["kappa"], Ewall=c["Ewall"], yp=wl.yp, Lx=wl.mesh.Lx, Ly=wl.mesh.Ly,
-                   omega=1 if getattr(wl, "omega", False) else 0, C3=c.get("C3", 5.0),
+                   omega=1 if getattr(wl, "omega", False) else 0, vbins=int(getattr(wl, "vbins", 2)),
+                   C3=c.get("C3", 5.0),
                    C4=c.get("C4", 0.25), Cw1=c.get("Cw1", 0.5), Cw2=c.get("Cw2", 0.73))
 
 

@@ -604,6 +604,29 @@ template <typename T> void seed_ensemble(orc_ctx* c, Ens<T>& en, uint32_t ens_in
 // element's particles in particle-id order.
 
 int nstat_of(const orc_params& p) {
+  return (p.moments >= 4 ? ORC_NSTAT_4 : ORC_NSTAT_2) + p.hist_bins + (p.omega ? 3 : 0) + (p.vbins == 5 ? 250 : 0);
+}
+
+// Five velocity bins per component: equal widths 1.2 sigma on [-3 sigma,
+// 3 sigma] about the element mean (edges at +-0.6 and +-1.8 sigma), the
+// outermost bins open; sigma from the element's central second moments; with
+// sigma = 0 the middle bin.  Bin = k_u + 5 k_v + 25 k_w.  s: the element's
+// record.
+int fine_component(double u, double mean, double m2) {
+  const double sd = std::sqrt(m2);
+  if (!(sd > 0.0)) return 2;
+  const double z = (u - mean) / sd;
+  const double k = std::floor((z + 3.0) / 1.2);
+  return k < 0.0 ? 0 : (k > 4.0 ? 4 : (int)k);
+}
+
+int fine_bin(double u, double v, double w, const double* s) {
+  return fine_component(u, s[ORC_ST_MEAN], s[ORC_ST_M2 + 0]) + 5 * fine_component(v, s[ORC_ST_MEAN + 1], s[ORC_ST_M2 + 4]) +
+         25 * fine_component(w, s[ORC_ST_MEAN + 2], s[ORC_ST_M2 + 7]);
+}
+
+// offset of the 125 fine-bin counts in the record (means follow)
+int fine_offset(const orc_params& p) {
   return (p.moments >= 4 ? ORC_NSTAT_4 : ORC_NSTAT_2) + p.hist_bins + (p.omega ? 3 : 0);
 }
 
@@ -705,6 +728,21 @@ template <typename T> void estimate(const orc_ctx* c, const Ens<T>& en, std::vec
       so[1] = om_var;
       so[2] = om_mean * (kh + (p.nu * (p.CT * p.CT)) * om_mean);
     }
+    if (p.vbins == 5) {
+      // <phi|V> on 5 x 5 x 5 bins (bins from this record's means and moments)
+      double fn[125] = {0}, fs[125] = {0};
+      for (int64_t j = start[e]; j < start[e + 1]; ++j) {
+        int64_t i = list[j];
+        const int b = fine_bin((double)en.u[i], (double)en.v[i], (double)en.w[i], s);
+        fn[b] += 1.0;
+        fs[b] += (double)en.psi[i];
+      }
+      double* sf = s + fine_offset(p);
+      for (int b = 0; b < 125; ++b) {
+        sf[b] = fn[b];
+        sf[125 + b] = fn[b] > 0.0 ? fs[b] / fn[b] : mean[3];
+      }
+    }
   }
 }
 
@@ -744,9 +782,14 @@ template <typename T> int advance(orc_ctx* c, Ens<T>& en, uint32_t ens_index, ui
     // IECM, eq. (7): relax toward the mean scalar of the particle's velocity bin
     if (p.mix && (p.flags & 4)) {
       const double* s = &st[(size_t)e * ns];
-      int bin = ((double)u > s[ORC_ST_MEAN] ? 1 : 0) + ((double)v > s[ORC_ST_MEAN + 1] ? 2 : 0) +
-                ((double)w > s[ORC_ST_MEAN + 2] ? 4 : 0);
-      T m = en.cm.empty() ? (T)s[ORC_ST_BINM + bin] : (T)en.cm[(size_t)e * 8 + bin];
+      T m;
+      if (p.vbins == 5) {
+        m = (T)s[fine_offset(p) + 125 + fine_bin((double)u, (double)v, (double)w, s)];
+      } else {
+        int bin = ((double)u > s[ORC_ST_MEAN] ? 1 : 0) + ((double)v > s[ORC_ST_MEAN + 1] ? 2 : 0) +
+                  ((double)w > s[ORC_ST_MEAN + 2] ? 4 : 0);
+        m = en.cm.empty() ? (T)s[ORC_ST_BINM + bin] : (T)en.cm[(size_t)e * 8 + bin];
+      }
       T r = (T)en.rate[e];
       psi = psi - r * (psi - m);
     }
@@ -853,6 +896,7 @@ orc_ctx* orc_create(const orc_params* p, int32_t nvert, const double* vtx, int32
                     const int32_t* tri, const int32_t* nbr, const int32_t* ekind,
                     const double* fields) {
   if (!p || nvert <= 0 || nelem <= 0) return nullptr;
+  if (!(p->vbins == 2 || p->vbins == 5)) return nullptr;
   orc_ctx* c = new orc_ctx();
   c->p = *p;
   c->nv = nvert;

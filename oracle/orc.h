@@ -65,6 +65,8 @@ typedef struct orc_params {
   int32_t psi_init;    /* 0 zero, 1 psi=1 for x<0.25 */
   int32_t flags;       /* sub-steps: 1 velocity, 2 position and tracking, 4 IECM, 8 source */
   int32_t omega;       /* 1: stochastic turbulent frequency per particle, eqs. (9)-(10), (27)-(28) */
+  int32_t vbins;       /* velocity bins per component for <phi|V> in IECM: 2 (signs) or 5 */
+  int32_t pad_;
   double dt, nu, C0;   /* time step, viscosity, SLM constant */
   double CT, Cs, Ct;   /* Table 2 */
   double Cmu, kappa, Ewall, yp;  /* wall functions */

@@ -61,6 +61,7 @@ class Workload:
     steps: int = 100
     yp: float = 0.0                 # wall-function distance of the stripped walls
     omega: bool = False             # stochastic turbulent frequency per particle, eqs. (9)-(10)
+    vbins: int = 2                  # velocity bins per component for <phi|V>: 2 (signs) or 5
     constants: dict = field(default_factory=lambda: dict(CT=6.0, Cs=0.02, Ct=0.7, Cmu=0.09,
                                                          kappa=0.41, Ewall=8.5, C3=5.0, C4=0.25,
                                                          Cw1=0.5, Cw2=0.73))
@@ -78,7 +79,7 @@ class Workload:
                     vertices=self.mesh.nvert, particles=self.n_total, ensembles=self.nens,
                     precision=self.precision, model=("SLM" if self.model == SLM else "GLM"),
                     dt=self.dt, steps=self.steps, moments=self.moments, hist_bins=self.hist_bins,
-                    omega=self.omega)
+                    omega=self.omega, vbins=self.vbins)
 
 
 def apportion(areas: np.ndarray, n: int) -> np.ndarray:
@@ -176,7 +177,7 @@ def config5(ppe: int = 20, seed: int = 101, steps: int = 500, target: int = 1000
 
 def small_canyon(target: int = 2000, ppe: int = 40, seed: int = 7, wallfn: bool = False,
                  precision: str = "f32", moments: int = 2, hist_bins: int = 0, nens: int = 1,
-                 steps: int = 20, omega: bool = False) -> Workload:
+                 steps: int = 20, omega: bool = False, vbins: int = 2) -> Workload:
     m, f = _canyon(target, wallfn)
     yp = 13.0 / 256.0 if wallfn else 0.0
     n = ppe * m.nelem
@@ -189,7 +190,7 @@ def small_canyon(target: int = 2000, ppe: int = 40, seed: int = 7, wallfn: bool 
     return Workload(name=f"small_canyon_{m.nelem}e", mesh=m, fields=f, ensembles=ens,
                     precision=precision, model=(SLM if wallfn else GLM), dt=1e-3,
                     nu=1.0 / 12000.0, C0=(3.5 if wallfn else 2.1), moments=moments,
-                    hist_bins=hist_bins, steps=steps, yp=yp, omega=omega)
+                    hist_bins=hist_bins, steps=steps, yp=yp, omega=omega, vbins=vbins)
 
 
 def tiny_canyon(**kw) -> Workload:
