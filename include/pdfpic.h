@@ -100,6 +100,16 @@ typedef struct pdf_params {
                          The record gains <omega>, <omega'^2> and eps =
                          <omega>(k + nu C_T^2 <omega>), k from the record's
                          stresses.  0: off (no memory or work for it).      */
+  int32_t vbins;      /* velocity bins per component for <phi|V> in IECM:
+                         2: by the sign of each fluctuation (8 bins);
+                         5: 5 x 5 x 5 bins of width 1.2 sigma on
+                         [-3 sigma, 3 sigma] about the element mean (sigma
+                         from its second moments, sigma = 0: the middle bin;
+                         bin = k_u + 5 k_v + 25 k_w), float state without
+                         omega only.  The record gains 125 counts and 125
+                         conditional means (the element mean for an empty
+                         bin) after everything else.                        */
+  int32_t reserved;
   double dt, nu, C0;  /* time step, kinematic viscosity, SLM constant           */
   double CT, Cs, Ct;  /* Table 2 constants used by eqs. (8) and (11)            */
   double Cmu, kappa, Ewall, yp; /* wall functions: C_mu, Karman constant, E,
@@ -198,7 +208,7 @@ int64_t pdf_repack_count(pdf_ctx* ctx);
 /* Estimate the statistics of the current state into out: nens x nelem x
    nstat doubles (nstat = PDF_NSTAT_2 or PDF_NSTAT_4, plus hist_bins, plus 3
    with the turbulent frequency: <omega>, <omega'^2>, eps, after the
-   histogram).
+   histogram, plus 250 with 5 x 5 x 5 velocity bins).
    out_on_host: 1 -> out is host memory and the call waits; 0 -> device. */
 pdf_status pdf_estimate_statistics(pdf_ctx* ctx, double* out, int32_t out_on_host);
 

@@ -43,7 +43,8 @@ class PdfError(RuntimeError):
 class PdfParams(ctypes.Structure):
     _fields_ = [("f32_state", ctypes.c_int32), ("model", ctypes.c_int32), ("moments", ctypes.c_int32),
                 ("hist_bins", ctypes.c_int32), ("mix", ctypes.c_int32), ("psi_init", ctypes.c_int32),
-                ("flags", ctypes.c_int32), ("omega", ctypes.c_int32),
+                ("flags", ctypes.c_int32), ("omega", ctypes.c_int32), ("vbins", ctypes.c_int32),
+                ("reserved", ctypes.c_int32),
                 ("dt", ctypes.c_double), ("nu", ctypes.c_double), ("C0", ctypes.c_double),
                 ("CT", ctypes.c_double), ("Cs", ctypes.c_double), ("Ct", ctypes.c_double),
                 ("Cmu", ctypes.c_double), ("kappa", ctypes.c_double), ("Ewall", ctypes.c_double),
@@ -169,7 +170,7 @@ class Simulation:
                  psi_init: int = 0, flags: int = 15, dt: float = 1e-3, nu: float = 0.0,
                  C0: float = 2.1, CT: float = 6.0, Cs: float = 0.02, Ct: float = 0.7,
                  Cmu: float = 0.09, kappa: float = 0.41, Ewall: float = 8.5, yp: float = 0.0,
-                 Lx: float = 1.0, Ly: float = 1.0, slack: float = 2.0, omega: bool = False,
+                 Lx: float = 1.0, Ly: float = 1.0, slack: float = 2.0, omega: bool = False, vbins: int = 2,
                  C3: float = 5.0, C4: float = 0.25, Cw1: float = 0.5, Cw2: float = 0.73,
                  device: str = "cuda:0", stream=None):
         import torch
@@ -180,7 +181,8 @@ class Simulation:
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.params = PdfParams(f32_state=1 if precision == "f32" else 0, model=int(model), moments=int(moments),
                                 hist_bins=int(hist_bins), mix=1 if mix else 0, psi_init=int(psi_init),
-                                flags=int(flags), omega=1 if omega else 0, dt=dt, nu=nu, C0=C0, CT=CT, Cs=Cs,
+                                flags=int(flags), omega=1 if omega else 0, vbins=int(vbins), reserved=0,
+                                dt=dt, nu=nu, C0=C0, CT=CT, Cs=Cs,
                                 Ct=Ct, Cmu=Cmu, kappa=kappa, Ewall=Ewall, yp=yp, Lx=Lx, Ly=Ly, slack=slack,
                                 C3=C3, C4=C4, Cw1=Cw1, Cw2=Cw2)
         self.ctx = ctypes.c_void_p()
@@ -228,6 +230,7 @@ class Simulation:
                     psi_init=wl.psi_init, flags=getattr(wl, "flags", 15), dt=wl.dt, nu=wl.nu, C0=wl.C0,
                     CT=c["CT"], Cs=c["Cs"], Ct=c["Ct"], Cmu=c["Cmu"], kappa=c["kappa"], Ewall=c["Ewall"],
                     yp=wl.yp, Lx=m.Lx, Ly=m.Ly, omega=bool(getattr(wl, "omega", False)),
+                    vbins=int(getattr(wl, "vbins", 2)),
                     C3=c.get("C3", 5.0), C4=c.get("C4", 0.25), Cw1=c.get("Cw1", 0.5), Cw2=c.get("Cw2", 0.73),
                     device=device)
         args.update(kw)

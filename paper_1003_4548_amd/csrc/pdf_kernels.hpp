@@ -371,6 +371,7 @@ template <typename T> struct CellConst {
   double mean[3];
   double cm[8];
   double om_mean, sw;  // turbulent frequency: the cell's <omega> and S_omega
+  double fsd[3];       // 5 x 5 x 5 bins: standard deviations of u, v, w
 };
 
 // orient_edge of (px, py) against edge k of a cell, from its CellConst data;
@@ -382,11 +383,26 @@ __device__ __forceinline__ double orient_cc(const CellConst<T>& C, int k, double
 
 // SCHED: 0 one work item per wavefront; 1 persistent grid; 2 one item per
 // wavefront with the learned conditional means computed inside the step.
-// OMG: the particles carry the stochastic turbulent frequency of eq. (9); the
-// record gains its mean, variance and the dissipation estimate of eq. (8).
-template <typename T, int MOM, int HIST, int G, bool ADVANCE, int SCHED, bool OMG>
+// XV, an extension of the model: XV_OMEGA, the particles carry the stochastic
+// turbulent frequency of eq. (9) and the record gains its mean, variance and
+// the dissipation estimate of eq. (8); XV_BINS5, <phi|V> on 5 x 5 x 5
+// velocity bins (the record gains their counts and means).
+enum { XV_NONE = 0, XV_OMEGA = 1, XV_BINS5 = 2 };
+
+// Five bins per velocity component: widths 1.2 sigma on [-3 sigma, 3 sigma]
+// about the element mean, the outermost bins open; sigma = 0: the middle bin.
+__device__ __forceinline__ int fine_component(double u, double mean, double sd) {
+  if (!(sd > 0.0)) return 2;
+  const double z = (u - mean) / sd;
+  const double k = floor((z + 3.0) / 1.2);
+  return k < 0.0 ? 0 : (k > 4.0 ? 4 : (int)k);
+}
+
+template <typename T, int MOM, int HIST, int G, bool ADVANCE, int SCHED, int XV>
 __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
-  static_assert(!(OMG && SCHED == 2), "the turbulent frequency runs with the separate learned-means pass");
+  constexpr bool OMG = XV == XV_OMEGA;
+  constexpr bool VB5 = XV == XV_BINS5;
+  static_assert(!(XV != XV_NONE && SCHED == 2), "model extensions run with the separate learned-means pass");
   constexpr bool PERSIST = SCHED == 1;
   constexpr int GPW = WAVE / G;             // cells per wavefront
   constexpr int TILEN = 4 * G;              // particles per cell staged in LDS
@@ -395,6 +411,9 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
   __shared__ int hist_lds[HIST > 0 ? CPB : 1][HIST > 0 ? HIST : 1];
   __shared__ CellConst<T> ccs[ADVANCE ? CPB : 1];
   __shared__ T otile[OMG ? CPB : 1][OMG ? TILEN : 1];
+  __shared__ double fsum[VB5 ? CPB : 1][VB5 ? 125 : 1];
+  __shared__ int fcnt[VB5 ? CPB : 1][VB5 ? 125 : 1];
+  __shared__ T fcm[VB5 && ADVANCE ? CPB : 1][VB5 && ADVANCE ? 125 : 1];
   Ctl* ctl = a.ctl;
   // after an error the state is void: later steps do nothing
   // (with the learned means inside the step every wavefront of a block must
@@ -738,6 +757,47 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
       for (int h = li; h < HIST; h += G)
         if (has) rec[off + h] = (double)hist_lds[slot_id][h];
     }
+    if constexpr (VB5) {
+      // <phi|V> on 5 x 5 x 5 bins: one more pass over the particles, bins from
+      // this record's means and second moments, per-bin counts and FP64
+      // scalar sums by LDS atomics (the order of the sums is not fixed; their
+      // rounding is that of any FP64 sum, relative to each bin's own values)
+      constexpr int FOFF = (MOM >= 4 ? NSTAT4 : NSTAT2) + HIST;
+      const double sdu = sqrt(acc[0] * inv_n), sdv = sqrt(acc[4] * inv_n), sdw = sqrt(acc[7] * inv_n);
+      for (int b = li; b < 125; b += G) {
+        fsum[slot_id][b] = 0.0;
+        fcnt[slot_id][b] = 0;
+      }
+      lds_sync_wave();
+      for (int base = 0; __ballot(base < n) != 0; base += G) {
+        const int j = base + li;
+        if (j < n) {
+          double val[4];
+          load4(j, val);
+          const int b = fine_component(val[0], mean[0], sdu) + 5 * fine_component(val[1], mean[1], sdv) +
+                        25 * fine_component(val[2], mean[2], sdw);
+          atomicAdd(&fcnt[slot_id][b], 1);
+          atomicAdd(&fsum[slot_id][b], val[3]);
+        }
+      }
+      lds_sync_wave();
+      for (int b = li; b < 125; b += G) {
+        const int cn = fcnt[slot_id][b];
+        const double fm = cn > 0 ? fsum[slot_id][b] / (double)cn : mean[3];
+        if (has) {
+          rec[FOFF + b] = (double)cn;
+          rec[FOFF + 125 + b] = fm;
+        }
+        if constexpr (ADVANCE) fcm[slot_id][b] = (T)fm;
+      }
+      if constexpr (ADVANCE) {
+        if (li == 0) {
+          ccs[slot_id].fsd[0] = sdu;
+          ccs[slot_id].fsd[1] = sdv;
+          ccs[slot_id].fsd[2] = sdw;
+        }
+      }
+    }
 
     if (ADVANCE) {
       // ---- C: advance ----
@@ -845,9 +905,17 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
 #pragma unroll
           for (int q = 0; q < NCOEF; ++q) f[q] = (l0 * CC.coef[q] + l1 * CC.coef[NCOEF + q]) + l2 * CC.coef[2 * NCOEF + q];
           if (do_mix) {
-            const int bin = ((double)u > CC.mean[0] ? 1 : 0) + ((double)v > CC.mean[1] ? 2 : 0) +
-                            ((double)w > CC.mean[2] ? 4 : 0);
-            const T m = (T)CC.cm[bin];
+            T m;
+            if constexpr (VB5) {
+              const int b = fine_component((double)u, CC.mean[0], CC.fsd[0]) +
+                            5 * fine_component((double)v, CC.mean[1], CC.fsd[1]) +
+                            25 * fine_component((double)w, CC.mean[2], CC.fsd[2]);
+              m = fcm[slot_id][b];
+            } else {
+              const int bin = ((double)u > CC.mean[0] ? 1 : 0) + ((double)v > CC.mean[1] ? 2 : 0) +
+                              ((double)w > CC.mean[2] ? 4 : 0);
+              m = (T)CC.cm[bin];
+            }
             psi = psi - rate * (psi - m);
           }
           const T dW1 = a.sdt * xi0, dW2 = a.sdt * xi1;

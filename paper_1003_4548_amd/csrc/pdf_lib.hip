@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "pdf_kernels.hpp"
@@ -143,7 +144,7 @@ namespace {
 int tsize_of(const pdf_params& p) { return p.f32_state ? 4 : 8; }
 
 int nstat_of(const pdf_params& p) {
-  return (p.moments >= 4 ? NSTAT4 : NSTAT2) + p.hist_bins + (p.omega ? 3 : 0);
+  return (p.moments >= 4 ? NSTAT4 : NSTAT2) + p.hist_bins + (p.omega ? 3 : 0) + (p.vbins == 5 ? 250 : 0);
 }
 
 int navg_of(const pdf_params& p) { return AV_HIST + p.hist_bins + (p.omega ? 2 : 0); }
@@ -248,14 +249,14 @@ int persist_chunk(int nitems, int blocks) {
   return std::max(1, std::min(16, nitems / (16 * waves)));
 }
 
-template <typename T, int MOM, int HIST, int G, bool ADV, int SCHED, bool OMG>
+template <typename T, int MOM, int HIST, int G, bool ADV, int SCHED, int XV>
 void launch_step(pdf_ctx* c, StepArgs<T> s, StepIndex si) {
   constexpr int GPW = WAVE / G;
   s.nitems = (s.ncell + GPW - 1) / GPW;
   int blocks = (s.nitems + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
   if (SCHED == 1) {
     int per_cu = 0;
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step<T, MOM, HIST, G, ADV, SCHED, OMG>, BLOCK, 0);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step<T, MOM, HIST, G, ADV, SCHED, XV>, BLOCK, 0);
     int cus = 0;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device);
     const int cap_blocks = std::max(1, per_cu) * std::max(1, cus);
@@ -263,7 +264,7 @@ void launch_step(pdf_ctx* c, StepArgs<T> s, StepIndex si) {
     c->persist_blocks = blocks;
   }
   s.pchunk = persist_chunk(s.nitems, blocks);
-  hipLaunchKernelGGL((k_step<T, MOM, HIST, G, ADV, SCHED, OMG>), dim3(blocks), dim3(BLOCK), 0, c->stream, s, si);
+  hipLaunchKernelGGL((k_step<T, MOM, HIST, G, ADV, SCHED, XV>), dim3(blocks), dim3(BLOCK), 0, c->stream, s, si);
 }
 
 // Scheduling variant of a step launch: persistent grid, or one work item per
@@ -274,34 +275,44 @@ int sched_of(const pdf_ctx* c, bool adv) {
   return (c->mlp_w && !mlp_separate(c)) ? 2 : 0;
 }
 
-template <typename T, int MOM, int HIST, bool ADV, bool OMG, int G>
+template <typename T, int MOM, int HIST, bool ADV, int XV, int G>
 void launch_shape(pdf_ctx* c, const StepArgs<T>& s, StepIndex si, int sc) {
-  if (!ADV || sc == 0) launch_step<T, MOM, HIST, G, ADV, 0, OMG>(c, s, si);
-  else if (sc == 1) launch_step<T, MOM, HIST, G, ADV, ADV ? 1 : 0, OMG>(c, s, si);
-  else if constexpr (!OMG) launch_step<T, MOM, HIST, G, ADV, ADV ? 2 : 0, OMG>(c, s, si);
+  if (!ADV || sc == 0) launch_step<T, MOM, HIST, G, ADV, 0, XV>(c, s, si);
+  else if (sc == 1) launch_step<T, MOM, HIST, G, ADV, ADV ? 1 : 0, XV>(c, s, si);
+  else if constexpr (XV == XV_NONE) launch_step<T, MOM, HIST, G, ADV, ADV ? 2 : 0, XV>(c, s, si);
 }
 
-template <typename T, int MOM, int HIST, bool ADV, bool OMG>
+template <typename T, int MOM, int HIST, bool ADV, int XV>
 void launch_group(pdf_ctx* c, const StepArgs<T>& s, StepIndex si) {
   const int sc = sched_of(c, ADV);
   switch (c->group) {
-    case 16: launch_shape<T, MOM, HIST, ADV, OMG, 16>(c, s, si, sc); break;
-    case 32: launch_shape<T, MOM, HIST, ADV, OMG, 32>(c, s, si, sc); break;
-    default: launch_shape<T, MOM, HIST, ADV, OMG, 64>(c, s, si, sc); break;
+    case 16: launch_shape<T, MOM, HIST, ADV, XV, 16>(c, s, si, sc); break;
+    case 32: launch_shape<T, MOM, HIST, ADV, XV, 32>(c, s, si, sc); break;
+    default: launch_shape<T, MOM, HIST, ADV, XV, 64>(c, s, si, sc); break;
   }
 }
 
 // The float state supports (moments, histogram) = (2, 0) and (4, 32); the
-// double state (2, 0).
+// double state (2, 0); velocity bins 2 (signs) or 5 per component.
 bool supported(const pdf_params& p) {
+  if (!(p.vbins == 2 || p.vbins == 5)) return false;
+  // the 5 x 5 x 5 bins: float state, without the turbulent frequency
+  if (p.vbins == 5 && (!p.f32_state || p.omega)) return false;
   if (p.f32_state) return (p.moments == 2 && p.hist_bins == 0) || (p.moments == 4 && p.hist_bins == 32);
   return p.moments == 2 && p.hist_bins == 0;
 }
 
+// The model extension of a context: turbulent frequency, 5 x 5 x 5 velocity
+// bins (float state only), or none.
 template <typename T, int MOM, int HIST, bool ADV>
-void launch_omega(pdf_ctx* c, const StepArgs<T>& s, StepIndex si) {
-  if (c->p.omega) launch_group<T, MOM, HIST, ADV, true>(c, s, si);
-  else launch_group<T, MOM, HIST, ADV, false>(c, s, si);
+void launch_ext(pdf_ctx* c, const StepArgs<T>& s, StepIndex si) {
+  if (c->p.omega) {
+    launch_group<T, MOM, HIST, ADV, XV_OMEGA>(c, s, si);
+  } else if (c->p.vbins == 5) {
+    if constexpr (std::is_same<T, float>::value) launch_group<T, MOM, HIST, ADV, XV_BINS5>(c, s, si);
+  } else {
+    launch_group<T, MOM, HIST, ADV, XV_NONE>(c, s, si);
+  }
 }
 
 template <bool ADV> pdf_status dispatch_step(pdf_ctx* c, StepIndex si) {
@@ -309,13 +320,13 @@ template <bool ADV> pdf_status dispatch_step(pdf_ctx* c, StepIndex si) {
     StepArgs<float> s = step_args<float>(c);
     if (ADV) s.cmean = mlp_separate(c) ? c->mlp_cm : nullptr;
     if (!ADV) s.mlp_w = nullptr;
-    if (c->p.moments == 2) launch_omega<float, 2, 0, ADV>(c, s, si);
-    else launch_omega<float, 4, 32, ADV>(c, s, si);
+    if (c->p.moments == 2) launch_ext<float, 2, 0, ADV>(c, s, si);
+    else launch_ext<float, 4, 32, ADV>(c, s, si);
   } else {
     StepArgs<double> s = step_args<double>(c);
     if (ADV) s.cmean = mlp_separate(c) ? c->mlp_cm : nullptr;
     if (!ADV) s.mlp_w = nullptr;
-    launch_omega<double, 2, 0, ADV>(c, s, si);
+    launch_ext<double, 2, 0, ADV>(c, s, si);
   }
   return hip_check(c, hipGetLastError(), "step launch");
 }
@@ -427,41 +438,50 @@ struct StepLaunch {
   int blocks = 0;
 };
 
-template <typename T, int MOM, int HIST, int G, int SCHED, bool OMG>
+template <typename T, int MOM, int HIST, int G, int SCHED, int XV>
 StepLaunch step_launch_of(pdf_ctx* c, StepArgs<T>& s) {
   constexpr int GPW = WAVE / G;
   s.nitems = (s.ncell + GPW - 1) / GPW;
   int blocks = (s.nitems + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
   if (SCHED == 1) {
     int per_cu = 0, cus = 0;
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step<T, MOM, HIST, G, true, SCHED, OMG>, BLOCK, 0);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step<T, MOM, HIST, G, true, SCHED, XV>, BLOCK, 0);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device);
     blocks = std::min(blocks, std::max(1, per_cu) * std::max(1, cus));
   }
   s.pchunk = persist_chunk(s.nitems, blocks);
   StepLaunch l;
-  l.func = reinterpret_cast<const void*>(&k_step<T, MOM, HIST, G, true, SCHED, OMG>);
+  l.func = reinterpret_cast<const void*>(&k_step<T, MOM, HIST, G, true, SCHED, XV>);
   l.blocks = blocks;
   return l;
 }
 
-template <typename T, int MOM, int HIST, bool OMG, int G>
+template <typename T, int MOM, int HIST, int XV, int G>
 StepLaunch step_launch_shape(pdf_ctx* c, StepArgs<T>& s, int sc) {
-  if (sc == 1) return step_launch_of<T, MOM, HIST, G, 1, OMG>(c, s);
-  if constexpr (!OMG) {
-    if (sc == 2) return step_launch_of<T, MOM, HIST, G, 2, OMG>(c, s);
+  if (sc == 1) return step_launch_of<T, MOM, HIST, G, 1, XV>(c, s);
+  if constexpr (XV == XV_NONE) {
+    if (sc == 2) return step_launch_of<T, MOM, HIST, G, 2, XV>(c, s);
   }
-  return step_launch_of<T, MOM, HIST, G, 0, OMG>(c, s);
+  return step_launch_of<T, MOM, HIST, G, 0, XV>(c, s);
 }
 
-template <typename T, int MOM, int HIST, bool OMG>
+template <typename T, int MOM, int HIST, int XV>
 StepLaunch step_launch_group(pdf_ctx* c, StepArgs<T>& s) {
   const int sc = sched_of(c, true);
   switch (c->group) {
-    case 16: return step_launch_shape<T, MOM, HIST, OMG, 16>(c, s, sc);
-    case 32: return step_launch_shape<T, MOM, HIST, OMG, 32>(c, s, sc);
-    default: return step_launch_shape<T, MOM, HIST, OMG, 64>(c, s, sc);
+    case 16: return step_launch_shape<T, MOM, HIST, XV, 16>(c, s, sc);
+    case 32: return step_launch_shape<T, MOM, HIST, XV, 32>(c, s, sc);
+    default: return step_launch_shape<T, MOM, HIST, XV, 64>(c, s, sc);
   }
+}
+
+template <typename T, int MOM, int HIST>
+StepLaunch step_launch_ext(pdf_ctx* c, StepArgs<T>& s) {
+  if (c->p.omega) return step_launch_group<T, MOM, HIST, XV_OMEGA>(c, s);
+  if constexpr (std::is_same<T, float>::value) {
+    if (c->p.vbins == 5) return step_launch_group<T, MOM, HIST, XV_BINS5>(c, s);
+  }
+  return step_launch_group<T, MOM, HIST, XV_NONE>(c, s);
 }
 
 constexpr int GRAPH_STEPS = 6;  // parity repeats every 2 steps, the counter sets every 3
@@ -473,10 +493,8 @@ template <typename T> pdf_status build_graph_t(pdf_ctx* c) {
   // the runtime copies kernel arguments into each node when it is added
   StepArgs<T> args_store = step_args<T>(c);
   StepLaunch l;
-  if (c->p.moments == 2)
-    l = c->p.omega ? step_launch_group<T, 2, 0, true>(c, args_store) : step_launch_group<T, 2, 0, false>(c, args_store);
-  else
-    l = c->p.omega ? step_launch_group<T, 4, 32, true>(c, args_store) : step_launch_group<T, 4, 32, false>(c, args_store);
+  if (c->p.moments == 2) l = step_launch_ext<T, 2, 0>(c, args_store);
+  else l = step_launch_ext<T, 4, 32>(c, args_store);
   pdf_status r;
   hipGraph_t g = nullptr;
   if ((r = hip_check(c, hipGraphCreate(&g, 0), "graph create"))) return r;
@@ -1190,6 +1208,7 @@ pdf_status pdf_mlp_attach(pdf_ctx* c, const uint16_t* w, const float* norm, doub
     return PDF_OK;
   }
   if (!norm || !cm) return fail(c, PDF_E_ARG, "pdf_mlp_attach: null normalisation or output");
+  if (c->p.vbins != 2) return fail(c, PDF_E_STATE, "pdf_mlp_attach: the network estimates the eight sign bins only");
   c->mlp_w = w;
   c->mlp_norm = norm;
   c->mlp_cm = cm;

@@ -36,8 +36,8 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_struct_layouts_match_header(tmp_path):
-    # pdf_params: 8 int32 + 17 doubles; pdf_mesh: 2 int32 + 5 pointers; pdf_sizes: 4 int32 + 3 int64
-    assert ctypes.sizeof(P.PdfParams) == 8 * 4 + 17 * 8
+    # pdf_params: 10 int32 + 17 doubles; pdf_mesh: 2 int32 + 5 pointers; pdf_sizes: 4 int32 + 3 int64
+    assert ctypes.sizeof(P.PdfParams) == 10 * 4 + 17 * 8
     assert ctypes.sizeof(P.PdfMesh) == 8 + 5 * 8
     assert ctypes.sizeof(P.PdfSizes) == 16 + 3 * 8
     # every field offset as the C compiler lays out the header's struct
@@ -64,7 +64,7 @@ def test_create_rejects_bad_frequency_constants():
     L = P.load_library()
 
     def create(**kw):
-        base = dict(f32_state=1, model=0, moments=2, hist_bins=0, mix=1, psi_init=0, flags=15, omega=1,
+        base = dict(f32_state=1, model=0, moments=2, hist_bins=0, mix=1, psi_init=0, flags=15, omega=1, vbins=2,
                     dt=1e-3, nu=1e-4, C0=3.5, CT=6.0, Cs=0.02, Ct=0.7, Cmu=0.09, kappa=0.41, Ewall=8.5,
                     yp=0.05, Lx=1.0, Ly=1.0, slack=2.0, C3=5.0, C4=0.25, Cw1=0.5, Cw2=0.73)
         base.update(kw)
@@ -76,3 +76,6 @@ def test_create_rejects_bad_frequency_constants():
     assert create(C3=0.0) == -1
     assert create(C4=-0.25) == -1
     assert create(Cw1=50.0) == -1          # 1/2 + 3/4 C0 + C3 + Cw2 - Cw1 <= 0: no finite beta
+    assert create(vbins=3) == -1
+    assert create(vbins=5) == -1           # fine bins run without the turbulent frequency
+    assert create(vbins=5, omega=0, f32_state=0) == -1
