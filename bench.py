@@ -30,6 +30,8 @@ WORKLOADS = {
     "canyon10m": ("config3", "wall-function canyon, 48618-element mesh, 10M particles, SLM, 4th moments + histograms"),
     "canyon10m_omega": ("config3w", "wall-function canyon, 48618-element mesh, 10M particles, SLM, 4th moments + "
                                     "histograms, stochastic turbulent frequency per particle"),
+    "canyon10m_bins5": ("config3b", "wall-function canyon, 48618-element mesh, 10M particles, SLM, 4th moments + "
+                                    "histograms, <phi|V> on 5x5x5 velocity bins"),
     "square40k": ("config1", "unit square 20x20x2, 40k particles, SLM, FP64"),
 }
 
@@ -55,7 +57,8 @@ def algorithmic_bytes(wl) -> dict:
     ts = 4 if wl.precision == "f32" else 8
     om = bool(getattr(wl, "omega", False))
     per_particle = 2 * ((7 if om else 6) * ts + 4)
-    nstat = (86 if wl.moments >= 4 else 31) + wl.hist_bins + (3 if om else 0)
+    nstat = (86 if wl.moments >= 4 else 31) + wl.hist_bins + (3 if om else 0) + \
+        (250 if getattr(wl, "vbins", 2) == 5 else 0)
     ne, nv = wl.mesh.nelem, wl.mesh.nvert
     ncell = ne * wl.nens
     per_cell = nstat * 8 + 4 * 4 + ts
@@ -244,7 +247,7 @@ def main() -> int:
     ap.add_argument("--workload", default="canyon1m", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--secondary", default="canyon10m,batched64,canyon10m_omega",
+    ap.add_argument("--secondary", default="canyon10m,batched64,canyon10m_omega,canyon10m_bins5",
                     help="further workloads reported in the same line, comma separated ('' for none)")
     ap.add_argument("--secondary-steps", type=int, default=100)
     ap.add_argument("--no-graph", action="store_true", help="launch steps one by one instead of graph replays")
@@ -316,6 +319,16 @@ def main() -> int:
         sim.sync()
         assert sim.steps_done() == tuned + warmup + steps
         repacks = sim.repacks()
+        # the same steps with time averaging on (one merge launch per step)
+        avg_steps = min(steps, 100)
+        sim.average_attach()
+        step_fn(avg_steps)
+        sim.sync()
+        t2 = time.perf_counter()
+        step_fn(avg_steps)
+        sim.sync()
+        avg_wall = time.perf_counter() - t2
+        sim.average_detach()
         wall = t1 - t0
         kern_ms = e0.elapsed_time(e1) / steps
         ab = algorithmic_bytes(wl)
@@ -335,10 +348,13 @@ def main() -> int:
                        "state_dtype": wl.precision, "statistics_dtype": "f64", "model": wl.describe()["model"],
                        "moments": wl.moments, "hist_bins": wl.hist_bins, "dt": wl.dt,
                        "turbulent_frequency": bool(getattr(wl, "omega", False)),
+                       "velocity_bins": "5x5x5" if getattr(wl, "vbins", 2) == 5 else "2x2x2 (signs)",
                        "launch": {"lanes_per_cell": shape[0], "persistent": bool(shape[1]),
                                   "autotune_steps_per_candidate": 0 if args.launch else autotune_steps,
                                   "hip_graph": not args.no_graph},
                        "segment_repacks": repacks,
+                       "with_time_averaging": {"steps": avg_steps, "ms_per_step": round(1e3 * avg_wall / avg_steps, 5),
+                                               "value": round(wl.n_total * avg_steps / avg_wall, 1)},
                        "kernel_source_hash": src_hash},
             "wl_fn": (cfg_fn, steps),
         }

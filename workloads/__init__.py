@@ -9,14 +9,14 @@ not available, so smooth synthetic stand-ins are generated instead.
 """
 from .mesh import Mesh, EDGE, unit_square_mesh, canyon_mesh, doubly_periodic_box
 from .fields import FIELD_NAMES, NFIELD, uniform_fields, canyon_fields
-from .configs import (Workload, Ensemble, config1, config2, config3, config3w, config4, config5,
+from .configs import (Workload, Ensemble, config1, config2, config3, config3w, config3b, config4, config5,
                       small_canyon,
                       tiny_canyon, square_box, apportion, SLM, GLM, PSI_ZERO, PSI_LEFT_QUARTER)
 
 __all__ = [
     "Mesh", "EDGE", "unit_square_mesh", "canyon_mesh", "doubly_periodic_box",
     "FIELD_NAMES", "NFIELD", "uniform_fields", "canyon_fields",
-    "Workload", "config1", "config2", "config3", "config3w", "config4", "config5",
+    "Workload", "config1", "config2", "config3", "config3w", "config3b", "config4", "config5",
     "small_canyon", "tiny_canyon", "square_box", "apportion", "Ensemble",
     "SLM", "GLM", "PSI_ZERO", "PSI_LEFT_QUARTER",
 ]

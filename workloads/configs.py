@@ -150,6 +150,15 @@ def config3w(steps: int = 1000, n: int = 10_000_000, seed: int = 0, target: int 
     return wl
 
 
+def config3b(steps: int = 1000, n: int = 10_000_000, seed: int = 0, target: int = 50000) -> Workload:
+    """The large wall-function canyon with <phi|V> on 5 x 5 x 5 velocity bins
+    (the bin structure of section 3)."""
+    wl = config3(steps=steps, n=n, seed=seed, target=target)
+    wl.vbins = 5
+    wl.name = wl.name + "_bins5"
+    return wl
+
+
 def config4(steps: int = 100, nens: int = 64, target: int = 10000) -> Workload:
     """64 independent canyon runs of uneven size on the 10k-element mesh."""
     m, f = _canyon(target, False)
