@@ -1470,37 +1470,69 @@ enum { AV_STEPS = 0, AV_N = 1, AV_MEAN = 2, AV_M2 = 6, AV_HIST = 16 };
 // Means and central moments are combined pairwise (Chan, Golub & LeVeque):
 // with counts na, nb and mean difference d, M' = M_a + d nb / n and
 // C' = (na C_a + nb C_b + d d^T na nb / n) / n.
-__global__ void k_average_merge(const double* stats, int nstat, int hoff, int hist, int omega, double* acc,
-                                int navg, int ncell) {
-  const int cell = blockIdx.x * blockDim.x + threadIdx.x;
-  if (cell >= ncell) return;
-  const double* r = stats + (size_t)cell * nstat;
-  double* A = acc + (size_t)cell * navg;
-  A[AV_STEPS] = A[AV_STEPS] + 1.0;
-  const double nb = r[ST_N];
-  if (!(nb > 0.0)) return;
-  const double na = A[AV_N], nn = na + nb;
-  const double fb = nb / nn, wab = na * fb;
-  double d[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) d[q] = r[ST_MEAN + q] - A[AV_MEAN + q];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) A[AV_MEAN + q] = A[AV_MEAN + q] + d[q] * fb;
-#pragma unroll
-  for (int x = 0; x < 4; ++x)
-#pragma unroll
-    for (int y = x; y < 4; ++y) {
-      const int t = pair_index(x, y);
-      A[AV_M2 + t] = ((na * A[AV_M2 + t] + nb * r[ST_M2 + t]) + wab * (d[x] * d[y])) / nn;
-    }
-  for (int h = 0; h < hist; ++h) A[AV_HIST + h] = A[AV_HIST + h] + r[hoff + h];
-  if (omega) {
-    double* W = A + AV_HIST + hist;
-    const double dw = r[nstat - 3] - W[0];
-    W[0] = W[0] + dw * fb;
-    W[1] = ((na * W[1] + nb * r[nstat - 2]) + wab * (dw * dw)) / nn;
+// A block takes MERGE_CELLS consecutive cells: the record fields it needs
+// (count, means, second moments, histogram, frequency statistics) and the
+// averages are staged through LDS with coalesced loads, one thread merges
+// each cell, and the averages go back coalesced.
+constexpr int MERGE_CELLS = 64;
+constexpr int MERGE_MAXAV = AV_HIST + 32 + 2;   // largest time-averaged record
+
+__global__ __launch_bounds__(BLOCK) void k_average_merge(const double* stats, int nstat, int hoff, int hist,
+                                                         int omega, double* acc, int navg, int ncell) {
+  __shared__ double rs[MERGE_CELLS][MERGE_MAXAV];   // record fields, in the average's order
+  __shared__ double as[MERGE_CELLS * MERGE_MAXAV];  // the averages, as stored
+  const int c0 = blockIdx.x * MERGE_CELLS;
+  const int nc = min(MERGE_CELLS, ncell - c0);
+  if (nc <= 0) return;
+  const int nrf = AV_HIST + hist + (omega ? 2 : 0);   // = navg
+  // record field f of the average's layout: 0 count, 1..14 means and moments,
+  // then histogram and frequency entries
+  for (int i = threadIdx.x; i < nc * nrf; i += BLOCK) {
+    const int c = i / nrf, f = i - c * nrf;
+    int src;
+    if (f < AV_HIST - 1) src = f;                       // ST_N, ST_MEAN.., ST_M2..
+    else if (f < AV_HIST) src = -1;                     // no record field
+    else if (f < AV_HIST + hist) src = hoff + (f - AV_HIST);
+    else src = nstat - 3 + (f - AV_HIST - hist);
+    rs[c][f] = src >= 0 ? stats[(size_t)(c0 + c) * nstat + src] : 0.0;
   }
-  A[AV_N] = nn;
+  double* A0 = acc + (size_t)c0 * navg;
+  for (int i = threadIdx.x; i < nc * navg; i += BLOCK) as[i] = A0[i];
+  __syncthreads();
+  const int c = threadIdx.x;
+  if (c < nc) {
+    const double* r = rs[c];
+    double* A = as + c * navg;
+    A[AV_STEPS] = A[AV_STEPS] + 1.0;
+    const double nb = r[ST_N];
+    if (nb > 0.0) {
+      const double na = A[AV_N], nn = na + nb;
+      const double fb = nb / nn, wab = na * fb;
+      double d[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) d[q] = r[ST_MEAN + q] - A[AV_MEAN + q];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) A[AV_MEAN + q] = A[AV_MEAN + q] + d[q] * fb;
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = x; y < 4; ++y) {
+          const int t = pair_index(x, y);
+          A[AV_M2 + t] = ((na * A[AV_M2 + t] + nb * r[ST_M2 + t]) + wab * (d[x] * d[y])) / nn;
+        }
+      for (int h = 0; h < hist; ++h) A[AV_HIST + h] = A[AV_HIST + h] + r[AV_HIST + h];
+      if (omega) {
+        double* W = A + AV_HIST + hist;
+        const double* rw = r + AV_HIST + hist;
+        const double dw = rw[0] - W[0];
+        W[0] = W[0] + dw * fb;
+        W[1] = ((na * W[1] + nb * rw[1]) + wab * (dw * dw)) / nn;
+      }
+      A[AV_N] = nn;
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nc * navg; i += BLOCK) A0[i] = as[i];
 }
 
 // Lowest-index element whose closed triangle contains each point (-1: none);

@@ -371,11 +371,11 @@ MergeArgs merge_args(pdf_ctx* c) {
   return m;
 }
 
-constexpr int MERGE_THREADS = 256;
+int merge_blocks(const MergeArgs& m) { return (m.ncell + MERGE_CELLS - 1) / MERGE_CELLS; }
 
 pdf_status enqueue_merge(pdf_ctx* c) {
   const MergeArgs m = merge_args(c);
-  hipLaunchKernelGGL(k_average_merge, dim3((m.ncell + MERGE_THREADS - 1) / MERGE_THREADS), dim3(MERGE_THREADS), 0,
+  hipLaunchKernelGGL(k_average_merge, dim3(merge_blocks(m)), dim3(BLOCK), 0,
                      c->stream, m.stats, m.nstat, m.hoff, m.hist, m.omega, m.acc, m.navg, m.ncell);
   return hip_check(c, hipGetLastError(), "average launch");
 }
@@ -521,8 +521,8 @@ template <typename T> pdf_status build_graph_t(pdf_ctx* c) {
     if (c->avg) {
       hipKernelNodeParams km{};
       km.func = reinterpret_cast<void*>(&k_average_merge);
-      km.gridDim = dim3((margs.ncell + MERGE_THREADS - 1) / MERGE_THREADS);
-      km.blockDim = dim3(MERGE_THREADS);
+      km.gridDim = dim3(merge_blocks(margs));
+      km.blockDim = dim3(BLOCK);
       km.kernelParams = mparams8;
       hipGraphNode_t mn;
       if ((r = hip_check(c, hipGraphAddKernelNode(&mn, g, &prev, 1, &km), "graph node"))) return r;
