@@ -122,8 +122,22 @@ def cpu_baseline(wl_fn, seconds: float = 15.0) -> dict:
         if el >= seconds or steps >= 2000:
             break
     n = wl.n_total
-    return {"value": n * steps / el, "unit": "particle-steps/s", "cores": threads, "kind": "oracle",
-            "sample": f"{wl.name}: all {n} particles, {steps} steps after one untimed step, {el:.1f} s"}
+    res = {"value": n * steps / el, "unit": "particle-steps/s", "cores": threads, "kind": "oracle",
+           "sample": f"{wl.name}: all {n} particles, {steps} steps after one untimed step, {el:.1f} s"}
+    # one host thread on the same state, a few seconds
+    O.lib().orc_set_threads(1)
+    orc.step(1)
+    s1 = 0
+    t0 = time.perf_counter()
+    while True:
+        orc.step(1)
+        s1 += 1
+        el1 = time.perf_counter() - t0
+        if el1 >= seconds / 3 or s1 >= 200:
+            break
+    res["single_thread"] = {"value": n * s1 / el1, "steps": s1, "seconds": round(el1, 1)}
+    O.lib().orc_set_threads(threads)
+    return res
 
 
 def learned_leg(torch, W, Simulation) -> dict:
@@ -385,6 +399,12 @@ def main() -> int:
         out.setdefault("secondary", {})[name] = {
             "value": round(sec["value"], 1), "unit": "particle-steps/s", "steps": args.secondary_steps,
             "ms_per_step": round(sec["ms_per_step"], 5), "config": sec["config"], "roofline": sec["roofline"]}
+    sec = out.get("secondary", {})
+    if "batched64" in sec and "canyon10m" in sec:
+        # the batched run's time against its particles at the large run's time per particle
+        per_particle = sec["canyon10m"]["ms_per_step"] / sec["canyon10m"]["config"]["particles"]
+        b = sec["batched64"]
+        b["balance_efficiency"] = round(b["config"]["particles"] * per_particle / b["ms_per_step"], 4)
     if not args.no_learned:
         out["learned_phi_given_v"] = learned_leg(torch, W, Simulation)
     if args.calibrate_copy:
