@@ -344,9 +344,13 @@ template <> struct MomCount<4> { static constexpr int M3 = 20, M4 = 35; };
 // position of (x, y), x <= y, in the lexicographic list of index pairs of (u, v, w, psi)
 __host__ __device__ constexpr int pair_index(int x, int y) { return x * 4 - (x * (x - 1)) / 2 + (y - x); }
 
+// A cell's first TILEN particles; in the advance, the slots of particles
+// already read also hold the queue of particles whose end point left the
+// element (start x y, end point tx ty, new u v w psi, id).
 template <typename T, int TILEN> struct Tile {
   T x[TILEN], y[TILEN], u[TILEN], v[TILEN], w[TILEN], psi[TILEN];
   uint32_t id[TILEN];
+  T tx[TILEN], ty[TILEN];
 };
 
 // LDS written by some lanes of a wavefront and read by others.  A wavefront's
@@ -843,9 +847,10 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
 
       // Writes a particle that ended in element e2 of ensemble qens: its own
       // cell's bottom run at index k, or the top run of the new cell.
-      auto put_mover = [&](int qens, int e2, T xn, T yn, T un, T vn, T wn, T psi, uint32_t id, T omv) {
-        const int t = qens * ne + e2;
-        const int k = atomicAdd(&a.nm[rn][t], 1);
+      // Writes a particle that moved to cell t into slot k of that cell's
+      // arrivals (counted from the top of its segment), or, when the segment
+      // is full, into the overflow area.
+      auto put_mover = [&](int t, int k, T xn, T yn, T un, T vn, T wn, T psi, uint32_t id, T omv) {
         const int capt = a.cap[t];
         const int limit = capt - (a.ns[rc][t] + a.nm[rc][t]);
         if (k < limit) {
@@ -874,10 +879,95 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
           if (ddx * ddx + ddy * ddy <= qsr * qsr) psi = (T)1;
         }
       };
-      for (int base = 0; __ballot(base < n) != 0; base += G) {
+      // Particles whose end point leaves the element wait in a queue held in
+      // slots of the cell's LDS tile that have already been read (entry q of
+      // the queue is never beyond the particle that fills it) and are walked
+      // together after the batches, or when the queue fills, so that the walk
+      // runs once for all the cell's crossing particles instead of once for
+      // the few crossing lanes of every batch.  Those that come back to the
+      // element join the stayers after the ones of the batches before.
+      int qn = 0;  // queued crossing particles (group-uniform)
+      // walks the queue of the groups with go set
+      auto walk_queue = [&](bool go) {
+        lds_sync_wave();
+        const int nq = go ? qn : 0;
+        for (int qb = 0; __ballot(qb < nq) != 0; qb += G) {
+          const int k = qb + li;
+          bool st = false, mv = false;
+          int t = 0;
+          T tx = 0, ty = 0, un = 0, vn = 0, wn = 0, psi = 0, omv = 0;
+          uint32_t id = 0;
+          if (k < nq) {
+            const double Sx = (double)L.x[k], Sy = (double)L.y[k];
+            tx = L.tx[k]; ty = L.ty[k]; un = L.u[k]; vn = L.v[k]; wn = L.w[k]; psi = L.psi[k]; id = L.id[k];
+            if constexpr (OMG) omv = LO[k];
+            const double Tx = (double)tx, Ty = (double)ty;
+            const int e2 = walk<T, OMG>(a, a.erec[e], e, Sx, Sy, tx, ty, un, vn, wn, omv, orient_cc(CC, 0, Tx, Ty),
+                                        orient_cc(CC, 1, Tx, Ty), orient_cc(CC, 2, Tx, Ty));
+            if (e2 < 0) {
+              err |= ERR_LOST;
+            } else {
+              finish(ens, tx, ty, psi);
+              if (!(isfinite(un) && isfinite(vn) && isfinite(wn) && isfinite(psi) && isfinite(tx) && isfinite(ty)) ||
+                  (OMG && !isfinite(omv)))
+                err |= ERR_NAN;
+              if (e2 == e) {
+                st = true;
+              } else {
+                mv = true;
+                t = ens * ne + e2;
+              }
+            }
+          }
+          // arrival slots: the movers of the wavefront are grouped by target
+          // cell (movers of a cell tend to cross the same edge, and
+          // same-address atomics of one instruction serialise); the lowest
+          // lane of each group takes the group's slots with one atomic, all
+          // groups' atomics in one instruction
+          uint64_t pend = __ballot(mv);
+          int leader = 0, rank = 0, cnt = 0;
+          while (pend) {
+            const int ld = __builtin_ctzll(pend);
+            const int tl = __builtin_amdgcn_readlane(t, ld);
+            const uint64_t same = __ballot(mv && t == tl);
+            if (mv && t == tl) {
+              leader = ld;
+              rank = (int)__popcll(same & lanemask_lt());
+            }
+            if (lane == ld) cnt = (int)__popcll(same);
+            pend &= ~same;
+          }
+          int kb = 0;
+          if (mv && lane == leader) kb = atomicAdd(&a.nm[rn][t], cnt);
+          kb = __shfl(kb, leader, WAVE);
+          if (mv) put_mover(t, kb + rank, tx, ty, un, vn, wn, psi, id, omv);
+          const uint64_t smask = __ballot(st) & gmask;
+          if (st) {
+            const int s = start + stay_count + (int)__popcll(smask & lanemask_lt());
+            dst.x[s] = tx; dst.y[s] = ty; dst.u[s] = un; dst.v[s] = vn; dst.w[s] = wn; dst.psi[s] = psi;
+            dst.id[s] = id;
+            if constexpr (OMG) dst.om[s] = omv;
+          }
+          stay_count += (int)__popcll(smask);
+        }
+        if (go) qn = 0;
+        lds_sync_wave();
+      };
+      // one loop with one walk site: a pass either walks the queues that are
+      // due (full enough to overflow the tile in the next batch, or final) or
+      // advances the next batch
+      for (int base = 0;;) {
+        const bool more = base < n;
+        const bool due = qn > 0 && (qn > TILEN - G || !more);
+        if (__ballot(due) != 0) {
+          walk_queue(due);
+          continue;
+        }
+        if (__ballot(more) == 0) break;
         const int j = base + li;
+        base += G;
         const bool act = j < n;
-        bool moved = false;
+        bool cross = false;
         T x = 0, y = 0, xn = 0, yn = 0, un = 0, vn = 0, wn = 0, psi = 0, omn = 0;
         uint32_t id = 0;
         if (act) {
@@ -945,29 +1035,12 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
             yn = (y + v * a.dt) + a.s2nu * dW2;
             // the walk's first test: is the end point still in the element?
             const double Tx = (double)xn, Ty = (double)yn;
-            const double o0 = orient_cc(CC, 0, Tx, Ty);
-            const double o1 = orient_cc(CC, 1, Tx, Ty);
-            const double o2 = orient_cc(CC, 2, Tx, Ty);
-            if (!(o0 >= 0.0 && o1 >= 0.0 && o2 >= 0.0)) {
-              // it left: the rest of the walk, with walls and periodic edges
-              const int e2 = walk<T, OMG>(a, a.erec[e], e, X, Y, xn, yn, un, vn, wn, omn, o0, o1, o2);
-              if (e2 != e) {
-                moved = true;
-                if (e2 < 0) {
-                  err |= ERR_LOST;
-                } else {
-                  finish(ens, xn, yn, psi);
-                  if (!(isfinite(un) && isfinite(vn) && isfinite(wn) && isfinite(psi) && isfinite(xn) && isfinite(yn)) ||
-                      (OMG && !isfinite(omn)))
-                    err |= ERR_NAN;
-                  put_mover(ens, e2, xn, yn, un, vn, wn, psi, id, omn);
-                }
-              }
-            }
+            cross = !(orient_cc(CC, 0, Tx, Ty) >= 0.0 && orient_cc(CC, 1, Tx, Ty) >= 0.0 &&
+                      orient_cc(CC, 2, Tx, Ty) >= 0.0);
           } else {
             xn = x; yn = y;
           }
-          if (!moved) {
+          if (!cross) {
             finish(ens, xn, yn, psi);
             if (!(isfinite(un) && isfinite(vn) && isfinite(wn) && isfinite(psi) && isfinite(xn) && isfinite(yn)) ||
                 (OMG && !isfinite(omn)))
@@ -975,7 +1048,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
           }
         }
         // stayers: own segment, bottom run, in lane order, no atomics
-        const bool stay = act && !moved;
+        const bool stay = act && !cross;
         const uint64_t smask = __ballot(stay) & gmask;
         if (stay) {
           const int s = start + stay_count + (int)__popcll(smask & lanemask_lt());
@@ -984,6 +1057,15 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
           if constexpr (OMG) dst.om[s] = omn;
         }
         stay_count += (int)__popcll(smask);
+        // crossing particles: into the queue
+        const uint64_t xmask = __ballot(cross) & gmask;
+        if (cross) {
+          const int q = qn + (int)__popcll(xmask & lanemask_lt());
+          L.x[q] = x; L.y[q] = y; L.tx[q] = xn; L.ty[q] = yn; L.u[q] = un; L.v[q] = vn; L.w[q] = wn; L.psi[q] = psi;
+          L.id[q] = id;
+          if constexpr (OMG) LO[q] = omn;
+        }
+        qn += (int)__popcll(xmask);
       }
       if (has && li == 0) {
         a.ns[rn][cell] = stay_count;
