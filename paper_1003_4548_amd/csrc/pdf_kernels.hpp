@@ -407,6 +407,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
   constexpr bool OMG = XV == XV_OMEGA;
   constexpr bool VB5 = XV == XV_BINS5;
   static_assert(!(XV != XV_NONE && SCHED == 2), "model extensions run with the separate learned-means pass");
+  static_assert(!(SCHED == 2 && G < 16), "the learned means inside the step need at most 16 cells per block");
   constexpr bool PERSIST = SCHED == 1;
   constexpr int GPW = WAVE / G;             // cells per wavefront
   constexpr int TILEN = 4 * G;              // particles per cell staged in LDS

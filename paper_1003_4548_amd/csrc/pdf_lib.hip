@@ -150,9 +150,10 @@ int nstat_of(const pdf_params& p) {
 int navg_of(const pdf_params& p) { return AV_HIST + p.hist_bins + (p.omega ? 2 : 0); }
 
 // The learned conditional means run as a statistics pass and an inference
-// launch before each step on persistent grids and with the turbulent
-// frequency; otherwise inside the step.
-bool mlp_separate(const pdf_ctx* c) { return c->mlp_w && (c->persist || c->p.omega); }
+// launch before each step on persistent grids, with the turbulent frequency
+// and with 8 lanes per cell (a block's cells then exceed one 16-column
+// network tile); otherwise inside the step.
+bool mlp_separate(const pdf_ctx* c) { return c->mlp_w && (c->persist || c->p.omega || c->group < 16); }
 
 pdf_status fail(pdf_ctx* c, pdf_status s, const std::string& msg) {
   if (c) {
@@ -279,13 +280,16 @@ template <typename T, int MOM, int HIST, bool ADV, int XV, int G>
 void launch_shape(pdf_ctx* c, const StepArgs<T>& s, StepIndex si, int sc) {
   if (!ADV || sc == 0) launch_step<T, MOM, HIST, G, ADV, 0, XV>(c, s, si);
   else if (sc == 1) launch_step<T, MOM, HIST, G, ADV, ADV ? 1 : 0, XV>(c, s, si);
-  else if constexpr (XV == XV_NONE) launch_step<T, MOM, HIST, G, ADV, ADV ? 2 : 0, XV>(c, s, si);
+  else if constexpr (XV == XV_NONE && G >= 16) launch_step<T, MOM, HIST, G, ADV, ADV ? 2 : 0, XV>(c, s, si);
 }
 
 template <typename T, int MOM, int HIST, bool ADV, int XV>
 void launch_group(pdf_ctx* c, const StepArgs<T>& s, StepIndex si) {
   const int sc = sched_of(c, ADV);
   switch (c->group) {
+    case 8:
+      if constexpr (std::is_same<T, float>::value) launch_shape<T, MOM, HIST, ADV, XV, 8>(c, s, si, sc);
+      break;
     case 16: launch_shape<T, MOM, HIST, ADV, XV, 16>(c, s, si, sc); break;
     case 32: launch_shape<T, MOM, HIST, ADV, XV, 32>(c, s, si, sc); break;
     default: launch_shape<T, MOM, HIST, ADV, XV, 64>(c, s, si, sc); break;
@@ -459,7 +463,7 @@ StepLaunch step_launch_of(pdf_ctx* c, StepArgs<T>& s) {
 template <typename T, int MOM, int HIST, int XV, int G>
 StepLaunch step_launch_shape(pdf_ctx* c, StepArgs<T>& s, int sc) {
   if (sc == 1) return step_launch_of<T, MOM, HIST, G, 1, XV>(c, s);
-  if constexpr (XV == XV_NONE) {
+  if constexpr (XV == XV_NONE && G >= 16) {
     if (sc == 2) return step_launch_of<T, MOM, HIST, G, 2, XV>(c, s);
   }
   return step_launch_of<T, MOM, HIST, G, 0, XV>(c, s);
@@ -469,6 +473,9 @@ template <typename T, int MOM, int HIST, int XV>
 StepLaunch step_launch_group(pdf_ctx* c, StepArgs<T>& s) {
   const int sc = sched_of(c, true);
   switch (c->group) {
+    case 8:
+      if constexpr (std::is_same<T, float>::value) return step_launch_shape<T, MOM, HIST, XV, 8>(c, s, sc);
+      return StepLaunch{};
     case 16: return step_launch_shape<T, MOM, HIST, XV, 16>(c, s, sc);
     case 32: return step_launch_shape<T, MOM, HIST, XV, 32>(c, s, sc);
     default: return step_launch_shape<T, MOM, HIST, XV, 64>(c, s, sc);
@@ -833,14 +840,14 @@ pdf_status pdf_step_graph(pdf_ctx* c, int32_t nsteps) {
 pdf_status pdf_autotune(pdf_ctx* c, int32_t steps_per_trial, int32_t* group, int32_t* persist) {
   if (!c || steps_per_trial <= 0) return fail(c, PDF_E_ARG, "pdf_autotune: bad argument");
   if (!c->seeded) return fail(c, PDF_E_STATE, "pdf_autotune before pdf_seed_particles");
-  const int groups[3] = {64, 32, 16};
+  const int groups[4] = {64, 32, 16, 8};
   float best = 1e30f;
   int bg = c->group, bp = c->persist;
   hipEvent_t e0, e1;
   pdf_status r;
   if ((r = hip_check(c, hipEventCreate(&e0), "event"))) return r;
   if ((r = hip_check(c, hipEventCreate(&e1), "event"))) return r;
-  for (int gi = 0; gi < 3; ++gi) {
+  for (int gi = 0; gi < 4; ++gi) {
     for (int pe = 0; pe < 2; ++pe) {
       if (!c->p.f32_state && groups[gi] != 64) continue;
       c->group = groups[gi];
@@ -870,8 +877,8 @@ pdf_status pdf_autotune(pdf_ctx* c, int32_t steps_per_trial, int32_t* group, int
 }
 
 pdf_status pdf_set_launch(pdf_ctx* c, int32_t group, int32_t persist) {
-  if (!c || !(group == 16 || group == 32 || group == 64) || persist < 0 || persist > 1)
-    return fail(c, PDF_E_ARG, "pdf_set_launch: group must be 16, 32 or 64, persist 0 or 1");
+  if (!c || !(group == 8 || group == 16 || group == 32 || group == 64) || persist < 0 || persist > 1)
+    return fail(c, PDF_E_ARG, "pdf_set_launch: group must be 8, 16, 32 or 64, persist 0 or 1");
   if (!c->p.f32_state && group != 64) return fail(c, PDF_E_ARG, "pdf_set_launch: double state runs with group 64");
   c->group = group;
   c->persist = persist;

@@ -82,7 +82,7 @@ def test_fine_bin_trajectory_and_statistics(gpu, case):
     assert (np.count_nonzero(so[:, _offset(wl):_offset(wl) + 125], axis=1) > 8).mean() > 0.5
 
 
-@pytest.mark.parametrize("shape", [(16, 0), (32, 1), (64, 1), (16, 1)])
+@pytest.mark.parametrize("shape", [(16, 0), (32, 1), (64, 1), (16, 1), (8, 0)])
 def test_fine_bin_launch_shapes(gpu, shape):
     wl = _wallfn()
     wl.steps = 6

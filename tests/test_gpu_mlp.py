@@ -224,7 +224,7 @@ def test_inference_matches_oracle(gpu):
     assert abs(int(served.cpu()[0]) - int(oko.sum())) <= int(edge.sum())
 
 
-@pytest.mark.parametrize("shape", [(64, 0), (16, 0), (32, 1)])
+@pytest.mark.parametrize("shape", [(64, 0), (16, 0), (32, 1), (8, 0)])
 def test_step_with_learned_means_matches_oracle(gpu, shape):
     """IECM toward the network's conditional means: the oracle, given the same
     means, reproduces the step bit for bit (inside the step kernel for the

@@ -114,7 +114,7 @@ def test_frequency_trajectory_parity(gpu, case):
         assert orc.wallfn_hits() > 20
 
 
-@pytest.mark.parametrize("shape", [(16, 0), (32, 1), (64, 1), (16, 1)])
+@pytest.mark.parametrize("shape", [(16, 0), (32, 1), (64, 1), (16, 1), (8, 0), (8, 1)])
 def test_frequency_launch_shapes(gpu, shape):
     wl = CASES["wallfn_m4_hist_f32"]()
     wl.steps = 8

@@ -203,7 +203,7 @@ def test_config2_full_size_parity(gpu):
     assert_stats_parity(sim.statistics()[0], orc.stats(), wl.moments, wl.hist_bins, what="config2 stats")
 
 
-SHAPES = [(64, 0), (64, 1), (32, 0), (32, 1), (16, 0), (16, 1)]
+SHAPES = [(64, 0), (64, 1), (32, 0), (32, 1), (16, 0), (16, 1), (8, 0), (8, 1)]
 
 
 @pytest.mark.parametrize("shape", SHAPES)
@@ -233,14 +233,14 @@ def test_autotune_keeps_parity(gpu):
     shape = sim.autotune(steps_per_trial=2)
     assert shape[0] in (16, 32, 64) and shape[1] in (0, 1)
     done = sim.steps_done()
-    assert done == 6 * 3
+    assert done == 8 * 3
     orc = O.Oracle(wl)
     orc.step(done)
     sim.sync()
     assert_state_parity(sim.state(), orc.state(), what="after autotune")
 
 
-@pytest.mark.parametrize("shape", [(64, 0), (32, 1)])
+@pytest.mark.parametrize("shape", [(64, 0), (32, 1), (8, 0)])
 def test_graph_replay_matches_eager(gpu, shape):
     """Six-step graph replays, with eager work and synchronisation between
     them, against a run launched step by step."""
