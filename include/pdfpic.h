@@ -223,6 +223,25 @@ pdf_status pdf_sync(pdf_ctx* ctx);
    n = pdf_count(ctx, ens).  Asynchronous. */
 pdf_status pdf_get_state(pdf_ctx* ctx, int32_t ens, double* xyuvwpsi, int32_t* elem);
 
+/* Checkpoint restore (and a test hook for the device error paths): replace
+   the state of ensemble ens with n = pdf_count(ctx, ens) particles given in
+   the layout of pdf_get_state (xyuvwpsi 6 x n doubles, elem n int32, om n
+   doubles with the turbulent frequency, else NULL; all device memory), in
+   id order: particle i gets id i (its Philox counter) and goes to the segment
+   of element elem[i]; values are rounded to the state type.  Positions are
+   not checked against their elements.  Waits for the stream.  Errors, with
+   the state left unchanged: PDF_E_ARG for an element index out of range,
+   PDF_E_CAPACITY when an element's particles exceed its segment (create the
+   context with a larger slack).  On success the device error word is
+   cleared: a restored state steps again. */
+pdf_status pdf_set_state(pdf_ctx* ctx, int32_t ens, const double* xyuvwpsi, const int32_t* elem, const double* om);
+
+/* Set the Philox step word of the next step (0 <= step < 2^32 - 1): with
+   pdf_set_state, a run resumed from a checkpoint taken after step s draws
+   the same numbers as the uninterrupted run.  pdf_steps_done is not
+   changed.  Asynchronous. */
+pdf_status pdf_set_step(pdf_ctx* ctx, int64_t step);
+
 /* As pdf_get_state, plus the turbulent frequency om (n doubles, device
    memory).  PDF_E_STATE if the context carries none. */
 pdf_status pdf_get_omega(pdf_ctx* ctx, int32_t ens, double* xyuvwpsi, int32_t* elem, double* om);

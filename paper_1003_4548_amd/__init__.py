@@ -30,7 +30,7 @@ ENTRY_POINTS = ("pdf_create", "pdf_query_sizes", "pdf_init_mesh", "pdf_seed_part
                 "pdf_estimate_statistics", "pdf_nstat", "pdf_sync",
                 "pdf_mlp_work_floats", "pdf_mlp_dataset", "pdf_mlp_forward", "pdf_mlp_grad", "pdf_mlp_train",
                 "pdf_mlp_norm", "pdf_mlp_round", "pdf_mlp_infer", "pdf_mlp_attach",
-                "pdf_get_state", "pdf_get_omega", "pdf_omega_fields", "pdf_navg", "pdf_average_attach",
+                "pdf_get_state", "pdf_set_state", "pdf_set_step", "pdf_get_omega", "pdf_omega_fields", "pdf_navg", "pdf_average_attach",
                 "pdf_locate", "pdf_average_probe", "pdf_count", "pdf_steps_done", "pdf_error_string", "pdf_destroy")
 
 
@@ -129,6 +129,10 @@ def load_library():
     L.pdf_sync.argtypes = [vp]
     L.pdf_get_state.restype = i32
     L.pdf_get_state.argtypes = [vp, i32, vp, vp]
+    L.pdf_set_state.restype = i32
+    L.pdf_set_state.argtypes = [vp, i32, vp, vp, vp]
+    L.pdf_set_step.restype = i32
+    L.pdf_set_step.argtypes = [vp, i64]
     L.pdf_get_omega.restype = i32
     L.pdf_get_omega.argtypes = [vp, i32, vp, vp, vp]
     L.pdf_omega_fields.restype = i32
@@ -371,6 +375,26 @@ class Simulation:
                                                      ctypes.c_void_p(out.data_ptr())), "pdf_average_probe")
         self.stream.synchronize()
         return out.cpu().numpy()
+
+    def set_state(self, st: dict, ens: int = 0) -> None:
+        """Replace ensemble ens's state with st (x y u v w psi elem, and omega
+        when carried), particle i becoming id i (checkpoint restore)."""
+        t = self.torch
+        vals = t.tensor(np.stack([np.asarray(st[k], np.float64) for k in ("x", "y", "u", "v", "w", "psi")]),
+                        device=self.device)
+        elem = t.tensor(np.asarray(st["elem"], np.int32), device=self.device)
+        om = None
+        if self.params.omega:
+            om = t.tensor(np.asarray(st["omega"], np.float64), device=self.device)
+        self.stream.synchronize()
+        self._check(load_library().pdf_set_state(self.ctx, int(ens), ctypes.c_void_p(vals.data_ptr()),
+                                                 ctypes.c_void_p(elem.data_ptr()),
+                                                 None if om is None else ctypes.c_void_p(om.data_ptr())),
+                    "pdf_set_state")
+
+    def set_step(self, step: int) -> None:
+        """Philox step word of the next step (resume from a checkpoint)."""
+        self._check(load_library().pdf_set_step(self.ctx, int(step)), "pdf_set_step")
 
     def omega_fields(self):
         """(<omega> per centroid, S_omega per element, <omega> per wall-function

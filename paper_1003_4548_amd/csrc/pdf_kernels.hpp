@@ -1381,6 +1381,75 @@ __global__ __launch_bounds__(BLOCK) void k_gather(StateDev<T> b0, StateDev<T> b1
   }
 }
 
+// ---------------------------------------------------------------------------
+// replacing the state of one ensemble (checkpoint restore)
+
+// Particles of ensemble ens per element (cnt: the cells' scratch counters,
+// zero on entry); flag bit 1: an element index out of range.
+__global__ void k_set_count(const int32_t* elem, int64_t n, int ne, int ens, int32_t* cnt, int32_t* flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int e = elem[i];
+  if (e < 0 || e >= ne) {
+    atomicOr(flag, 1);
+    return;
+  }
+  atomicAdd(&cnt[(size_t)ens * ne + e], 1);
+}
+
+// flag bit 2: a cell whose segment cannot hold its particles.
+__global__ void k_set_check(const int32_t* cnt, const int32_t* cap, int ne, int ens, int32_t* flag) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ne) return;
+  const int c = ens * ne + e;
+  if (cnt[c] > cap[c]) atomicOr(flag, 2);
+}
+
+// Installs the counts as the cells' current stayers (no arrivals) and clears
+// the scratch counters, which then number the particles of each cell.
+__global__ void k_set_counts(int32_t* cnt, int32_t* ns, int32_t* nm, int ne, int ens) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ne) return;
+  const int c = ens * ne + e;
+  ns[c] = cnt[c];
+  nm[c] = 0;
+  cnt[c] = 0;
+}
+
+// Writes particle i (id i) of the caller's arrays into its cell's segment of
+// the buffer holding the current state.
+template <typename T>
+__global__ void k_set_place(StateDev<T> b0, StateDev<T> b1, const Ctl* ctl, StepIndex si, const double* v,
+                            const int32_t* elem, const double* om, int64_t n, int ne, int ens, const int32_t* start,
+                            int32_t* pos) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const StateDev<T> st = (si.parity ^ (ctl->flip & 1u)) ? b1 : b0;
+  const int c = ens * ne + elem[i];
+  const int s = start[c] + atomicAdd(&pos[c], 1);
+  st.x[s] = (T)v[i];
+  st.y[s] = (T)v[n + i];
+  st.u[s] = (T)v[2 * n + i];
+  st.v[s] = (T)v[3 * n + i];
+  st.w[s] = (T)v[4 * n + i];
+  st.psi[s] = (T)v[5 * n + i];
+  st.id[s] = (uint32_t)i;
+  if (st.om) st.om[s] = (T)om[i];
+}
+
+__global__ void k_set_step(Ctl* ctl, uint32_t step) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) ctl->step_base = step;
+}
+
+// After a restore the state is valid again: the error word and the overflow
+// count start over.
+__global__ void k_clear_error(Ctl* ctl) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    ctl->error = 0;
+    ctl->ovf = 0;
+  }
+}
+
 __global__ void k_reset_ctl(Ctl* ctl) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     ctl->step_base = 0; ctl->error = 0; ctl->ovf = 0; ctl->next[0] = 0; ctl->next[1] = 0;

@@ -978,6 +978,60 @@ static pdf_status gather_state(pdf_ctx* c, int32_t ens, double* xyuvwpsi, int32_
   return hip_check(c, hipGetLastError(), "gather launch");
 }
 
+pdf_status pdf_set_state(pdf_ctx* c, int32_t ens, const double* xyuvwpsi, const int32_t* elem, const double* om) {
+  if (!c || !xyuvwpsi || !elem) return fail(c, PDF_E_ARG, "pdf_set_state: null input");
+  if (!c->seeded) return fail(c, PDF_E_STATE, "pdf_set_state before pdf_seed_particles");
+  if (ens < 0 || ens >= c->nens) return fail(c, PDF_E_ARG, "ensemble out of range");
+  if (c->p.omega && !om) return fail(c, PDF_E_ARG, "pdf_set_state: the context carries the turbulent frequency");
+  const int64_t n = c->ens_count[ens];
+  char* a = c->arena;
+  const Layout& L = c->L;
+  const int ne = c->ne;
+  const uint32_t rz = c->rot == 0 ? 2u : c->rot - 1u;   // counter set not read by the next step
+  int32_t* scratch = (int32_t*)(a + L.ns[rz]);
+  int32_t* flag = (int32_t*)(a + L.flag) + 1;
+  hipStream_t st = c->stream;
+  const int tb = 256;
+  const unsigned pb = (unsigned)std::max<int64_t>(1, (n + tb - 1) / tb), eb = (unsigned)((ne + tb - 1) / tb);
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, flag, 0, (int64_t)1);
+  hipLaunchKernelGGL(k_fill_i32, dim3(eb), dim3(tb), 0, st, scratch + (size_t)ens * ne, 0, (int64_t)ne);
+  hipLaunchKernelGGL(k_set_count, dim3(pb), dim3(tb), 0, st, elem, n, ne, ens, scratch, flag);
+  hipLaunchKernelGGL(k_set_check, dim3(eb), dim3(tb), 0, st, scratch, (const int32_t*)(a + L.cap), ne, ens, flag);
+  pdf_status r;
+  if ((r = hip_check(c, hipGetLastError(), "set-state launch"))) return r;
+  int32_t bad = 0;
+  if ((r = hip_check(c, hipMemcpyAsync(&bad, flag, 4, hipMemcpyDeviceToHost, st), "read flag"))) return r;
+  if ((r = hip_check(c, hipStreamSynchronize(st), "sync set-state"))) return r;
+  if (bad) {
+    hipLaunchKernelGGL(k_fill_i32, dim3(eb), dim3(tb), 0, st, scratch + (size_t)ens * ne, 0, (int64_t)ne);
+    (void)hipStreamSynchronize(st);
+    if (bad & 1) return fail(c, PDF_E_ARG, "pdf_set_state: element index out of range (state unchanged)");
+    return fail(c, PDF_E_CAPACITY, "pdf_set_state: an element segment cannot hold its particles (state unchanged)");
+  }
+  hipLaunchKernelGGL(k_set_counts, dim3(eb), dim3(tb), 0, st, scratch, (int32_t*)(a + L.ns[c->rot]),
+                     (int32_t*)(a + L.nm[c->rot]), ne, ens);
+  const StepIndex si{0, c->parity, c->rot, 0};
+  if (c->p.f32_state)
+    hipLaunchKernelGGL(k_set_place<float>, dim3(pb), dim3(tb), 0, st, state_at<float>(a, L.buf0, L.slots, L.omega),
+                       state_at<float>(a, L.buf1, L.slots, L.omega), (const Ctl*)(a + L.ctl), si, xyuvwpsi, elem, om,
+                       n, ne, ens, (const int32_t*)(a + L.start), scratch);
+  else
+    hipLaunchKernelGGL(k_set_place<double>, dim3(pb), dim3(tb), 0, st, state_at<double>(a, L.buf0, L.slots, L.omega),
+                       state_at<double>(a, L.buf1, L.slots, L.omega), (const Ctl*)(a + L.ctl), si, xyuvwpsi, elem, om,
+                       n, ne, ens, (const int32_t*)(a + L.start), scratch);
+  hipLaunchKernelGGL(k_fill_i32, dim3(eb), dim3(tb), 0, st, scratch + (size_t)ens * ne, 0, (int64_t)ne);
+  hipLaunchKernelGGL(k_clear_error, dim3(1), dim3(64), 0, st, (Ctl*)(a + L.ctl));
+  if ((r = hip_check(c, hipGetLastError(), "set-state launch"))) return r;
+  return hip_check(c, hipStreamSynchronize(st), "sync set-state");
+}
+
+pdf_status pdf_set_step(pdf_ctx* c, int64_t step) {
+  if (!c || step < 0 || step > 0xFFFFFFFEll) return fail(c, PDF_E_ARG, "pdf_set_step: bad step");
+  if (!c->seeded) return fail(c, PDF_E_STATE, "pdf_set_step before pdf_seed_particles");
+  hipLaunchKernelGGL(k_set_step, dim3(1), dim3(64), 0, c->stream, (Ctl*)(c->arena + c->L.ctl), (uint32_t)step);
+  return hip_check(c, hipGetLastError(), "set-step launch");
+}
+
 pdf_status pdf_get_state(pdf_ctx* c, int32_t ens, double* xyuvwpsi, int32_t* elem) {
   if (!c || !xyuvwpsi || !elem) return fail(c, PDF_E_ARG, "pdf_get_state: null output");
   return gather_state(c, ens, xyuvwpsi, elem, nullptr);
