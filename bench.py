@@ -333,6 +333,7 @@ def main() -> int:
         sim.sync()
         assert sim.steps_done() == tuned + warmup + steps
         repacks = sim.repacks()
+        metrics = sim.metrics()
         # the same steps with time averaging on (one merge launch per step)
         avg_steps = min(steps, 100)
         sim.average_attach()
@@ -367,6 +368,9 @@ def main() -> int:
                                   "autotune_steps_per_candidate": 0 if args.launch else autotune_steps,
                                   "hip_graph": not args.no_graph},
                        "segment_repacks": repacks,
+                       "last_step": {"mover_fraction": round(metrics["arrivals_last_step"] / max(1, wl.n_total), 5),
+                                     "min_per_cell": metrics["min_per_cell"],
+                                     "max_per_cell": metrics["max_per_cell"]},
                        "with_time_averaging": {"steps": avg_steps, "ms_per_step": round(1e3 * avg_wall / avg_steps, 5),
                                                "value": round(wl.n_total * avg_steps / avg_wall, 1)},
                        "kernel_source_hash": src_hash},

@@ -212,6 +212,15 @@ int64_t pdf_repack_count(pdf_ctx* ctx);
    out_on_host: 1 -> out is host memory and the call waits; 0 -> device. */
 pdf_status pdf_estimate_statistics(pdf_ctx* ctx, double* out, int32_t out_on_host);
 
+/* Run metrics from the device counters, into out (8 int64, host; waits):
+   particles; arrivals written by the last step (particles now in another
+   element than before it, 0 right after a repack, which folds them in);
+   smallest and largest particle count of a cell; cells filled beyond three
+   quarters of their segment; repacks since seeding; the device error word
+   (PDF_E_* as bits: 1 lost, 2 non-finite, 4 capacity, 8 overflow area full);
+   steps done. */
+pdf_status pdf_metrics(pdf_ctx* ctx, int64_t* out);
+
 /* Record length of the statistics. */
 int32_t pdf_nstat(const pdf_ctx* ctx);
 

@@ -27,7 +27,7 @@ NFIELD = 20
 # exported entry points (the declarations of include/pdfpic.h)
 ENTRY_POINTS = ("pdf_create", "pdf_query_sizes", "pdf_init_mesh", "pdf_seed_particles", "pdf_step",
                 "pdf_step_graph", "pdf_autotune", "pdf_set_launch", "pdf_repack", "pdf_repack_count",
-                "pdf_estimate_statistics", "pdf_nstat", "pdf_sync",
+                "pdf_estimate_statistics", "pdf_nstat", "pdf_sync", "pdf_metrics",
                 "pdf_mlp_work_floats", "pdf_mlp_dataset", "pdf_mlp_forward", "pdf_mlp_grad", "pdf_mlp_train",
                 "pdf_mlp_norm", "pdf_mlp_round", "pdf_mlp_infer", "pdf_mlp_attach",
                 "pdf_get_state", "pdf_set_state", "pdf_set_step", "pdf_get_omega", "pdf_omega_fields", "pdf_navg", "pdf_average_attach",
@@ -129,6 +129,8 @@ def load_library():
     L.pdf_sync.argtypes = [vp]
     L.pdf_get_state.restype = i32
     L.pdf_get_state.argtypes = [vp, i32, vp, vp]
+    L.pdf_metrics.restype = i32
+    L.pdf_metrics.argtypes = [vp, vp]
     L.pdf_set_state.restype = i32
     L.pdf_set_state.argtypes = [vp, i32, vp, vp, vp]
     L.pdf_set_step.restype = i32
@@ -391,6 +393,14 @@ class Simulation:
                                                  ctypes.c_void_p(elem.data_ptr()),
                                                  None if om is None else ctypes.c_void_p(om.data_ptr())),
                     "pdf_set_state")
+
+    def metrics(self) -> dict:
+        """Counters of the current state (see pdf_metrics)."""
+        out = np.zeros(8, np.int64)
+        self._check(load_library().pdf_metrics(self.ctx, _ptr(out)), "pdf_metrics")
+        keys = ("particles", "arrivals_last_step", "min_per_cell", "max_per_cell", "cells_over_three_quarters",
+                "repacks", "error_word", "steps_done")
+        return {k: int(v) for k, v in zip(keys, out)}
 
     def set_step(self, step: int) -> None:
         """Philox step word of the next step (resume from a checkpoint)."""

@@ -1382,6 +1382,56 @@ __global__ __launch_bounds__(BLOCK) void k_gather(StateDev<T> b0, StateDev<T> b1
 }
 
 // ---------------------------------------------------------------------------
+// run metrics from the cell counters
+
+// One block over the cells of the current counter set: out[0] particles,
+// out[1] arrivals written by the last step (particles now in another element
+// than before it; 0 right after a repack, which folds them in), out[2] and
+// out[3] the smallest and largest count of a cell, out[4] cells filled beyond
+// three quarters of their segment.
+constexpr int METRIC_THREADS = 1024;
+__global__ __launch_bounds__(METRIC_THREADS) void k_metrics(const int32_t* ns, const int32_t* nm, const int32_t* cap,
+                                                            int ncell, int64_t* out) {
+  __shared__ long long red[5][METRIC_THREADS / WAVE];
+  long long tot = 0, arr = 0, mn = 0x7fffffffffffll, mx = 0, full = 0;
+  for (int c = threadIdx.x; c < ncell; c += METRIC_THREADS) {
+    const long long k = (long long)ns[c] + nm[c];
+    tot += k;
+    arr += nm[c];
+    mn = k < mn ? k : mn;
+    mx = k > mx ? k : mx;
+    full += (4 * k > 3 * (long long)cap[c]) ? 1 : 0;
+  }
+  for (int off = WAVE / 2; off > 0; off >>= 1) {
+    tot += __shfl_xor(tot, off, WAVE);
+    arr += __shfl_xor(arr, off, WAVE);
+    const long long omn = __shfl_xor(mn, off, WAVE), omx = __shfl_xor(mx, off, WAVE);
+    mn = omn < mn ? omn : mn;
+    mx = omx > mx ? omx : mx;
+    full += __shfl_xor(full, off, WAVE);
+  }
+  const int w = threadIdx.x / WAVE;
+  if (lane_id() == 0) {
+    red[0][w] = tot; red[1][w] = arr; red[2][w] = mn; red[3][w] = mx; red[4][w] = full;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < METRIC_THREADS / WAVE; ++i) {
+      red[0][0] += red[0][i];
+      red[1][0] += red[1][i];
+      red[2][0] = red[2][i] < red[2][0] ? red[2][i] : red[2][0];
+      red[3][0] = red[3][i] > red[3][0] ? red[3][i] : red[3][0];
+      red[4][0] += red[4][i];
+    }
+    out[0] = red[0][0];
+    out[1] = red[1][0];
+    out[2] = ncell > 0 ? red[2][0] : 0;
+    out[3] = red[3][0];
+    out[4] = red[4][0];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // replacing the state of one ensemble (checkpoint restore)
 
 // Particles of ensemble ens per element (cnt: the cells' scratch counters,

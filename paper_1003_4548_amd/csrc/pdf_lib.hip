@@ -27,7 +27,7 @@ int64_t align_up(int64_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 struct Layout {
   int64_t vtx, tri, nbr, ekind, inv2a, alpha, wnorm, fields, coef, erec, om0, somega, omw;
   int64_t start, cap, cap0, nstart, ncap, ns[3], nm[3], rate, idoff, order, seed, src;
-  int64_t buf0, buf1, ovf, ovf_cell, stats, ctl, flag;
+  int64_t buf0, buf1, ovf, ovf_cell, stats, ctl, flag, metrics;
   int64_t total;
   int64_t slots;
   int64_t ovf_cap;
@@ -75,6 +75,7 @@ Layout make_layout(int32_t nv, int32_t ne, int32_t nens, int64_t slots, int32_t 
   L.stats = take(ncell * (int64_t)nstat * 8);
   L.ctl = take(sizeof(Ctl));
   L.flag = take(16);
+  L.metrics = take(64);
   L.total = o;
   L.slots = slots;
   L.omega = omega;
@@ -900,6 +901,27 @@ int64_t pdf_repack_count(pdf_ctx* c) {
   Ctl h{};
   if (hipMemcpy(&h, c->arena + c->L.ctl, sizeof(Ctl), hipMemcpyDeviceToHost) != hipSuccess) return -1;
   return (int64_t)h.repacks;
+}
+
+pdf_status pdf_metrics(pdf_ctx* c, int64_t* out) {
+  if (!c || !out) return fail(c, PDF_E_ARG, "pdf_metrics: null output");
+  if (!c->seeded) return fail(c, PDF_E_STATE, "pdf_metrics before pdf_seed_particles");
+  char* a = c->arena;
+  int64_t* m = (int64_t*)(a + c->L.metrics);
+  hipLaunchKernelGGL(k_metrics, dim3(1), dim3(METRIC_THREADS), 0, c->stream, (const int32_t*)(a + c->L.ns[c->rot]),
+                     (const int32_t*)(a + c->L.nm[c->rot]), (const int32_t*)(a + c->L.cap), c->ne * c->nens, m);
+  pdf_status r;
+  if ((r = hip_check(c, hipGetLastError(), "metrics launch"))) return r;
+  int64_t h[5];
+  Ctl ctl{};
+  if ((r = hip_check(c, hipMemcpyAsync(h, m, sizeof(h), hipMemcpyDeviceToHost, c->stream), "copy metrics"))) return r;
+  if ((r = hip_check(c, hipMemcpyAsync(&ctl, a + c->L.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream), "copy control"))) return r;
+  if ((r = hip_check(c, hipStreamSynchronize(c->stream), "sync metrics"))) return r;
+  for (int i = 0; i < 5; ++i) out[i] = h[i];
+  out[5] = ctl.repacks;
+  out[6] = ctl.error;
+  out[7] = c->steps_done;
+  return PDF_OK;
 }
 
 int32_t pdf_nstat(const pdf_ctx* c) { return c ? nstat_of(c->p) : 0; }
