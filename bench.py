@@ -144,7 +144,7 @@ def learned_leg(torch, W, Simulation) -> dict:
     """The learned conditional means on the 10k-element canyon with its street
     source.  Training rows: 20-particle subsamples of runs at 500 particles per
     element (seeds 1..4), taken every 100 steps from step 500 to 2000, eight
-    draws each, the rows with scalar spread kept.  Judged against a run at
+    draws each, the rows with scalar spread kept.  Compared with a run at
     4000 particles per element (seed 101) at the same steps, next to the
     binned estimate of 20- and 500-particle subsamples.  Then used inside the
     step of a 20-particle-per-element run on the 50k-element resolved-wall
@@ -180,7 +180,7 @@ def learned_leg(torch, W, Simulation) -> dict:
     train_ms = e0.elapsed_time(e1)
     loss = loss.cpu().numpy()
     del rows
-    # judged against 4000 particles per element
+    # compared with 4000 particles per element
     sim = Simulation.from_workload(W.config5(ppe=4000, seed=101), device="cuda:0")
     sim.step_graph(spin)
     r20, r500 = [], []
@@ -263,7 +263,10 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--secondary", default="canyon10m,batched64,canyon10m_omega,canyon10m_bins5",
                     help="further workloads reported in the same line, comma separated ('' for none)")
-    ap.add_argument("--secondary-steps", type=int, default=100)
+    ap.add_argument("--secondary-steps", type=int, default=1000)
+    ap.add_argument("--repeats", type=int, default=5,
+                    help="timed blocks of K steps on the main workload; the first is the reported one, "
+                         "all are listed with their median")
     ap.add_argument("--no-graph", action="store_true", help="launch steps one by one instead of graph replays")
     ap.add_argument("--autotune-steps", type=int, default=5,
                     help="steps per candidate launch shape before warmup (0: no tuning)")
@@ -303,7 +306,7 @@ def main() -> int:
                 "unit": "G VALU wavefront-instructions/s", "frac": round(rate / VALU_PEAK_WAVE_INSTS, 4),
                 "valu_wave_instructions_per_step": n}
 
-    def run(name, steps, warmup):
+    def run(name, steps, warmup, repeats=1):
         cfg_fn = getattr(W, WORKLOADS[name][0])
         wl = cfg_fn(steps=steps)
         sim = Simulation.from_workload(wl, device="cuda:0")
@@ -332,6 +335,14 @@ def main() -> int:
         t1 = time.perf_counter()
         sim.sync()
         assert sim.steps_done() == tuned + warmup + steps
+        # further timed blocks of the same length (spread of the measurement)
+        rep_ms = [1e3 * (t1 - t0) / steps]
+        for _ in range(repeats - 1):
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            step_fn(steps)
+            torch.cuda.synchronize()
+            rep_ms.append(1e3 * (time.perf_counter() - ta) / steps)
         repacks = sim.repacks()
         metrics = sim.metrics()
         # the same steps with time averaging on (one merge launch per step)
@@ -368,6 +379,8 @@ def main() -> int:
                                   "autotune_steps_per_candidate": 0 if args.launch else autotune_steps,
                                   "hip_graph": not args.no_graph},
                        "segment_repacks": repacks,
+                       "repeat_ms_per_step": [round(v, 5) for v in rep_ms],
+                       "median_ms_per_step": round(sorted(rep_ms)[len(rep_ms) // 2], 5),
                        "last_step": {"mover_fraction": round(metrics["arrivals_last_step"] / max(1, wl.n_total), 5),
                                      "min_per_cell": metrics["min_per_cell"],
                                      "max_per_cell": metrics["max_per_cell"]},
@@ -381,7 +394,7 @@ def main() -> int:
         torch.cuda.empty_cache()
         return res
 
-    main_res = run(args.workload, args.steps, args.warmup)
+    main_res = run(args.workload, args.steps, args.warmup, max(1, args.repeats))
     out = {
         "metric": "particle-steps/s",
         "value": round(main_res["value"], 1),
