@@ -175,16 +175,18 @@ pdf_status pdf_step(pdf_ctx* ctx, int32_t nsteps);
 pdf_status pdf_step_graph(pdf_ctx* ctx, int32_t nsteps);
 
 /* Choose the launch shape of the step by timing: lanes per element cell
-   (64, 32 or 16; a wavefront then serves 1, 2 or 4 cells) and a one-item-
-   per-wavefront grid or a persistent grid pulling work from a counter.
+   (64, 32, 16 or 8; a wavefront then serves 1, 2, 4 or 8 cells; 8 with the
+   float state only) and a one-item-per-wavefront grid or a persistent grid
+   pulling work from a counter.
    Runs 1 + steps_per_trial real steps per candidate (the simulation advances
    by them; particle trajectories do not depend on the shape).  The choice is
    kept in the context and returned in *group, *persist (either may be NULL).
    Synchronizes the stream. */
 pdf_status pdf_autotune(pdf_ctx* ctx, int32_t steps_per_trial, int32_t* group, int32_t* persist);
 
-/* Set the launch shape directly (group 16, 32 or 64; persist 0 or 1).  The
-   double state supports group 64 only. */
+/* Set the launch shape directly (group 8, 16, 32 or 64; persist 0 or 1).
+   The double state supports group 64 only; group 8 runs the learned
+   conditional means as a separate pass. */
 pdf_status pdf_set_launch(pdf_ctx* ctx, int32_t group, int32_t persist);
 
 /* Re-sort by element (the particle-in-cell bookkeeping of section 2.4).
