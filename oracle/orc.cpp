@@ -806,13 +806,15 @@ template <typename T> int advance(orc_ctx* c, Ens<T>& en, uint32_t ens_index, ui
     if (!(p.flags & 1)) {
       un = u; vn = v; wn = w;
     }
-    // turbulent frequency, eq. (9), with <omega> the element's estimate and the
-    // sixth normal; Euler-Maruyama, reflected at zero (part of sub-step 1)
+    // turbulent frequency, eq. (9), with the sixth normal; Euler-Maruyama,
+    // reflected at zero (part of sub-step 1).  <omega> is the element's frozen
+    // value, the one the velocity model takes (eq. 19): with the fields frozen
+    // one <omega> drives both; the particles' own <omega> is estimated and
+    // reported, not fed back
     T omn = p.omega ? en.om[i] : (T)0;
     if (p.omega && (p.flags & 1)) {
-      const double* s = &st[(size_t)e * ns];
       const T om = en.om[i];
-      const T mw = (T)s[ns - 3];
+      const T mw = (T)c->om0[e];
       const T c3 = (T)p.C3, c34 = (T)(2.0 * p.C3 * p.C4), sw = (T)c->somega[e];
       const T drift = (c3 * mw) * (om - mw) + (sw * mw) * om;
       const T diff = std::sqrt((c34 * (mw * mw)) * om);

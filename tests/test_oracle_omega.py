@@ -6,13 +6,14 @@
   <omega> returns the frozen eps (eq. 8 read the other way).
 * S_omega (eq. 10) for simple shear, its transpose and plane strain, where
   the production reduces to the textbook forms.
-* Eq. (9) under homogeneous fields: one Euler-Maruyama step from a
-  deterministic omega has mean <omega>(1 - S_omega <omega> dt) and variance
-  2 C3 C4 <omega>^3 dt; the variance then follows
-  V' = (1 - (C3 + S_omega)<omega> dt)^2 V + 2 C3 C4 <omega>^3 dt; with
-  S_omega = 0 the stationary law is the gamma distribution of the model
-  (variance 2 C4 <omega>^2 / (2 - C3 <omega> dt) discretely, skewness
-  2 sqrt(C4)).
+* Eq. (9) under homogeneous fields, with <omega> = M the frozen value that
+  also drives the velocity model: one Euler-Maruyama step from omega = M
+  has mean M(1 - S_omega M dt) and variance 2 C3 C4 M^3 dt; from a sample
+  of mean m and variance V the next has mean m - C3 M (m - M) dt -
+  S_omega M m dt and variance (1 - (C3 + S_omega) M dt)^2 V +
+  2 C3 C4 M^2 m dt; with S_omega = 0 the stationary law is the gamma
+  distribution of the model (mean M, variance 2 C4 M^2 / (2 - C3 M dt)
+  discretely, skewness 2 sqrt(C4)).
 * Wall condition (eqs. 27-28): log(omega_R / omega_I) is linear in the
   incident wall-normal velocity with slope beta / (y_p <omega>_p), beta from
   Table 2 with C0 = 3.5; resolved walls and periodic seams leave omega alone.
@@ -131,12 +132,14 @@ def test_somega_production_special_cases(case):
     np.testing.assert_allclose(sw, CW2 - CW1 * prod / eps, rtol=1e-13)
 
 
-def test_one_step_mean_and_variance_from_deterministic_state():
-    wl = _omega_box(dt=0.05)
+@pytest.mark.parametrize("eps", [1.0, 2.5])
+def test_one_step_mean_and_variance_from_deterministic_state(eps):
+    # k = 1, nu = 0: the frozen <omega> is eps / k
+    wl = _omega_box(dt=0.05 / eps, fields=lambda mesh: uniform_fields(mesh.nvert, k=1.0, eps=eps))
     orc = O.Oracle(wl)
     om0, sw, _ = orc.omega_fields()
     m, s_om, dt = om0[0], sw[0], wl.dt
-    assert m == pytest.approx(1.0, rel=1e-14) and s_om == pytest.approx(CW2, rel=1e-14)
+    assert m == pytest.approx(eps, rel=1e-14) and s_om == pytest.approx(CW2, rel=1e-14)
     w0 = orc.omega()
     np.testing.assert_array_equal(w0, m)
     orc.step(1)
@@ -153,7 +156,7 @@ def test_one_step_mean_and_variance_from_deterministic_state():
 def test_variance_recursion_per_element():
     wl = _omega_box(dt=0.05, ppe=5000)
     orc = O.Oracle(wl)
-    _, sw, _ = orc.omega_fields()
+    om0, sw, _ = orc.omega_fields()
     dt = wl.dt
     orc.step(1)
     el = orc.state()["elem"]
@@ -163,11 +166,11 @@ def test_variance_recursion_per_element():
     rel = []
     for e in range(wl.mesh.nelem):
         a, b = w1[el == e], w2[el == e]
-        m, v = a.mean(), a.var()
-        pred_v = (1 - (C3 + sw[e]) * m * dt) ** 2 * v + 2 * C3 * C4 * m ** 3 * dt
-        pred_m = m * (1 - sw[e] * m * dt)
+        m, v, M = a.mean(), a.var(), om0[e]
+        pred_v = (1 - (C3 + sw[e]) * M * dt) ** 2 * v + 2 * C3 * C4 * M * M * m * dt
+        pred_m = m - C3 * M * (m - M) * dt - sw[e] * M * m * dt
         rel.append(b.var() / pred_v - 1)
-        assert abs(b.mean() - pred_m) < 5 * math.sqrt(2 * C3 * C4 * m ** 3 * dt / len(b))
+        assert abs(b.mean() - pred_m) < 5 * math.sqrt(2 * C3 * C4 * M * M * m * dt / len(b))
     rel = np.array(rel)
     # per-element sampling error ~ sqrt(2 / 5000) = 2 %
     assert abs(rel.mean()) < 0.03 and np.abs(rel).max() < 0.1
@@ -182,7 +185,7 @@ def test_variance_recursion_per_element():
 def test_stationary_gamma_without_source():
     wl = _omega_box(dt=0.02, ppe=5000, constants=dict(Cw2=0.0))
     orc = O.Oracle(wl)
-    _, sw, _ = orc.omega_fields()
+    om0, sw, _ = orc.omega_fields()
     np.testing.assert_array_equal(sw, 0.0)       # no production, no C_w2
     dt = wl.dt
     orc.step(200)                                # 20 relaxation times 1 / (C3 <omega>)
@@ -191,14 +194,14 @@ def test_stationary_gamma_without_source():
     ratios, z = [], []
     for e in range(wl.mesh.nelem):
         a = w[el == e]
-        m = a.mean()
-        ratios.append(a.var() / (2 * C4 * m * m / (2 - C3 * m * dt)))
-        z.append((a - m) / a.std())
+        M = om0[e]
+        ratios.append(a.var() / (2 * C4 * M * M / (2 - C3 * M * dt)))
+        z.append((a - a.mean()) / a.std())
     ratios = np.array(ratios)
     z = np.concatenate(z)
     assert abs(ratios.mean() - 1) < 0.04
-    # without a source the mean only diffuses: 1 within a few of its random-walk sigma
-    assert abs(w.mean() - 1.0) < 0.08
+    # without a source the mean is M = 1, within a few standard errors
+    assert abs(w.mean() - 1.0) < 0.02
     assert abs((z ** 3).mean() - 2 * math.sqrt(C4)) < 0.12
     assert w.min() > 0
 
