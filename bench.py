@@ -36,6 +36,12 @@ WORKLOADS = {
 }
 
 
+# Workloads timed over fewer steps than asked for: on the frozen synthetic
+# fields the wall-function condition on the turbulent frequency is not in
+# balance and near-wall frequencies grow without bound over 10^3 steps.
+MAX_STEPS = {"canyon10m_omega": 200}
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_1003_4548_amd", "csrc")
@@ -412,9 +418,10 @@ def main() -> int:
         "roofline": main_res["roofline"],
     }
     for name in [w for w in args.secondary.split(",") if w and w != args.workload]:
-        sec = run(name, args.secondary_steps, max(5, args.warmup // 2))
+        sec_steps = min(args.secondary_steps, MAX_STEPS.get(name, args.secondary_steps))
+        sec = run(name, sec_steps, max(5, args.warmup // 2))
         out.setdefault("secondary", {})[name] = {
-            "value": round(sec["value"], 1), "unit": "particle-steps/s", "steps": args.secondary_steps,
+            "value": round(sec["value"], 1), "unit": "particle-steps/s", "steps": sec_steps,
             "ms_per_step": round(sec["ms_per_step"], 5), "config": sec["config"], "roofline": sec["roofline"]}
     sec = out.get("secondary", {})
     if "batched64" in sec and "canyon10m" in sec:

@@ -195,13 +195,16 @@ pdf_status pdf_set_launch(pdf_ctx* ctx, int32_t group, int32_t persist);
    their cell's segment or are appended to their new cell's segment, so the
    statistics of a cell read one contiguous range (two runs).  When the
    density drifts, a step flags every segment whose free room falls under
-   half its count (or under 16), and every sixth step (the end of the
-   six-step cycle of pdf_step_graph; pdf_step checks at the same step counts)
-   a device-side repack gives each cell max(initial, floor(max(2, slack) n)
-   + 32) slots (floor(slack n) + 32 if that would not fit), copies the
-   particles and continues; no host synchronisation is involved.  Particle
-   trajectories do not depend on the layout.  pdf_query_sizes reserves
-   ceil(slack N / 4) slots beyond the seeding layout for the growth.
+   half its count (or under 16) or under twice its arrivals of the last step
+   (a step's arrivals may only use the room beyond the current count), and
+   every sixth step (the end of the six-step cycle of pdf_step_graph;
+   pdf_step checks at the same step counts) a device-side repack gives each
+   cell max(initial, floor(g (n + a)) + 32) slots, g = max(3, slack + 1) and
+   a its arrivals of the last step (floor(slack n) + 32 if that would not
+   fit), copies the particles and continues; no host synchronisation is
+   involved.  Particle trajectories do not depend on the layout.
+   pdf_query_sizes reserves ceil(1.5 g N) + 32 ncell slots beyond the
+   seeding layout for the growth.
    pdf_repack enqueues a repack now (asynchronous); pdf_repack_count waits
    for the stream and returns the repacks done since seeding (-1 on error). */
 pdf_status pdf_repack(pdf_ctx* ctx);

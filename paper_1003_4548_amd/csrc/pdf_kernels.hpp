@@ -58,10 +58,13 @@ struct Ctl {
 static_assert(sizeof(Ctl) == 64, "control block is 64 bytes");
 
 // A segment needs a repack when its free room is under half its count (or
-// under 16 slots): arrivals in one step stay well below that.
-__device__ __forceinline__ bool repack_due(int n, int cap) {
+// under 16 slots), or under twice the arrivals of the last step: the
+// arrivals of a step may only use the room beyond the current count, and a
+// cell whose particles turn over quickly (near walls many cross every step)
+// needs that room every step until the repack.  nm: arrivals of the last step.
+__device__ __forceinline__ bool repack_due(int n, int nm, int cap) {
   const int room = cap - n;
-  return 2 * room < max(32, n);
+  return 2 * room < max(32, n) || room < 2 * nm;
 }
 
 // Per-launch step indices, passed by value: the Philox step word is
@@ -128,8 +131,10 @@ template <typename T> struct StepArgs {
   double* mlp_cm;
   uint32_t* mlp_served;
   // stochastic turbulent frequency, eqs. (9)-(10) and the wall condition:
-  // S_omega per element, frozen <omega> at the wall-function edges (ne x 3),
-  // beta, y_p, nu C_T^2 (for the dissipation estimate, eq. 8), C3, 2 C3 C4
+  // frozen <omega> and S_omega per element, frozen <omega> at the
+  // wall-function edges (ne x 3), beta, y_p, nu C_T^2 (for the dissipation
+  // estimate, eq. 8), C3, 2 C3 C4
+  const double* om0;
   const double* somega;
   const double* omw;
   double om_beta, om_yp, om_nuct2;
@@ -374,7 +379,7 @@ template <typename T> struct CellConst {
   double ox[3], oy[3], dx[3], dy[3], sg[3];
   double mean[3];
   double cm[8];
-  double om_mean, sw;  // turbulent frequency: the cell's <omega> and S_omega
+  double om_mean, sw;  // turbulent frequency: the element's frozen <omega> and S_omega
   double fsd[3];       // 5 x 5 x 5 bins: standard deviations of u, v, w
 };
 
@@ -471,7 +476,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
       // counts are clamped to the segment so that reads stay inside it
       ns = min(a.ns[rc][cell], capc);
       nm = min(a.nm[rc][cell], capc - ns);
-      if (ADVANCE && li == 0 && repack_due(ns + nm, capc)) ctl->repack = 1u;
+      if (ADVANCE && li == 0 && repack_due(ns + nm, nm, capc)) ctl->repack = 1u;
     }
     const int n = ns + nm;
     const double dn = (double)n;
@@ -832,7 +837,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
 #pragma unroll
           for (int q = 0; q < 8; ++q) CC.cm[q] = cm[q];
           if constexpr (OMG) {
-            CC.om_mean = om_mean;
+            CC.om_mean = a.om0[e];
             CC.sw = a.somega[e];
           }
         }
@@ -1020,8 +1025,10 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
           wn = (w + (f[C_G33] * w) * a.dt) + sq * dWp3;
           if (!(a.flags & FLAG_VEL)) { un = u; vn = v; wn = w; }
           if constexpr (OMG) {
-            // turbulent frequency, eq. (9), with the cell's <omega> and the
-            // sixth normal; reflected at zero
+            // turbulent frequency, eq. (9), with the sixth normal; reflected
+            // at zero.  <omega>: the element's frozen value, the one the
+            // velocity model takes (the particles' own is estimated for the
+            // record, not fed back)
             omn = om;
             if (a.flags & FLAG_VEL) {
               const T mw = (T)CC.om_mean, sw = (T)CC.sw;
@@ -1513,8 +1520,9 @@ __global__ void k_reset_ctl(Ctl* ctl) {
 // Segments are sized at seeding from the initial counts.  When the particle
 // density drifts, a step flags the segments that run short of room
 // (repack_due) and, at the next check, the planner gives every cell
-// capacity max(initial, floor(grow n) + pad) (or floor(slack n) + pad if that
-// does not fit the slots), the mover copies each cell's particles, in their
+// capacity max(initial, floor(grow (n + a)) + pad), a the cell's arrivals of
+// the last step (or floor(slack n) + pad if that does not fit the slots), the
+// mover copies each cell's particles, in their
 // logical order, into the other buffer at the new offsets, and the buffer
 // parity flips.  Without the flag both kernels return at once.
 
@@ -1540,7 +1548,8 @@ __device__ __forceinline__ int64_t plan_cap(const RepackPlan& p, int c, bool fal
   const int nm = min(p.nm[c], capc - ns);
   const double n = (double)(ns + nm);
   if (fallback) return (int64_t)floor(p.slack * n) + p.pad;
-  return max((int64_t)p.cap0[c], (int64_t)floor(p.grow * n) + p.pad);
+  // room for the count to grow and for a step's arrivals (nm: the last step's)
+  return max((int64_t)p.cap0[c], (int64_t)floor(p.grow * (n + (double)nm)) + p.pad);
 }
 
 // One block: capacities, then an exclusive scan over the cells.

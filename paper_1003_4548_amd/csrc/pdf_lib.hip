@@ -174,18 +174,23 @@ pdf_status hip_check(pdf_ctx* c, hipError_t e, const char* what) {
   return fail(c, PDF_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+// Capacity factor of segments that a repack grows: room for the count to
+// double again before the next repack.
+double grow_factor(double slack) { return std::max(3.0, slack + 1.0); }
+
 // Slots beyond the seeding layout, kept for segments that grow at a repack.
-int64_t growth_reserve(int64_t nparticles, double slack) {
-  return (int64_t)std::ceil(0.25 * slack * (double)nparticles);
+// A repack gives a cell max(initial, grow (n + a) + pad) slots, a its last
+// arrivals; the reserve covers that sum while the arrivals of a step stay
+// under half the particles.
+int64_t growth_reserve(int64_t nparticles, int64_t ncell, double slack) {
+  return (int64_t)std::ceil(1.5 * grow_factor(slack) * (double)nparticles) + (int64_t)SEG_PAD * ncell;
 }
 
 int64_t slots_bound(int64_t nparticles, int64_t ncell, double slack) {
   return (int64_t)std::ceil(slack * (double)nparticles) + (int64_t)(SEG_PAD + 1) * ncell +
-         growth_reserve(nparticles, slack);
+         growth_reserve(nparticles, ncell, slack);
 }
 
-// Capacity factor of segments that a repack grows (at least 2 counts).
-double grow_factor(const pdf_params& p) { return std::max(2.0, p.slack); }
 
 template <typename T> StepArgs<T> step_args(pdf_ctx* c) {
   const Layout& L = c->L;
@@ -233,6 +238,7 @@ template <typename T> StepArgs<T> step_args(pdf_ctx* c) {
   s.nu2 = (T)(2.0 * c->p.nu);
   s.s2nu = (T)std::sqrt((T)(2.0 * c->p.nu));
   if (c->p.omega) {
+    s.om0 = (const double*)(a + L.om0);
     s.somega = (const double*)(a + L.somega);
     s.omw = (const double*)(a + L.omw);
     s.om_beta = omega_beta(c->p);
@@ -399,7 +405,7 @@ RepackPlan repack_plan_args(pdf_ctx* c, uint32_t rot) {
   p.ncell = c->ne * c->nens;
   p.pad = SEG_PAD;
   p.slots = L.slots;
-  p.grow = grow_factor(c->p);
+  p.grow = grow_factor(c->p.slack);
   p.slack = c->p.slack;
   return p;
 }
@@ -744,7 +750,7 @@ pdf_status pdf_seed_particles(pdf_ctx* c, int32_t nens, const int64_t* counts, c
     std::stable_sort(c->h_order.begin() + w0, c->h_order.begin() + w1,
                      [&](int32_t x, int32_t y) { return c->h_cnt[x] > c->h_cnt[y]; });
   }
-  const int64_t slots = slot + growth_reserve(total, slack);
+  const int64_t slots = slot + growth_reserve(total, ncell, slack);
   const Layout L = make_layout(c->nv, c->ne, nens, slots, nstat_of(c->p), tsize_of(c->p), c->p.omega != 0);
   if (L.total > c->arena_bytes)
     return fail(c, PDF_E_SIZE, "arena too small for the particle layout (query with slack >= 2)");

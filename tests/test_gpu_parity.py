@@ -379,3 +379,22 @@ def test_host_rejects_bad_input(gpu):
     with pytest.raises(gpu.PdfError) as ex:
         sim.set_launch(48, 0)
     assert ex.value.code == -1
+
+
+@pytest.mark.parametrize("cfg", ["config3", "config2"])
+def test_long_run_keeps_every_particle(gpu, cfg):
+    """1200 graph steps at full size and the tuned shape: the segments keep
+    room for every step's arrivals (repacks as needed), no particle is lost
+    and the state stays finite."""
+    wl = getattr(W, cfg)(steps=1200)
+    _label(wl, "long run")
+    sim = gpu.Simulation.from_workload(wl)
+    shape = sim.autotune(steps_per_trial=1)
+    print(f"[case] tuned shape {shape}", flush=True)
+    for _ in range(4):
+        sim.step_graph(300)
+        sim.sync()
+        m = sim.metrics()
+        print(f"[case] {m}", flush=True)
+        assert m["particles"] == wl.n_total and m["error_word"] == 0
+    assert sim.repacks() >= 1 or cfg == "config2"
