@@ -21,6 +21,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "pdf_math.hpp"
 #include "pdf_mlp_core.hpp"
 
@@ -195,6 +197,85 @@ template <int G> __device__ __forceinline__ double group_sum(double v) {
   if constexpr (G >= 32) v += shfl_xor_f64(v, 16);
   if constexpr (G >= 64) v += shfl_xor_f64(v, 32);
   return v;
+}
+
+__device__ __forceinline__ double lo_hi_f64(unsigned lo, unsigned hi) {
+  return __longlong_as_double((long long)lo | ((long long)hi << 32));
+}
+
+// Sums of K values over a group of G consecutive lanes by a transposing
+// butterfly: at the stage of lane bit d, lanes with the bit clear keep the
+// first ceil(Kc/2) of the Kc values the stage starts with, lanes with it set
+// the rest, each adding its partner's copy of the ones it keeps, so the
+// values per lane halve at every stage (a value without a partner in the
+// second half is summed by both).  Bits 32 and 16 pair by the gfx950 lane
+// swaps (the first value's upper half against the second's lower half),
+// bits 8, 4, 2, 1 by DPP row rotation, half-row mirror and quad swaps.  Each
+// sum ends in the lanes whose bits select it, which store it to out[index]
+// (scaled by f) unless store is false; a caller that reads it from other
+// lanes orders the two.  All lanes of the wavefront take part.
+template <int G, int K>
+__device__ __forceinline__ void group_sum_many(double (&v)[K], double* out, double f = 1.0, bool store = true) {
+  const int li = lane_id() & (G - 1);
+  int off = 0, cnt = K;  // this lane's first index and count of valid values
+  auto stage = [&](auto dtag, auto kctag) {
+    constexpr int D = decltype(dtag)::value, KC = decltype(kctag)::value, KN = (KC + 1) / 2;
+    const bool hi = (li & D) != 0;
+#pragma unroll
+    for (int i = 0; i < KN; ++i) {
+      const double a = v[i], b = (i + KN < KC) ? v[i + KN] : a;
+      if constexpr (D >= 16) {
+        const long long ab = __double_as_longlong(a), bb = __double_as_longlong(b);
+        const auto l = D == 32 ? __builtin_amdgcn_permlane32_swap((unsigned)ab, (unsigned)bb, false, false)
+                               : __builtin_amdgcn_permlane16_swap((unsigned)ab, (unsigned)bb, false, false);
+        const auto h = D == 32 ? __builtin_amdgcn_permlane32_swap((unsigned)(ab >> 32), (unsigned)(bb >> 32), false, false)
+                               : __builtin_amdgcn_permlane16_swap((unsigned)(ab >> 32), (unsigned)(bb >> 32), false, false);
+        v[i] = lo_hi_f64(l[0], h[0]) + lo_hi_f64(l[1], h[1]);
+      } else {
+        const double keep = hi ? b : a, send = hi ? a : b;
+        constexpr int CTRL = D == 8 ? 0x128 : (D == 4 ? 0x141 : (D == 2 ? 0x4E : 0xB1));
+        v[i] = keep + dpp_f64<CTRL>(send);
+      }
+    }
+    if (hi) {
+      off += KN;
+      cnt = cnt > KN ? cnt - KN : 0;
+    } else {
+      cnt = cnt < KN ? cnt : KN;
+    }
+  };
+  using I = int;
+  constexpr int K1 = (K + 1) / 2, K2 = (K1 + 1) / 2, K3 = (K2 + 1) / 2, K4 = (K3 + 1) / 2, K5 = (K4 + 1) / 2;
+  // stages from the highest lane bit of the group down, the value count
+  // halving from K as they go
+  if constexpr (G == 64) {
+    stage(std::integral_constant<I, 32>{}, std::integral_constant<I, K>{});
+    stage(std::integral_constant<I, 16>{}, std::integral_constant<I, K1>{});
+    stage(std::integral_constant<I, 8>{}, std::integral_constant<I, K2>{});
+    stage(std::integral_constant<I, 4>{}, std::integral_constant<I, K3>{});
+    stage(std::integral_constant<I, 2>{}, std::integral_constant<I, K4>{});
+    stage(std::integral_constant<I, 1>{}, std::integral_constant<I, K5>{});
+  } else if constexpr (G == 32) {
+    stage(std::integral_constant<I, 16>{}, std::integral_constant<I, K>{});
+    stage(std::integral_constant<I, 8>{}, std::integral_constant<I, K1>{});
+    stage(std::integral_constant<I, 4>{}, std::integral_constant<I, K2>{});
+    stage(std::integral_constant<I, 2>{}, std::integral_constant<I, K3>{});
+    stage(std::integral_constant<I, 1>{}, std::integral_constant<I, K4>{});
+  } else if constexpr (G == 16) {
+    stage(std::integral_constant<I, 8>{}, std::integral_constant<I, K>{});
+    stage(std::integral_constant<I, 4>{}, std::integral_constant<I, K1>{});
+    stage(std::integral_constant<I, 2>{}, std::integral_constant<I, K2>{});
+    stage(std::integral_constant<I, 1>{}, std::integral_constant<I, K3>{});
+  } else {
+    static_assert(G == 8, "groups of 8, 16, 32 or 64 lanes");
+    stage(std::integral_constant<I, 4>{}, std::integral_constant<I, K>{});
+    stage(std::integral_constant<I, 2>{}, std::integral_constant<I, K1>{});
+    stage(std::integral_constant<I, 1>{}, std::integral_constant<I, K2>{});
+  }
+  constexpr int KF = G == 64 ? (K5 + 1) / 2 : (G == 32 ? K5 : (G == 16 ? K4 : K3));
+#pragma unroll
+  for (int i = 0; i < KF; ++i)
+    if (store && i < cnt) out[off + i] = v[i] * f;
 }
 
 template <int G> __device__ __forceinline__ uint64_t group_mask(int grp) {
@@ -424,6 +505,8 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
   __shared__ double fsum[VB5 ? CPB : 1][VB5 ? 125 : 1];
   __shared__ int fcnt[VB5 ? CPB : 1][VB5 ? 125 : 1];
   __shared__ T fcm[VB5 && ADVANCE ? CPB : 1][VB5 && ADVANCE ? 125 : 1];
+  constexpr int NRED = OMG ? 19 : 18;       // group sums of pass B (A takes the first 4 or 5)
+  __shared__ double red[CPB][NRED];
   Ctl* ctl = a.ctl;
   // after an error the state is void: later steps do nothing
   // (with the learned means inside the step every wavefront of a block must
@@ -526,13 +609,20 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
       }
     }
     const double inv_n = n > 0 ? 1.0 / dn : 0.0;
+    double* redc = red[slot_id];
     double mean[4];
-    mean[0] = group_sum<G>(s0) * inv_n;
-    mean[1] = group_sum<G>(s1) * inv_n;
-    mean[2] = group_sum<G>(s2) * inv_n;
-    mean[3] = group_sum<G>(s3) * inv_n;
     double om_mean = 0.0;
-    if constexpr (OMG) om_mean = group_sum<G>(s4) * inv_n;
+    {
+      double sa[OMG ? 5 : 4];
+      sa[0] = s0; sa[1] = s1; sa[2] = s2; sa[3] = s3;
+      if constexpr (OMG) sa[4] = s4;
+      lds_sync_wave();  // the previous item's sums are read before these are written
+      group_sum_many<G>(sa, redc);
+      lds_sync_wave();
+#pragma unroll
+      for (int q = 0; q < 4; ++q) mean[q] = redc[q] * inv_n;
+      if constexpr (OMG) om_mean = redc[4] * inv_n;
+    }
 
     auto load4 = [&](int j, double* val) {
       if (j < TILEN) {
@@ -584,10 +674,19 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
 #pragma unroll
       for (int q = 0; q < 8; ++q) bcount[q] += (int)__popcll(__ballot(bin == q) & gmask);
     }
-#pragma unroll
-    for (int q = 0; q < 18; ++q) acc[q] = group_sum<G>(acc[q]);
     double om_var = 0.0;
-    if constexpr (OMG) om_var = group_sum<G>(accw) * inv_n;
+    {
+      double sb[NRED];
+#pragma unroll
+      for (int q = 0; q < 18; ++q) sb[q] = acc[q];
+      if constexpr (OMG) sb[18] = accw;
+      lds_sync_wave();  // the means above are read before the sums below are written
+      group_sum_many<G>(sb, redc);
+      lds_sync_wave();
+#pragma unroll
+      for (int q = 0; q < 18; ++q) acc[q] = redc[q];
+      if constexpr (OMG) om_var = redc[18] * inv_n;
+    }
     double bm[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) bm[q] = bcount[q] > 0 ? acc[10 + q] / (double)bcount[q] : mean[3];
@@ -753,11 +852,18 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
                   }
           }
         }
-        // M3 (20 entries) and M4 (35) are contiguous in the record
+        // M3 (20 entries) and M4 (35) are contiguous in the record; the
+        // lanes that end with a sum store it
+        if (part == 0) {
+          double t[SPLIT];
 #pragma unroll
-        for (int q = 0; q < (part == 0 ? SPLIT : NM - SPLIT); ++q) {
-          const double r = group_sum<G>(acc3[q]) * inv_n;
-          if (has && li == 0) rec[ST_M3 + lo + q] = r;
+          for (int q = 0; q < SPLIT; ++q) t[q] = acc3[q];
+          group_sum_many<G>(t, rec + ST_M3, inv_n, has);
+        } else {
+          double t[NM - SPLIT];
+#pragma unroll
+          for (int q = 0; q < NM - SPLIT; ++q) t[q] = acc3[q];
+          group_sum_many<G>(t, rec + ST_M3 + SPLIT, inv_n, has);
         }
       }
     }
