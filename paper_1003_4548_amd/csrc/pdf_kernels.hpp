@@ -505,8 +505,10 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
   __shared__ double fsum[VB5 ? CPB : 1][VB5 ? 125 : 1];
   __shared__ int fcnt[VB5 ? CPB : 1][VB5 ? 125 : 1];
   __shared__ T fcm[VB5 && ADVANCE ? CPB : 1][VB5 && ADVANCE ? 125 : 1];
-  constexpr int NRED = OMG ? 19 : 18;       // group sums of pass B (A takes the first 4 or 5)
+  constexpr int NRED = OMG ? 11 : 10;       // group sums of pass B (A takes the first 4 or 5)
   __shared__ double red[CPB][NRED];
+  __shared__ double bsum_lds[CPB][8];       // per-bin scalar sums, then bin means
+  __shared__ int bcnt_lds[CPB][8];          // per-bin counts
   Ctl* ctl = a.ctl;
   // after an error the state is void: later steps do nothing
   // (with the learned means inside the step every wavefront of a block must
@@ -634,16 +636,22 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
     };
 
     // ---- B: second moments, bins, histogram ----
-    double acc[18];  // 10 second moments, 8 per-bin scalar sums
+    double acc[10];  // second moments
 #pragma unroll
-    for (int q = 0; q < 18; ++q) acc[q] = 0.0;
+    for (int q = 0; q < 10; ++q) acc[q] = 0.0;
     double accw = 0.0;  // turbulent frequency: sum of squared fluctuations
-    int bcount[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) bcount[q] = 0;
+    // bin counts and scalar sums by LDS atomics (the order of the FP64 sums
+    // is free, their rounding that of any FP64 sum of the bin's values)
+    double* bsum = bsum_lds[slot_id];
+    int* bcnt = bcnt_lds[slot_id];
+    if (li < 8) {
+      bsum[li] = 0.0;
+      bcnt[li] = 0;
+    }
     if (HIST > 0) {
       for (int h = li; h < HIST; h += G) hist_lds[slot_id][h] = 0;
     }
+    lds_sync_wave();
     for (int base = 0; __ballot(base < n) != 0; base += G) {
       const int j = base + li;
       const bool act = j < n;
@@ -659,8 +667,8 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
 #pragma unroll
           for (int y = x; y < 4; ++y) acc[pair_index(x, y)] += d[x] * d[y];
         bin = (val[0] > mean[0] ? 1 : 0) + (val[1] > mean[1] ? 2 : 0) + (val[2] > mean[2] ? 4 : 0);
-#pragma unroll
-        for (int q = 0; q < 8; ++q) acc[10 + q] += (bin == q) ? val[3] : 0.0;
+        atomicAdd(&bcnt[bin], 1);
+        atomicAdd(&bsum[bin], val[3]);
         if constexpr (OMG) {
           const double dw = (double)(j < TILEN ? LO[j] : src.om[slot_of(j, start, ns, nm, capc)]) - om_mean;
           accw += dw * dw;
@@ -671,25 +679,33 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
           atomicAdd(&hist_lds[slot_id][hb], 1);
         }
       }
-#pragma unroll
-      for (int q = 0; q < 8; ++q) bcount[q] += (int)__popcll(__ballot(bin == q) & gmask);
     }
     double om_var = 0.0;
     {
       double sb[NRED];
 #pragma unroll
-      for (int q = 0; q < 18; ++q) sb[q] = acc[q];
-      if constexpr (OMG) sb[18] = accw;
+      for (int q = 0; q < 10; ++q) sb[q] = acc[q];
+      if constexpr (OMG) sb[10] = accw;
       lds_sync_wave();  // the means above are read before the sums below are written
       group_sum_many<G>(sb, redc);
       lds_sync_wave();
 #pragma unroll
-      for (int q = 0; q < 18; ++q) acc[q] = redc[q];
-      if constexpr (OMG) om_var = redc[18] * inv_n;
+      for (int q = 0; q < 10; ++q) acc[q] = redc[q];
+      if constexpr (OMG) om_var = redc[10] * inv_n;
     }
+    // bin means, lane q of the group taking bin q
+    if (li < 8) {
+      const int c = bcnt[li];
+      bsum[li] = c > 0 ? bsum[li] / (double)c : mean[3];
+    }
+    lds_sync_wave();
+    int bcount[8];
     double bm[8];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) bm[q] = bcount[q] > 0 ? acc[10 + q] / (double)bcount[q] : mean[3];
+    for (int q = 0; q < 8; ++q) {
+      bcount[q] = bcnt[q];
+      bm[q] = bsum[q];
+    }
     double cm[8];
     if constexpr (fused_mlp) {
       // learned conditional means: the block's cells form one 16-column tile
@@ -1093,7 +1109,18 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
             if constexpr (OMG) om = src.om[s];
           }
           uint32_t rw[8];
-          philox_words<2>(id, step, (uint32_t)ens, k0, k1, rw);
+          uint32_t kk0 = k0, kk1 = k1, st = step, en = (uint32_t)ens;
+          if constexpr (G == WAVE) {
+            // wavefront-uniform key and counter words: rebuilt from four
+            // scalars each batch (scalar adds) rather than twenty round
+            // keys held across the loop
+            kk0 = __builtin_amdgcn_readfirstlane(kk0);
+            kk1 = __builtin_amdgcn_readfirstlane(kk1);
+            st = __builtin_amdgcn_readfirstlane(st);
+            en = __builtin_amdgcn_readfirstlane(en);
+            asm volatile("" : "+s"(kk0), "+s"(kk1), "+s"(st), "+s"(en));
+          }
+          philox_words<2>(id, st, en, kk0, kk1, rw);
           T xi0, xi1, xi2, xi3, xi4, xi5;
           box_muller<T>(rw[0], rw[1], &xi0, &xi1);
           box_muller<T>(rw[2], rw[3], &xi2, &xi3);
