@@ -496,11 +496,12 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
   static_assert(!(SCHED == 2 && G < 16), "the learned means inside the step need at most 16 cells per block");
   constexpr bool PERSIST = SCHED == 1;
   constexpr int GPW = WAVE / G;             // cells per wavefront
-  // particles per cell staged in LDS: four per lane, five for the
-  // fourth-order float kernels of 32 or 64 lanes per cell, whose registers
-  // already hold them to three blocks per CU (the deeper tile still fits
-  // three blocks' LDS and saves re-reads of larger cells in each pass)
-  constexpr int TILEN = ((MOM >= 4 && XV == XV_NONE && sizeof(T) == 4 && G >= 32) ? 5 : 4) * G;
+  // particles per cell staged in LDS: four per lane; deeper where registers
+  // already set the blocks per CU and the deeper tile still fits their LDS
+  // (it saves re-reads of larger cells in each pass): five for the
+  // fourth-order float kernels of 32 or 64 lanes per cell (three blocks),
+  // six at 8 lanes per cell (two blocks)
+  constexpr int TILEN = ((MOM >= 4 && XV == XV_NONE && sizeof(T) == 4 && G >= 32) ? 5 : (G == 8 ? 6 : 4)) * G;
   constexpr int CPB = WAVES_PER_BLOCK * GPW;
   __shared__ Tile<T, TILEN> tiles[CPB];
   __shared__ int hist_lds[HIST > 0 ? CPB : 1][HIST > 0 ? HIST : 1];
