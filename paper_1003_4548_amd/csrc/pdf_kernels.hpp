@@ -802,20 +802,21 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
       for (int q = 0; q < 8; ++q) cm[q] = bm[q];
     }
     double* rec = a.stats + (size_t)(has ? cell : 0) * a.nstat;
-    // the record is written by the group's first lane straight from the
-    // (group-uniform) accumulators
+    // the record: count and means by the group's first lane, second moments
+    // and bins by one lane each from the group sums in LDS
+    if (has) {
+      const double z = n > 0 ? 1.0 : 0.0;
+      for (int q = li; q < 10; q += G) rec[ST_M2 + q] = redc[q] * inv_n;
+      if (li < 8) {
+        rec[ST_BINN + li] = (double)bcnt[li];
+        rec[ST_BINM + li] = bsum[li] * z;
+      }
+    }
     if (has && li == 0) {
       const double z = n > 0 ? 1.0 : 0.0;
       rec[ST_N] = dn;
 #pragma unroll
       for (int q = 0; q < 4; ++q) rec[ST_MEAN + q] = mean[q] * z;
-#pragma unroll
-      for (int q = 0; q < 10; ++q) rec[ST_M2 + q] = acc[q] * inv_n;
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        rec[ST_BINN + q] = (double)bcount[q];
-        rec[ST_BINM + q] = bm[q] * z;
-      }
       if constexpr (OMG) {
         // after the moments and the histogram: <omega>, its variance, and
         // eps = <omega>(k + nu C_T^2 <omega>) with k from the estimated stresses
@@ -946,23 +947,30 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
           const int vk = k == 0 ? vtx[0] : (k == 1 ? vtx[1] : vtx[2]);
           CC.coef[q] = a.coef[(size_t)vk * NCOEF + (q - k * NCOEF)];
         }
-        if (li == 0) {
-          const ERec R = a.erec[e];
+        // edge k by lane k
+        if (li < 3) {
+          const int k = li, k1 = k == 2 ? 0 : k + 1;
+          const ERec& R = a.erec[e];
+          const double ax = R.x[k], ay = R.y[k], bx = R.x[k1], by = R.y[k1];
+          const bool a_first = (ax < bx) || (ax == bx && ay < by);
+          CC.ox[k] = a_first ? ax : bx;
+          CC.oy[k] = a_first ? ay : by;
+          CC.dx[k] = a_first ? bx - ax : ax - bx;
+          CC.dy[k] = a_first ? by - ay : ay - by;
+          CC.sg[k] = a_first ? 1.0 : -1.0;
+        }
+        // conditional mean of bin q by lane q
+        if constexpr (fused_mlp) {
+          if (li == 0) {
 #pragma unroll
-          for (int k = 0; k < 3; ++k) {
-            const int k1 = k == 2 ? 0 : k + 1;
-            const double ax = R.x[k], ay = R.y[k], bx = R.x[k1], by = R.y[k1];
-            const bool a_first = (ax < bx) || (ax == bx && ay < by);
-            CC.ox[k] = a_first ? ax : bx;
-            CC.oy[k] = a_first ? ay : by;
-            CC.dx[k] = a_first ? bx - ax : ax - bx;
-            CC.dy[k] = a_first ? by - ay : ay - by;
-            CC.sg[k] = a_first ? 1.0 : -1.0;
+            for (int q = 0; q < 8; ++q) CC.cm[q] = cm[q];
           }
+        } else if (li < 8) {
+          CC.cm[li] = (a.cmean != nullptr && has) ? a.cmean[(size_t)cell * 8 + li] : bsum[li];
+        }
+        if (li == 0) {
 #pragma unroll
           for (int q = 0; q < 3; ++q) CC.mean[q] = mean[q];
-#pragma unroll
-          for (int q = 0; q < 8; ++q) CC.cm[q] = cm[q];
           if constexpr (OMG) {
             CC.om_mean = a.om0[e];
             CC.sw = a.somega[e];
