@@ -212,7 +212,7 @@ def learned_leg(torch, W, Simulation) -> dict:
     # inside the step: 20 particles per element on the 50k-element resolved-wall canyon
     wl = W.config5(ppe=20, seed=101, target=50000)
     sim = Simulation.from_workload(wl, device="cuda:0")
-    in_step_shape = sim.autotune(steps_per_trial=5)
+    in_step_shape = sim.autotune(steps_per_trial=8)
     if in_step_shape[1]:
         in_step_shape = (in_step_shape[0], 0)      # the learned means run inside one-item-per-wavefront steps
         sim.set_launch(*in_step_shape)
@@ -274,8 +274,9 @@ def main() -> int:
                     help="timed blocks of K steps on the main workload; the first is the reported one, "
                          "all are listed with their median")
     ap.add_argument("--no-graph", action="store_true", help="launch steps one by one instead of graph replays")
-    ap.add_argument("--autotune-steps", type=int, default=5,
-                    help="steps per candidate launch shape before warmup (0: no tuning)")
+    ap.add_argument("--autotune-steps", type=int, default=8,
+                    help="steps per trial of a candidate launch shape (two trials each) before warmup "
+                         "(0: no tuning)")
     ap.add_argument("--launch", default="",
                     help="fixed launch shape 'lanes_per_cell,persistent' (e.g. 32,1) instead of tuning")
     ap.add_argument("--no-learned", action="store_true",

@@ -178,8 +178,10 @@ pdf_status pdf_step_graph(pdf_ctx* ctx, int32_t nsteps);
    (64, 32, 16 or 8; a wavefront then serves 1, 2, 4 or 8 cells; 8 with the
    float state only) and a one-item-per-wavefront grid or a persistent grid
    pulling work from a counter.
-   Runs 1 + steps_per_trial real steps per candidate (the simulation advances
-   by them; particle trajectories do not depend on the shape).  The choice is
+   Runs two rounds over the candidates (the second in reverse order), each of
+   1 + steps_per_trial real steps per candidate, and scores a candidate by
+   its faster trial (the simulation advances by all of them; particle
+   trajectories do not depend on the shape).  The choice is
    kept in the context and returned in *group, *persist (either may be NULL).
    Synchronizes the stream. */
 pdf_status pdf_autotune(pdf_ctx* ctx, int32_t steps_per_trial, int32_t* group, int32_t* persist);

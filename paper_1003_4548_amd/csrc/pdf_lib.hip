@@ -848,30 +848,52 @@ pdf_status pdf_autotune(pdf_ctx* c, int32_t steps_per_trial, int32_t* group, int
   if (!c || steps_per_trial <= 0) return fail(c, PDF_E_ARG, "pdf_autotune: bad argument");
   if (!c->seeded) return fail(c, PDF_E_STATE, "pdf_autotune before pdf_seed_particles");
   const int groups[4] = {64, 32, 16, 8};
-  float best = 1e30f;
-  int bg = c->group, bp = c->persist;
+  // two rounds over the candidates, the second in reverse order, each
+  // candidate scored by its faster trial: the state drifts as the trials
+  // advance it (cells fill, a repack may fall into one trial)
+  float score[8];
+  for (int i = 0; i < 8; ++i) score[i] = 1e30f;
   hipEvent_t e0, e1;
   pdf_status r;
   if ((r = hip_check(c, hipEventCreate(&e0), "event"))) return r;
-  if ((r = hip_check(c, hipEventCreate(&e1), "event"))) return r;
-  for (int gi = 0; gi < 4; ++gi) {
-    for (int pe = 0; pe < 2; ++pe) {
+  if ((r = hip_check(c, hipEventCreate(&e1), "event"))) {
+    (void)hipEventDestroy(e0);
+    return r;
+  }
+  for (int round = 0; round < 2; ++round) {
+    for (int t = 0; t < 8; ++t) {
+      const int i = round == 0 ? t : 7 - t;
+      const int gi = i / 2, pe = i % 2;
       if (!c->p.f32_state && groups[gi] != 64) continue;
       c->group = groups[gi];
       c->persist = pe;
       // one untimed step with this shape, then the timed trial
-      if ((r = enqueue_steps(c, 1))) return r;
-      (void)hipEventRecord(e0, c->stream);
-      if ((r = enqueue_steps(c, steps_per_trial))) return r;
-      (void)hipEventRecord(e1, c->stream);
-      if ((r = hip_check(c, hipEventSynchronize(e1), "autotune sync"))) return r;
+      r = enqueue_steps(c, 1);
+      if (!r) {
+        (void)hipEventRecord(e0, c->stream);
+        r = enqueue_steps(c, steps_per_trial);
+      }
+      if (!r) {
+        (void)hipEventRecord(e1, c->stream);
+        r = hip_check(c, hipEventSynchronize(e1), "autotune sync");
+      }
+      if (r) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        return r;
+      }
       float ms = 0.0f;
       (void)hipEventElapsedTime(&ms, e0, e1);
-      if (ms < best) {
-        best = ms;
-        bg = groups[gi];
-        bp = pe;
-      }
+      score[i] = std::min(score[i], ms);
+    }
+  }
+  int bg = 64, bp = 0;
+  float best = 1e30f;
+  for (int i = 0; i < 8; ++i) {
+    if (score[i] < best) {
+      best = score[i];
+      bg = groups[i / 2];
+      bp = i % 2;
     }
   }
   (void)hipEventDestroy(e0);

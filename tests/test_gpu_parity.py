@@ -231,9 +231,9 @@ def test_autotune_keeps_parity(gpu):
     _label(wl, "autotune")
     sim = gpu.Simulation.from_workload(wl)
     shape = sim.autotune(steps_per_trial=2)
-    assert shape[0] in (16, 32, 64) and shape[1] in (0, 1)
+    assert shape[0] in (8, 16, 32, 64) and shape[1] in (0, 1)
     done = sim.steps_done()
-    assert done == 8 * 3
+    assert done == 2 * 8 * 3      # two rounds of eight candidates, 1 + 2 steps each
     orc = O.Oracle(wl)
     orc.step(done)
     sim.sync()
