@@ -69,6 +69,27 @@ __device__ __forceinline__ double floor_t(double x) { return floor(x); }
 __device__ __forceinline__ float sqrt_t(float x) { return sqrtf(x); }
 __device__ __forceinline__ double sqrt_t(double x) { return sqrt(x); }
 
+// a / b for b in [1, 4) and a zero or of magnitude at least 2^-30 (no
+// operand or quotient near the exponent limits), correctly rounded: the
+// reciprocal estimate refined by Newton's step, the quotient by two residual
+// corrections (Markstein).  These are the steps the compiler emits for a
+// float division, without the operand rescaling and special-case fix-up that
+// such operands never need.
+__device__ __forceinline__ float div_moderate(float a, float b) {
+  float y = __builtin_amdgcn_rcpf(b);
+  const float e = __builtin_fmaf(-b, y, 1.0f);
+  y = __builtin_fmaf(e, y, y);
+  float q = a * y;
+  float r = __builtin_fmaf(-b, q, a);
+  q = __builtin_fmaf(r, y, q);
+  r = __builtin_fmaf(-b, q, a);
+  return __builtin_fmaf(r, y, q);
+}
+// (m - 1) / (m + 1) for m in [sqrt(1/2), sqrt(2)): m - 1 is zero or at least
+// 2^-24 in magnitude
+__device__ __forceinline__ float atanh_arg(float m) { return div_moderate(m - 1.0f, m + 1.0f); }
+__device__ __forceinline__ double atanh_arg(double m) { return (m - 1.0) / (m + 1.0); }
+
 template <typename T> __device__ __forceinline__ T series_log(T x) {
   int e0 = 0;
   const T f = frexp_t(x, &e0);
@@ -81,7 +102,7 @@ template <typename T> __device__ __forceinline__ T series_log(T x) {
     m = f;
     e = e0;
   }
-  const T s = (m - (T)1) / (m + (T)1);
+  const T s = atanh_arg(m);
   const T z = s * s;
   constexpr int K = SeriesTerms<T>::LOG;
   T p = (T)1 / (T)(2 * K + 1);
@@ -138,10 +159,28 @@ __device__ __forceinline__ double series_exp(double x) {
   return ldexp(p, (int)k);
 }
 
+// Square root of a positive normal float (at least 2^-96), correctly
+// rounded: the hardware estimate, then the one-ulp neighbour that the fma
+// residuals select.  These are the steps the compiler emits for sqrtf on
+// such inputs, without its rescaling of tiny inputs and its special-value
+// cases, which the Box-Muller radius (-2 log u1 in [1.2e-7, 34]) never takes.
+__device__ __forceinline__ float sqrt_pos_normal(float x) {
+  float s = __builtin_amdgcn_sqrtf(x);
+  const float sdn = __uint_as_float(__float_as_uint(s) - 1u);
+  const float sup = __uint_as_float(__float_as_uint(s) + 1u);
+  const float rdn = __builtin_fmaf(-sdn, s, x);
+  const float rup = __builtin_fmaf(-sup, s, x);
+  if (rdn <= 0.0f) s = sdn;
+  if (rup > 0.0f) s = sup;
+  return s;
+}
+__device__ __forceinline__ float sqrt_radius(float x) { return sqrt_pos_normal(x); }
+__device__ __forceinline__ double sqrt_radius(double x) { return sqrt(x); }
+
 // Box-Muller (Box & Muller 1958) on two words.
 template <typename T> __device__ __forceinline__ void box_muller(uint32_t r1, uint32_t r2, T* z0, T* z1) {
   const T u1 = uniform01<T>(r1), u2 = uniform01<T>(r2);
-  const T rad = sqrt_t((T)-2 * series_log<T>(u1));
+  const T rad = sqrt_radius((T)-2 * series_log<T>(u1));
   T sn, cs;
   series_sincos2pi<T>(u2, &sn, &cs);
   *z0 = rad * cs;
