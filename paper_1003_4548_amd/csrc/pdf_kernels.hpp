@@ -414,7 +414,7 @@ __device__ int walk(const StepArgs<T>& a, ERec R, int e, double Sx, double Sy, T
 // per wavefront, taken from a list ordered so that the cells of a wavefront
 // have similar particle counts):
 //   A  read the cell's particles once from HBM into an LDS tile (the first
-//      4G of them; a larger cell re-reads the rest from L2) and sum the
+//      4G to 6G of them; a larger cell re-reads the rest from L2) and sum the
 //      velocity and scalar: the means;
 //   B  central moments, velocity-bin scalar sums and counts, histogram: the
 //      statistics record of the cell;
@@ -1684,6 +1684,8 @@ struct RepackPlan {
   int32_t pad;
   int64_t slots;
   double grow, slack;
+  uint32_t advance;       // steps to add to the Philox step base first (0: none)
+  uint32_t unused;
 };
 
 constexpr int PLAN_THREADS = 1024;
@@ -1703,6 +1705,9 @@ __global__ __launch_bounds__(PLAN_THREADS) void k_repack_plan(RepackPlan p) {
   __shared__ int64_t wsum[PLAN_THREADS / WAVE];
   __shared__ int64_t total_s;
   Ctl* ctl = p.ctl;
+  // a graph cycle ends here: its steps join the step base (no other thread
+  // of this launch reads it)
+  if (p.advance != 0u && threadIdx.x == 0) ctl->step_base = ctl->step_base + p.advance;
   if (ctl->repack == 0u || ctl->error != 0) {
     if (threadIdx.x == 0) ctl->active = 0u;
     return;
@@ -1781,30 +1786,34 @@ template <typename T> struct RepackMove {
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_repack_move(RepackMove<T> m, StepIndex si) {
   if (m.ctl->active == 0u) return;
-  const int cell = blockIdx.x * WAVES_PER_BLOCK + (int)(threadIdx.x / WAVE);
-  if (cell >= m.ncell) return;
   const int lane = lane_id();
   // the planner has flipped the parity: the current state is in the other buffer
   const uint32_t bnew = si.parity ^ (m.ctl->flip & 1u);
   const StateDev<T> src = m.buf[bnew ^ 1u];
   const StateDev<T> dst = m.buf[bnew];
-  const int capc = m.cap[cell], s0 = m.start[cell];
-  const int ns = min(m.ns[cell], capc);
-  const int nm = min(m.nm[cell], capc - ns);
-  const int n = ns + nm;
-  const int d0 = m.nstart[cell];
-  for (int j = lane; j < n; j += WAVE) {
-    const int s = slot_of(j, s0, ns, nm, capc);
-    const int d = d0 + j;
-    dst.x[d] = src.x[s]; dst.y[d] = src.y[s]; dst.u[d] = src.u[s]; dst.v[d] = src.v[s]; dst.w[d] = src.w[s];
-    dst.psi[d] = src.psi[s]; dst.id[d] = src.id[s];
-    if (src.om) dst.om[d] = src.om[s];
-  }
-  if (lane == 0) {
-    m.start[cell] = d0;
-    m.cap[cell] = m.ncap[cell];
-    m.ns[cell] = n;
-    m.nm[cell] = 0;
+  // one wavefront per cell, the grid's wavefronts striding over the cells
+  // (a grid of bounded size: it is launched at every capacity check and
+  // mostly returns at once)
+  for (int cell = blockIdx.x * WAVES_PER_BLOCK + (int)(threadIdx.x / WAVE); cell < m.ncell;
+       cell += gridDim.x * WAVES_PER_BLOCK) {
+    const int capc = m.cap[cell], s0 = m.start[cell];
+    const int ns = min(m.ns[cell], capc);
+    const int nm = min(m.nm[cell], capc - ns);
+    const int n = ns + nm;
+    const int d0 = m.nstart[cell];
+    for (int j = lane; j < n; j += WAVE) {
+      const int s = slot_of(j, s0, ns, nm, capc);
+      const int d = d0 + j;
+      dst.x[d] = src.x[s]; dst.y[d] = src.y[s]; dst.u[d] = src.u[s]; dst.v[d] = src.v[s]; dst.w[d] = src.w[s];
+      dst.psi[d] = src.psi[s]; dst.id[d] = src.id[s];
+      if (src.om) dst.om[d] = src.om[s];
+    }
+    if (lane == 0) {
+      m.start[cell] = d0;
+      m.cap[cell] = m.ncap[cell];
+      m.ns[cell] = n;
+      m.nm[cell] = 0;
+    }
   }
 }
 

@@ -427,7 +427,11 @@ template <typename T> RepackMove<T> repack_move_args(pdf_ctx* c, uint32_t rot) {
   return m;
 }
 
-int repack_move_blocks(const pdf_ctx* c) { return (c->ne * c->nens + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK; }
+// the mover's grid: one wavefront per cell up to 2048 blocks, beyond that the
+// wavefronts stride over the cells
+int repack_move_blocks(const pdf_ctx* c) {
+  return std::min(2048, (c->ne * c->nens + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK);
+}
 
 // The planner and the mover at a step boundary; both return at once unless a
 // repack was requested.
@@ -500,7 +504,8 @@ StepLaunch step_launch_ext(pdf_ctx* c, StepArgs<T>& s) {
 
 constexpr int GRAPH_STEPS = 6;  // parity repeats every 2 steps, the counter sets every 3
 
-// Builds a graph of GRAPH_STEPS consecutive steps (plus the step-base update)
+// Builds a graph of GRAPH_STEPS consecutive steps (and the capacity check,
+// whose planner also advances the step base)
 // for the current launch shape.  Nodes are added explicitly, so no stream
 // capture is involved and nothing but kernel nodes is recorded.
 template <typename T> pdf_status build_graph_t(pdf_ctx* c) {
@@ -543,18 +548,10 @@ template <typename T> pdf_status build_graph_t(pdf_ctx* c) {
       prev = mn;
     }
   }
-  Ctl* ctl = (Ctl*)(c->arena + c->L.ctl);
-  uint32_t nst = GRAPH_STEPS;
-  void* bparams[2] = {&ctl, &nst};
-  hipKernelNodeParams kb{};
-  kb.func = reinterpret_cast<void*>(&k_advance_base);
-  kb.gridDim = dim3(1);
-  kb.blockDim = dim3(64);
-  kb.kernelParams = bparams;
-  hipGraphNode_t bnode;
-  if ((r = hip_check(c, hipGraphAddKernelNode(&bnode, g, &prev, 1, &kb), "graph node"))) return r;
-  // capacity check at the end of the cycle (parity 0, counter set 0)
+  // capacity check at the end of the cycle (parity 0, counter set 0); the
+  // planner also adds the cycle's steps to the step base
   RepackPlan plan = repack_plan_args(c, 0);
+  plan.advance = GRAPH_STEPS;
   void* pparams[1] = {&plan};
   hipKernelNodeParams kpl{};
   kpl.func = reinterpret_cast<void*>(&k_repack_plan);
@@ -562,7 +559,7 @@ template <typename T> pdf_status build_graph_t(pdf_ctx* c) {
   kpl.blockDim = dim3(PLAN_THREADS);
   kpl.kernelParams = pparams;
   hipGraphNode_t pnode;
-  if ((r = hip_check(c, hipGraphAddKernelNode(&pnode, g, &bnode, 1, &kpl), "graph node"))) return r;
+  if ((r = hip_check(c, hipGraphAddKernelNode(&pnode, g, &prev, 1, &kpl), "graph node"))) return r;
   RepackMove<T> mv = repack_move_args<T>(c, 0);
   StepIndex si0{0, 0, 0, 0};
   void* mparams[2] = {&mv, &si0};
