@@ -488,8 +488,13 @@ __device__ __forceinline__ int fine_component(double u, double mean, double sd) 
   return k < 0.0 ? 0 : (k > 4.0 ? 4 : (int)k);
 }
 
+// Threads per block of the step: two wavefronts (smaller blocks free their
+// LDS sooner), four with the learned means inside the step, where each
+// wavefront computes one output tile of a hidden layer.
+template <int SCHED> __host__ __device__ constexpr int step_block() { return SCHED == 2 ? 256 : 128; }
+
 template <typename T, int MOM, int HIST, int G, bool ADVANCE, int SCHED, int XV>
-__global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
+__global__ __launch_bounds__(step_block<SCHED>()) void k_step(StepArgs<T> a, StepIndex si) {
   constexpr bool OMG = XV == XV_OMEGA;
   constexpr bool VB5 = XV == XV_BINS5;
   static_assert(!(XV != XV_NONE && SCHED == 2), "model extensions run with the separate learned-means pass");
@@ -502,7 +507,8 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
   // fourth-order float kernels of 32 or 64 lanes per cell (three blocks),
   // six at 8 lanes per cell (two blocks)
   constexpr int TILEN = ((MOM >= 4 && XV == XV_NONE && sizeof(T) == 4 && G >= 32) ? 5 : (G == 8 ? 6 : 4)) * G;
-  constexpr int CPB = WAVES_PER_BLOCK * GPW;
+  constexpr int SWPB = step_block<SCHED>() / WAVE;  // wavefronts per block
+  constexpr int CPB = SWPB * GPW;
   __shared__ Tile<T, TILEN> tiles[CPB];
   __shared__ int hist_lds[HIST > 0 ? CPB : 1][HIST > 0 ? HIST : 1];
   __shared__ CellConst<T> ccs[ADVANCE ? CPB : 1];
@@ -538,7 +544,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs<T> a, StepIndex si) {
 
   // persistent grid: a wavefront claims a.pchunk consecutive work items per
   // atomic on the shared counter (one address: its atomics serialise in L2)
-  int item = PERSIST ? 0 : xcd_block(blockIdx.x, gridDim.x) * WAVES_PER_BLOCK + wid;
+  int item = PERSIST ? 0 : xcd_block(blockIdx.x, gridDim.x) * SWPB + wid;
   int chunk_end = 0;
   for (;;) {
     if (PERSIST) {

@@ -252,27 +252,28 @@ template <typename T> StepArgs<T> step_args(pdf_ctx* c) {
 
 // Work items per claim of a persistent wavefront: about a sixteenth of its
 // fair share, between 1 and 16.
-int persist_chunk(int nitems, int blocks) {
-  const int waves = std::max(1, blocks * WAVES_PER_BLOCK);
+int persist_chunk(int nitems, int waves) {
+  waves = std::max(1, waves);
   return std::max(1, std::min(16, nitems / (16 * waves)));
 }
 
 template <typename T, int MOM, int HIST, int G, bool ADV, int SCHED, int XV>
 void launch_step(pdf_ctx* c, StepArgs<T> s, StepIndex si) {
   constexpr int GPW = WAVE / G;
+  constexpr int TB = step_block<SCHED>(), WPB = TB / WAVE;
   s.nitems = (s.ncell + GPW - 1) / GPW;
-  int blocks = (s.nitems + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
+  int blocks = (s.nitems + WPB - 1) / WPB;
   if (SCHED == 1) {
     int per_cu = 0;
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step<T, MOM, HIST, G, ADV, SCHED, XV>, BLOCK, 0);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step<T, MOM, HIST, G, ADV, SCHED, XV>, TB, 0);
     int cus = 0;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device);
     const int cap_blocks = std::max(1, per_cu) * std::max(1, cus);
     blocks = std::min(blocks, cap_blocks);
     c->persist_blocks = blocks;
   }
-  s.pchunk = persist_chunk(s.nitems, blocks);
-  hipLaunchKernelGGL((k_step<T, MOM, HIST, G, ADV, SCHED, XV>), dim3(blocks), dim3(BLOCK), 0, c->stream, s, si);
+  s.pchunk = persist_chunk(s.nitems, blocks * WPB);
+  hipLaunchKernelGGL((k_step<T, MOM, HIST, G, ADV, SCHED, XV>), dim3(blocks), dim3(TB), 0, c->stream, s, si);
 }
 
 // Scheduling variant of a step launch: persistent grid, or one work item per
@@ -451,23 +452,26 @@ pdf_status enqueue_repack(pdf_ctx* c) {
 struct StepLaunch {
   const void* func = nullptr;
   int blocks = 0;
+  int threads = 0;
 };
 
 template <typename T, int MOM, int HIST, int G, int SCHED, int XV>
 StepLaunch step_launch_of(pdf_ctx* c, StepArgs<T>& s) {
   constexpr int GPW = WAVE / G;
+  constexpr int TB = step_block<SCHED>(), WPB = TB / WAVE;
   s.nitems = (s.ncell + GPW - 1) / GPW;
-  int blocks = (s.nitems + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
+  int blocks = (s.nitems + WPB - 1) / WPB;
   if (SCHED == 1) {
     int per_cu = 0, cus = 0;
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step<T, MOM, HIST, G, true, SCHED, XV>, BLOCK, 0);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step<T, MOM, HIST, G, true, SCHED, XV>, TB, 0);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device);
     blocks = std::min(blocks, std::max(1, per_cu) * std::max(1, cus));
   }
-  s.pchunk = persist_chunk(s.nitems, blocks);
+  s.pchunk = persist_chunk(s.nitems, blocks * WPB);
   StepLaunch l;
   l.func = reinterpret_cast<const void*>(&k_step<T, MOM, HIST, G, true, SCHED, XV>);
   l.blocks = blocks;
+  l.threads = TB;
   return l;
 }
 
@@ -530,7 +534,7 @@ template <typename T> pdf_status build_graph_t(pdf_ctx* c) {
     hipKernelNodeParams kp{};
     kp.func = const_cast<void*>(l.func);
     kp.gridDim = dim3(l.blocks);
-    kp.blockDim = dim3(BLOCK);
+    kp.blockDim = dim3(l.threads);
     kp.sharedMemBytes = 0;
     kp.kernelParams = params[i];
     kp.extra = nullptr;
