@@ -488,10 +488,10 @@ __device__ __forceinline__ int fine_component(double u, double mean, double sd) 
   return k < 0.0 ? 0 : (k > 4.0 ? 4 : (int)k);
 }
 
-// Threads per block of the step: two wavefronts (smaller blocks free their
-// LDS sooner), four with the learned means inside the step, where each
-// wavefront computes one output tile of a hidden layer.
-template <int SCHED> __host__ __device__ constexpr int step_block() { return SCHED == 2 ? 256 : 128; }
+// Threads per block of the step: one wavefront (a block's LDS is freed as
+// soon as its cells are done), four with the learned means inside the step,
+// where each wavefront computes one output tile of a hidden layer.
+template <int SCHED> __host__ __device__ constexpr int step_block() { return SCHED == 2 ? 256 : WAVE; }
 
 template <typename T, int MOM, int HIST, int G, bool ADVANCE, int SCHED, int XV>
 __global__ __launch_bounds__(step_block<SCHED>()) void k_step(StepArgs<T> a, StepIndex si) {
