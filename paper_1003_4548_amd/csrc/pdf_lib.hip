@@ -741,13 +741,18 @@ pdf_status pdf_seed_particles(pdf_ctx* c, int32_t nens, const int64_t* counts, c
     c->h_cap[cell] = (int32_t)capc;
     slot += capc;
   }
-  // processing order: within windows of 256 consecutive cells (neighbouring
+  // processing order: within windows of consecutive cells (neighbouring
   // elements), cells by decreasing particle count, so that the cells sharing
-  // a wavefront have similar counts
+  // a wavefront have similar counts and the larger cells start first.
+  // Windows of 256 keep the mesh data of a stretch of wavefronts in L2; a
+  // launch of few cells (a few wavefronts per slot of the chip) takes windows
+  // of 2048, which even out its last wavefronts (measured with 2048: 6 %
+  // shorter steps on a 10k-element canyon, 1-2 % longer on a 50k-element one)
+  const int64_t window = ncell <= 16384 ? 2048 : 256;
   c->h_order.resize(ncell);
   for (int64_t i = 0; i < ncell; ++i) c->h_order[i] = (int32_t)i;
-  for (int64_t w0 = 0; w0 < ncell; w0 += 256) {
-    const int64_t w1 = std::min<int64_t>(ncell, w0 + 256);
+  for (int64_t w0 = 0; w0 < ncell; w0 += window) {
+    const int64_t w1 = std::min<int64_t>(ncell, w0 + window);
     std::stable_sort(c->h_order.begin() + w0, c->h_order.begin() + w1,
                      [&](int32_t x, int32_t y) { return c->h_cnt[x] > c->h_cnt[y]; });
   }
