@@ -20,6 +20,10 @@ namespace {
 
 constexpr int64_t ALIGN = 256;
 constexpr int32_t SEG_PAD = 32;
+// cells whose particles at seeding fit one batch of SMALL_GROUP lanes may take
+// a step launch of their own at that width (see pdf_seed_particles)
+constexpr int32_t SMALL_GROUP = 8;
+constexpr int32_t SMALL_COUNT = SMALL_GROUP;
 
 int64_t align_up(int64_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
@@ -122,6 +126,9 @@ struct pdf_ctx {
   int32_t group = 64;     // lanes per cell
   int32_t persist = 0;    // persistent scheduler
   int32_t persist_blocks = 0;
+  // cells of the order's first part (the rest are small cells, stepped by a
+  // launch of their own at SMALL_GROUP lanes per cell); 0: one launch
+  int64_t nsplit = 0;
   // replayable graph of GRAPH_STEPS steps (built for one launch shape)
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
@@ -327,13 +334,32 @@ void launch_ext(pdf_ctx* c, const StepArgs<T>& s, StepIndex si) {
   }
 }
 
+// The small cells' launch of a split order (nsplit > 0), not with a
+// network attached (its means inside the step need 16 or more lanes per cell).
+bool split_launch(const pdf_ctx* c) { return c->nsplit > 0 && !c->mlp_w && c->p.f32_state; }
+
 template <bool ADV> pdf_status dispatch_step(pdf_ctx* c, StepIndex si) {
   if (c->p.f32_state) {
     StepArgs<float> s = step_args<float>(c);
     if (ADV) s.cmean = mlp_separate(c) ? c->mlp_cm : nullptr;
     if (!ADV) s.mlp_w = nullptr;
+    const bool split = split_launch(c);
+    const int32_t ncell = s.ncell;
+    if (split) s.ncell = (int32_t)c->nsplit;
     if (c->p.moments == 2) launch_ext<float, 2, 0, ADV>(c, s, si);
     else launch_ext<float, 4, 32, ADV>(c, s, si);
+    if (split) {
+      // the small cells at the end of the order
+      s.order = s.order + c->nsplit;
+      s.ncell = ncell - (int32_t)c->nsplit;
+      const int32_t g = c->group, pe = c->persist;
+      c->group = SMALL_GROUP;
+      c->persist = 0;
+      if (c->p.moments == 2) launch_ext<float, 2, 0, ADV>(c, s, si);
+      else launch_ext<float, 4, 32, ADV>(c, s, si);
+      c->group = g;
+      c->persist = pe;
+    }
   } else {
     StepArgs<double> s = step_args<double>(c);
     if (ADV) s.cmean = mlp_separate(c) ? c->mlp_cm : nullptr;
@@ -515,15 +541,33 @@ constexpr int GRAPH_STEPS = 6;  // parity repeats every 2 steps, the counter set
 template <typename T> pdf_status build_graph_t(pdf_ctx* c) {
   // the runtime copies kernel arguments into each node when it is added
   StepArgs<T> args_store = step_args<T>(c);
-  StepLaunch l;
+  // with a split order, a second node per step for the small cells
+  const bool split = split_launch(c);
+  StepArgs<T> args_small = args_store;
+  StepLaunch l, ls;
+  if (split) {
+    args_store.ncell = (int32_t)c->nsplit;
+    args_small.order = args_small.order + c->nsplit;
+    args_small.ncell = args_small.ncell - (int32_t)c->nsplit;
+  }
   if (c->p.moments == 2) l = step_launch_ext<T, 2, 0>(c, args_store);
   else l = step_launch_ext<T, 4, 32>(c, args_store);
+  if (split) {
+    const int32_t g = c->group, pe = c->persist;
+    c->group = SMALL_GROUP;
+    c->persist = 0;
+    if (c->p.moments == 2) ls = step_launch_ext<T, 2, 0>(c, args_small);
+    else ls = step_launch_ext<T, 4, 32>(c, args_small);
+    c->group = g;
+    c->persist = pe;
+  }
   pdf_status r;
   hipGraph_t g = nullptr;
   if ((r = hip_check(c, hipGraphCreate(&g, 0), "graph create"))) return r;
   hipGraphNode_t prev = nullptr;
   StepIndex sis[GRAPH_STEPS];
   void* params[GRAPH_STEPS][2];
+  void* params_small[GRAPH_STEPS][2];
   MergeArgs margs = merge_args(c);
   void* mparams8[8] = {&margs.stats, &margs.nstat, &margs.hoff, &margs.hist, &margs.omega, &margs.acc, &margs.navg,
                        &margs.ncell};
@@ -541,6 +585,18 @@ template <typename T> pdf_status build_graph_t(pdf_ctx* c) {
     hipGraphNode_t node;
     if ((r = hip_check(c, hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &kp), "graph node"))) return r;
     prev = node;
+    if (split) {
+      params_small[i][0] = &args_small;
+      params_small[i][1] = &sis[i];
+      hipKernelNodeParams ks = kp;
+      ks.func = const_cast<void*>(ls.func);
+      ks.gridDim = dim3(ls.blocks);
+      ks.blockDim = dim3(ls.threads);
+      ks.kernelParams = params_small[i];
+      hipGraphNode_t sn;
+      if ((r = hip_check(c, hipGraphAddKernelNode(&sn, g, &prev, 1, &ks), "graph node"))) return r;
+      prev = sn;
+    }
     if (c->avg) {
       hipKernelNodeParams km{};
       km.func = reinterpret_cast<void*>(&k_average_merge);
@@ -748,14 +804,29 @@ pdf_status pdf_seed_particles(pdf_ctx* c, int32_t nens, const int64_t* counts, c
   // launch of few cells (a few wavefronts per slot of the chip) takes windows
   // of 2048, which even out its last wavefronts (measured with 2048: 6 %
   // shorter steps on a 10k-element canyon, 1-2 % longer on a 50k-element one)
+  // With the float state, when both the cells of at most SMALL_COUNT
+  // particles and the others make up at least an eighth of the cells, the
+  // small ones go to the end of the order and take a launch of their own at
+  // SMALL_GROUP lanes per cell (the batched ensembles of very different
+  // sizes); each part is ordered as above.
   const int64_t window = ncell <= 16384 ? 2048 : 256;
-  c->h_order.resize(ncell);
-  for (int64_t i = 0; i < ncell; ++i) c->h_order[i] = (int32_t)i;
-  for (int64_t w0 = 0; w0 < ncell; w0 += window) {
-    const int64_t w1 = std::min<int64_t>(ncell, w0 + window);
-    std::stable_sort(c->h_order.begin() + w0, c->h_order.begin() + w1,
-                     [&](int32_t x, int32_t y) { return c->h_cnt[x] > c->h_cnt[y]; });
+  c->h_order.clear();
+  c->h_order.reserve(ncell);
+  int64_t nsmall = 0;
+  for (int64_t i = 0; i < ncell; ++i) nsmall += c->h_cnt[i] <= SMALL_COUNT ? 1 : 0;
+  const bool split = c->p.f32_state && 8 * nsmall >= ncell && 8 * (ncell - nsmall) >= ncell;
+  for (int part = 0; part < (split ? 2 : 1); ++part) {
+    const int64_t b = (int64_t)c->h_order.size();
+    for (int64_t i = 0; i < ncell; ++i)
+      if (!split || (c->h_cnt[i] <= SMALL_COUNT) == (part == 1)) c->h_order.push_back((int32_t)i);
+    const int64_t e = (int64_t)c->h_order.size();
+    for (int64_t w0 = b; w0 < e; w0 += window) {
+      const int64_t w1 = std::min<int64_t>(e, w0 + window);
+      std::stable_sort(c->h_order.begin() + w0, c->h_order.begin() + w1,
+                       [&](int32_t x, int32_t y) { return c->h_cnt[x] > c->h_cnt[y]; });
+    }
   }
+  c->nsplit = split ? ncell - nsmall : 0;
   const int64_t slots = slot + growth_reserve(total, ncell, slack);
   const Layout L = make_layout(c->nv, c->ne, nens, slots, nstat_of(c->p), tsize_of(c->p), c->p.omega != 0);
   if (L.total > c->arena_bytes)
