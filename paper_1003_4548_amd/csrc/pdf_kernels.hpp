@@ -147,16 +147,12 @@ template <typename T> struct StepArgs {
   int32_t mix;
   int32_t nitems;         // work items (wavefronts' worth of cells)
   int32_t pchunk;         // work items a persistent wavefront claims per atomic
+  // one item per wavefront: the work items XCD x runs are [xcd[x], xcd[x+1]),
+  // ranges of equal estimated cost (blocks reach the XCDs round-robin)
+  int32_t xcd[9];
   T dt, sdt, nu2, s2nu;
 };
 
-// Logical block index that gives each XCD a contiguous range of work:
-// hardware dispatches consecutive workgroups round-robin over the 8 XCDs.
-__device__ __forceinline__ int xcd_block(int b, int G) {
-  const int NX = 8;
-  const int q = G / NX, r = G % NX, x = b % NX, i = b / NX;
-  return (x < r) ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
-}
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (WAVE - 1); }
 
@@ -544,7 +540,15 @@ __global__ __launch_bounds__(step_block<SCHED>()) void k_step(StepArgs<T> a, Ste
 
   // persistent grid: a wavefront claims a.pchunk consecutive work items per
   // atomic on the shared counter (one address: its atomics serialise in L2)
-  int item = PERSIST ? 0 : xcd_block(blockIdx.x, gridDim.x) * SWPB + wid;
+  int item = 0;
+  if (!PERSIST) {
+    // block b runs on XCD b mod 8; each XCD walks its own contiguous range of
+    // the order (neighbouring cells share the XCD's L2), the ranges balanced
+    // by estimated cost rather than by length
+    const int x = (int)(blockIdx.x % 8u), i = (int)(blockIdx.x / 8u);
+    item = a.xcd[x] + i * SWPB + wid;
+    if (item >= a.xcd[x + 1]) item = a.nitems;
+  }
   int chunk_end = 0;
   for (;;) {
     if (PERSIST) {

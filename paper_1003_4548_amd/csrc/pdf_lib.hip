@@ -129,6 +129,10 @@ struct pdf_ctx {
   // cells of the order's first part (the rest are small cells, stepped by a
   // launch of their own at SMALL_GROUP lanes per cell); 0: one launch
   int64_t nsplit = 0;
+  // per lanes-per-cell (64, 32, 16, 8) and order part: the XCD ranges of
+  // work items (valid once computed for the current seeding)
+  int32_t xcd[4][2][9] = {};
+  bool xcd_ok[4][2] = {};
   // replayable graph of GRAPH_STEPS steps (built for one launch shape)
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
@@ -259,6 +263,47 @@ template <typename T> StepArgs<T> step_args(pdf_ctx* c) {
 
 // Work items per claim of a persistent wavefront: about a sixteenth of its
 // fair share, between 1 and 16.
+// Work items of a one-item-per-wavefront launch over the order cells [off,
+// off + n) at G lanes per cell, split into 8 contiguous ranges of equal
+// estimated cost, one per XCD.  A wavefront's cost: one unit for its cells'
+// set-up and statistics, one per batch of its largest cell (counts at
+// seeding; the flow keeps the particle density near its initial one).
+const int32_t* xcd_ranges(pdf_ctx* c, int G, int64_t off, int64_t n) {
+  const int gi = G == 64 ? 0 : (G == 32 ? 1 : (G == 16 ? 2 : 3));
+  const int part = off == 0 ? 0 : 1;
+  int32_t* r = c->xcd[gi][part];
+  if (c->xcd_ok[gi][part]) return r;
+  const int gpw = WAVE / G;
+  const int64_t items = (n + gpw - 1) / gpw;
+  std::vector<double> pre((size_t)items + 1, 0.0);
+  for (int64_t it = 0; it < items; ++it) {
+    int32_t mx = 0;
+    for (int j = 0; j < gpw; ++j) {
+      const int64_t k = it * gpw + j;
+      if (k < n) mx = std::max(mx, c->h_cnt[c->h_order[off + k]]);
+    }
+    pre[it + 1] = pre[it] + 1.0 + (double)((mx + G - 1) / G);
+  }
+  r[0] = 0;
+  int64_t it = 0;
+  for (int x = 1; x < 8; ++x) {
+    const double target = pre[items] * x / 8.0;
+    while (it < items && pre[it + 1] <= target) ++it;
+    r[x] = (int32_t)std::max<int64_t>(it, r[x - 1]);
+  }
+  r[8] = (int32_t)items;
+  c->xcd_ok[gi][part] = true;
+  return r;
+}
+
+// Blocks of a launch over those ranges: each XCD's blocks cover its longest
+// range (the others' surplus blocks return at once).
+int xcd_blocks(const int32_t* r, int wpb) {
+  int m = 0;
+  for (int x = 0; x < 8; ++x) m = std::max(m, r[x + 1] - r[x]);
+  return 8 * std::max(1, (m + wpb - 1) / wpb);
+}
+
 int persist_chunk(int nitems, int waves) {
   waves = std::max(1, waves);
   return std::max(1, std::min(16, nitems / (16 * waves)));
@@ -270,6 +315,11 @@ void launch_step(pdf_ctx* c, StepArgs<T> s, StepIndex si) {
   constexpr int TB = step_block<SCHED>(), WPB = TB / WAVE;
   s.nitems = (s.ncell + GPW - 1) / GPW;
   int blocks = (s.nitems + WPB - 1) / WPB;
+  if (SCHED != 1) {
+    const int32_t* r = xcd_ranges(c, G, s.order - (const int32_t*)(c->arena + c->L.order), s.ncell);
+    for (int x = 0; x < 9; ++x) s.xcd[x] = r[x];
+    blocks = xcd_blocks(r, WPB);
+  }
   if (SCHED == 1) {
     int per_cu = 0;
     (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step<T, MOM, HIST, G, ADV, SCHED, XV>, TB, 0);
@@ -487,6 +537,11 @@ StepLaunch step_launch_of(pdf_ctx* c, StepArgs<T>& s) {
   constexpr int TB = step_block<SCHED>(), WPB = TB / WAVE;
   s.nitems = (s.ncell + GPW - 1) / GPW;
   int blocks = (s.nitems + WPB - 1) / WPB;
+  if (SCHED != 1) {
+    const int32_t* r = xcd_ranges(c, G, s.order - (const int32_t*)(c->arena + c->L.order), s.ncell);
+    for (int x = 0; x < 9; ++x) s.xcd[x] = r[x];
+    blocks = xcd_blocks(r, WPB);
+  }
   if (SCHED == 1) {
     int per_cu = 0, cus = 0;
     (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step<T, MOM, HIST, G, true, SCHED, XV>, TB, 0);
@@ -827,6 +882,7 @@ pdf_status pdf_seed_particles(pdf_ctx* c, int32_t nens, const int64_t* counts, c
     }
   }
   c->nsplit = split ? ncell - nsmall : 0;
+  for (int gi = 0; gi < 4; ++gi) c->xcd_ok[gi][0] = c->xcd_ok[gi][1] = false;
   const int64_t slots = slot + growth_reserve(total, ncell, slack);
   const Layout L = make_layout(c->nv, c->ne, nens, slots, nstat_of(c->p), tsize_of(c->p), c->p.omega != 0);
   if (L.total > c->arena_bytes)
