@@ -265,9 +265,11 @@ template <typename T> StepArgs<T> step_args(pdf_ctx* c) {
 // fair share, between 1 and 16.
 // Work items of a one-item-per-wavefront launch over the order cells [off,
 // off + n) at G lanes per cell, split into 8 contiguous ranges of equal
-// estimated cost, one per XCD.  A wavefront's cost: one unit for its cells'
-// set-up and statistics, one per batch of its largest cell (counts at
-// seeding; the flow keeps the particle density near its initial one).
+// estimated cost, one per XCD.  A wavefront's cost: two units for its cells'
+// set-up, statistics and crossing particles, one per batch of its largest
+// cell (counts at seeding; the flow keeps the particle density near its
+// initial one).  Weights measured best among 1-4 units per wavefront and a
+// cost proportional to the count.
 const int32_t* xcd_ranges(pdf_ctx* c, int G, int64_t off, int64_t n) {
   const int gi = G == 64 ? 0 : (G == 32 ? 1 : (G == 16 ? 2 : 3));
   const int part = off == 0 ? 0 : 1;
@@ -282,7 +284,7 @@ const int32_t* xcd_ranges(pdf_ctx* c, int G, int64_t off, int64_t n) {
       const int64_t k = it * gpw + j;
       if (k < n) mx = std::max(mx, c->h_cnt[c->h_order[off + k]]);
     }
-    pre[it + 1] = pre[it] + 1.0 + (double)((mx + G - 1) / G);
+    pre[it + 1] = pre[it] + 2.0 + (double)((mx + G - 1) / G);
   }
   r[0] = 0;
   int64_t it = 0;
