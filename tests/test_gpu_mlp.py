@@ -335,3 +335,38 @@ def test_learned_means_same_in_step_and_in_separate_pass(gpu):
         np.testing.assert_array_equal(s1[q], s2[q])
     np.testing.assert_allclose(s1["psi"], s2["psi"], rtol=1e-6, atol=1e-7)
     np.testing.assert_allclose(lm.cm.cpu().numpy(), lm3.cm.cpu().numpy(), rtol=1e-6, atol=1e-7)
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_network_over_a_split_order(gpu, graph):
+    """Three ensembles of uneven size, whose cells of at most eight particles
+    step in a launch of their own at 8 lanes per cell: with a network attached
+    every cell steps in one launch, and after detaching the two launches
+    resume.  Positions, velocities and elements do not depend on the scalar's
+    means and stay bit-exact with the oracle for every ensemble."""
+    P, PM, torch = gpu
+    wl = W.tiny_canyon(precision="f32", nens=3, steps=2)
+    counts = np.concatenate([np.asarray(e.counts) for e in wl.ensembles])
+    small = int((counts <= 8).sum())
+    assert 8 * small >= counts.size and 8 * (counts.size - small) >= counts.size   # the order splits
+    _label(f"mlp over a split order {wl.name} graph={graph}")
+    sim = P.Simulation.from_workload(wl)
+    run = sim.step_graph if graph else sim.step
+    run(2)
+    sim.sync()
+    stats = sim.statistics()[2]
+    feat = M.features_from_stats(stats)
+    norm = M.feature_norm(feat[stats[:, O.ST_N] > 0])
+    net = _net(PM, torch, _small_output(M.init_params(7)), norm)
+    lm = net.attach(sim)
+    run(4)
+    sim.sync()
+    lm.detach()
+    run(6)
+    sim.sync()
+    orc = O.Oracle(wl)
+    orc.step(12)
+    for en in range(wl.nens):
+        g, o = sim.state(en), orc.state(en)
+        for q in ("x", "y", "u", "v", "w", "elem"):
+            np.testing.assert_array_equal(g[q], o[q], err_msg=f"ensemble {en} {q}")
