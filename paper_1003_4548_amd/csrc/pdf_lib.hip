@@ -269,9 +269,8 @@ template <typename T> StepArgs<T> step_args(pdf_ctx* c) {
 // set-up, statistics and crossing particles, one per batch of its largest
 // cell (counts at seeding; the flow keeps the particle density near its
 // initial one).  Weights measured best among 1-4 units per wavefront and a
-// cost proportional to the count.  A launch of at most 16384 cells (the
-// windows of 2048 above already even out its few wavefronts per slot) keeps
-// ranges of equal length, which measured 0.5 % faster there.
+// cost proportional to the count.  A launch of at most 16384 cells keeps
+// ranges of equal length, the eighths its order is sorted within.
 const int32_t* xcd_ranges(pdf_ctx* c, int G, int64_t off, int64_t n) {
   const int gi = G == 64 ? 0 : (G == 32 ? 1 : (G == 16 ? 2 : 3));
   const int part = off == 0 ? 0 : 1;
@@ -864,16 +863,18 @@ pdf_status pdf_seed_particles(pdf_ctx* c, int32_t nens, const int64_t* counts, c
   // processing order: within windows of consecutive cells (neighbouring
   // elements), cells by decreasing particle count, so that the cells sharing
   // a wavefront have similar counts and the larger cells start first.
-  // Windows of 256 keep the mesh data of a stretch of wavefronts in L2; a
-  // launch of few cells (a few wavefronts per slot of the chip) takes windows
-  // of 2048, which even out its last wavefronts (measured with 2048: 6 %
-  // shorter steps on a 10k-element canyon, 1-2 % longer on a 50k-element one)
+  // Windows of 256 keep the mesh data of a stretch of wavefronts in L2.  A
+  // launch of at most 16384 cells (a few wavefronts per slot of the chip)
+  // sorts each eighth of the order as a whole instead: the XCDs take equal
+  // contiguous eighths (see xcd_ranges), so every XCD starts with its largest
+  // cells and ends with its smallest (12 % shorter steps on a 10k-element
+  // canyon than windows of 256; windows of 2048, not aligned with the
+  // eighths: 6 %; larger windows on a 50k-element canyon: 1-7 % longer).
   // With the float state, when both the cells of at most SMALL_COUNT
   // particles and the others make up at least an eighth of the cells, the
   // small ones go to the end of the order and take a launch of their own at
   // SMALL_GROUP lanes per cell (the batched ensembles of very different
   // sizes); each part is ordered as above.
-  const int64_t window = ncell <= 16384 ? 2048 : 256;
   c->h_order.clear();
   c->h_order.reserve(ncell);
   int64_t nsmall = 0;
@@ -884,10 +885,14 @@ pdf_status pdf_seed_particles(pdf_ctx* c, int32_t nens, const int64_t* counts, c
     for (int64_t i = 0; i < ncell; ++i)
       if (!split || (c->h_cnt[i] <= SMALL_COUNT) == (part == 1)) c->h_order.push_back((int32_t)i);
     const int64_t e = (int64_t)c->h_order.size();
-    for (int64_t w0 = b; w0 < e; w0 += window) {
-      const int64_t w1 = std::min<int64_t>(e, w0 + window);
+    auto sort_window = [&](int64_t w0, int64_t w1) {
       std::stable_sort(c->h_order.begin() + w0, c->h_order.begin() + w1,
                        [&](int32_t x, int32_t y) { return c->h_cnt[x] > c->h_cnt[y]; });
+    };
+    if (ncell <= 16384) {
+      for (int x = 0; x < 8; ++x) sort_window(b + (e - b) * x / 8, b + (e - b) * (x + 1) / 8);
+    } else {
+      for (int64_t w0 = b; w0 < e; w0 += 256) sort_window(w0, std::min<int64_t>(e, w0 + 256));
     }
   }
   c->nsplit = split ? ncell - nsmall : 0;
