@@ -893,6 +893,25 @@ pdf_status pdf_seed_particles(pdf_ctx* c, int32_t nens, const int64_t* counts, c
       for (int x = 0; x < 8; ++x) sort_window(b + (e - b) * x / 8, b + (e - b) * (x + 1) / 8);
     } else {
       for (int64_t w0 = b; w0 < e; w0 += 256) sort_window(w0, std::min<int64_t>(e, w0 + 256));
+      // and the last fifth of each XCD's range (cut as xcd_ranges cuts them
+      // at 64 lanes per cell) largest-first, so that the XCDs end with their
+      // smallest cells: 1.5 % shorter steps on a 50k-element canyon (a third
+      // or all of the range: less)
+      std::vector<double> pre((size_t)(e - b) + 1, 0.0);
+      for (int64_t k = b; k < e; ++k)
+        pre[k - b + 1] = pre[k - b] + 2.0 + (double)((c->h_cnt[c->h_order[k]] + WAVE - 1) / WAVE);
+      int64_t it = 0, prev = 0;
+      for (int x = 1; x <= 8; ++x) {
+        int64_t bx = e - b;
+        if (x < 8) {
+          const double target = pre[e - b] * x / 8.0;
+          while (it < e - b && pre[it + 1] <= target) ++it;
+          bx = std::max(it, prev);
+        }
+        const int64_t tail = (bx - prev) / 5;
+        if (tail > 1) sort_window(b + bx - tail, b + bx);
+        prev = bx;
+      }
     }
   }
   c->nsplit = split ? ncell - nsmall : 0;
