@@ -182,10 +182,10 @@ pdf_status pdf_step_graph(pdf_ctx* ctx, int32_t nsteps);
    1 + steps_per_trial real steps per candidate, and scores a candidate by
    its faster trial (the simulation advances by all of them; particle
    trajectories do not depend on the shape).  With the float state and no
-   network attached, when the cells whose particles fit one batch of 8 lanes
-   at seeding and the other cells each make up an eighth of the cells or
-   more, the former take a launch of their own at 8 lanes per cell and the
-   shape applies to the others.  The choice is
+   network attached, when the cells of at most 8 particles at seeding and
+   the other cells each make up an eighth of the cells or more, the former
+   take a launch of their own at 4 lanes per cell and the shape applies to
+   the others.  The choice is
    kept in the context and returned in *group, *persist (either may be NULL).
    Synchronizes the stream. */
 pdf_status pdf_autotune(pdf_ctx* ctx, int32_t steps_per_trial, int32_t* group, int32_t* persist);

@@ -262,16 +262,30 @@ __device__ __forceinline__ void group_sum_many(double (&v)[K], double* out, doub
     stage(std::integral_constant<I, 4>{}, std::integral_constant<I, K1>{});
     stage(std::integral_constant<I, 2>{}, std::integral_constant<I, K2>{});
     stage(std::integral_constant<I, 1>{}, std::integral_constant<I, K3>{});
-  } else {
-    static_assert(G == 8, "groups of 8, 16, 32 or 64 lanes");
+  } else if constexpr (G == 8) {
     stage(std::integral_constant<I, 4>{}, std::integral_constant<I, K>{});
     stage(std::integral_constant<I, 2>{}, std::integral_constant<I, K1>{});
     stage(std::integral_constant<I, 1>{}, std::integral_constant<I, K2>{});
+  } else {
+    static_assert(G == 4, "groups of 4, 8, 16, 32 or 64 lanes");
+    stage(std::integral_constant<I, 2>{}, std::integral_constant<I, K>{});
+    stage(std::integral_constant<I, 1>{}, std::integral_constant<I, K1>{});
   }
-  constexpr int KF = G == 64 ? (K5 + 1) / 2 : (G == 32 ? K5 : (G == 16 ? K4 : K3));
+  constexpr int KF = G == 64 ? (K5 + 1) / 2 : (G == 32 ? K5 : (G == 16 ? K4 : (G == 8 ? K3 : K2)));
 #pragma unroll
   for (int i = 0; i < KF; ++i)
     if (store && i < cnt) out[off + i] = v[i] * f;
+}
+
+// f(q) for each of the eight velocity bins q, by lane q of a group of 8 or
+// more lanes, by lanes q mod 4 of a group of 4
+template <int G, typename F> __device__ __forceinline__ void per_bin(int li, F&& f) {
+  if constexpr (G >= 8) {
+    if (li < 8) f(li);
+  } else {
+#pragma unroll
+    for (int q = li; q < 8; q += G) f(q);
+  }
 }
 
 template <int G> __device__ __forceinline__ uint64_t group_mask(int grp) {
@@ -659,10 +673,10 @@ __global__ __launch_bounds__(step_block<SCHED>()) void k_step(StepArgs<T> a, Ste
     // is free, their rounding that of any FP64 sum of the bin's values)
     double* bsum = bsum_lds[slot_id];
     int* bcnt = bcnt_lds[slot_id];
-    if (li < 8) {
-      bsum[li] = 0.0;
-      bcnt[li] = 0;
-    }
+    per_bin<G>(li, [&](int q) {
+      bsum[q] = 0.0;
+      bcnt[q] = 0;
+    });
     if (HIST > 0) {
       for (int h = li; h < HIST; h += G) hist_lds[slot_id][h] = 0;
     }
@@ -708,11 +722,11 @@ __global__ __launch_bounds__(step_block<SCHED>()) void k_step(StepArgs<T> a, Ste
       for (int q = 0; q < 10; ++q) acc[q] = redc[q];
       if constexpr (OMG) om_var = redc[10] * inv_n;
     }
-    // bin means, lane q of the group taking bin q
-    if (li < 8) {
-      const int c = bcnt[li];
-      bsum[li] = c > 0 ? bsum[li] / (double)c : mean[3];
-    }
+    // bin means, one lane of the group per bin
+    per_bin<G>(li, [&](int q) {
+      const int c = bcnt[q];
+      bsum[q] = c > 0 ? bsum[q] / (double)c : mean[3];
+    });
     lds_sync_wave();
     int bcount[8];
     double bm[8];
@@ -817,10 +831,10 @@ __global__ __launch_bounds__(step_block<SCHED>()) void k_step(StepArgs<T> a, Ste
     if (has) {
       const double z = n > 0 ? 1.0 : 0.0;
       for (int q = li; q < 10; q += G) rec[ST_M2 + q] = redc[q] * inv_n;
-      if (li < 8) {
-        rec[ST_BINN + li] = (double)bcnt[li];
-        rec[ST_BINM + li] = bsum[li] * z;
-      }
+      per_bin<G>(li, [&](int q) {
+        rec[ST_BINN + q] = (double)bcnt[q];
+        rec[ST_BINM + q] = bsum[q] * z;
+      });
     }
     if (has && li == 0) {
       const double z = n > 0 ? 1.0 : 0.0;
@@ -969,14 +983,14 @@ __global__ __launch_bounds__(step_block<SCHED>()) void k_step(StepArgs<T> a, Ste
           CC.dy[k] = a_first ? by - ay : ay - by;
           CC.sg[k] = a_first ? 1.0 : -1.0;
         }
-        // conditional mean of bin q by lane q
+        // conditional mean of each bin by one lane
         if constexpr (fused_mlp) {
           if (li == 0) {
 #pragma unroll
             for (int q = 0; q < 8; ++q) CC.cm[q] = cm[q];
           }
-        } else if (li < 8) {
-          CC.cm[li] = (a.cmean != nullptr && has) ? a.cmean[(size_t)cell * 8 + li] : bsum[li];
+        } else {
+          per_bin<G>(li, [&](int q) { CC.cm[q] = (a.cmean != nullptr && has) ? a.cmean[(size_t)cell * 8 + q] : bsum[q]; });
         }
         if (li == 0) {
 #pragma unroll

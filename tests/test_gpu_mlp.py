@@ -340,7 +340,7 @@ def test_learned_means_same_in_step_and_in_separate_pass(gpu):
 @pytest.mark.parametrize("graph", [False, True])
 def test_network_over_a_split_order(gpu, graph):
     """Three ensembles of uneven size, whose cells of at most eight particles
-    step in a launch of their own at 8 lanes per cell: with a network attached
+    step in a launch of their own at 4 lanes per cell: with a network attached
     every cell steps in one launch, and after detaching the two launches
     resume.  Positions, velocities and elements do not depend on the scalar's
     means and stay bit-exact with the oracle for every ensemble."""
