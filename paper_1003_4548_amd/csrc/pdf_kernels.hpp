@@ -594,6 +594,41 @@ __global__ __launch_bounds__(step_block<SCHED>()) void k_step(StepArgs<T> a, Ste
     }
     const int n = ns + nm;
     const double dn = (double)n;
+    // The cell's constants for the advance (vertex coefficients, edge
+    // geometry, 1/(2A), rate, seed), issued here, ahead of the statistics
+    // passes, where groups of 16 lanes or fewer take many small cells per
+    // wavefront or the 5 x 5 x 5 bins make the passes long: 8 % shorter
+    // batched steps, 2 % with the bins; 2 % longer on the 64-lane canyons,
+    // whose registers they would hold through the passes.
+    constexpr bool PRE = ADVANCE && (G <= 16 || VB5);
+    constexpr int NPRE = PRE ? (3 * NCOEF + G - 1) / G : 1;
+    T pre_coef[NPRE];
+    double pre_ax = 0.0, pre_ay = 0.0, pre_bx = 0.0, pre_by = 0.0, pre_ia = 0.0;
+    T pre_rate = (T)0;
+    uint64_t pre_seed = 0;
+    if constexpr (PRE) {
+      const int vtx[3] = {a.tri[3 * e], a.tri[3 * e + 1], a.tri[3 * e + 2]};
+#pragma unroll
+      for (int i = 0; i < NPRE; ++i) {
+        const int q = li + i * G;
+        if (q < 3 * NCOEF) {
+          const int k = q / NCOEF;
+          const int vk = k == 0 ? vtx[0] : (k == 1 ? vtx[1] : vtx[2]);
+          pre_coef[i] = a.coef[(size_t)vk * NCOEF + (q - k * NCOEF)];
+        }
+      }
+      if (li < 3) {
+        const int k = li, k1 = k == 2 ? 0 : k + 1;
+        const ERec& R = a.erec[e];
+        pre_ax = R.x[k];
+        pre_ay = R.y[k];
+        pre_bx = R.x[k1];
+        pre_by = R.y[k1];
+      }
+      pre_ia = a.inv2a[e];
+      pre_rate = has ? a.rate[cell] : (T)0;
+      pre_seed = a.seed[ens];
+    }
 
     // ---- A: load, stage, means ----
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0;
@@ -965,17 +1000,26 @@ __global__ __launch_bounds__(step_block<SCHED>()) void k_step(StepArgs<T> a, Ste
       // ---- C: advance ----
       CellConst<T>& CC = ccs[ADVANCE ? slot_id : 0];
       {
-        const int vtx[3] = {a.tri[3 * e], a.tri[3 * e + 1], a.tri[3 * e + 2]};
-        for (int q = li; q < 3 * NCOEF; q += G) {
-          const int k = q / NCOEF;
-          const int vk = k == 0 ? vtx[0] : (k == 1 ? vtx[1] : vtx[2]);
-          CC.coef[q] = a.coef[(size_t)vk * NCOEF + (q - k * NCOEF)];
+        if constexpr (PRE) {
+#pragma unroll
+          for (int i = 0; i < NPRE; ++i) {
+            const int q = li + i * G;
+            if (q < 3 * NCOEF) CC.coef[q] = pre_coef[i];
+          }
+        } else {
+          const int vtx[3] = {a.tri[3 * e], a.tri[3 * e + 1], a.tri[3 * e + 2]};
+          for (int q = li; q < 3 * NCOEF; q += G) {
+            const int k = q / NCOEF;
+            const int vk = k == 0 ? vtx[0] : (k == 1 ? vtx[1] : vtx[2]);
+            CC.coef[q] = a.coef[(size_t)vk * NCOEF + (q - k * NCOEF)];
+          }
         }
         // edge k by lane k
         if (li < 3) {
           const int k = li, k1 = k == 2 ? 0 : k + 1;
           const ERec& R = a.erec[e];
-          const double ax = R.x[k], ay = R.y[k], bx = R.x[k1], by = R.y[k1];
+          const double ax = PRE ? pre_ax : R.x[k], ay = PRE ? pre_ay : R.y[k];
+          const double bx = PRE ? pre_bx : R.x[k1], by = PRE ? pre_by : R.y[k1];
           const bool a_first = (ax < bx) || (ax == bx && ay < by);
           CC.ox[k] = a_first ? ax : bx;
           CC.oy[k] = a_first ? ay : by;
@@ -1002,9 +1046,9 @@ __global__ __launch_bounds__(step_block<SCHED>()) void k_step(StepArgs<T> a, Ste
         }
         lds_sync_wave();
       }
-      const double ia = a.inv2a[e];
-      const T rate = has ? a.rate[cell] : (T)0;
-      const uint64_t seed = a.seed[ens];
+      const double ia = PRE ? pre_ia : a.inv2a[e];
+      const T rate = PRE ? pre_rate : (has ? a.rate[cell] : (T)0);
+      const uint64_t seed = PRE ? pre_seed : a.seed[ens];
       const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
       const bool do_mix = a.mix && (a.flags & FLAG_MIX);
       int err = 0;
