@@ -598,15 +598,17 @@ __global__ __launch_bounds__(step_block<SCHED>()) void k_step(StepArgs<T> a, Ste
     // geometry, 1/(2A), rate, seed), issued here, ahead of the statistics
     // passes, where groups of 16 lanes or fewer take many small cells per
     // wavefront or the 5 x 5 x 5 bins make the passes long: 8 % shorter
-    // batched steps, 2 % with the bins; 2 % longer on the 64-lane canyons,
-    // whose registers they would hold through the passes.
+    // batched steps, 2 % with the bins.  With the turbulent frequency all
+    // but the edge geometry (6 % shorter steps; with it: no gain).  The
+    // plain 64-lane steps take 2 % longer with any of them issued early.
     constexpr bool PRE = ADVANCE && (G <= 16 || VB5);
-    constexpr int NPRE = PRE ? (3 * NCOEF + G - 1) / G : 1;
+    constexpr bool PRE_SC = PRE || (ADVANCE && OMG);
+    constexpr int NPRE = PRE_SC ? (3 * NCOEF + G - 1) / G : 1;
     T pre_coef[NPRE];
     double pre_ax = 0.0, pre_ay = 0.0, pre_bx = 0.0, pre_by = 0.0, pre_ia = 0.0;
     T pre_rate = (T)0;
     uint64_t pre_seed = 0;
-    if constexpr (PRE) {
+    if constexpr (PRE_SC) {
       const int vtx[3] = {a.tri[3 * e], a.tri[3 * e + 1], a.tri[3 * e + 2]};
 #pragma unroll
       for (int i = 0; i < NPRE; ++i) {
@@ -617,6 +619,8 @@ __global__ __launch_bounds__(step_block<SCHED>()) void k_step(StepArgs<T> a, Ste
           pre_coef[i] = a.coef[(size_t)vk * NCOEF + (q - k * NCOEF)];
         }
       }
+    }
+    if constexpr (PRE) {
       if (li < 3) {
         const int k = li, k1 = k == 2 ? 0 : k + 1;
         const ERec& R = a.erec[e];
@@ -625,6 +629,10 @@ __global__ __launch_bounds__(step_block<SCHED>()) void k_step(StepArgs<T> a, Ste
         pre_bx = R.x[k1];
         pre_by = R.y[k1];
       }
+    }
+    // (after the edge geometry: the 5 x 5 x 5 bin steps took 4 % longer
+    // with these before it)
+    if constexpr (PRE_SC) {
       pre_ia = a.inv2a[e];
       pre_rate = has ? a.rate[cell] : (T)0;
       pre_seed = a.seed[ens];
@@ -1000,7 +1008,7 @@ __global__ __launch_bounds__(step_block<SCHED>()) void k_step(StepArgs<T> a, Ste
       // ---- C: advance ----
       CellConst<T>& CC = ccs[ADVANCE ? slot_id : 0];
       {
-        if constexpr (PRE) {
+        if constexpr (PRE_SC) {
 #pragma unroll
           for (int i = 0; i < NPRE; ++i) {
             const int q = li + i * G;
@@ -1046,9 +1054,9 @@ __global__ __launch_bounds__(step_block<SCHED>()) void k_step(StepArgs<T> a, Ste
         }
         lds_sync_wave();
       }
-      const double ia = PRE ? pre_ia : a.inv2a[e];
-      const T rate = PRE ? pre_rate : (has ? a.rate[cell] : (T)0);
-      const uint64_t seed = PRE ? pre_seed : a.seed[ens];
+      const double ia = PRE_SC ? pre_ia : a.inv2a[e];
+      const T rate = PRE_SC ? pre_rate : (has ? a.rate[cell] : (T)0);
+      const uint64_t seed = PRE_SC ? pre_seed : a.seed[ens];
       const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
       const bool do_mix = a.mix && (a.flags & FLAG_MIX);
       int err = 0;
