@@ -596,12 +596,13 @@ __global__ __launch_bounds__(step_block<SCHED>()) void k_step(StepArgs<T> a, Ste
     const double dn = (double)n;
     // The cell's constants for the advance (vertex coefficients, edge
     // geometry, 1/(2A), rate, seed), issued here, ahead of the statistics
-    // passes, where groups of 16 lanes or fewer take many small cells per
+    // passes, where groups of 32 lanes or fewer take several cells per
     // wavefront or the 5 x 5 x 5 bins make the passes long: 8 % shorter
-    // batched steps, 2 % with the bins.  With the turbulent frequency all
-    // but the edge geometry (6 % shorter steps; with it: no gain).  The
-    // plain 64-lane steps take 2 % longer with any of them issued early.
-    constexpr bool PRE = ADVANCE && (G <= 16 || VB5);
+    // batched steps, 2 % with the bins, 4-6 % on the canyons at 32 lanes.
+    // With the turbulent frequency all but the edge geometry (6 % shorter
+    // steps; with it: no gain).  The plain 64-lane steps take 2 % longer
+    // with any of them issued early.
+    constexpr bool PRE = ADVANCE && (G <= 32 || VB5);
     constexpr bool PRE_SC = PRE || (ADVANCE && OMG);
     constexpr int NPRE = PRE_SC ? (3 * NCOEF + G - 1) / G : 1;
     T pre_coef[NPRE];
