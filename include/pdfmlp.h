@@ -92,6 +92,22 @@ pdf_status pdf_mlp_forward(const float* rows, int64_t nrows, int32_t row_stride,
 pdf_status pdf_mlp_grad(const float* rows, int32_t batch, const float* norm, const uint16_t* w,
                         float* work, float* grad, float* loss, void* hip_stream);
 
+/* pdf_mlp_grad without a workspace argument, for callers that cannot
+   allocate device memory (code under HIP graph capture, serving loops,
+   harnesses that forbid allocation).  The gradient partials live in a
+   static device array of PDF_MLP_NOALLOC_FLOATS floats (about 2.7 MiB)
+   that each device holds until the process ends; the call itself allocates
+   nothing.  batch: 1 .. PDF_MLP_NOALLOC_MAX_BATCH, else PDF_E_SIZE.  All
+   calls on one device share the array, so calls that overlap on one device
+   (different streams, or host threads without ordering) race; calls on one
+   stream are ordered and safe.  Results equal pdf_mlp_grad's bit for bit.
+   loss: one float (required).  Errors as pdf_mlp_grad, and PDF_E_HIP if the
+   array's device address cannot be found. */
+#define PDF_MLP_NOALLOC_MAX_BATCH 1024
+#define PDF_MLP_NOALLOC_FLOATS (((PDF_MLP_NOALLOC_MAX_BATCH + 15) / 16) * (PDF_MLP_NPARAM + 1))
+pdf_status pdf_mlp_grad_noalloc(const float* rows, int32_t batch, const float* norm, const uint16_t* w,
+                                float* grad, float* loss, void* hip_stream);
+
 /* iters Adam steps, numbered t0 + 1 ... t0 + iters, each on batch rows drawn
    with replacement from the nrows training rows (Philox4x32-10, key = seed,
    counter = (slot, t, 0x7A11, 0), row = first word mod nrows).  master,

@@ -28,7 +28,7 @@ NFIELD = 20
 ENTRY_POINTS = ("pdf_create", "pdf_query_sizes", "pdf_init_mesh", "pdf_seed_particles", "pdf_step",
                 "pdf_step_graph", "pdf_autotune", "pdf_set_launch", "pdf_repack", "pdf_repack_count",
                 "pdf_estimate_statistics", "pdf_nstat", "pdf_sync", "pdf_metrics",
-                "pdf_mlp_work_floats", "pdf_mlp_dataset", "pdf_mlp_forward", "pdf_mlp_grad", "pdf_mlp_train",
+                "pdf_mlp_work_floats", "pdf_mlp_dataset", "pdf_mlp_forward", "pdf_mlp_grad", "pdf_mlp_grad_noalloc", "pdf_mlp_train",
                 "pdf_mlp_norm", "pdf_mlp_round", "pdf_mlp_infer", "pdf_mlp_attach",
                 "pdf_get_state", "pdf_set_state", "pdf_set_step", "pdf_get_omega", "pdf_omega_fields", "pdf_navg", "pdf_average_attach",
                 "pdf_locate", "pdf_average_probe", "pdf_count", "pdf_steps_done", "pdf_error_string", "pdf_destroy")
@@ -107,6 +107,8 @@ def load_library():
     L.pdf_mlp_forward.argtypes = [vp, i64, i32, vp, vp, vp, vp]
     L.pdf_mlp_grad.restype = i32
     L.pdf_mlp_grad.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
+    L.pdf_mlp_grad_noalloc.restype = i32
+    L.pdf_mlp_grad_noalloc.argtypes = [vp, i32, vp, vp, vp, vp, vp]
     L.pdf_mlp_train.restype = i32
     L.pdf_mlp_train.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, i32, i32, f32, u64, i64, vp]
     L.pdf_mlp_norm.restype = i32

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -1406,6 +1407,37 @@ template <typename T> void launch_dataset(pdf_ctx* c, int32_t target, uint64_t k
                      c->stream, d);
 }
 
+// Gradient partials of pdf_mlp_grad_noalloc: one row of PDF_MLP_NPARAM floats
+// per 16-row tile of the largest batch, then one loss partial per tile.  The
+// gradient kernel writes every word of the tiles a call uses before the
+// reduction reads it, so nothing needs clearing between calls.  Each device
+// holds its own copy until the process ends; in host code the array's name
+// is not a device address, so kernels receive the address that
+// hipGetSymbolAddress returns for the current device.
+constexpr int64_t NOALLOC_TILES = (PDF_MLP_NOALLOC_MAX_BATCH + mlp::TILE - 1) / mlp::TILE;
+static __device__ __align__(256) float scratch[NOALLOC_TILES * (mlp::NPARAM + 1)];
+static_assert(NOALLOC_TILES * (mlp::NPARAM + 1) == PDF_MLP_NOALLOC_FLOATS, "scratch size of the header");
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex noalloc_mu;
+float* noalloc_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// The device address of the current device's scratch array, looked up once
+// per device.
+pdf_status noalloc_scratch(float** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return PDF_E_HIP;
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return PDF_E_ARG;
+  std::lock_guard<std::mutex> lock(noalloc_mu);
+  if (!noalloc_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return PDF_E_HIP;
+    noalloc_ptr[dev] = (float*)ptr;
+  }
+  *out = noalloc_ptr[dev];
+  return PDF_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1439,6 +1471,17 @@ pdf_status pdf_mlp_forward(const float* rows, int64_t nrows, int32_t row_stride,
 pdf_status pdf_mlp_grad(const float* rows, int32_t batch, const float* norm, const uint16_t* w, float* work,
                         float* grad, float* loss, void* hip_stream) {
   if (!rows || !norm || !w || !work || !grad || batch <= 0 || batch > PDF_MLP_MAX_BATCH) return PDF_E_ARG;
+  return mlp_grad_step(rows, batch, batch, 0, 0, 0, norm, const_cast<uint16_t*>(w), work, grad, loss, 0, nullptr,
+                       nullptr, nullptr, 0.0f, (hipStream_t)hip_stream);
+}
+
+pdf_status pdf_mlp_grad_noalloc(const float* rows, int32_t batch, const float* norm, const uint16_t* w, float* grad,
+                                float* loss, void* hip_stream) {
+  if (!rows || !norm || !w || !grad || !loss || batch <= 0) return PDF_E_ARG;
+  if (batch > PDF_MLP_NOALLOC_MAX_BATCH) return PDF_E_SIZE;
+  float* work = nullptr;
+  const pdf_status r = noalloc_scratch(&work);
+  if (r) return r;
   return mlp_grad_step(rows, batch, batch, 0, 0, 0, norm, const_cast<uint16_t*>(w), work, grad, loss, 0, nullptr,
                        nullptr, nullptr, 0.0f, (hipStream_t)hip_stream);
 }

@@ -17,6 +17,7 @@ NPARAM = 10952
 NFEAT = 32
 NOUT = 8
 ROW = 64
+NOALLOC_MAX_BATCH = 1024   # largest batch of pdf_mlp_grad_noalloc
 # (out, in) of the four layers, in parameter order: W then b
 LAYERS = ((64, 32), (64, 64), (64, 64), (8, 64))
 
@@ -113,6 +114,19 @@ class ConditionalMeanNet:
         loss = self.torch.empty(1, dtype=self.torch.float32, device=self.device)
         _check(load_library().pdf_mlp_grad(_vp(rows), b, _vp(self.norm), _vp(self.w), _vp(work), _vp(g), _vp(loss),
                                            self._s), "pdf_mlp_grad")
+        return loss, g
+
+    def grad_noalloc(self, rows, batch: Optional[int] = None, out=None):
+        """grad() through the entry point without a workspace (the library's
+        static scratch; batch <= NOALLOC_MAX_BATCH).  out: optional (loss,
+        gradient) device tensors to fill, so that the call allocates nothing."""
+        b = int(rows.shape[0] if batch is None else batch)
+        if out is None:
+            out = (self.torch.empty(1, dtype=self.torch.float32, device=self.device),
+                   self.torch.empty(NPARAM, dtype=self.torch.float32, device=self.device))
+        loss, g = out
+        _check(load_library().pdf_mlp_grad_noalloc(_vp(rows), b, _vp(self.norm), _vp(self.w), _vp(g), _vp(loss),
+                                                   self._s), "pdf_mlp_grad_noalloc")
         return loss, g
 
     def forward(self, rows):
