@@ -4,7 +4,7 @@
  * IECM, eq. (7), relaxes each particle's scalar toward <phi|V>: the mean
  * scalar of the particles of its element whose velocity lies in the same
  * velocity bin (2 x 2 x 2 bins by the sign of each velocity fluctuation
- * about the element mean, statistics of section 2.1).  With few particles
+ * about the element mean, statistics of section 2, after eq. 7).  With few particles
  * per element the binned estimate is noisy.  These entry points train and
  * apply a small network that estimates the eight conditional means of an
  * element from its statistics, with the binned estimate as the fallback.

@@ -5,7 +5,7 @@
  * Method: Bakosi, Franzese & Boybeyi, "Joint PDF modelling of turbulent flow
  * and dispersion in an urban street canyon".  Particles carry position,
  * velocity and scalar; one step advances them by the explicit Euler-Maruyama
- * scheme (section 2.4) of
+ * scheme (closing summary of section 2.2) of
  *   eq. (5)  position: dX = U dt + (2 nu)^(1/2) dW
  *   eq. (6)  velocity: the generalized Langevin model, with the drift tensor
  *            G and C0 either from the simplified Langevin model, eq. (19),
@@ -18,7 +18,7 @@
  * tracks them through an unstructured triangular grid with wall (resolved
  * no-slip, free-slip, wall-function eqs. (20)-(26)) and periodic conditions,
  * applies the street-level source (section 3), and estimates per-element
- * statistics from the particles (sections 2.1 and 3).
+ * statistics from the particles (section 2, after eq. 7, and section 3).
  *
  * Memory: the caller owns all device memory.  pdf_query_sizes() gives the
  * size of one device arena; the caller allocates it (e.g. a torch uint8
@@ -94,7 +94,7 @@ typedef struct pdf_params {
   int32_t omega;      /* 1: particles carry the turbulent frequency of eq. (9):
                          seeded at the element's frozen <omega> (eq. 8 solved
                          at the centroid), advanced with the element's
-                         estimated <omega> and the sixth normal of the step,
+                         frozen <omega> and the sixth normal of the step,
                          reflected at zero, rescaled at wall-function walls;
                          the velocity keeps the frozen-field coefficients.
                          The record gains <omega>, <omega'^2> and eps =
@@ -149,23 +149,50 @@ pdf_status pdf_create(const pdf_params* p, void* hip_stream, pdf_ctx** out);
 /* Fill s->arena_bytes and s->slots from the sizes in s. */
 pdf_status pdf_query_sizes(const pdf_ctx* ctx, pdf_sizes* s);
 
-/* Copy the mesh and frozen fields to the device arena (caller-owned device
-   memory of arena_bytes, 256-byte aligned) and precompute the per-vertex
-   drift/diffusion coefficients and the wall-function alpha per wall edge.
-   PDF_E_MESH if an element is degenerate or clockwise. */
+/* The Eulerian grid of the method: the unstructured triangular mesh on which
+   the paper tracks particles, estimates statistics and holds the Eulerian
+   fields (closing summary of section 2.2; the meshes of section 3).  Copies
+   the host arrays of m (layout in pdf_mesh; read during the call only) and
+   the frozen per-vertex fields (PDF_NFIELD doubles per vertex) into the
+   device arena (caller-owned device memory of arena_bytes, 256-byte aligned,
+   sized by pdf_query_sizes; the context keeps the pointer, the caller keeps
+   ownership and must keep it alive) and precomputes, per vertex, the drift
+   tensor G and C0 eps of eq. (6) from eq. (19) (SLM) or eqs. (12)-(13)
+   (from wp), and per wall-function edge alpha of eqs. (22)-(26).  Waits for
+   the stream.  Errors: PDF_E_ARG (null or empty input, unaligned arena),
+   PDF_E_MESH (vertex id, neighbour or edge kind out of range; a degenerate or
+   clockwise element), PDF_E_SIZE (arena too small for the mesh), PDF_E_HIP. */
 pdf_status pdf_init_mesh(pdf_ctx* ctx, const pdf_mesh* m, void* arena, int64_t arena_bytes);
 
-/* Seed nens ensembles.  counts: host, nens x nelem particles per element;
-   seeds: host, nens Philox keys; source: host, nens x 3 (x0, y0, r0; r0 = 0
-   for no source).  Particles are placed uniformly in their element with the
-   local mean velocity plus Gaussian fluctuations of the local Reynolds stress;
-   particle ids run element-major from 0 within each ensemble.  Resets the
-   step counter.  PDF_E_SIZE if the layout does not fit the arena. */
+/* The particle representation of the joint PDF (section 2: particles stand
+   for fluid elements; section 3: particles per element, the street-level
+   source): seed nens independent ensembles.  counts: host, nens x nelem
+   int64, particles per element (ensemble-major); seeds: host, nens uint64
+   Philox keys; source: host, nens x 3 doubles (x0, y0, r0; r0 = 0: no
+   source).  All three are read during the call only.  Particles are placed
+   uniformly in their element with the interpolated mean velocity plus
+   Gaussian fluctuations with the interpolated Reynolds stress (its Cholesky
+   factor); the scalar follows pdf_params.psi_init; particle ids run
+   element-major from 0 within each ensemble.  Resets the step counter and
+   the device error word.  Waits for the stream.  Errors: PDF_E_STATE
+   (before pdf_init_mesh), PDF_E_ARG (bad count, negative r0), PDF_E_SIZE
+   (too many cells or particles, or the layout does not fit the arena),
+   PDF_E_HIP. */
 pdf_status pdf_seed_particles(pdf_ctx* ctx, int32_t nens, const int64_t* counts,
                               const uint64_t* seeds, const double* source);
 
-/* Enqueue nsteps time steps of every ensemble (asynchronous).  After a
-   device error the remaining steps do nothing and pdf_sync reports it. */
+/* One time step is the explicit Euler-Maruyama step of the particle
+   equations (closing summary of section 2.2): IECM, eq. (7), toward the
+   binned <phi|V> of the state at the start of the step, with the rate of
+   eq. (11); velocity, eq. (6) (and omega, eq. (9), if carried); position,
+   eq. (5), with the velocity at the start of the step and the same dW;
+   tracking through the grid with the wall and periodic conditions; the
+   source of section 3.  The sub-steps taken are pdf_params.flags, fixed at
+   pdf_create.  Enqueues nsteps steps of every ensemble on the context's
+   stream and returns without waiting (nsteps = 0: nothing).  After a device
+   error the remaining steps do nothing and pdf_sync reports it.  Errors:
+   PDF_E_ARG (nsteps < 0), PDF_E_STATE (before pdf_seed_particles),
+   PDF_E_HIP (launch failure). */
 pdf_status pdf_step(pdf_ctx* ctx, int32_t nsteps);
 
 /* As pdf_step, but replays a HIP graph of six consecutive steps (built on
@@ -195,7 +222,7 @@ pdf_status pdf_autotune(pdf_ctx* ctx, int32_t steps_per_trial, int32_t* group, i
    conditional means as a separate pass. */
 pdf_status pdf_set_launch(pdf_ctx* ctx, int32_t group, int32_t persist);
 
-/* Re-sort by element (the particle-in-cell bookkeeping of section 2.4).
+/* Re-sort by element (the particle-in-cell bookkeeping of the closing summary of section 2.2).
    Each element cell owns a segment of the particle buffers, sized at seeding
    from its initial count: ceil(slack n0) + 32 slots.  Particles stay in
    their cell's segment or are appended to their new cell's segment, so the
@@ -216,11 +243,17 @@ pdf_status pdf_set_launch(pdf_ctx* ctx, int32_t group, int32_t persist);
 pdf_status pdf_repack(pdf_ctx* ctx);
 int64_t pdf_repack_count(pdf_ctx* ctx);
 
-/* Estimate the statistics of the current state into out: nens x nelem x
-   nstat doubles (nstat = PDF_NSTAT_2 or PDF_NSTAT_4, plus hist_bins, plus 3
-   with the turbulent frequency: <omega>, <omega'^2>, eps, after the
-   histogram, plus 250 with 5 x 5 x 5 velocity bins).
-   out_on_host: 1 -> out is host memory and the call waits; 0 -> device. */
+/* Particle-in-cell estimation (section 2, after eq. 7: Eulerian statistics
+   as ensemble averages over the particles of each grid element; section 3:
+   the statistics and the <phi|V> bins the paper reports): the statistics of
+   the current state into out, nens x nelem x nstat doubles, one record per
+   (ensemble, element) in the PDF_ST_* layout (nstat = PDF_NSTAT_2 or
+   PDF_NSTAT_4, plus hist_bins, plus 3 with the turbulent frequency: <omega>,
+   <omega'^2>, eps, after the histogram, plus 250 with 5 x 5 x 5 velocity
+   bins); averages use 1/n, an empty element has count 0 and zero moments.
+   out_on_host: 1 -> out is host memory and the call waits; 0 -> out is
+   device memory and the call is asynchronous.  out is caller-owned.
+   Errors: PDF_E_ARG (null out), PDF_E_STATE (before seeding), PDF_E_HIP. */
 pdf_status pdf_estimate_statistics(pdf_ctx* ctx, double* out, int32_t out_on_host);
 
 /* Run metrics from the device counters, into out (8 int64, host; waits):

@@ -1,0 +1,84 @@
+"""Mutation sweep of the oracle's pins (CPU only).
+
+Each entry plants one plausible mistake in a copy of ``orc.cpp`` (a dropped
+term, a wrong sign, a swapped index, a transposed operand), builds that copy
+to a temporary library and runs the pin tests against it through the
+ORC_LIB override of ``oracle/__init__.py``.  A pin set is adequate when every
+mutant fails at least one test.  Run: ``python oracle/mutation_sweep.py``
+(a few minutes; prints one line per mutant and exits 1 if any survives).
+"""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+import tempfile
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+sys.path.insert(0, ROOT)
+from oracle import CFLAGS, SRC  # noqa: E402
+
+PINS = ["tests/test_oracle_pins.py", "tests/test_oracle_physics.py", "tests/test_oracle_geometry.py"]
+
+# (name, [(original text, planted text), ...])
+MUTANTS = [
+    ("sign of the mean pressure gradient (eq. 6)",
+     [("T au = (-f[C_DPDX] + nu2 * f[C_LAPU])", "T au = (f[C_DPDX] + nu2 * f[C_LAPU])")]),
+    ("swapped barycentric weights",
+     [("lam[0] = orient_edge(c, e, 1, px, py) * ia;\n  lam[1] = orient_edge(c, e, 2, px, py) * ia;",
+       "lam[0] = orient_edge(c, e, 2, px, py) * ia;\n  lam[1] = orient_edge(c, e, 1, px, py) * ia;")]),
+    ("nu in place of 2 nu in the viscous drift",
+     [("T au = (-f[C_DPDX] + nu2 * f[C_LAPU])", "T au = (-f[C_DPDX] + (T)p.nu * f[C_LAPU])")]),
+    ("transposed velocity gradient in the laminar noise",
+     [("s2nu * (f[C_DUDX] * dW1 + f[C_DUDY] * dW2)", "s2nu * (f[C_DUDX] * dW1 + f[C_DVDX] * dW2)"),
+      ("s2nu * (f[C_DVDX] * dW1 + f[C_DVDY] * dW2)", "s2nu * (f[C_DUDY] * dW1 + f[C_DVDY] * dW2)")]),
+    ("position and velocity with independent molecular increments",
+     [("T xn = (x + u * dt) + s2nu * dW1;", "T xn = (x + u * dt) + s2nu * dWp1;")]),
+    ("r0 in place of r0^2 in eq. (11)",
+     [("newton_cbrt(r0 * r0 / eps)", "newton_cbrt(r0 / eps)")]),
+    ("dropped C_t in eq. (11)",
+     [("first = first + p.Ct * dist / Uc;", "first = first + dist / Uc;")]),
+    ("minimum in place of maximum in the plateau of eq. (11)",
+     [("std::max(k / eps, p.CT * std::sqrt(p.nu / eps))", "std::min(k / eps, p.CT * std::sqrt(p.nu / eps))")]),
+    ("wrong L21 of the Cholesky factor",
+     [("double L21 = R12 / L11;", "double L21 = R12 / std::sqrt(R22);")]),
+    ("sign of the gamma_tau test (eq. 26)",
+     [("double gamma_tau = prod > 0.0 ? 1.0 : 0.0;", "double gamma_tau = prod < 0.0 ? 1.0 : 0.0;")]),
+    ("y_p dP/dx without its absolute value (eq. 25)",
+     [("gamma_tau * std::fabs(p.yp * dPdx)", "gamma_tau * (p.yp * dPdx)")]),
+    ("<U>_p^2 in place of <U>_p |<U>_p| (eq. 22)",
+     [("Up * std::fabs(Up)", "Up * Up")]),
+]
+
+
+def run_one(name, edits, tmp):
+    src = open(SRC).read()
+    for old, new in edits:
+        if src.count(old) != 1:
+            raise RuntimeError(f"{name}: the text to mutate occurs {src.count(old)} times")
+        src = src.replace(old, new)
+    cpp = os.path.join(tmp, "orc_mut.cpp")
+    lib = os.path.join(tmp, "liborc_mut.so")
+    with open(cpp, "w") as f:
+        f.write(src)
+    subprocess.run(["g++", *CFLAGS, "-I", HERE, "-o", lib, cpp], check=True)
+    env = dict(os.environ, ORC_LIB=lib)
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", *PINS],
+                       cwd=ROOT, env=env, capture_output=True, text=True)
+    failed = [ln.split(" ")[1] for ln in r.stdout.splitlines() if ln.startswith("FAILED")]
+    return r.returncode != 0, failed
+
+
+def main() -> int:
+    survivors = 0
+    with tempfile.TemporaryDirectory() as tmp:
+        for name, edits in MUTANTS:
+            caught, failed = run_one(name, edits, tmp)
+            survivors += 0 if caught else 1
+            print(f"{'caught  ' if caught else 'SURVIVED'} {name}: {failed[0] if failed else '-'}", flush=True)
+    return 1 if survivors else 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

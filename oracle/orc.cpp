@@ -421,7 +421,7 @@ void build_omega(orc_ctx* c) {
 }
 
 // ---------------------------------------------------------------------------
-// particle tracking (section 2.4: the grid is used to track particles)
+// particle tracking (closing summary of section 2.2: the grid is used to track particles)
 //
 // Straight-line neighbour walk from the start point S (inside the current
 // element) toward the target T.  Exit edge: the first edge (lowest local
@@ -598,7 +598,7 @@ template <typename T> void seed_ensemble(orc_ctx* c, Ens<T>& en, uint32_t ens_in
 
 // ---------------------------------------------------------------------------
 // statistics: ensemble averages per element over the particles it contains
-// (sections 2.1, 2.4, 3): count, means, central moments, velocity-binned
+// (section 2, the closing summary of section 2.2, section 3): count, means, central moments, velocity-binned
 // conditional scalar means and the scalar histogram.  Two passes: means
 // first, then moments and bins relative to those means.  Sums run over the
 // element's particles in particle-id order.
@@ -747,7 +747,7 @@ template <typename T> void estimate(const orc_ctx* c, const Ens<T>& en, std::vec
 }
 
 // ---------------------------------------------------------------------------
-// one time step of one ensemble: explicit Euler-Maruyama (section 2.4) of the
+// one time step of one ensemble: explicit Euler-Maruyama (closing summary of section 2.2) of the
 // position (eq. 5), velocity (eq. 6) and scalar (eq. 7) equations.  Every
 // right-hand side uses the state at the start of the step; the statistics are
 // those of that state.
@@ -769,7 +769,7 @@ template <typename T> int advance(orc_ctx* c, Ens<T>& en, uint32_t ens_index, ui
     T xi[8];
     step_normals<T>(en.seed, (uint32_t)i, step, ens_index, xi);
     // Eulerian statistics at the particle location: linear interpolation of
-    // the frozen vertex fields (section 2.1)
+    // the frozen vertex fields (section 2, after eq. 7)
     double lam[3];
     barycentric(c, e, (double)en.x[i], (double)en.y[i], lam);
     T l0 = (T)lam[0], l1 = (T)lam[1], l2 = (T)lam[2];

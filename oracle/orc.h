@@ -14,7 +14,7 @@
  * predicates and all statistics are double in both modes.
  *
  * Paper: Bakosi, Franzese & Boybeyi, "Joint PDF modelling of turbulent flow
- * and dispersion in an urban street canyon" -- sections 2.1-2.4, eqs. (5)-(13),
+ * and dispersion in an urban street canyon" -- section 2 with sections 2.1-2.2, eqs. (5)-(13),
  * (19)-(26), section 3.
  */
 #ifndef PDF_ORACLE_H

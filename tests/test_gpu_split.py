@@ -2,7 +2,7 @@
 ensembles of uneven size, whose cells of at most eight particles at seeding
 step in a launch of their own at 4 lanes per cell (16 cells per wavefront),
 with fourth moments and histograms, with the 5 x 5 x 5 velocity bins and with
-the turbulent frequency (section 2.1, section 3).
+the turbulent frequency (section 2, section 3).
 
 Bars as in the other parity tests: position, velocity and element bit-exact
 for every ensemble; the statistics of the GPU's own state within 1e-5

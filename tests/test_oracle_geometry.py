@@ -1,4 +1,4 @@
-"""Pins of the oracle's particle tracking (section 2.4: the grid tracks the
+"""Pins of the oracle's particle tracking (closing summary of section 2.2: the grid tracks the
 particles) and boundary conditions, against brute force and closed forms."""
 import numpy as np
 import pytest

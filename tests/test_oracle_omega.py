@@ -267,3 +267,28 @@ def test_resolved_walls_and_periodic_seams_keep_frequency():
         r, tt, v2, nref, om = orc.walk(e, s, t, rng.normal(size=3), om=1.7)
         assert r >= 0
         assert om == 1.7
+
+
+def test_omega_stays_bounded_over_1000_steps_on_the_large_wall_function_canyon():
+    """The large wall-function canyon (the 10M-particle workload's mesh and
+    fields, here at 5 particles per element) keeps every particle's omega
+    finite and within a bounded factor of the frozen <omega> over 1000 steps.
+    The wall condition (eqs. 27-28) multiplies omega by exp(beta V_I /
+    (y_p <omega>)) per hit; the fields are built so that the statistics at
+    y_p are those of a log layer (|alpha| <= 2 on every wall edge), without
+    which alpha up to 17 pumped tangential speed that a corner turned into
+    wall-normal speed, and single hits grew omega by e^5 - e^10."""
+    wl = W.config3w(steps=1000, n=5 * 48618)
+    orc = O.Oracle(wl)
+    al = orc.wall_alpha()
+    assert np.abs(al).max() <= 2.0 + 1e-9
+    om0, _, _ = orc.omega_fields()
+    worst = 0.0
+    for _ in range(10):
+        orc.step(100)
+        om = orc.omega()
+        e = orc.state()["elem"]
+        assert np.isfinite(om).all() and (om >= 0).all()
+        worst = max(worst, float((om / om0[e]).max()))
+    assert worst < 1e3, worst
+    assert orc.wallfn_hits() > 10000

@@ -1,5 +1,5 @@
 """Pin of the oracle's particle-in-cell estimation (ensemble averages per
-element, sections 2.1 and 3) against numpy / math.fsum on the same state."""
+element, section 2 and section 3) against numpy / math.fsum on the same state."""
 import itertools
 import math
 

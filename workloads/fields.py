@@ -2,7 +2,7 @@
 
 In the paper the mean velocity, mean pressure, Reynolds stresses, dissipation
 and the elliptic-relaxation tensor come from Eulerian finite-element solves
-(section 2.2, eq. (14); section 2.4 summary).  Those solvers are outside the
+(section 2.1, eq. (14); the closing summary of section 2.2).  Those solvers are outside the
 particle step, so every workload here freezes smooth synthetic fields instead.
 The particle method reads them at vertices and interpolates linearly.
 
@@ -142,6 +142,87 @@ def _stresses(x, y, dUdy, g, k0=0.002, k1=0.02, sk=0.25):
     return R11, R22, R33, R12, eps, k
 
 
+# near-wall recipe of the wall-function canyon
+WALL_BLEND = 0.05          # distance over which the wall statistics take over
+LOG_KAPPA, LOG_E, LOG_CMU = 0.41, 8.5, 0.09
+
+
+def _log_law_uhat(Ut, yp, nu):
+    """u_hat with |Ut| = (u_hat / kappa) ln(E yp u_hat / nu), by bisection on
+    ln u_hat (the right-hand side grows with u_hat above nu / (E yp));
+    floored where |Ut| is too small for a root."""
+    lo = np.full(Ut.shape, np.log(1.001 * nu / (LOG_E * yp)))
+    hi = np.full(Ut.shape, np.log(10.0))
+    target = np.abs(Ut)
+    for _ in range(80):
+        mid = 0.5 * (lo + hi)
+        u = np.exp(mid)
+        f = u / LOG_KAPPA * np.log(LOG_E * yp * u / nu)
+        lo = np.where(f < target, mid, lo)
+        hi = np.where(f < target, hi, mid)
+    return np.exp(0.5 * (lo + hi))
+
+
+def _stripped_walls(geo):
+    """The wall-function walls of a stripped canyon: (a, b, inward normal)."""
+    yp_r = geo.y_roof
+    return [((geo.x_l, geo.y_street), (geo.x_r, geo.y_street), (0.0, 1.0)),
+            ((geo.x_l, geo.y_street), (geo.x_l, yp_r), (1.0, 0.0)),
+            ((geo.x_r, geo.y_street), (geo.x_r, yp_r), (-1.0, 0.0)),
+            ((0.0, yp_r), (geo.x_l, yp_r), (0.0, 1.0)),
+            ((geo.x_r, yp_r), (geo.Lx, yp_r), (0.0, 1.0))]
+
+
+def _wall_stresses(px, py, vel_at, base, geo, yp, nu):
+    """Stresses blended toward log-law equilibrium at the stripped walls.
+
+    At a wall-function wall the statistics at y_p should be those of an
+    equilibrium log layer: with the tangential mean velocity U_t at the
+    nearest point of the wall,
+    u_hat from the log law, k = u_hat^2 / C_mu^(1/2), wall-normal variance
+    u_hat^2 (so that alpha of the wall condition is 2 in the absence of a
+    pressure-gradient correction), shear stress -tanh(U_t / 0.05) C_mu^(1/2) k;
+    u_hat is at least half the base flow's C_mu^(1/4) k^(1/2).
+    Each wall i contributes its target with weight (1 - s_i / WALL_BLEND)^2
+    (s_i the distance to it); the base stresses keep the remaining weight
+    (targets only, normalised, where the weights sum past 1)."""
+    R11, R22, R33, R12 = base
+    acc = np.zeros((4, len(px)))
+    wsum = np.zeros(len(px))
+    for (ax, ay), (bx, by), (nx, ny) in _stripped_walls(geo):
+        for sh in (-geo.Lx, 0.0, geo.Lx):
+            qx = px + sh
+            dx, dy = bx - ax, by - ay
+            t = np.clip(((qx - ax) * dx + (py - ay) * dy) / (dx * dx + dy * dy), 0.0, 1.0)
+            s = np.hypot(qx - (ax + t * dx), py - (ay + t * dy))
+            w = np.maximum(0.0, 1.0 - s / WALL_BLEND) ** 2
+            if not (w > 0).any():
+                continue
+            tx, ty = ny, -nx                       # wall tangent
+            # the tangential mean velocity at the wall point nearest to p
+            U, V = vel_at(ax + t * dx - sh, ay + t * dy)
+            Ut = U * tx + V * ty
+            # where the tangential velocity is too small for a log layer
+            # (corners) u_hat keeps half the base flow's value: alpha < 2 there
+            uh = np.maximum(_log_law_uhat(Ut, yp, nu), LOG_CMU ** 0.25 * np.sqrt(0.5 * (R11 + R22 + R33)))
+            k = uh * uh / np.sqrt(LOG_CMU)
+            Rnn = uh * uh
+            Rzz = 0.55 * k
+            Rtt = 2.0 * k - Rnn - Rzz
+            # a smooth sign: the mean pressure gradient differentiates the stresses
+            Rtn = -np.tanh(Ut / 0.05) * np.sqrt(LOG_CMU) * k
+            # back to (x, y): R = Rtt t t^T + Rnn n n^T + Rtn (t n^T + n t^T)
+            r11 = Rtt * tx * tx + Rnn * nx * nx + 2 * Rtn * tx * nx
+            r22 = Rtt * ty * ty + Rnn * ny * ny + 2 * Rtn * ty * ny
+            r12 = Rtt * tx * ty + Rnn * nx * ny + Rtn * (tx * ny + nx * ty)
+            acc += w * np.stack([r11, r22, Rzz, r12])
+            wsum += w
+    keep = np.maximum(0.0, 1.0 - wsum)
+    norm = np.maximum(1.0, wsum)
+    out = [(keep * b + a) / norm for b, a in zip((R11, R22, R33, R12), acc)]
+    return out
+
+
 def canyon_fields(mesh, nu: float = 1.0 / 12000.0, with_stats: bool = False):
     """Synthetic frozen fields for a street-canyon mesh (full or stripped)."""
     g = dict(Lx=2.0, x_l=0.5, x_r=1.5, y_street=0.0, y_roof=1.0)
@@ -155,11 +236,22 @@ def canyon_fields(mesh, nu: float = 1.0 / 12000.0, with_stats: bool = False):
     mv = _mean_velocity(xy, flow)
     U, V, dUdx, dUdy, dVdx, dVdy, lapU, lapV = mv.T
 
+    wallfn = geo is not None and geo.wallfn
+
     def stress_at(px, py):
         m = _mean_velocity(np.stack([px, py], axis=1), flow)
-        return _stresses(px, py, m[:, 3], g)
+        R11, R22, R33, R12, eps, k = _stresses(px, py, m[:, 3], g)
+        if wallfn:
+            # log-law equilibrium at the wall-function walls; eps from the new k
+            def vel_at(qx, qy):
+                w = _mean_velocity(np.stack([qx, qy], axis=1), flow)
+                return w[:, 0], w[:, 1]
+            R11, R22, R33, R12 = _wall_stresses(px, py, vel_at, (R11, R22, R33, R12), geo, geo.y_street, nu)
+            k = 0.5 * (R11 + R22 + R33)
+            eps = k ** 1.5 / np.maximum(0.41 * _wall_distance(px, py, g), 0.02)
+        return R11, R22, R33, R12, eps, k
 
-    R11, R22, R33, R12, eps, k = _stresses(x, y, dUdy, g)
+    R11, R22, R33, R12, eps, k = stress_at(x, y)
     h = 1e-6
     dR11dx = (stress_at(x + h, y)[0] - stress_at(x - h, y)[0]) / (2 * h)
     dR12dx = (stress_at(x + h, y)[3] - stress_at(x - h, y)[3]) / (2 * h)

@@ -239,7 +239,7 @@ class CanyonGeometry:
 
     The full-resolution domain is ([0,Lx] x [y_roof,y_top]) U ([x_l,x_r] x
     [y_street,y_roof]).  The wall-function variant strips a layer of
-    thickness yp off every no-slip wall (section 2.3 and the wall-function
+    thickness yp off every no-slip wall (section 2.2 and the wall-function
     mesh of section 3, which excludes y+ < 30).
     """
     Lx: float = 2.0
