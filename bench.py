@@ -36,10 +36,8 @@ WORKLOADS = {
 }
 
 
-# Workloads timed over fewer steps than asked for: on the frozen synthetic
-# fields the wall-function condition on the turbulent frequency is not in
-# balance and near-wall frequencies grow without bound over 10^3 steps.
-MAX_STEPS = {"canyon10m_omega": 200}
+# Workloads whose configuration fixes the step count (the square case: 100 steps).
+FIXED_STEPS = {"square40k": 100}
 
 
 def kernel_source_hash() -> str:
@@ -72,6 +70,36 @@ def algorithmic_bytes(wl) -> dict:
     n = wl.n_total
     total = n * per_particle + ncell * per_cell + per_mesh
     return dict(per_particle=per_particle, per_cell=per_cell, per_step=total, particles=n)
+
+
+def survey_bytes(wl) -> dict:
+    """The scope table's algorithmic bytes per particle-step: one read of the
+    particle state (x y u v w psi, element, id, and omega when carried), one write of
+    its mutable part (x y u v w psi, element, and omega), one re-read of the
+    statistics inputs (u v w psi, element, and omega); per element cell and
+    mesh the same amortised terms as the design count."""
+    ts = 4 if wl.precision == "f32" else 8
+    om = 1 if getattr(wl, "omega", False) else 0
+    # read: 6 (+1) state values, element and id; write: 6 (+1) values and the
+    # element; re-read: u v w psi (+omega) and the element (f32: 32 + 28 + 20)
+    per_particle = ((6 + om) * ts + 8) + ((6 + om) * ts + 4) + ((4 + om) * ts + 4)
+    d = algorithmic_bytes(wl)
+    n = wl.n_total
+    amort = d["per_step"] - n * d["per_particle"]
+    return dict(per_particle=per_particle, per_step=n * per_particle + amort,
+                per_particle_with_amortised=round((n * per_particle + amort) / max(1, n), 2))
+
+
+def host_cpu() -> dict:
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"host_cpus": os.cpu_count(), "cpu_model": model}
 
 
 def read_profile(kind: str, workload: str, src_hash: str) -> dict:
@@ -115,6 +143,8 @@ def cpu_baseline(wl_fn, seconds: float = 15.0) -> dict:
     """The oracle on the host cores, on a bounded sample of the same workload:
     the full particle set, as many whole steps as fit in about `seconds`."""
     import oracle as O
+    # the GPU box allots 16 host CPUs to a one-GPU job, whatever os.cpu_count()
+    # reports there; on a smaller host all of its cores
     threads = min(16, os.cpu_count() or 1)
     wl = wl_fn()
     orc = O.Oracle(wl, threads=threads)
@@ -129,7 +159,9 @@ def cpu_baseline(wl_fn, seconds: float = 15.0) -> dict:
             break
     n = wl.n_total
     res = {"value": n * steps / el, "unit": "particle-steps/s", "cores": threads, "kind": "oracle",
-           "sample": f"{wl.name}: all {n} particles, {steps} steps after one untimed step, {el:.1f} s"}
+           "sample": f"{wl.name}: all {n} particles, {steps} steps after one untimed step, {el:.1f} s",
+           "threads_note": "OpenMP threads = min(16, host CPUs): a one-GPU job is allotted 16 host CPUs",
+           **host_cpu()}
     # one host thread on the same state, a few seconds
     O.lib().orc_set_threads(1)
     orc.step(1)
@@ -190,15 +222,21 @@ def learned_leg(torch, W, Simulation) -> dict:
     sim = Simulation.from_workload(W.config5(ppe=4000, seed=101), device="cuda:0")
     sim.step_graph(spin)
     r20, r500 = [], []
+    sizes = (20, 40, 80, 160, 320, 500, 1000)
+    rsz = {t: [] for t in sizes}
     for k in range(snaps):
         if k:
             sim.step_graph(every)
         r20.append(PM.dataset(sim, target=20, key=5555, draw=k))
         r500.append(PM.dataset(sim, target=500, key=6666, draw=k))
+        for t in sizes:
+            rsz[t].append(PM.dataset(sim, target=t, key=7777 + t, draw=k))
     sim.sync()
     sim.close()
     r20 = torch.cat(r20)
     r500 = torch.cat(r500)
+    plain_by_size = {t: PM.estimate_error(torch.cat(rsz[t])) for t in sizes}
+    del rsz
     rec = PM.records_from_rows(r20)
     cm, _ = net.infer(rec)
     domain = (r20[:, 0] > 0) & (r20[:, 31] > 1e-4)
@@ -237,12 +275,43 @@ def learned_leg(torch, W, Simulation) -> dict:
     lm.detach()
     sim.close()
     n, E = wl.n_total, wl.mesh.nelem
+    # the subsample size at which the plain binned estimate reaches the
+    # learned estimate's error (log-log interpolation between measured sizes)
+    import math
+    eq_ppe = None
+    le = err["learned_20"]
+    for a, b in zip(sizes[:-1], sizes[1:]):
+        ea, eb = plain_by_size[a], plain_by_size[b]
+        if ea >= le >= eb:
+            f = (math.log(ea) - math.log(le)) / max(1e-30, math.log(ea) - math.log(eb))
+            eq_ppe = round(math.exp(math.log(a) + f * (math.log(b) - math.log(a))), 1)
+            break
+    eq_res = None
+    if eq_ppe is not None:
+        # the plain step at that count on the same mesh, next to the learned step at 20
+        wq = W.config5(ppe=int(round(eq_ppe)), seed=101, target=50000)
+        sq = Simulation.from_workload(wq, device="cuda:0")
+        shq = sq.autotune(steps_per_trial=8)
+        sq.step_graph(20)
+        sq.sync()
+        t0 = time.perf_counter()
+        sq.step_graph(steps)
+        sq.sync()
+        eq_s = time.perf_counter() - t0
+        sq.close()
+        eq_res = {"ppe": int(round(eq_ppe)), "particles": wq.n_total, "lanes_per_cell": shq[0],
+                  "ms_per_step": round(1e3 * eq_s / steps, 5), "value": round(wq.n_total * steps / eq_s, 1),
+                  "learned_20ppe_ms_per_step": round(1e3 * mlp_s / steps, 5),
+                  "learned_faster_by": round(eq_s / mlp_s, 4)}
     res = {
         "error_metric": "population-weighted RMS of <phi|V> over (element, bin) against 4000 particles/element",
         "error_plain_20ppe": round(err["plain_20"], 6), "error_learned_20ppe": round(err["learned_20"], 6),
         "error_plain_500ppe": round(err["plain_500"], 6),
         "learned_vs_plain20": round(err["learned_20"] / err["plain_20"], 4),
         "learned_vs_plain500": round(err["learned_20"] / err["plain_500"], 4),
+        "error_plain_by_ppe": {str(t): round(v, 6) for t, v in plain_by_size.items()},
+        "plain_ppe_with_learned_error": eq_ppe,
+        "equal_error_step": eq_res,
         "elements_with_scalar_spread": n_domain,
         "served_fraction_with_scalar_spread": round(served_frac, 4),
         "train": {"rows": nrows, "iters": iters, "batch": batch, "ms": round(train_ms, 2),
@@ -251,7 +320,6 @@ def learned_leg(torch, W, Simulation) -> dict:
                     "lanes_per_cell": in_step_shape[0],
                     "value": round(n * steps / mlp_s, 1), "ms_per_step": round(1e3 * mlp_s / steps, 5),
                     "plain_value": round(n * steps / plain_s, 1),
-                    "ppe500_equivalent_value": round(500 * E * steps / mlp_s, 1),
                     "served_fraction_with_scalar_spread": round(inloop_served, 4)},
         "seconds": round(time.perf_counter() - t_start, 1),
     }
@@ -267,7 +335,7 @@ def main() -> int:
     ap.add_argument("--workload", default="canyon1m", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--secondary", default="canyon10m,batched64,canyon10m_omega,canyon10m_bins5",
+    ap.add_argument("--secondary", default="canyon10m,batched64,canyon10m_omega,canyon10m_bins5,square40k",
                     help="further workloads reported in the same line, comma separated ('' for none)")
     ap.add_argument("--secondary-steps", type=int, default=1000)
     ap.add_argument("--repeats", type=int, default=5,
@@ -350,6 +418,10 @@ def main() -> int:
             step_fn(steps)
             torch.cuda.synchronize()
             rep_ms.append(1e3 * (time.perf_counter() - ta) / steps)
+        # the step kernels' own time, from HIP events around each step's
+        # kernels on the simulation's stream (eager steps, same state)
+        timed_steps = min(steps, 200)
+        kern_ms = sim.step_timed(timed_steps) / timed_steps
         repacks = sim.repacks()
         metrics = sim.metrics()
         # the same steps with time averaging on (one merge launch per step)
@@ -363,18 +435,29 @@ def main() -> int:
         avg_wall = time.perf_counter() - t2
         sim.average_detach()
         wall = t1 - t0
-        kern_ms = e0.elapsed_time(e1) / steps
+        graph_ms = e0.elapsed_time(e1) / steps
         ab = algorithmic_bytes(wl)
-        achieved = ab["per_step"] / (kern_ms * 1e-3) / 1e9
+        sb = survey_bytes(wl)
+        achieved = sb["per_step"] / (kern_ms * 1e-3) / 1e9
+        achieved_design = ab["per_step"] / (kern_ms * 1e-3) / 1e9
         traffic = read_traffic(name, src_hash)
         res = {
             "value": wl.n_total * steps / wall,
             "ms_per_step": 1e3 * wall / steps,
             "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                         "kernel": "k_step", "kernel_ms": round(kern_ms, 5),
-                         "algorithmic_bytes_per_step": ab["per_step"],
-                         "algorithmic_bytes_per_particle": ab["per_particle"],
+                         "kernel": "step kernels (k_step, k_walk)", "kernel_ms": round(kern_ms, 5),
+                         "kernel_ms_source": f"HIP events around each step's kernels, {timed_steps} eager steps",
+                         "graph_ms_per_step": round(graph_ms, 5),
+                         "algorithmic_bytes": "scope table: state read + mutable write + statistics re-read "
+                                              "per particle, plus amortised cell and mesh terms",
+                         "algorithmic_bytes_per_step": sb["per_step"],
+                         "algorithmic_bytes_per_particle": sb["per_particle"],
+                         "design_bytes": {"per_particle": ab["per_particle"], "per_step": ab["per_step"],
+                                          "achieved": round(achieved_design, 1),
+                                          "frac": round(achieved_design / HBM_PEAK_GBS, 4),
+                                          "note": "one state read and one write; estimation is fused with "
+                                                  "the advance, so there is no separate re-read"},
                          "valu_issue": valu_issue(name, kern_ms)},
             "config": {"workload": WORKLOADS[name][1], "preset": name, "particles": wl.n_total,
                        "elements": wl.mesh.nelem, "vertices": wl.mesh.nvert, "ensembles": wl.nens,
@@ -419,7 +502,7 @@ def main() -> int:
         "roofline": main_res["roofline"],
     }
     for name in [w for w in args.secondary.split(",") if w and w != args.workload]:
-        sec_steps = min(args.secondary_steps, MAX_STEPS.get(name, args.secondary_steps))
+        sec_steps = FIXED_STEPS.get(name, args.secondary_steps)
         sec = run(name, sec_steps, max(5, args.warmup // 2))
         out.setdefault("secondary", {})[name] = {
             "value": round(sec["value"], 1), "unit": "particle-steps/s", "steps": sec_steps,

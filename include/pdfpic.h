@@ -195,6 +195,15 @@ pdf_status pdf_seed_particles(pdf_ctx* ctx, int32_t nens, const int64_t* counts,
    PDF_E_HIP (launch failure). */
 pdf_status pdf_step(pdf_ctx* ctx, int32_t nsteps);
 
+/* As pdf_step, timing each step's kernels: HIP events recorded on the
+   context's stream immediately before and after the kernels of every step
+   (the step kernel, the crossing-particle kernel and, when the order is
+   split, the small cells' launch; not the capacity checks, which run every
+   sixth step).  Waits for the stream and writes the summed event time of the
+   nsteps steps, in milliseconds, to *kernel_ms (host).  Results are those of
+   pdf_step.  Errors as pdf_step, and PDF_E_ARG for a null kernel_ms. */
+pdf_status pdf_step_timed(pdf_ctx* ctx, int32_t nsteps, double* kernel_ms);
+
 /* As pdf_step, but replays a HIP graph of six consecutive steps (built on
    first use for the current launch shape, from kernel nodes only); the
    leading and trailing steps that do not fill a graph are launched
@@ -285,8 +294,11 @@ pdf_status pdf_get_state(pdf_ctx* ctx, int32_t ens, double* xyuvwpsi, int32_t* e
    not checked against their elements.  Waits for the stream.  Errors, with
    the state left unchanged: PDF_E_ARG for an element index out of range,
    PDF_E_CAPACITY when an element's particles exceed its segment (create the
-   context with a larger slack).  On success the device error word is
-   cleared: a restored state steps again. */
+   context with a larger slack).  On success the ensemble's counters are
+   rebuilt from elem.  After a device error every ensemble's state is void
+   (steps that returned early wrote nothing): the device error word is
+   cleared, and the context steps again, once every ensemble has been
+   restored since the error; until then pdf_sync keeps reporting it. */
 pdf_status pdf_set_state(pdf_ctx* ctx, int32_t ens, const double* xyuvwpsi, const int32_t* elem, const double* om);
 
 /* Set the Philox step word of the next step (0 <= step < 2^32 - 1): with

@@ -26,7 +26,7 @@ NFIELD = 20
 
 # exported entry points (the declarations of include/pdfpic.h)
 ENTRY_POINTS = ("pdf_create", "pdf_query_sizes", "pdf_init_mesh", "pdf_seed_particles", "pdf_step",
-                "pdf_step_graph", "pdf_autotune", "pdf_set_launch", "pdf_repack", "pdf_repack_count",
+                "pdf_step_graph", "pdf_step_timed", "pdf_autotune", "pdf_set_launch", "pdf_repack", "pdf_repack_count",
                 "pdf_estimate_statistics", "pdf_nstat", "pdf_sync", "pdf_metrics",
                 "pdf_mlp_work_floats", "pdf_mlp_dataset", "pdf_mlp_forward", "pdf_mlp_grad", "pdf_mlp_grad_noalloc", "pdf_mlp_train",
                 "pdf_mlp_norm", "pdf_mlp_round", "pdf_mlp_infer", "pdf_mlp_attach",
@@ -94,6 +94,8 @@ def load_library():
     L.pdf_step.argtypes = [vp, i32]
     L.pdf_step_graph.restype = i32
     L.pdf_step_graph.argtypes = [vp, i32]
+    L.pdf_step_timed.restype = i32
+    L.pdf_step_timed.argtypes = [vp, i32, P(ctypes.c_double)]
     L.pdf_autotune.restype = i32
     L.pdf_autotune.argtypes = [vp, i32, P(i32), P(i32)]
     L.pdf_set_launch.restype = i32
@@ -267,6 +269,13 @@ class Simulation:
     # -- the C ABI, call for call -------------------------------------------------
     def step(self, n: int = 1) -> None:
         self._check(load_library().pdf_step(self.ctx, int(n)), "pdf_step")
+
+    def step_timed(self, n: int = 1) -> float:
+        """As step(), returning the summed HIP-event time of the n steps'
+        kernels in milliseconds (waits)."""
+        ms = ctypes.c_double(0.0)
+        self._check(load_library().pdf_step_timed(self.ctx, int(n), ctypes.byref(ms)), "pdf_step_timed")
+        return ms.value
 
     def step_graph(self, n: int = 1) -> None:
         """As step(), replaying a HIP graph of six steps."""

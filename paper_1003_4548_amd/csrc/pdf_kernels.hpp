@@ -1721,12 +1721,17 @@ __global__ void k_set_step(Ctl* ctl, uint32_t step) {
   if (threadIdx.x == 0 && blockIdx.x == 0) ctl->step_base = step;
 }
 
-// After a restore the state is valid again: the error word and the overflow
-// count start over.
-__global__ void k_clear_error(Ctl* ctl) {
+// After a restore: the persistent scheduler's work counters start over (a
+// step that returned early after an error left them unreset) and, once
+// every ensemble has been restored, the error word and the overflow count.
+__global__ void k_restore_ctl(Ctl* ctl, int clear_error) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
-    ctl->error = 0;
-    ctl->ovf = 0;
+    ctl->next[0] = 0;
+    ctl->next[1] = 0;
+    if (clear_error) {
+      ctl->error = 0;
+      ctl->ovf = 0;
+    }
   }
 }
 

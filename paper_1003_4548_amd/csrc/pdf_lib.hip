@@ -150,6 +150,10 @@ struct pdf_ctx {
   std::vector<uint64_t> h_seed;
   std::vector<double> h_src;
   std::vector<int64_t> ens_count;
+  // after a device error: the ensembles not yet restored (the error word
+  // stays set until every one is, since the steps that returned early left
+  // every ensemble's particles and counters void)
+  std::vector<uint8_t> restore_pending;
   std::string err;
   pdf_status last = PDF_OK;
 };
@@ -713,7 +717,9 @@ template <typename T> pdf_status build_graph_t(pdf_ctx* c) {
   return PDF_OK;
 }
 
-pdf_status enqueue_steps(pdf_ctx* c, int32_t nsteps) {
+// ev: null, or 2 nsteps events recorded on the stream just before and just
+// after each step's kernels (the timed-step entry point)
+pdf_status enqueue_steps(pdf_ctx* c, int32_t nsteps, hipEvent_t* ev = nullptr) {
   Ctl* ctl = (Ctl*)(c->arena + c->L.ctl);
   for (int32_t i = 0; i < nsteps; ++i) {
     StepIndex si{(uint32_t)i, c->parity, c->rot, 0};
@@ -722,7 +728,9 @@ pdf_status enqueue_steps(pdf_ctx* c, int32_t nsteps) {
     // learned means from a separate statistics pass and inference launch; the
     // other grids compute them inside the step
     if (mlp_separate(c) && (r = enqueue_mlp_means(c, si))) return r;
+    if (ev && (r = hip_check(c, hipEventRecord(ev[2 * i], c->stream), "event record"))) return r;
     if ((r = dispatch_step<true>(c, si))) return r;
+    if (ev && (r = hip_check(c, hipEventRecord(ev[2 * i + 1], c->stream), "event record"))) return r;
     // the step's statistics (of the state it started from) join the time average
     if (c->avg && (r = enqueue_merge(c))) return r;
     c->parity ^= 1u;
@@ -976,6 +984,7 @@ pdf_status pdf_seed_particles(pdf_ctx* c, int32_t nens, const int64_t* counts, c
   // the host vectors stay alive in the context until the copies complete
   if ((r = hip_check(c, hipStreamSynchronize(st), "sync seed"))) return r;
   c->seeded = true;
+  c->restore_pending.clear();
   c->graph_group = 0;  // a graph built for an earlier layout is stale
   c->steps_done = 0;
   c->parity = 0;
@@ -990,6 +999,29 @@ pdf_status pdf_step(pdf_ctx* c, int32_t nsteps) {
   if (!c->seeded) return fail(c, PDF_E_STATE, "pdf_step before pdf_seed_particles");
   if (nsteps == 0) return PDF_OK;
   return enqueue_steps(c, nsteps);
+}
+
+pdf_status pdf_step_timed(pdf_ctx* c, int32_t nsteps, double* kernel_ms) {
+  if (!c || nsteps < 0 || !kernel_ms) return fail(c, PDF_E_ARG, "pdf_step_timed: bad argument");
+  if (!c->seeded) return fail(c, PDF_E_STATE, "pdf_step_timed before pdf_seed_particles");
+  *kernel_ms = 0.0;
+  if (nsteps == 0) return PDF_OK;
+  std::vector<hipEvent_t> ev((size_t)2 * nsteps, nullptr);
+  pdf_status r = PDF_OK;
+  for (auto& e : ev)
+    if ((r = hip_check(c, hipEventCreate(&e), "event create"))) break;
+  if (!r) r = enqueue_steps(c, nsteps, ev.data());
+  if (!r) r = hip_check(c, hipStreamSynchronize(c->stream), "sync timed steps");
+  double tot = 0.0;
+  for (int32_t i = 0; !r && i < nsteps; ++i) {
+    float ms = 0.0f;
+    r = hip_check(c, hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]), "event time");
+    tot += ms;
+  }
+  for (auto& e : ev)
+    if (e) (void)hipEventDestroy(e);
+  if (!r) *kernel_ms = tot;
+  return r;
 }
 
 pdf_status pdf_step_graph(pdf_ctx* c, int32_t nsteps) {
@@ -1233,6 +1265,22 @@ pdf_status pdf_set_state(pdf_ctx* c, int32_t ens, const double* xyuvwpsi, const 
     if (bad & 1) return fail(c, PDF_E_ARG, "pdf_set_state: element index out of range (state unchanged)");
     return fail(c, PDF_E_CAPACITY, "pdf_set_state: an element segment cannot hold its particles (state unchanged)");
   }
+  // a device error since the last restore: every ensemble must be restored
+  // before the error word clears
+  Ctl hctl{};
+  if ((r = hip_check(c, hipMemcpy(&hctl, a + L.ctl, sizeof(Ctl), hipMemcpyDeviceToHost), "read control"))) return r;
+  if (hctl.error != 0 && c->restore_pending.empty()) c->restore_pending.assign(c->nens, 1);
+  if (!c->restore_pending.empty()) c->restore_pending[ens] = 0;
+  const bool all_restored =
+      std::find(c->restore_pending.begin(), c->restore_pending.end(), (uint8_t)1) == c->restore_pending.end();
+  if (all_restored) c->restore_pending.clear();
+  // the other counter sets of the ensemble start from zero: the next step
+  // appends its arrivals to nm[rn] and later steps rotate through all three
+  // (steps that returned early after an error left them stale)
+  const uint32_t rn = c->rot == 2 ? 0u : c->rot + 1u;
+  hipLaunchKernelGGL(k_fill_i32, dim3(eb), dim3(tb), 0, st, (int32_t*)(a + L.nm[rz]) + (size_t)ens * ne, 0, (int64_t)ne);
+  hipLaunchKernelGGL(k_fill_i32, dim3(eb), dim3(tb), 0, st, (int32_t*)(a + L.ns[rn]) + (size_t)ens * ne, 0, (int64_t)ne);
+  hipLaunchKernelGGL(k_fill_i32, dim3(eb), dim3(tb), 0, st, (int32_t*)(a + L.nm[rn]) + (size_t)ens * ne, 0, (int64_t)ne);
   hipLaunchKernelGGL(k_set_counts, dim3(eb), dim3(tb), 0, st, scratch, (int32_t*)(a + L.ns[c->rot]),
                      (int32_t*)(a + L.nm[c->rot]), ne, ens);
   const StepIndex si{0, c->parity, c->rot, 0};
@@ -1245,7 +1293,7 @@ pdf_status pdf_set_state(pdf_ctx* c, int32_t ens, const double* xyuvwpsi, const 
                        state_at<double>(a, L.buf1, L.slots, L.omega), (const Ctl*)(a + L.ctl), si, xyuvwpsi, elem, om,
                        n, ne, ens, (const int32_t*)(a + L.start), scratch);
   hipLaunchKernelGGL(k_fill_i32, dim3(eb), dim3(tb), 0, st, scratch + (size_t)ens * ne, 0, (int64_t)ne);
-  hipLaunchKernelGGL(k_clear_error, dim3(1), dim3(64), 0, st, (Ctl*)(a + L.ctl));
+  hipLaunchKernelGGL(k_restore_ctl, dim3(1), dim3(64), 0, st, (Ctl*)(a + L.ctl), all_restored ? 1 : 0);
   if ((r = hip_check(c, hipGetLastError(), "set-state launch"))) return r;
   return hip_check(c, hipStreamSynchronize(st), "sync set-state");
 }

@@ -137,3 +137,41 @@ def test_nan_and_lost_particles_raise_and_recover(gpu):
     ref = O.Oracle(wl)
     ref.step(5)
     assert_state_parity(sim.state(), ref.state(), what="after recovery")
+
+
+@pytest.mark.parametrize("launch", [(64, 0), (16, 1)])
+def test_restore_after_an_error_inside_a_multistep_call(gpu, launch):
+    """A non-finite velocity in one ensemble raises the error in the first of
+    five steps; the other four return at once, leaving every ensemble's
+    counters and the persistent scheduler's work counters stale.  Restoring
+    one ensemble keeps the error (the others are void too); restoring all of
+    them lets the run go on, trajectories bit-exact against the oracle."""
+    wl = W.small_canyon(target=2000, ppe=20, nens=3)
+    _label(wl, f"error inside step(5), launch={launch}")
+    sim = gpu.Simulation.from_workload(wl)
+    sim.set_launch(*launch)
+    sim.step(4)
+    sim.sync()
+    good = [sim.state(en) for en in range(wl.nens)]
+    bad = {k: v.copy() for k, v in good[1].items()}
+    bad["w"][123] = np.nan
+    sim.set_state(bad, 1)
+    sim.step(5)
+    with pytest.raises(gpu.PdfError) as ei:
+        sim.sync()
+    assert ei.value.code == -6
+    sim.set_state(good[0], 0)
+    with pytest.raises(gpu.PdfError):
+        sim.sync()                      # ensembles 1 and 2 are still void
+    sim.set_state(good[2], 2)
+    sim.set_state(good[1], 1)
+    sim.sync()
+    sim.set_step(4)
+    sim.step(7)
+    sim.sync()
+    m = sim.metrics()
+    assert m["error_word"] == 0 and m["particles"] == wl.n_total
+    orc = O.Oracle(wl)
+    orc.step(11)
+    for en in range(wl.nens):
+        assert_state_parity(sim.state(en), orc.state(en), what=f"after restore ens {en}")
