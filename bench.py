@@ -446,7 +446,7 @@ def main() -> int:
             "ms_per_step": 1e3 * wall / steps,
             "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                         "kernel": "step kernels (k_step, k_walk)", "kernel_ms": round(kern_ms, 5),
+                         "kernel": "k_step (one or two launches per step)", "kernel_ms": round(kern_ms, 5),
                          "kernel_ms_source": f"HIP events around each step's kernels, {timed_steps} eager steps",
                          "graph_ms_per_step": round(graph_ms, 5),
                          "algorithmic_bytes": "scope table: state read + mutable write + statistics re-read "

@@ -197,9 +197,8 @@ pdf_status pdf_step(pdf_ctx* ctx, int32_t nsteps);
 
 /* As pdf_step, timing each step's kernels: HIP events recorded on the
    context's stream immediately before and after the kernels of every step
-   (the step kernel, the crossing-particle kernel and, when the order is
-   split, the small cells' launch; not the capacity checks, which run every
-   sixth step).  Waits for the stream and writes the summed event time of the
+   (the step kernel and, when the order is split, the small cells' launch;
+   not the capacity checks, which run every sixth step).  Waits for the stream and writes the summed event time of the
    nsteps steps, in milliseconds, to *kernel_ms (host).  Results are those of
    pdf_step.  Errors as pdf_step, and PDF_E_ARG for a null kernel_ms. */
 pdf_status pdf_step_timed(pdf_ctx* ctx, int32_t nsteps, double* kernel_ms);

@@ -13,7 +13,11 @@
 //
 // Readings of points the paper leaves open are listed in the design notes and
 // repeated at the place they are used.  Every function below follows its
-// definition directly: no blocking, fusion or reordering.
+// definition directly: no blocking, fusion or reordering.  Floating point:
+// no contraction by the compiler; a fused multiply-add appears only where
+// it is written out (std::fma: the Horner steps of the series, the P1
+// interpolation, the IECM, velocity, frequency and position updates), so
+// that an implementation in another language can repeat every rounding.
 #include "orc.h"
 
 #include <algorithm>
@@ -88,11 +92,11 @@ template <typename T> T series_log(T x) {
   T z = s * s;
   const int K = LogTerms<T>::K;
   T p = (T)1 / (T)(2 * K + 1);
-  for (int j = K - 1; j >= 1; --j) p = p * z + (T)1 / (T)(2 * j + 1);
-  T t = s + s * (z * p);
+  for (int j = K - 1; j >= 1; --j) p = std::fma(p, z, (T)1 / (T)(2 * j + 1));
+  T t = std::fma(s, z * p, s);
   T lm = t + t;
   const T ln2 = (T)0.69314718055994530942;
-  return (T)e * ln2 + lm;
+  return std::fma((T)e, ln2, lm);
 }
 
 // sin and cos of 2 pi t.  The turn t is split exactly into a quarter-turn
@@ -120,17 +124,17 @@ template <typename T> void series_sincos2pi(T t, T* s_out, T* c_out) {
   T ps = ((NS % 2) ? (T)-1 : (T)1) * inv_factorial<T>(2 * NS + 1);
   for (int j = NS - 1; j >= 1; --j) {
     T cj = ((j % 2) ? (T)-1 : (T)1) * inv_factorial<T>(2 * j + 1);
-    ps = ps * z + cj;
+    ps = std::fma(ps, z, cj);
   }
-  T sn = th + th * (z * ps);
+  T sn = std::fma(th, z * ps, th);
   // cos th = 1 + z (-1/2! + z (1/4! - ...))
   const int NC = TrigTerms<T>::C;
   T pc = ((NC % 2) ? (T)-1 : (T)1) * inv_factorial<T>(2 * NC);
   for (int j = NC - 1; j >= 1; --j) {
     T cj = ((j % 2) ? (T)-1 : (T)1) * inv_factorial<T>(2 * j);
-    pc = pc * z + cj;
+    pc = std::fma(pc, z, cj);
   }
-  T cs = (T)1 + z * pc;
+  T cs = std::fma(z, pc, (T)1);
   int qi = ((int)q) & 3;
   switch (qi) {
     case 0: *s_out = sn; *c_out = cs; break;
@@ -777,7 +781,7 @@ template <typename T> int advance(orc_ctx* c, Ens<T>& en, uint32_t ens_index, ui
     const double* q1 = &c->coef[(size_t)c->tri[3 * e + 1] * NC];
     const double* q2 = &c->coef[(size_t)c->tri[3 * e + 2] * NC];
     T f[NC];
-    for (int j = 0; j < NC; ++j) f[j] = (l0 * (T)q0[j] + l1 * (T)q1[j]) + l2 * (T)q2[j];
+    for (int j = 0; j < NC; ++j) f[j] = std::fma(l2, (T)q2[j], std::fma(l1, (T)q1[j], l0 * (T)q0[j]));
     T x = en.x[i], y = en.y[i], u = en.u[i], v = en.v[i], w = en.w[i], psi = en.psi[i];
     // IECM, eq. (7): relax toward the mean scalar of the particle's velocity bin
     if (p.mix && (p.flags & 4)) {
@@ -791,18 +795,19 @@ template <typename T> int advance(orc_ctx* c, Ens<T>& en, uint32_t ens_index, ui
         m = en.cm.empty() ? (T)s[ORC_ST_BINM + bin] : (T)en.cm[(size_t)e * 8 + bin];
       }
       T r = (T)en.rate[e];
-      psi = psi - r * (psi - m);
+      psi = std::fma(-r, psi - m, psi);
     }
     // velocity, eq. (6)
     T dW1 = sdt * xi[0], dW2 = sdt * xi[1];
     T dWp1 = sdt * xi[2], dWp2 = sdt * xi[3], dWp3 = sdt * xi[4];
     T uf = u - f[C_U], vf = v - f[C_V];
     T sq = std::sqrt(f[C_C0EPS]);
-    T au = (-f[C_DPDX] + nu2 * f[C_LAPU]) + (f[C_G11] * uf + f[C_G12] * vf);
-    T av = (-f[C_DPDY] + nu2 * f[C_LAPV]) + (f[C_G21] * uf + f[C_G22] * vf);
-    T un = ((u + au * dt) + s2nu * (f[C_DUDX] * dW1 + f[C_DUDY] * dW2)) + sq * dWp1;
-    T vn = ((v + av * dt) + s2nu * (f[C_DVDX] * dW1 + f[C_DVDY] * dW2)) + sq * dWp2;
-    T wn = (w + (f[C_G33] * w) * dt) + sq * dWp3;
+    T au = std::fma(f[C_G12], vf, std::fma(f[C_G11], uf, std::fma(nu2, f[C_LAPU], -f[C_DPDX])));
+    T av = std::fma(f[C_G22], vf, std::fma(f[C_G21], uf, std::fma(nu2, f[C_LAPV], -f[C_DPDY])));
+    T gu = std::fma(f[C_DUDY], dW2, f[C_DUDX] * dW1), gv = std::fma(f[C_DVDY], dW2, f[C_DVDX] * dW1);
+    T un = std::fma(sq, dWp1, std::fma(s2nu, gu, std::fma(au, dt, u)));
+    T vn = std::fma(sq, dWp2, std::fma(s2nu, gv, std::fma(av, dt, v)));
+    T wn = std::fma(sq, dWp3, std::fma(f[C_G33] * w, dt, w));
     if (!(p.flags & 1)) {
       un = u; vn = v; wn = w;
     }
@@ -816,14 +821,14 @@ template <typename T> int advance(orc_ctx* c, Ens<T>& en, uint32_t ens_index, ui
       const T om = en.om[i];
       const T mw = (T)c->om0[e];
       const T c3 = (T)p.C3, c34 = (T)(2.0 * p.C3 * p.C4), sw = (T)c->somega[e];
-      const T drift = (c3 * mw) * (om - mw) + (sw * mw) * om;
+      const T drift = std::fma(sw * mw, om, (c3 * mw) * (om - mw));
       const T diff = std::sqrt((c34 * (mw * mw)) * om);
-      omn = (om - drift * dt) + diff * (sdt * xi[5]);
+      omn = std::fma(diff, sdt * xi[5], std::fma(-drift, dt, om));
       omn = std::fabs(omn);
     }
     // position, eq. (5), with the velocity at the start of the step
-    T xn = (x + u * dt) + s2nu * dW1;
-    T yn = (y + v * dt) + s2nu * dW2;
+    T xn = std::fma(s2nu, dW1, std::fma(u, dt, x));
+    T yn = std::fma(s2nu, dW2, std::fma(v, dt, y));
     int e2 = e;
     if (p.flags & 2) {
       const T om_before = omn;

@@ -503,8 +503,18 @@ __device__ __forceinline__ int fine_component(double u, double mean, double sd) 
 // where each wavefront computes one output tile of a hidden layer.
 template <int SCHED> __host__ __device__ constexpr int step_block() { return SCHED == 2 ? 256 : WAVE; }
 
+// Wavefronts per SIMD the compiler must leave room for: four for the float
+// second-moment steps at 64 lanes per cell (their LDS allows four; one
+// register more than four wavefronts' 128 made them 10 % slower).
+template <typename T, int MOM, int G, bool ADVANCE, int SCHED, int XV>
+__host__ __device__ constexpr int step_waves_per_eu() {
+  return (sizeof(T) == 4 && MOM == 2 && G == 64 && ADVANCE && SCHED == 0 && XV == XV_NONE) ? 4 : 1;
+}
+
 template <typename T, int MOM, int HIST, int G, bool ADVANCE, int SCHED, int XV>
-__global__ __launch_bounds__(step_block<SCHED>()) void k_step(StepArgs<T> a, StepIndex si) {
+__global__ __launch_bounds__(step_block<SCHED>())
+__attribute__((amdgpu_waves_per_eu(step_waves_per_eu<T, MOM, G, ADVANCE, SCHED, XV>())))
+void k_step(StepArgs<T> a, StepIndex si) {
   constexpr bool OMG = XV == XV_OMEGA;
   constexpr bool VB5 = XV == XV_BINS5;
   static_assert(!(XV != XV_NONE && SCHED == 2), "model extensions run with the separate learned-means pass");
@@ -1222,7 +1232,7 @@ __global__ __launch_bounds__(step_block<SCHED>()) void k_step(StepArgs<T> a, Ste
           const T l2 = (T)(orient_cc(CC, 0, X, Y) * ia);
           T f[NCOEF];
 #pragma unroll
-          for (int q = 0; q < NCOEF; ++q) f[q] = (l0 * CC.coef[q] + l1 * CC.coef[NCOEF + q]) + l2 * CC.coef[2 * NCOEF + q];
+          for (int q = 0; q < NCOEF; ++q) f[q] = fma_t(l2, CC.coef[2 * NCOEF + q], fma_t(l1, CC.coef[NCOEF + q], l0 * CC.coef[q]));
           if (do_mix) {
             T m;
             if constexpr (VB5) {
@@ -1235,17 +1245,18 @@ __global__ __launch_bounds__(step_block<SCHED>()) void k_step(StepArgs<T> a, Ste
                               ((double)w > CC.mean[2] ? 4 : 0);
               m = (T)CC.cm[bin];
             }
-            psi = psi - rate * (psi - m);
+            psi = fma_t(-rate, psi - m, psi);
           }
           const T dW1 = a.sdt * xi0, dW2 = a.sdt * xi1;
           const T dWp1 = a.sdt * xi2, dWp2 = a.sdt * xi3, dWp3 = a.sdt * xi4;
           const T uf = u - f[C_U], vf = v - f[C_V];
           const T sq = sqrt_t(f[C_C0EPS]);
-          const T au = (-f[C_DPDX] + a.nu2 * f[C_LAPU]) + (f[C_G11] * uf + f[C_G12] * vf);
-          const T av = (-f[C_DPDY] + a.nu2 * f[C_LAPV]) + (f[C_G21] * uf + f[C_G22] * vf);
-          un = ((u + au * a.dt) + a.s2nu * (f[C_DUDX] * dW1 + f[C_DUDY] * dW2)) + sq * dWp1;
-          vn = ((v + av * a.dt) + a.s2nu * (f[C_DVDX] * dW1 + f[C_DVDY] * dW2)) + sq * dWp2;
-          wn = (w + (f[C_G33] * w) * a.dt) + sq * dWp3;
+          const T au = fma_t(f[C_G12], vf, fma_t(f[C_G11], uf, fma_t(a.nu2, f[C_LAPU], -f[C_DPDX])));
+          const T av = fma_t(f[C_G22], vf, fma_t(f[C_G21], uf, fma_t(a.nu2, f[C_LAPV], -f[C_DPDY])));
+          const T gu = fma_t(f[C_DUDY], dW2, f[C_DUDX] * dW1), gv = fma_t(f[C_DVDY], dW2, f[C_DVDX] * dW1);
+          un = fma_t(sq, dWp1, fma_t(a.s2nu, gu, fma_t(au, a.dt, u)));
+          vn = fma_t(sq, dWp2, fma_t(a.s2nu, gv, fma_t(av, a.dt, v)));
+          wn = fma_t(sq, dWp3, fma_t(f[C_G33] * w, a.dt, w));
           if (!(a.flags & FLAG_VEL)) { un = u; vn = v; wn = w; }
           if constexpr (OMG) {
             // turbulent frequency, eq. (9), with the sixth normal; reflected
@@ -1255,15 +1266,15 @@ __global__ __launch_bounds__(step_block<SCHED>()) void k_step(StepArgs<T> a, Ste
             omn = om;
             if (a.flags & FLAG_VEL) {
               const T mw = (T)CC.om_mean, sw = (T)CC.sw;
-              const T drift = (a.om_c3 * mw) * (om - mw) + (sw * mw) * om;
+              const T drift = fma_t(sw * mw, om, (a.om_c3 * mw) * (om - mw));
               const T diff = sqrt_t((a.om_c34 * (mw * mw)) * om);
-              omn = (om - drift * a.dt) + diff * (a.sdt * xi5);
+              omn = fma_t(diff, a.sdt * xi5, fma_t(-drift, a.dt, om));
               omn = fabs(omn);
             }
           }
           if (a.flags & FLAG_POS) {
-            xn = (x + u * a.dt) + a.s2nu * dW1;
-            yn = (y + v * a.dt) + a.s2nu * dW2;
+            xn = fma_t(a.s2nu, dW1, fma_t(u, a.dt, x));
+            yn = fma_t(a.s2nu, dW2, fma_t(v, a.dt, y));
             // the walk's first test: is the end point still in the element?
             const double Tx = (double)xn, Ty = (double)yn;
             cross = !(orient_cc(CC, 0, Tx, Ty) >= 0.0 && orient_cc(CC, 1, Tx, Ty) >= 0.0 &&

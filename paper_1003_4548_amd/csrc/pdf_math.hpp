@@ -1,8 +1,9 @@
 // Device arithmetic of the particle step: counter-based normals, the series
 // log / sincos / cube root they and the mixing time need, and the geometric
 // predicates of the tracking.  Every routine is a fixed sequence of IEEE
-// +, -, *, / and sqrt (no contraction: the library is built with
-// -ffp-contract=off), so its result is reproducible bit for bit.
+// +, -, *, /, sqrt and fused multiply-adds written out where the definition
+// fuses (no other contraction: the library is built with -ffp-contract=off),
+// so its result is reproducible bit for bit.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -68,6 +69,9 @@ __device__ __forceinline__ float floor_t(float x) { return floorf(x); }
 __device__ __forceinline__ double floor_t(double x) { return floor(x); }
 __device__ __forceinline__ float sqrt_t(float x) { return sqrtf(x); }
 __device__ __forceinline__ double sqrt_t(double x) { return sqrt(x); }
+// a * b + c with one rounding (where the step's definition fuses them)
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
 // a / b for b in [1, 4) and a zero or of magnitude at least 2^-30 (no
 // operand or quotient near the exponent limits), correctly rounded: the
@@ -107,9 +111,9 @@ template <typename T> __device__ __forceinline__ T series_log(T x) {
   constexpr int K = SeriesTerms<T>::LOG;
   T p = (T)1 / (T)(2 * K + 1);
 #pragma unroll
-  for (int j = K - 1; j >= 1; --j) p = p * z + (T)1 / (T)(2 * j + 1);
-  const T t = s + s * (z * p);
-  return (T)e * (T)0.69314718055994530942 + (t + t);
+  for (int j = K - 1; j >= 1; --j) p = fma_t(p, z, (T)1 / (T)(2 * j + 1));
+  const T t = fma_t(s, z * p, s);
+  return fma_t((T)e, (T)0.69314718055994530942, t + t);
 }
 
 template <typename T> __device__ __forceinline__ constexpr T inv_fact(int n) {
@@ -128,13 +132,13 @@ template <typename T> __device__ __forceinline__ void series_sincos2pi(T t, T* s
   constexpr int NS = SeriesTerms<T>::SIN;
   T ps = ((NS % 2) ? (T)-1 : (T)1) * inv_fact<T>(2 * NS + 1);
 #pragma unroll
-  for (int j = NS - 1; j >= 1; --j) ps = ps * z + ((j % 2) ? (T)-1 : (T)1) * inv_fact<T>(2 * j + 1);
-  const T sn = th + th * (z * ps);
+  for (int j = NS - 1; j >= 1; --j) ps = fma_t(ps, z, ((j % 2) ? (T)-1 : (T)1) * inv_fact<T>(2 * j + 1));
+  const T sn = fma_t(th, z * ps, th);
   constexpr int NC = SeriesTerms<T>::COS;
   T pc = ((NC % 2) ? (T)-1 : (T)1) * inv_fact<T>(2 * NC);
 #pragma unroll
-  for (int j = NC - 1; j >= 1; --j) pc = pc * z + ((j % 2) ? (T)-1 : (T)1) * inv_fact<T>(2 * j);
-  const T cs = (T)1 + z * pc;
+  for (int j = NC - 1; j >= 1; --j) pc = fma_t(pc, z, ((j % 2) ? (T)-1 : (T)1) * inv_fact<T>(2 * j));
+  const T cs = fma_t(z, pc, (T)1);
   const int qi = ((int)q) & 3;
   T so = sn, co = cs;
   if (qi == 1) { so = cs; co = -sn; }
