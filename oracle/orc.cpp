@@ -187,8 +187,10 @@ const uint32_t SEED_STEP = 0xFFFFFFFFu;  // step counter word of the initial dra
 // ---------------------------------------------------------------------------
 // geometry
 
+// (b - a) x (p - a): twice the signed area of (a, b, p), positive when p lies
+// to the left of a -> b; one fused multiply-add after the second product.
 inline double orient2d(double ax, double ay, double bx, double by, double px, double py) {
-  return (bx - ax) * (py - ay) - (by - ay) * (px - ax);
+  return std::fma(bx - ax, py - ay, -((by - ay) * (px - ax)));
 }
 
 enum { NF = 20, NC = 16 };

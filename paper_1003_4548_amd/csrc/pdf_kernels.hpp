@@ -465,20 +465,22 @@ __device__ __forceinline__ void lds_sync_wave() {
 template <typename T> struct CellConst {
   T coef[3 * NCOEF];
   // edge k (vertex k -> k+1) from its lexicographically smaller endpoint:
-  // origin, direction and the sign that turns the result into the
-  // orientation against the element's own edge (orient_edge)
-  double ox[3], oy[3], dx[3], dy[3], sg[3];
+  // origin, and direction times the sign that turns the result into the
+  // orientation against the element's own edge (orient_edge; the sign is
+  // exact, so the product is the same number as orient_edge's)
+  double ox[3], oy[3], dx[3], dy[3];
   double mean[3];
   double cm[8];
   double om_mean, sw;  // turbulent frequency: the element's frozen <omega> and S_omega
   double fsd[3];       // 5 x 5 x 5 bins: standard deviations of u, v, w
 };
 
-// orient_edge of (px, py) against edge k of a cell, from its CellConst data;
-// the same operations in the same order, so the same bits.
+// orient_edge of (px, py) against edge k of a cell, from its CellConst data:
+// the sign carried by the direction flips the result exactly (the rounding
+// of a fused multiply-add is symmetric), so it is orient_edge's number.
 template <typename T>
 __device__ __forceinline__ double orient_cc(const CellConst<T>& C, int k, double px, double py) {
-  return ((C.dx[k] * (py - C.oy[k])) - (C.dy[k] * (px - C.ox[k]))) * C.sg[k];
+  return __builtin_fma(C.dx[k], py - C.oy[k], -(C.dy[k] * (px - C.ox[k])));
 }
 
 // SCHED: 0 one work item per wavefront; 1 persistent grid; 2 one item per
@@ -748,7 +750,7 @@ void k_step(StepArgs<T> a, StepIndex si) {
 #pragma unroll
         for (int x = 0; x < 4; ++x)
 #pragma unroll
-          for (int y = x; y < 4; ++y) acc[pair_index(x, y)] += d[x] * d[y];
+          for (int y = x; y < 4; ++y) acc[pair_index(x, y)] = __builtin_fma(d[x], d[y], acc[pair_index(x, y)]);
         bin = (val[0] > mean[0] ? 1 : 0) + (val[1] > mean[1] ? 2 : 0) + (val[2] > mean[2] ? 4 : 0);
         atomicAdd(&bcnt[bin], 1);
         atomicAdd(&bsum[bin], val[3]);
@@ -1042,9 +1044,8 @@ void k_step(StepArgs<T> a, StepIndex si) {
           const bool a_first = (ax < bx) || (ax == bx && ay < by);
           CC.ox[k] = a_first ? ax : bx;
           CC.oy[k] = a_first ? ay : by;
-          CC.dx[k] = a_first ? bx - ax : ax - bx;
-          CC.dy[k] = a_first ? by - ay : ay - by;
-          CC.sg[k] = a_first ? 1.0 : -1.0;
+          CC.dx[k] = a_first ? bx - ax : -(ax - bx);
+          CC.dy[k] = a_first ? by - ay : -(ay - by);
         }
         // conditional mean of each bin by one lane
         if constexpr (fused_mlp) {

@@ -206,7 +206,7 @@ __device__ __forceinline__ double newton_cbrt(double x) {
 
 __device__ __forceinline__ double orient2d(double ax, double ay, double bx, double by, double px,
                                            double py) {
-  return (bx - ax) * (py - ay) - (by - ay) * (px - ax);
+  return __builtin_fma(bx - ax, py - ay, -((by - ay) * (px - ax)));
 }
 
 // Orientation of p against the edge a->b of a counter-clockwise element,
