@@ -11,12 +11,17 @@
 //              kinds (i32), 1/(2 area) (f64), wall-function alpha per edge.
 //   vertices   16 drift/diffusion coefficients per vertex (T), row-major.
 //
-// One wavefront (64 lanes) owns one cell per step.  It reads the segment once
-// into LDS, estimates the cell's statistics with lane-strided FP64
-// accumulators and DPP row reductions (no atomics), uses them for IECM,
-// advances every particle, tracks it through the mesh, writes the particles
-// that stay back to its own segment in order, and appends the ones that move
-// to their new cell's segment with one atomic per particle.
+// A group of G lanes (4 to 64) owns one cell per step.  It reads the
+// segment once into LDS, estimates the cell's statistics (per-lane FP64
+// partial sums, then a fixed-order cross-lane tree, compensated for the
+// fourth-order statistics; bin counts, bin scalar sums and the histogram by
+// LDS atomics of the group's own wavefront, in its program order), uses them
+// for IECM, advances every particle, tracks it through the mesh, writes the
+// particles that stay back to its own segment in order, and appends the ones
+// that move to their new cell's segment (one atomic per target cell and
+// wavefront).  The order of arrivals from different wavefronts is not fixed,
+// so sums over a cell's particles can differ in their last bits from run to
+// run; trajectories do not depend on it.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -209,28 +214,59 @@ __device__ __forceinline__ double lo_hi_f64(unsigned lo, unsigned hi) {
 // bits 8, 4, 2, 1 by DPP row rotation, half-row mirror and quad swaps.  Each
 // sum ends in the lanes whose bits select it, which store it to out[index]
 // (scaled by f) unless store is false; a caller that reads it from other
-// lanes orders the two.  All lanes of the wavefront take part.
-template <int G, int K>
+// lanes orders the two.  All lanes of the wavefront take part.  COMP: every
+// addition of the tree is an error-free transformation (Knuth's TwoSum), the
+// rounding errors travel with the values and are added once at the end, so
+// the tree adds no rounding of its own beyond that last addition.
+__device__ __forceinline__ double two_sum_err(double a, double b, double s) {
+  const double bp = s - a;
+  const double ap = s - bp;
+  return (a - ap) + (b - bp);
+}
+
+template <int G, int K, bool COMP = false>
 __device__ __forceinline__ void group_sum_many(double (&v)[K], double* out, double f = 1.0, bool store = true) {
   const int li = lane_id() & (G - 1);
   int off = 0, cnt = K;  // this lane's first index and count of valid values
+  double c[COMP ? K : 1];
+#pragma unroll
+  for (int i = 0; i < (COMP ? K : 1); ++i) c[i] = 0.0;
+  auto swap_pair = [&](auto dtag, double a, double b, double& x, double& y) {
+    constexpr int D = decltype(dtag)::value;
+    const long long ab = __double_as_longlong(a), bb = __double_as_longlong(b);
+    const auto l = D == 32 ? __builtin_amdgcn_permlane32_swap((unsigned)ab, (unsigned)bb, false, false)
+                           : __builtin_amdgcn_permlane16_swap((unsigned)ab, (unsigned)bb, false, false);
+    const auto h = D == 32 ? __builtin_amdgcn_permlane32_swap((unsigned)(ab >> 32), (unsigned)(bb >> 32), false, false)
+                           : __builtin_amdgcn_permlane16_swap((unsigned)(ab >> 32), (unsigned)(bb >> 32), false, false);
+    x = lo_hi_f64(l[0], h[0]);
+    y = lo_hi_f64(l[1], h[1]);
+  };
   auto stage = [&](auto dtag, auto kctag) {
     constexpr int D = decltype(dtag)::value, KC = decltype(kctag)::value, KN = (KC + 1) / 2;
     const bool hi = (li & D) != 0;
 #pragma unroll
     for (int i = 0; i < KN; ++i) {
       const double a = v[i], b = (i + KN < KC) ? v[i + KN] : a;
+      double x, y;   // the kept value and the partner's copy of it
       if constexpr (D >= 16) {
-        const long long ab = __double_as_longlong(a), bb = __double_as_longlong(b);
-        const auto l = D == 32 ? __builtin_amdgcn_permlane32_swap((unsigned)ab, (unsigned)bb, false, false)
-                               : __builtin_amdgcn_permlane16_swap((unsigned)ab, (unsigned)bb, false, false);
-        const auto h = D == 32 ? __builtin_amdgcn_permlane32_swap((unsigned)(ab >> 32), (unsigned)(bb >> 32), false, false)
-                               : __builtin_amdgcn_permlane16_swap((unsigned)(ab >> 32), (unsigned)(bb >> 32), false, false);
-        v[i] = lo_hi_f64(l[0], h[0]) + lo_hi_f64(l[1], h[1]);
+        swap_pair(dtag, a, b, x, y);
       } else {
-        const double keep = hi ? b : a, send = hi ? a : b;
         constexpr int CTRL = D == 8 ? 0x128 : (D == 4 ? 0x141 : (D == 2 ? 0x4E : 0xB1));
-        v[i] = keep + dpp_f64<CTRL>(send);
+        x = hi ? b : a;
+        y = dpp_f64<CTRL>(hi ? a : b);
+      }
+      v[i] = x + y;
+      if constexpr (COMP) {
+        const double ca = c[i], cb = (i + KN < KC) ? c[i + KN] : ca;
+        double cx, cy;
+        if constexpr (D >= 16) {
+          swap_pair(dtag, ca, cb, cx, cy);
+        } else {
+          constexpr int CTRL = D == 8 ? 0x128 : (D == 4 ? 0x141 : (D == 2 ? 0x4E : 0xB1));
+          cx = hi ? cb : ca;
+          cy = dpp_f64<CTRL>(hi ? ca : cb);
+        }
+        c[i] = (cx + cy) + two_sum_err(x, y, v[i]);
       }
     }
     if (hi) {
@@ -273,8 +309,11 @@ __device__ __forceinline__ void group_sum_many(double (&v)[K], double* out, doub
   }
   constexpr int KF = G == 64 ? (K5 + 1) / 2 : (G == 32 ? K5 : (G == 16 ? K4 : (G == 8 ? K3 : K2)));
 #pragma unroll
-  for (int i = 0; i < KF; ++i)
-    if (store && i < cnt) out[off + i] = v[i] * f;
+  for (int i = 0; i < KF; ++i) {
+    double r = v[i];
+    if constexpr (COMP) r = r + c[i];
+    if (store && i < cnt) out[off + i] = r * f;
+  }
 }
 
 // f(q) for each of the eight velocity bins q, by lane q of a group of 8 or
@@ -519,6 +558,9 @@ __attribute__((amdgpu_waves_per_eu(step_waves_per_eu<T, MOM, G, ADVANCE, SCHED, 
 void k_step(StepArgs<T> a, StepIndex si) {
   constexpr bool OMG = XV == XV_OMEGA;
   constexpr bool VB5 = XV == XV_BINS5;
+  // the fourth-order statistics (the large canyon) reduce across lanes with
+  // compensated additions
+  constexpr bool CMP = MOM >= 4;
   static_assert(!(XV != XV_NONE && SCHED == 2), "model extensions run with the separate learned-means pass");
   static_assert(!(SCHED == 2 && G < 16), "the learned means inside the step need at most 16 cells per block");
   constexpr bool PERSIST = SCHED == 1;
@@ -704,7 +746,7 @@ void k_step(StepArgs<T> a, StepIndex si) {
       sa[0] = s0; sa[1] = s1; sa[2] = s2; sa[3] = s3;
       if constexpr (OMG) sa[4] = s4;
       lds_sync_wave();  // the previous item's sums are read before these are written
-      group_sum_many<G>(sa, redc);
+      group_sum_many<G, OMG ? 5 : 4, CMP>(sa, redc);
       lds_sync_wave();
 #pragma unroll
       for (int q = 0; q < 4; ++q) mean[q] = redc[q] * inv_n;
@@ -772,7 +814,7 @@ void k_step(StepArgs<T> a, StepIndex si) {
       for (int q = 0; q < 10; ++q) sb[q] = acc[q];
       if constexpr (OMG) sb[10] = accw;
       lds_sync_wave();  // the means above are read before the sums below are written
-      group_sum_many<G>(sb, redc);
+      group_sum_many<G, NRED, CMP>(sb, redc);
       lds_sync_wave();
 #pragma unroll
       for (int q = 0; q < 10; ++q) acc[q] = redc[q];
@@ -960,12 +1002,12 @@ void k_step(StepArgs<T> a, StepIndex si) {
           double t[SPLIT];
 #pragma unroll
           for (int q = 0; q < SPLIT; ++q) t[q] = acc3[q];
-          group_sum_many<G>(t, rec + ST_M3, inv_n, has);
+          group_sum_many<G, SPLIT, CMP>(t, rec + ST_M3, inv_n, has);
         } else {
           double t[NM - SPLIT];
 #pragma unroll
           for (int q = 0; q < NM - SPLIT; ++q) t[q] = acc3[q];
-          group_sum_many<G>(t, rec + ST_M3 + SPLIT, inv_n, has);
+          group_sum_many<G, NM - SPLIT, CMP>(t, rec + ST_M3 + SPLIT, inv_n, has);
         }
       }
     }
