@@ -3,7 +3,8 @@
 Each entry plants one plausible mistake in a copy of ``orc.cpp`` (a dropped
 term, a wrong sign, a swapped index, a transposed operand), builds that copy
 to a temporary library and runs the pin tests against it through the
-ORC_LIB override of ``oracle/__init__.py``.  A pin set is adequate when every
+ORC_LIB override of ``oracle/__init__.py``; the entries for the Python
+oracle of the elliptic-relaxation solve replace ``relax.py`` for their run.  A pin set is adequate when every
 mutant fails at least one test.  Run: ``python oracle/mutation_sweep.py``
 (a few minutes; prints one line per mutant and exits 1 if any survives).
 """
@@ -20,6 +21,8 @@ sys.path.insert(0, ROOT)
 from oracle import CFLAGS, SRC  # noqa: E402
 
 PINS = ["tests/test_oracle_pins.py", "tests/test_oracle_physics.py", "tests/test_oracle_geometry.py"]
+RELAX = os.path.join(HERE, "relax.py")
+RELAX_PINS = ["tests/test_oracle_relax.py"]
 
 # (name, [(original text, planted text), ...])
 MUTANTS = [
@@ -52,6 +55,46 @@ MUTANTS = [
 ]
 
 
+# mistakes planted in the Python oracle of the elliptic-relaxation solve
+# (relax.py is replaced in place for the run and restored afterwards)
+RELAX_MUTANTS = [
+    ("sign of the gamma5/3 term of H (eq. 15)",
+     [("- GAMMA5 / 3.0 * I[i, ll] * I[j, kk]", "+ GAMMA5 / 3.0 * I[i, ll] * I[j, kk]")]),
+    ("sign of the b_ik term of H (eq. 15)",
+     [("+ GAMMA5 * b[:, i, kk] * I[j, ll]", "- GAMMA5 * b[:, i, kk] * I[j, ll]")]),
+    ("transposed mean velocity gradient in eq. (14)",
+     [("acc = acc + H * grad[:, kk, ll]", "acc = acc + H * grad[:, ll, kk]")]),
+    ("C_xi = 1.3 in eq. (18)", [("C_XI = 2.3", "C_XI = 1.3")]),
+    ("L in place of L^2 in eq. (14)", [("L2=L * L", "L2=L")]),
+    ("load with half the element area", [("S[:, c] * area / 3.0", "S[:, c] * area / 2.0")]),
+    ("lumped diagonal of the mass matrix", [("(2.0 if a == b else 1.0)", "(1.0 if a == b else 1.0)")]),
+    ("periodic seams not joined", [("parent[max(ra, rb)] = min(ra, rb)", "pass")]),
+    ("wp in place of 2 wp in eq. (12)", [("G = (2.0 * w - eps * np.eye(3))", "G = (w - eps * np.eye(3))")]),
+    ("factor 2 dropped in eq. (13)", [("C0 = -2.0 * np.sum(w * Rv[c])", "C0 = -np.sum(w * Rv[c])")]),
+    ("C2 = 0.36 (Table 2)", [("C1, C2, CT, CL, CETA, CV, GAMMA5 = 1.85, 0.63,",
+                              "C1, C2, CT, CL, CETA, CV, GAMMA5 = 1.85, 0.36,")]),
+]
+
+
+def run_relax_one(name, edits):
+    orig = open(RELAX).read()
+    src = orig
+    for old, new in edits:
+        if src.count(old) != 1:
+            raise RuntimeError(f"{name}: the text to mutate occurs {src.count(old)} times")
+        src = src.replace(old, new)
+    try:
+        with open(RELAX, "w") as f:
+            f.write(src)
+        r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", *RELAX_PINS],
+                           cwd=ROOT, capture_output=True, text=True)
+    finally:
+        with open(RELAX, "w") as f:
+            f.write(orig)
+    failed = [ln.split(" ")[1] for ln in r.stdout.splitlines() if ln.startswith("FAILED")]
+    return r.returncode != 0, failed
+
+
 def run_one(name, edits, tmp):
     src = open(SRC).read()
     for old, new in edits:
@@ -77,6 +120,10 @@ def main() -> int:
             caught, failed = run_one(name, edits, tmp)
             survivors += 0 if caught else 1
             print(f"{'caught  ' if caught else 'SURVIVED'} {name}: {failed[0] if failed else '-'}", flush=True)
+    for name, edits in RELAX_MUTANTS:
+        caught, failed = run_relax_one(name, edits)
+        survivors += 0 if caught else 1
+        print(f"{'caught  ' if caught else 'SURVIVED'} {name}: {failed[0] if failed else '-'}", flush=True)
     return 1 if survivors else 0
 
 
