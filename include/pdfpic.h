@@ -264,6 +264,37 @@ int64_t pdf_repack_count(pdf_ctx* ctx);
    Errors: PDF_E_ARG (null out), PDF_E_STATE (before seeding), PDF_E_HIP. */
 pdf_status pdf_estimate_statistics(pdf_ctx* ctx, double* out, int32_t out_on_host);
 
+/* Elliptic relaxation (section 2.1, eqs. 12-18): wp_ij of eq. (14),
+     wp_ij - L^2 lap wp_ij = 1/2 (1 - C1) k <omega> delta_ij + k H_ijkl d<U_k>/dx_l,
+   with H of eqs. (15)-(17) and L of eq. (18), solved on the mesh from the
+   particle statistics of the current state, then G_ij and C0 eps of eqs.
+   (12)-(13) per vertex written into the coefficient table the step reads
+   (rounded to the state type), so that later steps use them.  Contexts with
+   model = 1 only; the records of ensemble 0.  Readings:
+   * per element, the Reynolds stress from the record's second moments
+     (<u'w'> = <v'w'> = 0), the frozen stress of the centroid where the
+     element holds fewer than 10 particles; k = tr R / 2; eps and d<U>/dx
+     the frozen fields at the centroid; <omega> from eq. (8); C_xi = 2.3;
+   * Galerkin P1 elements on the vertices, the copies of a periodic-seam
+     vertex one unknown, L^2 and the right-hand side constant per element,
+     zero normal derivative on every wall; the components wp_11, wp_12,
+     wp_21, wp_22, wp_33;
+   * per vertex, R and k area-weighted over the elements around it, eps the
+     frozen field; a negative C0 is set to zero (and counted).
+   The linear systems (one matrix, five right-hand sides) are solved by
+   Jacobi-preconditioned conjugate gradients from the previous solution
+   (the frozen wp fields at the first call) until ||r|| <= tol ||b|| for
+   every component, or max_iters iterations (1..20000; tol in (0, 1)).
+   Outputs, each may be NULL: wp (device, nvert x 5 doubles: wp_11 wp_12
+   wp_21 wp_22 wp_33 per vertex); coef (device, nvert x 6 doubles: G_11 G_12
+   G_21 G_22 G_33 C0 eps before rounding); info (host, 4 int32: iterations,
+   1 if converged, vertices whose C0 was clamped, elements whose stresses came
+   from the statistics); resid (host, 5 doubles: ||r|| / ||b|| per component,
+   0 for b = 0).  Waits for the stream.  Errors: PDF_E_ARG, PDF_E_STATE
+   (before seeding, or model 0), PDF_E_HIP. */
+pdf_status pdf_elliptic_relaxation(pdf_ctx* ctx, int32_t max_iters, double tol, double* wp, double* coef,
+                                   int32_t* info, double* resid);
+
 /* Run metrics from the device counters, into out (8 int64, host; waits):
    particles; arrivals written by the last step (particles now in another
    element than before it, 0 right after a repack, which folds them in);

@@ -98,6 +98,7 @@ def lib():
         L.orc_cbrt64.restype = d
         L.orc_cbrt64.argtypes = [d]
         L.orc_coefficients.argtypes = [vp, vp]
+        L.orc_set_drift.argtypes = [vp, vp]
         L.orc_mix_rate.argtypes = [vp, i32, vp]
         L.orc_wall_alpha.argtypes = [vp, vp]
         L.orc_exp64.restype = d
@@ -257,6 +258,11 @@ class Oracle:
         out = np.zeros((self.wl.mesh.nvert, 16))
         lib().orc_coefficients(self.ctx, _ptr(out))
         return out
+
+    def set_drift(self, g6) -> None:
+        """Replace G_11 G_12 G_21 G_22 G_33 C0 eps of every vertex (nvert x 6)."""
+        a = np.ascontiguousarray(g6, np.float64).reshape(self.wl.mesh.nvert, 6)
+        lib().orc_set_drift(self.ctx, _ptr(a))
 
     def mix_rate(self, ens: int = 0) -> np.ndarray:
         out = np.zeros(self.wl.mesh.nelem)

@@ -1143,6 +1143,11 @@ void orc_coefficients(const orc_ctx* c, double* out) {
     out[i] = c->p.f32_state ? (double)(float)c->coef[i] : c->coef[i];
 }
 
+void orc_set_drift(orc_ctx* c, const double* g6) {
+  for (int v = 0; v < c->nv; ++v)
+    for (int j = 0; j < 6; ++j) c->coef[(size_t)v * NC + C_G11 + j] = g6[(size_t)v * 6 + j];
+}
+
 void orc_mix_rate(const orc_ctx* c, int32_t ens, double* out) {
   const std::vector<double>& r = c->p.f32_state ? c->ensF[ens].rate : c->ensD[ens].rate;
   for (int e = 0; e < c->ne; ++e) out[e] = c->p.f32_state ? (double)(float)r[e] : r[e];

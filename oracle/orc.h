@@ -143,6 +143,9 @@ double orc_cbrt64(double x);
 /* per-vertex coefficient table: nvert x 16 (U V dUdx dUdy dVdx dVdy lapU lapV dPdx dPdy
    G11 G12 G21 G22 G33 C0eps), rounded to the state type */
 void orc_coefficients(const orc_ctx* c, double* out);
+/* replace G11 G12 G21 G22 G33 C0eps of every vertex (g6: nvert x 6), e.g.
+   with the result of the elliptic relaxation, eqs. (12)-(13) */
+void orc_set_drift(orc_ctx* c, const double* g6);
 /* IECM relaxation factor r = min(dt/t_m, 1) per element of one ensemble */
 void orc_mix_rate(const orc_ctx* c, int32_t ens, double* out);
 /* wall-function alpha per element edge (0 elsewhere): nelem x 3 */

@@ -27,7 +27,7 @@ NFIELD = 20
 # exported entry points (the declarations of include/pdfpic.h)
 ENTRY_POINTS = ("pdf_create", "pdf_query_sizes", "pdf_init_mesh", "pdf_seed_particles", "pdf_step",
                 "pdf_step_graph", "pdf_step_timed", "pdf_autotune", "pdf_set_launch", "pdf_repack", "pdf_repack_count",
-                "pdf_estimate_statistics", "pdf_nstat", "pdf_sync", "pdf_metrics",
+                "pdf_estimate_statistics", "pdf_elliptic_relaxation", "pdf_nstat", "pdf_sync", "pdf_metrics",
                 "pdf_mlp_work_floats", "pdf_mlp_dataset", "pdf_mlp_forward", "pdf_mlp_grad", "pdf_mlp_grad_noalloc", "pdf_mlp_train",
                 "pdf_mlp_norm", "pdf_mlp_round", "pdf_mlp_infer", "pdf_mlp_attach",
                 "pdf_get_state", "pdf_set_state", "pdf_set_step", "pdf_get_omega", "pdf_omega_fields", "pdf_navg", "pdf_average_attach",
@@ -127,6 +127,8 @@ def load_library():
     L.pdf_repack_count.argtypes = [vp]
     L.pdf_estimate_statistics.restype = i32
     L.pdf_estimate_statistics.argtypes = [vp, vp, i32]
+    L.pdf_elliptic_relaxation.restype = i32
+    L.pdf_elliptic_relaxation.argtypes = [vp, i32, ctypes.c_double, vp, vp, vp, vp]
     L.pdf_nstat.restype = i32
     L.pdf_nstat.argtypes = [vp]
     L.pdf_sync.restype = i32
@@ -321,6 +323,29 @@ class Simulation:
     def statistics(self) -> np.ndarray:
         out = np.zeros((self.nens, self.nelem, self.nstat))
         self._check(load_library().pdf_estimate_statistics(self.ctx, _ptr(out), 1), "pdf_estimate_statistics")
+        return out
+
+    def elliptic_relaxation(self, max_iters: int = 4000, tol: float = 1e-10, outputs: bool = True) -> dict:
+        """Solve the elliptic relaxation from the statistics of the current
+        state and write G and C0 eps into the coefficient table (waits).
+        Returns iterations, converged, clamped (vertices whose C0 was
+        negative), from_stats (elements whose stresses came from the
+        particles), resid (||r|| / ||b|| per component) and, with outputs,
+        wp (nvert x 5) and coef (nvert x 6) as numpy arrays."""
+        info = np.zeros(4, np.int32)
+        resid = np.zeros(5)
+        wp = coef = None
+        if outputs:
+            wp = self.torch.empty((self.nvert, 5), dtype=self.torch.float64, device=self.device)
+            coef = self.torch.empty((self.nvert, 6), dtype=self.torch.float64, device=self.device)
+        self._check(load_library().pdf_elliptic_relaxation(
+            self.ctx, int(max_iters), float(tol), ctypes.c_void_p(wp.data_ptr() if outputs else 0),
+            ctypes.c_void_p(coef.data_ptr() if outputs else 0), _ptr(info), _ptr(resid)), "pdf_elliptic_relaxation")
+        out = dict(iterations=int(info[0]), converged=bool(info[1]), clamped=int(info[2]), from_stats=int(info[3]),
+                   resid=resid)
+        if outputs:
+            out["wp"] = wp.cpu().numpy()
+            out["coef"] = coef.cpu().numpy()
         return out
 
     def state_device(self, ens: int = 0):

@@ -12,6 +12,7 @@
 
 #include "pdf_kernels.hpp"
 #include "pdf_mlp.hpp"
+#include "pdf_relax.hpp"
 #include "pdfmlp.h"
 #include "pdfpic.h"
 
@@ -33,6 +34,9 @@ int64_t align_up(int64_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 // Byte offsets of the arena sections.
 struct Layout {
   int64_t vtx, tri, nbr, ekind, inv2a, alpha, wnorm, fields, coef, erec, om0, somega, omw;
+  // elliptic relaxation (model 1 only): sparsity, element data, solver vectors
+  int64_t rx_canon, rx_rep, rx_rowptr, rx_col, rx_cptr, rx_cidx, rx_incptr, rx_inc, rx_Ke, rx_area;
+  int64_t rx_S, rx_L2, rx_Rk, rx_aval, rx_diag, rx_x, rx_r, rx_z, rx_q, rx_p0, rx_p1, rx_part, rx_hist, rx_flag;
   int64_t start, cap, cap0, nstart, ncap, ns[3], nm[3], rate, idoff, order, seed, src;
   int64_t buf0, buf1, ovf, ovf_cell, stats, ctl, flag, metrics;
   int64_t total;
@@ -41,7 +45,15 @@ struct Layout {
   bool omega;  // the particle buffers carry the turbulent frequency
 };
 
-Layout make_layout(int32_t nv, int32_t ne, int32_t nens, int64_t slots, int32_t nstat, int tsize, bool omega) {
+// Iterations of one relaxation solve at most (the residual history is kept).
+constexpr int32_t RELAX_MAX_ITERS = 20000;
+// Nonzeros of the relaxation matrix at most: the diagonal and the six
+// ordered vertex pairs of every element.
+int64_t relax_nnz_bound(int32_t nv, int32_t ne) { return (int64_t)nv + 6 * (int64_t)ne; }
+int32_t relax_blocks(int32_t nv) { return std::max(1, (nv + relax::BLK - 1) / relax::BLK); }
+
+Layout make_layout(int32_t nv, int32_t ne, int32_t nens, int64_t slots, int32_t nstat, int tsize, bool omega,
+                   bool relaxation) {
   Layout L{};
   int64_t o = 0;
   auto take = [&](int64_t bytes) { int64_t r = o; o = align_up(o + bytes); return r; };
@@ -59,6 +71,34 @@ Layout make_layout(int32_t nv, int32_t ne, int32_t nens, int64_t slots, int32_t 
   L.om0 = take(omega ? (int64_t)ne * 8 : 0);
   L.somega = take(omega ? (int64_t)ne * 8 : 0);
   L.omw = take(omega ? (int64_t)ne * 3 * 8 : 0);
+  {
+    const int64_t on = relaxation ? 1 : 0;
+    const int64_t nnz = relax_nnz_bound(nv, ne), nc = nv, E = ne;
+    L.rx_canon = take(on * nv * 4);
+    L.rx_rep = take(on * nc * 4);
+    L.rx_rowptr = take(on * (nc + 1) * 4);
+    L.rx_col = take(on * nnz * 4);
+    L.rx_cptr = take(on * (nnz + 1) * 4);
+    L.rx_cidx = take(on * 9 * E * 4);
+    L.rx_incptr = take(on * (nc + 1) * 4);
+    L.rx_inc = take(on * 3 * E * 4);
+    L.rx_Ke = take(on * 9 * E * 8);
+    L.rx_area = take(on * E * 8);
+    L.rx_S = take(on * relax::NC * E * 8);
+    L.rx_L2 = take(on * E * 8);
+    L.rx_Rk = take(on * relax::NC * E * 8);
+    L.rx_aval = take(on * nnz * 8);
+    L.rx_diag = take(on * nc * 8);
+    L.rx_x = take(on * relax::NC * nc * 8);
+    L.rx_r = take(on * relax::NC * nc * 8);
+    L.rx_z = take(on * relax::NC * nc * 8);
+    L.rx_q = take(on * relax::NC * nc * 8);
+    L.rx_p0 = take(on * relax::NC * nc * 8);
+    L.rx_p1 = take(on * relax::NC * nc * 8);
+    L.rx_part = take(on * (int64_t)relax_blocks(nv) * 3 * relax::NC * 8);
+    L.rx_hist = take(on * (int64_t)(RELAX_MAX_ITERS + 2) * relax::NC * 8);
+    L.rx_flag = take(on * (16 + 2 * relax::NC * 8));
+  }
   L.start = take(ncell * 4);
   L.cap = take(ncell * 4);
   L.cap0 = take(ncell * 4);
@@ -154,6 +194,9 @@ struct pdf_ctx {
   // stays set until every one is, since the steps that returned early left
   // every ensemble's particles and counters void)
   std::vector<uint8_t> restore_pending;
+  // elliptic relaxation (model 1): unknowns and nonzeros of its matrix
+  int32_t rx_nc = 0;
+  int64_t rx_nnz = 0;
   std::string err;
   pdf_status last = PDF_OK;
 };
@@ -190,6 +233,122 @@ double omega_beta(const pdf_params& p) {
 pdf_status hip_check(pdf_ctx* c, hipError_t e, const char* what) {
   if (e == hipSuccess) return PDF_OK;
   return fail(c, PDF_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// The structure of the relaxation solve, from the mesh (host bookkeeping; the
+// numbers are computed on the device):
+// * unknowns: the vertices, with the copies of one point of the periodic
+//   domain joined (across a periodic edge, the partner element's vertex that
+//   equals an edge vertex shifted by the edge's period), numbered by their
+//   lowest vertex index;
+// * the matrix rows in CSR form, each nonzero with its element contributions
+//   (element, local row, local column) in increasing order, so that the
+//   device gathers every entry in a fixed order;
+// * the (element, local vertex) pairs of every unknown, in increasing order.
+// Then the element matrices and the first guess (the frozen wp at each
+// unknown's lowest vertex) on the device.  Waits for the stream.
+pdf_status relax_setup(pdf_ctx* c, const pdf_mesh* m) {
+  const int32_t nv = m->nvert, ne = m->nelem;
+  std::vector<int32_t> root(nv);
+  for (int32_t v = 0; v < nv; ++v) root[v] = v;
+  auto find = [&](int32_t v) {
+    while (root[v] != v) {
+      root[v] = root[root[v]];
+      v = root[v];
+    }
+    return v;
+  };
+  for (int32_t e = 0; e < ne; ++e) {
+    for (int k = 0; k < 3; ++k) {
+      const int32_t kind = m->ekind[3 * e + k];
+      if (kind < PDF_EDGE_PERIODIC_XP) continue;
+      const double sx = kind == PDF_EDGE_PERIODIC_XP ? c->p.Lx : (kind == PDF_EDGE_PERIODIC_XM ? -c->p.Lx : 0.0);
+      const double sy = kind == PDF_EDGE_PERIODIC_YP ? c->p.Ly : (kind == PDF_EDGE_PERIODIC_YM ? -c->p.Ly : 0.0);
+      const int32_t nb = m->nbr[3 * e + k];
+      for (int j = 0; j < 2; ++j) {
+        const int32_t v = m->tri[3 * e + (k + j) % 3];
+        const double px = m->vtx[2 * v] + sx, py = m->vtx[2 * v + 1] + sy;
+        for (int t = 0; t < 3; ++t) {
+          const int32_t w = m->tri[3 * nb + t];
+          if (m->vtx[2 * w] != px || m->vtx[2 * w + 1] != py) continue;
+          const int32_t a = find(v), b = find(w);
+          if (a != b) root[std::max(a, b)] = std::min(a, b);   // a class's root is its lowest vertex
+        }
+      }
+    }
+  }
+  std::vector<int32_t> canon(nv), rep, id_of(nv, -1);
+  for (int32_t v = 0; v < nv; ++v) {
+    const int32_t r = find(v);
+    if (r == v) {
+      id_of[v] = (int32_t)rep.size();
+      rep.push_back(v);
+    }
+    canon[v] = id_of[r];
+  }
+  const int32_t nc = (int32_t)rep.size();
+  struct Ent {
+    int32_t row, col, cid;
+  };
+  std::vector<Ent> ent((size_t)9 * ne);
+  for (int32_t e = 0; e < ne; ++e)
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b)
+        ent[(size_t)9 * e + 3 * a + b] = Ent{canon[m->tri[3 * e + a]], canon[m->tri[3 * e + b]], 9 * e + 3 * a + b};
+  std::sort(ent.begin(), ent.end(), [](const Ent& x, const Ent& y) {
+    if (x.row != y.row) return x.row < y.row;
+    if (x.col != y.col) return x.col < y.col;
+    return x.cid < y.cid;
+  });
+  std::vector<int32_t> rowptr((size_t)nc + 1, 0), col, cptr, cidx(ent.size());
+  for (size_t i = 0; i < ent.size(); ++i) {
+    cidx[i] = ent[i].cid;
+    if (i == 0 || ent[i].row != ent[i - 1].row || ent[i].col != ent[i - 1].col) {
+      col.push_back(ent[i].col);
+      cptr.push_back((int32_t)i);
+      ++rowptr[ent[i].row + 1];
+    }
+  }
+  cptr.push_back((int32_t)ent.size());
+  for (int32_t i = 0; i < nc; ++i) rowptr[i + 1] += rowptr[i];
+  const int64_t nnz = (int64_t)col.size();
+  if (nnz > relax_nnz_bound(nv, ne)) return fail(c, PDF_E_MESH, "relaxation: more nonzeros than the layout holds");
+  std::vector<int32_t> incptr((size_t)nc + 1, 0), inc((size_t)3 * ne), fill;
+  for (int32_t e = 0; e < ne; ++e)
+    for (int a = 0; a < 3; ++a) ++incptr[canon[m->tri[3 * e + a]] + 1];
+  for (int32_t i = 0; i < nc; ++i) {
+    if (incptr[i + 1] == 0) return fail(c, PDF_E_MESH, "relaxation: a vertex belongs to no element");
+    incptr[i + 1] += incptr[i];
+  }
+  fill.assign(incptr.begin(), incptr.end() - 1);
+  for (int32_t e = 0; e < ne; ++e)
+    for (int a = 0; a < 3; ++a) inc[fill[canon[m->tri[3 * e + a]]]++] = 3 * e + a;
+  const Layout& L = c->L;
+  char* d = c->arena;
+  hipStream_t st = c->stream;
+  pdf_status r;
+  auto put = [&](int64_t off, const std::vector<int32_t>& h, const char* what) {
+    return hip_check(c, hipMemcpyAsync(d + off, h.data(), h.size() * 4, hipMemcpyHostToDevice, st), what);
+  };
+  if ((r = put(L.rx_canon, canon, "copy relaxation unknowns"))) return r;
+  if ((r = put(L.rx_rep, rep, "copy relaxation unknowns"))) return r;
+  if ((r = put(L.rx_rowptr, rowptr, "copy relaxation rows"))) return r;
+  if ((r = put(L.rx_col, col, "copy relaxation columns"))) return r;
+  if ((r = put(L.rx_cptr, cptr, "copy relaxation contributions"))) return r;
+  if ((r = put(L.rx_cidx, cidx, "copy relaxation contributions"))) return r;
+  if ((r = put(L.rx_incptr, incptr, "copy relaxation incidence"))) return r;
+  if ((r = put(L.rx_inc, inc, "copy relaxation incidence"))) return r;
+  const int tb = 256;
+  hipLaunchKernelGGL(relax::k_relax_geom, dim3((ne + tb - 1) / tb), dim3(tb), 0, st, (const double*)(d + L.vtx),
+                     (const int32_t*)(d + L.tri), (double*)(d + L.rx_Ke), (double*)(d + L.rx_area), ne);
+  hipLaunchKernelGGL(relax::k_relax_warm, dim3((nc + tb - 1) / tb), dim3(tb), 0, st, (const double*)(d + L.fields),
+                     (const int32_t*)(d + L.rx_rep), (double*)(d + L.rx_x), nc);
+  if ((r = hip_check(c, hipGetLastError(), "relaxation set-up kernels"))) return r;
+  // the host vectors stay alive until the copies complete
+  if ((r = hip_check(c, hipStreamSynchronize(st), "sync relaxation set-up"))) return r;
+  c->rx_nc = nc;
+  c->rx_nnz = nnz;
+  return PDF_OK;
 }
 
 // Capacity factor of segments that a repack grows: room for the count to
@@ -772,7 +931,8 @@ pdf_status pdf_query_sizes(const pdf_ctx* c, pdf_sizes* s) {
   const int64_t ncell = (int64_t)s->nelem * s->nens;
   const int64_t slots = slots_bound(s->nparticles, ncell, c->p.slack);
   if (slots >= (int64_t)1 << 31) return PDF_E_SIZE;
-  const Layout L = make_layout(s->nvert, s->nelem, s->nens, slots, nstat_of(c->p), tsize_of(c->p), c->p.omega != 0);
+  const Layout L = make_layout(s->nvert, s->nelem, s->nens, slots, nstat_of(c->p), tsize_of(c->p), c->p.omega != 0,
+                                 c->p.model == 1);
   s->arena_bytes = L.total;
   s->slots = slots;
   return PDF_OK;
@@ -794,7 +954,7 @@ pdf_status pdf_init_mesh(pdf_ctx* c, const pdf_mesh* m, void* arena, int64_t are
   c->arena = (char*)arena;
   c->arena_bytes = arena_bytes;
   // the mesh part of the layout does not depend on the ensembles
-  Layout L = make_layout(c->nv, c->ne, 1, 1, nstat_of(c->p), tsize_of(c->p), c->p.omega != 0);
+  Layout L = make_layout(c->nv, c->ne, 1, 1, nstat_of(c->p), tsize_of(c->p), c->p.omega != 0, c->p.model == 1);
   if (L.start > arena_bytes) return fail(c, PDF_E_SIZE, "arena too small for the mesh");
   c->L = L;
   hipStream_t st = c->stream;
@@ -832,6 +992,7 @@ pdf_status pdf_init_mesh(pdf_ctx* c, const pdf_mesh* m, void* arena, int64_t are
                        (double*)(c->arena + L.om0), (double*)(c->arena + L.somega), (double*)(c->arena + L.omw), c->ne,
                        c->p.nu, c->p.CT, c->p.Cw1, c->p.Cw2);
   if ((r = hip_check(c, hipGetLastError(), "init kernels"))) return r;
+  if (c->p.model == 1 && (r = relax_setup(c, m))) return r;
   int32_t bad = 0;
   if ((r = hip_check(c, hipMemcpyAsync(&bad, flag, 4, hipMemcpyDeviceToHost, st), "read mesh flag"))) return r;
   if ((r = hip_check(c, hipStreamSynchronize(st), "sync init"))) return r;
@@ -934,7 +1095,8 @@ pdf_status pdf_seed_particles(pdf_ctx* c, int32_t nens, const int64_t* counts, c
   c->nsplit = split ? ncell - nsmall : 0;
   for (int gi = 0; gi < 5; ++gi) c->xcd_n[gi][0] = c->xcd_n[gi][1] = -1;
   const int64_t slots = slot + growth_reserve(total, ncell, slack);
-  const Layout L = make_layout(c->nv, c->ne, nens, slots, nstat_of(c->p), tsize_of(c->p), c->p.omega != 0);
+  const Layout L = make_layout(c->nv, c->ne, nens, slots, nstat_of(c->p), tsize_of(c->p), c->p.omega != 0,
+                               c->p.model == 1);
   if (L.total > c->arena_bytes)
     return fail(c, PDF_E_SIZE, "arena too small for the particle layout (query with slack >= 2)");
   c->L = L;
@@ -1172,6 +1334,108 @@ pdf_status pdf_estimate_statistics(pdf_ctx* c, double* out, int32_t out_on_host)
                      "copy statistics")))
     return r;
   if (out_on_host) return hip_check(c, hipStreamSynchronize(c->stream), "sync statistics");
+  return PDF_OK;
+}
+
+// Kernel arguments of the relaxation solve, statistics of ensemble 0.
+static relax::Args relax_args(pdf_ctx* c, int32_t max_iters, double tol) {
+  const Layout& L = c->L;
+  char* d = c->arena;
+  relax::Args a{};
+  a.ne = c->ne;
+  a.nv = c->nv;
+  a.nc = c->rx_nc;
+  a.tri = (const int32_t*)(d + L.tri);
+  a.fields = (const double*)(d + L.fields);
+  a.canon = (const int32_t*)(d + L.rx_canon);
+  a.rowptr = (const int32_t*)(d + L.rx_rowptr);
+  a.col = (const int32_t*)(d + L.rx_col);
+  a.cptr = (const int32_t*)(d + L.rx_cptr);
+  a.cidx = (const int32_t*)(d + L.rx_cidx);
+  a.incptr = (const int32_t*)(d + L.rx_incptr);
+  a.inc = (const int32_t*)(d + L.rx_inc);
+  a.Ke = (const double*)(d + L.rx_Ke);
+  a.area = (const double*)(d + L.rx_area);
+  a.stats = (const double*)(d + L.stats);
+  a.nstat = nstat_of(c->p);
+  a.nu = c->p.nu;
+  a.S = (double*)(d + L.rx_S);
+  a.L2 = (double*)(d + L.rx_L2);
+  a.Rk = (double*)(d + L.rx_Rk);
+  a.aval = (double*)(d + L.rx_aval);
+  a.diag = (double*)(d + L.rx_diag);
+  a.x = (double*)(d + L.rx_x);
+  a.r = (double*)(d + L.rx_r);
+  a.z = (double*)(d + L.rx_z);
+  a.q = (double*)(d + L.rx_q);
+  a.p[0] = (double*)(d + L.rx_p0);
+  a.p[1] = (double*)(d + L.rx_p1);
+  a.part = (double*)(d + L.rx_part);
+  a.hist = (double*)(d + L.rx_hist);
+  a.flag = (int32_t*)(d + L.rx_flag);
+  a.res = (double*)(d + L.rx_flag + 16);
+  a.tol2 = tol * tol;
+  a.nblk = relax_blocks(c->rx_nc);
+  a.max_iters = max_iters;
+  return a;
+}
+
+pdf_status pdf_elliptic_relaxation(pdf_ctx* c, int32_t max_iters, double tol, double* wp, double* coef,
+                                   int32_t* info, double* resid) {
+  if (!c || max_iters < 1 || max_iters > RELAX_MAX_ITERS || !(tol > 0.0) || !(tol < 1.0))
+    return fail(c, PDF_E_ARG, "pdf_elliptic_relaxation: bad argument");
+  if (!c->seeded) return fail(c, PDF_E_STATE, "pdf_elliptic_relaxation before pdf_seed_particles");
+  if (c->p.model != 1) return fail(c, PDF_E_STATE, "pdf_elliptic_relaxation: the context uses the SLM (model 0)");
+  // the statistics of the current state
+  pdf_status r = dispatch_step<false>(c, StepIndex{0, c->parity, c->rot, 0});
+  if (r) return r;
+  const relax::Args a = relax_args(c, max_iters, tol);
+  hipStream_t st = c->stream;
+  const int tb = 256;
+  const unsigned eb = (unsigned)((c->ne + tb - 1) / tb), vb = (unsigned)((c->nv + tb - 1) / tb);
+  const unsigned nb = (unsigned)a.nblk;
+  hipLaunchKernelGGL(relax::k_relax_inputs, dim3(eb), dim3(tb), 0, st, a);
+  hipLaunchKernelGGL(relax::k_relax_matrix, dim3((a.nc + tb - 1) / tb), dim3(tb), 0, st, a);
+  hipLaunchKernelGGL(relax::k_relax_start, dim3(nb), dim3(relax::BLK), 0, st, a);
+  hipLaunchKernelGGL(relax::k_relax_norm, dim3(1), dim3(relax::BLK), 0, st, a);
+  if ((r = hip_check(c, hipGetLastError(), "relaxation launch"))) return r;
+  // conjugate-gradient iterations; after convergence the kernels return at
+  // once, and the host stops enqueuing at the next check of the flag
+  constexpr int32_t POLL = 64;
+  int32_t it = 0;
+  while (it < max_iters) {
+    const int32_t end = std::min(max_iters, it + POLL);
+    for (; it < end; ++it) {
+      hipLaunchKernelGGL(relax::k_relax_cg_a, dim3(nb), dim3(relax::BLK), 0, st, a, it);
+      hipLaunchKernelGGL(relax::k_relax_cg_b, dim3(nb), dim3(relax::BLK), 0, st, a, it);
+    }
+    if ((r = hip_check(c, hipGetLastError(), "relaxation launch"))) return r;
+    if (it >= max_iters) break;
+    int32_t done = 0;
+    if ((r = hip_check(c, hipMemcpyAsync(&done, a.flag, 4, hipMemcpyDeviceToHost, st), "read relaxation flag"))) return r;
+    if ((r = hip_check(c, hipStreamSynchronize(st), "sync relaxation"))) return r;
+    if (done) break;
+  }
+  hipLaunchKernelGGL(relax::k_relax_finish, dim3(1), dim3(relax::BLK), 0, st, a, it);
+  if (c->p.f32_state)
+    hipLaunchKernelGGL(relax::k_relax_coef<float>, dim3(vb), dim3(tb), 0, st, a, (float*)(c->arena + c->L.coef), wp, coef);
+  else
+    hipLaunchKernelGGL(relax::k_relax_coef<double>, dim3(vb), dim3(tb), 0, st, a, (double*)(c->arena + c->L.coef), wp, coef);
+  hipLaunchKernelGGL(relax::k_relax_count, dim3(1), dim3(relax::BLK), 0, st, a);
+  if ((r = hip_check(c, hipGetLastError(), "relaxation launch"))) return r;
+  int32_t hf[4];
+  double hr[2 * relax::NC];
+  if ((r = hip_check(c, hipMemcpyAsync(hf, a.flag, sizeof(hf), hipMemcpyDeviceToHost, st), "read relaxation flag"))) return r;
+  if ((r = hip_check(c, hipMemcpyAsync(hr, a.res, sizeof(hr), hipMemcpyDeviceToHost, st), "read relaxation residual"))) return r;
+  if ((r = hip_check(c, hipStreamSynchronize(st), "sync relaxation"))) return r;
+  if (info) {
+    info[0] = hf[1];
+    info[1] = hf[0];
+    info[2] = hf[2];
+    info[3] = hf[3];
+  }
+  if (resid)
+    for (int q = 0; q < relax::NC; ++q) resid[q] = hr[relax::NC + q] > 0.0 ? std::sqrt(hr[q] / hr[relax::NC + q]) : 0.0;
   return PDF_OK;
 }
 
