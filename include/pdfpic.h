@@ -23,7 +23,9 @@
  * Memory: the caller owns all device memory.  pdf_query_sizes() gives the
  * size of one device arena; the caller allocates it (e.g. a torch uint8
  * tensor) and hands it to pdf_init_mesh().  The library never allocates
- * device memory.  Host input arrays are copied during the call.
+ * device memory (the elliptic relaxation keeps two words of pinned host
+ * memory per context for its convergence flag).  Host input arrays are
+ * copied during the call.
  *
  * Streams: every call enqueues on the HIP stream given to pdf_create() and
  * returns without waiting, except pdf_sync(), the host-copy variants of
@@ -282,16 +284,18 @@ pdf_status pdf_estimate_statistics(pdf_ctx* ctx, double* out, int32_t out_on_hos
    * per vertex, R and k area-weighted over the elements around it, eps the
      frozen field; a negative C0 is set to zero (and counted).
    The linear systems (one matrix, five right-hand sides) are solved by
-   Jacobi-preconditioned conjugate gradients from the previous solution
-   (the frozen wp fields at the first call) until ||r|| <= tol ||b|| for
-   every component, or max_iters iterations (1..20000; tol in (0, 1)).
+   Jacobi-preconditioned conjugate gradients (the Chronopoulos-Gear form:
+   one reduction per iteration) from the previous solution (the frozen wp
+   fields at the first call) until ||r|| <= tol ||b|| for every component
+   (tol ||r0|| where b = 0; r of the recurrence), or max_iters iterations
+   (1..20000; tol in (0, 1)).
    Outputs, each may be NULL: wp (device, nvert x 5 doubles: wp_11 wp_12
    wp_21 wp_22 wp_33 per vertex); coef (device, nvert x 6 doubles: G_11 G_12
    G_21 G_22 G_33 C0 eps before rounding); info (host, 4 int32: iterations,
    1 if converged, vertices whose C0 was clamped, elements whose stresses came
-   from the statistics); resid (host, 5 doubles: ||r|| / ||b|| per component,
-   0 for b = 0).  Waits for the stream.  Errors: PDF_E_ARG, PDF_E_STATE
-   (before seeding, or model 0), PDF_E_HIP. */
+   from the statistics); resid (host, 5 doubles: ||r|| / ||b|| per component
+   at exit).  Waits for the stream.  Errors: PDF_E_ARG, PDF_E_STATE (before
+   seeding, or model 0), PDF_E_HIP. */
 pdf_status pdf_elliptic_relaxation(pdf_ctx* ctx, int32_t max_iters, double tol, double* wp, double* coef,
                                    int32_t* info, double* resid);
 

@@ -35,8 +35,8 @@ int64_t align_up(int64_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 struct Layout {
   int64_t vtx, tri, nbr, ekind, inv2a, alpha, wnorm, fields, coef, erec, om0, somega, omw;
   // elliptic relaxation (model 1 only): sparsity, element data, solver vectors
-  int64_t rx_canon, rx_rep, rx_rowptr, rx_col, rx_cptr, rx_cidx, rx_incptr, rx_inc, rx_Ke, rx_area;
-  int64_t rx_S, rx_L2, rx_Rk, rx_aval, rx_diag, rx_x, rx_r, rx_z, rx_q, rx_p0, rx_p1, rx_part, rx_hist, rx_flag;
+  int64_t rx_canon, rx_rep, rx_ecol, rx_enz, rx_dpos, rx_cptr, rx_cidx, rx_incptr, rx_inc, rx_Ke, rx_area;
+  int64_t rx_S, rx_L2, rx_Rk, rx_aval, rx_dinv, rx_x, rx_p, rx_r[2], rx_w[2], rx_s[2], rx_part[2], rx_pbb, rx_ctl;
   int64_t start, cap, cap0, nstart, ncap, ns[3], nm[3], rate, idoff, order, seed, src;
   int64_t buf0, buf1, ovf, ovf_cell, stats, ctl, flag, metrics;
   int64_t total;
@@ -45,8 +45,11 @@ struct Layout {
   bool omega;  // the particle buffers carry the turbulent frequency
 };
 
-// Iterations of one relaxation solve at most (the residual history is kept).
+// Iterations of one relaxation solve at most.
 constexpr int32_t RELAX_MAX_ITERS = 20000;
+// Iterations of the two replayed relaxation graphs (even: the parity of an
+// iteration continues across replays).
+constexpr int32_t RELAX_LONG = 32, RELAX_SHORT = 8;
 // Nonzeros of the relaxation matrix at most: the diagonal and the six
 // ordered vertex pairs of every element.
 int64_t relax_nnz_bound(int32_t nv, int32_t ne) { return (int64_t)nv + 6 * (int64_t)ne; }
@@ -73,11 +76,13 @@ Layout make_layout(int32_t nv, int32_t ne, int32_t nens, int64_t slots, int32_t 
   L.omw = take(omega ? (int64_t)ne * 3 * 8 : 0);
   {
     const int64_t on = relaxation ? 1 : 0;
-    const int64_t nnz = relax_nnz_bound(nv, ne), nc = nv, E = ne;
+    const int64_t nnz = relax_nnz_bound(nv, ne), nc = nv, E = ne, vec = relax::NC * nc * 8;
+    const int64_t ell = (int64_t)relax::ELL_MAX * nc, nbx = relax_blocks(nv);
     L.rx_canon = take(on * nv * 4);
     L.rx_rep = take(on * nc * 4);
-    L.rx_rowptr = take(on * (nc + 1) * 4);
-    L.rx_col = take(on * nnz * 4);
+    L.rx_ecol = take(on * ell * 4);
+    L.rx_enz = take(on * ell * 4);
+    L.rx_dpos = take(on * nc * 4);
     L.rx_cptr = take(on * (nnz + 1) * 4);
     L.rx_cidx = take(on * 9 * E * 4);
     L.rx_incptr = take(on * (nc + 1) * 4);
@@ -86,18 +91,19 @@ Layout make_layout(int32_t nv, int32_t ne, int32_t nens, int64_t slots, int32_t 
     L.rx_area = take(on * E * 8);
     L.rx_S = take(on * relax::NC * E * 8);
     L.rx_L2 = take(on * E * 8);
-    L.rx_Rk = take(on * relax::NC * E * 8);
-    L.rx_aval = take(on * nnz * 8);
-    L.rx_diag = take(on * nc * 8);
-    L.rx_x = take(on * relax::NC * nc * 8);
-    L.rx_r = take(on * relax::NC * nc * 8);
-    L.rx_z = take(on * relax::NC * nc * 8);
-    L.rx_q = take(on * relax::NC * nc * 8);
-    L.rx_p0 = take(on * relax::NC * nc * 8);
-    L.rx_p1 = take(on * relax::NC * nc * 8);
-    L.rx_part = take(on * (int64_t)relax_blocks(nv) * 3 * relax::NC * 8);
-    L.rx_hist = take(on * (int64_t)(RELAX_MAX_ITERS + 2) * relax::NC * 8);
-    L.rx_flag = take(on * (16 + 2 * relax::NC * 8));
+    L.rx_Rk = take(on * 4 * E * 8);
+    L.rx_aval = take(on * ell * 8);
+    L.rx_dinv = take(on * nc * 8);
+    L.rx_x = take(on * vec);
+    L.rx_p = take(on * vec);
+    for (int b = 0; b < 2; ++b) {
+      L.rx_r[b] = take(on * vec);
+      L.rx_w[b] = take(on * vec);
+      L.rx_s[b] = take(on * vec);
+      L.rx_part[b] = take(on * relax::NC * nbx * 3 * 8);
+    }
+    L.rx_pbb = take(on * relax::NC * nbx * 8);
+    L.rx_ctl = take(on * (int64_t)sizeof(relax::Ctl));
   }
   L.start = take(ncell * 4);
   L.cap = take(ncell * 4);
@@ -195,8 +201,19 @@ struct pdf_ctx {
   // every ensemble's particles and counters void)
   std::vector<uint8_t> restore_pending;
   // elliptic relaxation (model 1): unknowns and nonzeros of its matrix
-  int32_t rx_nc = 0;
+  int32_t rx_nc = 0, rx_ellw = 0;
   int64_t rx_nnz = 0;
+  std::string rx_err;          // why the relaxation is unavailable on this mesh
+  // the solver control after each batch of replays, copied to pinned host
+  // memory behind it
+  relax::Ctl* rx_pin = nullptr;
+  hipEvent_t rx_ev[2] = {nullptr, nullptr};
+  // replayable graphs of RELAX_LONG and RELAX_SHORT iterations (pointers of
+  // the mesh part)
+  hipGraph_t rx_graph[2] = {nullptr, nullptr};
+  hipGraphExec_t rx_graph_exec[2] = {nullptr, nullptr};
+  bool rx_graph_ok = false;
+  int32_t rx_last_iters = 0;   // iterations of the last solve
   std::string err;
   pdf_status last = PDF_OK;
 };
@@ -312,6 +329,24 @@ pdf_status relax_setup(pdf_ctx* c, const pdf_mesh* m) {
   cptr.push_back((int32_t)ent.size());
   for (int32_t i = 0; i < nc; ++i) rowptr[i + 1] += rowptr[i];
   const int64_t nnz = (int64_t)col.size();
+  // rows padded to the longest (padding: the row itself, no nonzero)
+  int32_t ellw = 0;
+  for (int32_t i = 0; i < nc; ++i) ellw = std::max(ellw, rowptr[i + 1] - rowptr[i]);
+  if (ellw > relax::ELL_MAX) {
+    c->rx_nc = 0;
+    c->rx_err = "relaxation: a matrix row has more than " + std::to_string(relax::ELL_MAX) +
+                " entries (a vertex with more than " + std::to_string(relax::ELL_MAX - 1) + " neighbours)";
+    return PDF_OK;
+  }
+  std::vector<int32_t> dpos((size_t)nc, -1), ecol((size_t)ellw * nc), enz((size_t)ellw * nc);
+  for (int32_t i = 0; i < nc; ++i)
+    for (int32_t t = 0; t < ellw; ++t) {
+      const int32_t j = rowptr[i] + t;
+      const bool has = j < rowptr[i + 1];
+      ecol[(size_t)t * nc + i] = has ? col[j] : i;
+      enz[(size_t)t * nc + i] = has ? j : -1;
+      if (has && col[j] == i) dpos[i] = j;
+    }
   if (nnz > relax_nnz_bound(nv, ne)) return fail(c, PDF_E_MESH, "relaxation: more nonzeros than the layout holds");
   std::vector<int32_t> incptr((size_t)nc + 1, 0), inc((size_t)3 * ne), fill;
   for (int32_t e = 0; e < ne; ++e)
@@ -332,8 +367,9 @@ pdf_status relax_setup(pdf_ctx* c, const pdf_mesh* m) {
   };
   if ((r = put(L.rx_canon, canon, "copy relaxation unknowns"))) return r;
   if ((r = put(L.rx_rep, rep, "copy relaxation unknowns"))) return r;
-  if ((r = put(L.rx_rowptr, rowptr, "copy relaxation rows"))) return r;
-  if ((r = put(L.rx_col, col, "copy relaxation columns"))) return r;
+  if ((r = put(L.rx_ecol, ecol, "copy relaxation columns"))) return r;
+  if ((r = put(L.rx_enz, enz, "copy relaxation nonzeros"))) return r;
+  if ((r = put(L.rx_dpos, dpos, "copy relaxation diagonal"))) return r;
   if ((r = put(L.rx_cptr, cptr, "copy relaxation contributions"))) return r;
   if ((r = put(L.rx_cidx, cidx, "copy relaxation contributions"))) return r;
   if ((r = put(L.rx_incptr, incptr, "copy relaxation incidence"))) return r;
@@ -348,6 +384,10 @@ pdf_status relax_setup(pdf_ctx* c, const pdf_mesh* m) {
   if ((r = hip_check(c, hipStreamSynchronize(st), "sync relaxation set-up"))) return r;
   c->rx_nc = nc;
   c->rx_nnz = nnz;
+  c->rx_ellw = ellw;
+  c->rx_err.clear();
+  c->rx_graph_ok = false;
+  c->rx_last_iters = 0;
   return PDF_OK;
 }
 
@@ -1338,18 +1378,21 @@ pdf_status pdf_estimate_statistics(pdf_ctx* c, double* out, int32_t out_on_host)
 }
 
 // Kernel arguments of the relaxation solve, statistics of ensemble 0.
-static relax::Args relax_args(pdf_ctx* c, int32_t max_iters, double tol) {
+static relax::Args relax_args(pdf_ctx* c) {
   const Layout& L = c->L;
   char* d = c->arena;
   relax::Args a{};
   a.ne = c->ne;
   a.nv = c->nv;
   a.nc = c->rx_nc;
+  a.nbx = relax_blocks(c->rx_nc);
+  a.ellw = c->rx_ellw;
   a.tri = (const int32_t*)(d + L.tri);
   a.fields = (const double*)(d + L.fields);
   a.canon = (const int32_t*)(d + L.rx_canon);
-  a.rowptr = (const int32_t*)(d + L.rx_rowptr);
-  a.col = (const int32_t*)(d + L.rx_col);
+  a.ecol = (const int32_t*)(d + L.rx_ecol);
+  a.enz = (const int32_t*)(d + L.rx_enz);
+  a.dpos = (const int32_t*)(d + L.rx_dpos);
   a.cptr = (const int32_t*)(d + L.rx_cptr);
   a.cidx = (const int32_t*)(d + L.rx_cidx);
   a.incptr = (const int32_t*)(d + L.rx_incptr);
@@ -1363,21 +1406,65 @@ static relax::Args relax_args(pdf_ctx* c, int32_t max_iters, double tol) {
   a.L2 = (double*)(d + L.rx_L2);
   a.Rk = (double*)(d + L.rx_Rk);
   a.aval = (double*)(d + L.rx_aval);
-  a.diag = (double*)(d + L.rx_diag);
+  a.dinv = (double*)(d + L.rx_dinv);
   a.x = (double*)(d + L.rx_x);
-  a.r = (double*)(d + L.rx_r);
-  a.z = (double*)(d + L.rx_z);
-  a.q = (double*)(d + L.rx_q);
-  a.p[0] = (double*)(d + L.rx_p0);
-  a.p[1] = (double*)(d + L.rx_p1);
-  a.part = (double*)(d + L.rx_part);
-  a.hist = (double*)(d + L.rx_hist);
-  a.flag = (int32_t*)(d + L.rx_flag);
-  a.res = (double*)(d + L.rx_flag + 16);
-  a.tol2 = tol * tol;
-  a.nblk = relax_blocks(c->rx_nc);
-  a.max_iters = max_iters;
+  a.p = (double*)(d + L.rx_p);
+  for (int b = 0; b < 2; ++b) {
+    a.r[b] = (double*)(d + L.rx_r[b]);
+    a.w[b] = (double*)(d + L.rx_w[b]);
+    a.s[b] = (double*)(d + L.rx_s[b]);
+  }
+  a.part[0] = (double*)(d + L.rx_part[0]);
+  a.part[1] = (double*)(d + L.rx_part[1]);
+  a.pbb = (double*)(d + L.rx_pbb);
+  a.ctl = (relax::Ctl*)(d + L.rx_ctl);
   return a;
+}
+
+// The graphs of RELAX_LONG and RELAX_SHORT iteration launches (kernel nodes
+// only; every launch after the stop returns at once).
+static pdf_status relax_graph(pdf_ctx* c, const relax::Args& a) {
+  if (c->rx_graph_ok) return PDF_OK;
+  static_assert(RELAX_LONG % 2 == 0 && RELAX_SHORT % 2 == 0, "iteration parity continues across replays");
+  pdf_status r;
+  for (int gi = 0; gi < 2; ++gi) {
+    if (c->rx_graph_exec[gi]) (void)hipGraphExecDestroy(c->rx_graph_exec[gi]);
+    if (c->rx_graph[gi]) (void)hipGraphDestroy(c->rx_graph[gi]);
+    c->rx_graph_exec[gi] = nullptr;
+    c->rx_graph[gi] = nullptr;
+    hipGraph_t g = nullptr;
+    if ((r = hip_check(c, hipGraphCreate(&g, 0), "relaxation graph create"))) return r;
+    relax::Args store = a;   // kernel parameters are copied into the nodes at creation
+    int32_t pars[2] = {0, 1};
+    hipGraphNode_t prev = nullptr;
+    const int n = gi == 0 ? RELAX_LONG : RELAX_SHORT;
+    for (int i = 0; i < n; ++i) {
+      void* params[2] = {&store, &pars[i & 1]};
+      hipKernelNodeParams kp{};
+      kp.func = const_cast<void*>(relax::relax_iter_kernel(a.ellw));
+      kp.gridDim = dim3((unsigned)a.nbx, relax::NC);
+      kp.blockDim = dim3(relax::BLK);
+      kp.sharedMemBytes = 0;
+      kp.kernelParams = params;
+      kp.extra = nullptr;
+      hipGraphNode_t node;
+      if ((r = hip_check(c, hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &kp),
+                         "relaxation graph node"))) {
+        (void)hipGraphDestroy(g);
+        return r;
+      }
+      prev = node;
+    }
+    hipGraphExec_t ex = nullptr;
+    if ((r = hip_check(c, hipGraphInstantiate(&ex, g, nullptr, nullptr, 0), "relaxation graph instantiate"))) {
+      (void)hipGraphDestroy(g);
+      return r;
+    }
+    c->rx_graph[gi] = g;
+    c->rx_graph_exec[gi] = ex;
+  }
+  c->rx_graph_ok = true;
+  return PDF_OK;
 }
 
 pdf_status pdf_elliptic_relaxation(pdf_ctx* c, int32_t max_iters, double tol, double* wp, double* coef,
@@ -1386,56 +1473,85 @@ pdf_status pdf_elliptic_relaxation(pdf_ctx* c, int32_t max_iters, double tol, do
     return fail(c, PDF_E_ARG, "pdf_elliptic_relaxation: bad argument");
   if (!c->seeded) return fail(c, PDF_E_STATE, "pdf_elliptic_relaxation before pdf_seed_particles");
   if (c->p.model != 1) return fail(c, PDF_E_STATE, "pdf_elliptic_relaxation: the context uses the SLM (model 0)");
+  if (c->rx_nc == 0) return fail(c, PDF_E_MESH, c->rx_err);
   // the statistics of the current state
   pdf_status r = dispatch_step<false>(c, StepIndex{0, c->parity, c->rot, 0});
   if (r) return r;
-  const relax::Args a = relax_args(c, max_iters, tol);
+  const relax::Args a = relax_args(c);
+  if ((r = relax_graph(c, a))) return r;
   hipStream_t st = c->stream;
-  const int tb = 256;
+  const int tb = relax::BLK;
   const unsigned eb = (unsigned)((c->ne + tb - 1) / tb), vb = (unsigned)((c->nv + tb - 1) / tb);
-  const unsigned nb = (unsigned)a.nblk;
+  const unsigned zb = (unsigned)(((int64_t)c->rx_ellw * c->rx_nc + tb - 1) / tb);
+  const dim3 grid((unsigned)a.nbx, relax::NC);
+  hipLaunchKernelGGL(relax::k_relax_reset, dim3(1), dim3(64), 0, st, a.ctl, max_iters, tol * tol);
   hipLaunchKernelGGL(relax::k_relax_inputs, dim3(eb), dim3(tb), 0, st, a);
-  hipLaunchKernelGGL(relax::k_relax_matrix, dim3((a.nc + tb - 1) / tb), dim3(tb), 0, st, a);
-  hipLaunchKernelGGL(relax::k_relax_start, dim3(nb), dim3(relax::BLK), 0, st, a);
-  hipLaunchKernelGGL(relax::k_relax_norm, dim3(1), dim3(relax::BLK), 0, st, a);
+  hipLaunchKernelGGL(relax::k_relax_matrix, dim3(zb), dim3(tb), 0, st, a);
+  hipLaunchKernelGGL(relax::k_relax_start1, grid, dim3(tb), 0, st, a);
+  hipLaunchKernelGGL(relax::k_relax_start2, grid, dim3(tb), 0, st, a);
   if ((r = hip_check(c, hipGetLastError(), "relaxation launch"))) return r;
-  // conjugate-gradient iterations; after convergence the kernels return at
-  // once, and the host stops enqueuing at the next check of the flag
-  constexpr int32_t POLL = 64;
-  int32_t it = 0;
-  while (it < max_iters) {
-    const int32_t end = std::min(max_iters, it + POLL);
-    for (; it < end; ++it) {
-      hipLaunchKernelGGL(relax::k_relax_cg_a, dim3(nb), dim3(relax::BLK), 0, st, a, it);
-      hipLaunchKernelGGL(relax::k_relax_cg_b, dim3(nb), dim3(relax::BLK), 0, st, a, it);
-    }
-    if ((r = hip_check(c, hipGetLastError(), "relaxation launch"))) return r;
-    if (it >= max_iters) break;
-    int32_t done = 0;
-    if ((r = hip_check(c, hipMemcpyAsync(&done, a.flag, 4, hipMemcpyDeviceToHost, st), "read relaxation flag"))) return r;
-    if ((r = hip_check(c, hipStreamSynchronize(st), "sync relaxation"))) return r;
-    if (done) break;
+  // Iterations in graph replays until the device reports the stop (launch i
+  // checks the stop after i iterations, so up to max_iters + 1 launches run;
+  // launches after the stop return at once).  The first batch covers the
+  // iteration count of the last solve; the coefficient update and a copy of
+  // the solver control into pinned host memory follow it, and the host waits
+  // once.  If the solve has not stopped, batches of RELAX_SHORT follow, each
+  // with its control copy and event, the next one enqueued before the host
+  // waits for the previous one, and the coefficients are updated again.
+  if (!c->rx_pin) {
+    if ((r = hip_check(c, hipHostMalloc((void**)&c->rx_pin, 2 * sizeof(relax::Ctl), hipHostMallocDefault), "pinned control"))) return r;
+    for (auto& e : c->rx_ev)
+      if ((r = hip_check(c, hipEventCreateWithFlags(&e, hipEventDisableTiming), "relaxation event"))) return r;
   }
-  hipLaunchKernelGGL(relax::k_relax_finish, dim3(1), dim3(relax::BLK), 0, st, a, it);
-  if (c->p.f32_state)
-    hipLaunchKernelGGL(relax::k_relax_coef<float>, dim3(vb), dim3(tb), 0, st, a, (float*)(c->arena + c->L.coef), wp, coef);
-  else
-    hipLaunchKernelGGL(relax::k_relax_coef<double>, dim3(vb), dim3(tb), 0, st, a, (double*)(c->arena + c->L.coef), wp, coef);
-  hipLaunchKernelGGL(relax::k_relax_count, dim3(1), dim3(relax::BLK), 0, st, a);
-  if ((r = hip_check(c, hipGetLastError(), "relaxation launch"))) return r;
-  int32_t hf[4];
-  double hr[2 * relax::NC];
-  if ((r = hip_check(c, hipMemcpyAsync(hf, a.flag, sizeof(hf), hipMemcpyDeviceToHost, st), "read relaxation flag"))) return r;
-  if ((r = hip_check(c, hipMemcpyAsync(hr, a.res, sizeof(hr), hipMemcpyDeviceToHost, st), "read relaxation residual"))) return r;
-  if ((r = hip_check(c, hipStreamSynchronize(st), "sync relaxation"))) return r;
+  int32_t launched = 0;
+  auto replay = [&](int gi) -> pdf_status {
+    launched += gi == 0 ? RELAX_LONG : RELAX_SHORT;
+    return hip_check(c, hipGraphLaunch(c->rx_graph_exec[gi], st), "relaxation graph launch");
+  };
+  auto mark = [&](int slot) -> pdf_status {
+    pdf_status q;
+    if ((q = hip_check(c, hipMemcpyAsync(c->rx_pin + slot, a.ctl, sizeof(relax::Ctl), hipMemcpyDeviceToHost, st), "read relaxation control"))) return q;
+    return hip_check(c, hipEventRecord(c->rx_ev[slot], st), "relaxation event");
+  };
+  auto update = [&]() -> pdf_status {
+    if (c->p.f32_state)
+      hipLaunchKernelGGL(relax::k_relax_coef<float>, dim3(vb), dim3(tb), 0, st, a, (float*)(c->arena + c->L.coef), wp, coef);
+    else
+      hipLaunchKernelGGL(relax::k_relax_coef<double>, dim3(vb), dim3(tb), 0, st, a, (double*)(c->arena + c->L.coef), wp, coef);
+    return hip_check(c, hipGetLastError(), "relaxation launch");
+  };
+  const int32_t first = std::max(1, std::min(c->rx_last_iters, max_iters) + 1);
+  while (launched + RELAX_LONG <= first)
+    if ((r = replay(0))) return r;
+  while (launched < first)
+    if ((r = replay(1))) return r;
+  int slot = 0;
+  if ((r = update()) || (r = mark(slot))) return r;
+  if ((r = hip_check(c, hipEventSynchronize(c->rx_ev[slot]), "sync relaxation"))) return r;
+  if (!c->rx_pin[slot].done && launched <= max_iters) {
+    if ((r = replay(1)) || (r = mark(slot))) return r;
+    for (;;) {
+      const bool more = launched <= max_iters;
+      if (more && ((r = replay(1)) || (r = mark(slot ^ 1)))) return r;
+      if ((r = hip_check(c, hipEventSynchronize(c->rx_ev[slot]), "sync relaxation"))) return r;
+      if (c->rx_pin[slot].done || !more) break;
+      slot ^= 1;
+    }
+    // the coefficients of the final solution (the count of clamped C0 anew)
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, &a.ctl->clamped, 0, (int64_t)1);
+    if ((r = update()) || (r = mark(slot))) return r;
+    if ((r = hip_check(c, hipEventSynchronize(c->rx_ev[slot]), "sync relaxation"))) return r;
+  }
+  const relax::Ctl& h = c->rx_pin[slot];
+  c->rx_last_iters = h.iter;
   if (info) {
-    info[0] = hf[1];
-    info[1] = hf[0];
-    info[2] = hf[2];
-    info[3] = hf[3];
+    info[0] = h.iter;
+    info[1] = h.converged;
+    info[2] = h.clamped;
+    info[3] = h.from_stats;
   }
   if (resid)
-    for (int q = 0; q < relax::NC; ++q) resid[q] = hr[relax::NC + q] > 0.0 ? std::sqrt(hr[q] / hr[relax::NC + q]) : 0.0;
+    for (int q = 0; q < relax::NC; ++q) resid[q] = h.ref[q] > 0.0 ? std::sqrt(h.rho[q] / h.ref[q]) : 0.0;
   return PDF_OK;
 }
 
@@ -1638,9 +1754,16 @@ const char* pdf_error_string(const pdf_ctx* c) { return c ? c->err.c_str() : "nu
 
 void pdf_destroy(pdf_ctx* c) {
   if (!c) return;
+  if (c->stream || c->seeded) (void)hipStreamSynchronize(c->stream);
   if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
   if (c->graph) (void)hipGraphDestroy(c->graph);
-  if (c->stream || c->seeded) (void)hipStreamSynchronize(c->stream);
+  for (int gi = 0; gi < 2; ++gi) {
+    if (c->rx_graph_exec[gi]) (void)hipGraphExecDestroy(c->rx_graph_exec[gi]);
+    if (c->rx_graph[gi]) (void)hipGraphDestroy(c->rx_graph[gi]);
+  }
+  for (auto& e : c->rx_ev)
+    if (e) (void)hipEventDestroy(e);
+  if (c->rx_pin) (void)hipHostFree(c->rx_pin);
   delete c;
 }
 

@@ -10,12 +10,21 @@
 // vertex joined; L^2 and the right-hand side are constant per element; every
 // wall carries the natural (zero normal derivative) condition.  The five
 // components wp_11, wp_12, wp_21, wp_22, wp_33 share the matrix and are
-// solved together; vectors are stored component-major (5 x nc doubles).
+// solved together; vectors are stored component-major (5 x nc doubles), and
+// a solver launch runs one block per (BLK unknowns, component).
 //
-// Determinism: the matrix entries are gathered per nonzero from a fixed list
-// of element contributions; every inner product is a fixed-order sum of
-// per-block partial sums, which every block of the next kernel recomputes
-// identically (no atomics on floating point).
+// The iteration is the Chronopoulos-Gear form of preconditioned CG: its two
+// inner products come from the same vectors, so one launch per iteration
+// does the vector updates, the product with the matrix and the partial inner
+// products.  The product needs the new preconditioned residual u = M^-1 r of
+// the neighbouring unknowns; each thread recomputes it from their values of
+// the previous iteration (r, w = A u, s = A p, kept in two buffers by
+// iteration parity), with the same operations as their owners, so the
+// product is exactly A u.  Every block sums the previous launch's block
+// partials in the same fixed order and derives the iteration's scalars
+// itself, so a launch has two dependent rounds of memory accesses (its own
+// loads, then the gathers of the neighbours' values), no atomics, and every
+// result is reproducible.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -26,21 +35,48 @@ namespace pdf {
 namespace relax {
 
 constexpr int NC = 5;            // solved components
-constexpr int BLK = 256;         // threads per block of the solver kernels
-constexpr int MAX_BLOCKS = 1024; // blocks of a solver launch (nc <= MAX_BLOCKS * BLK)
+constexpr int BLK = 128;         // threads of a solver block (one component, BLK unknowns)
+constexpr int WPB = BLK / WAVE;  // its wavefronts
 constexpr int N_MIN = 10;        // fewer particles: the element takes the frozen stresses
+constexpr int ELL_MAX = 16;      // matrix entries per row at most
 // Table 2
 constexpr double C1 = 1.85, C2 = 0.63, CT = 6.0, CL = 0.134, CETA = 72.0, CV = 1.4, GAMMA5 = 0.1;
 constexpr double C_XI = 2.3;     // 1 + 1.3 n_i n_i with a unit normal n
 
+// Scalars of one iteration, written by block (0, 0) of its launch into the
+// slot of its parity and read by the next launch.
+struct Scal {
+  double alpha[NC];             // alpha of the iteration
+  double gamma[NC];             // (r, u) of the iteration
+  int32_t iter;                 // the next iteration's index
+  int32_t done;                 // the solve has stopped
+};
+
+// Solver control in device memory.
+struct Ctl {
+  Scal sc[2];
+  double ref[NC];               // (b, b), or (r0, r0) where b = 0
+  double rho[NC];               // (r, r) at the stop
+  double tol2;
+  int32_t iter;                 // iterations done at the stop
+  int32_t max_iters;
+  int32_t done;                 // converged or out of iterations
+  int32_t converged;
+  int32_t clamped;              // vertices whose C0 was negative
+  int32_t from_stats;           // elements whose stresses came from the particles
+};
+
 struct Args {
   // mesh (device)
-  int32_t ne, nv, nc;
+  int32_t ne, nv, nc, nbx, ellw;
   const int32_t* tri;      // ne x 3
   const double* fields;    // nv x NFIELD (frozen)
   const int32_t* canon;    // nv: unknown of each vertex
-  const int32_t* rowptr;   // nc + 1
-  const int32_t* col;      // nnz
+  // matrix rows padded to ellw entries, slot t of row i at t * nc + i;
+  // padding points at the row itself with a zero entry
+  const int32_t* ecol;     // ellw x nc column
+  const int32_t* enz;      // ellw x nc nonzero index (-1: padding)
+  const int32_t* dpos;     // nc: nonzero index of the diagonal entry of each row
   const int32_t* cptr;     // nnz + 1: contributions of each nonzero
   const int32_t* cidx;     // e * 9 + a * 3 + b
   const int32_t* incptr;   // nc + 1: (element, local vertex) pairs of each unknown
@@ -54,21 +90,17 @@ struct Args {
   // work (device)
   double* S;               // 5 x ne right-hand side per element
   double* L2;              // ne
-  double* Rk;              // 5 x ne: R11 R22 R33 R12 and the count of particles used (0: frozen)
-  double* aval;            // nnz
-  double* diag;            // nc
+  double* Rk;              // 4 x ne: R11 R22 R33 R12
+  double* aval;            // ellw x nc matrix entries
+  double* dinv;            // nc: 1 / diagonal
   double* x;               // 5 x nc (the solution; the previous one is the first guess)
-  double* r;               // 5 x nc
-  double* z;               // 5 x nc
-  double* q;               // 5 x nc
-  double* p[2];            // 5 x nc each
-  double* part;            // MAX_BLOCKS x 3 x 5 partial sums: p.q, r.z, r.r
-  double* hist;            // (max_iters + 2) x 5: r.z of every iteration
-  int32_t* flag;           // [0] done, [1] iterations, [2] C0 clamped, [3] elements from statistics
-  double* res;             // 10: r.r and b.b per component at exit
-  double tol2;             // squared relative residual bound
-  int32_t nblk;            // blocks of the solver launches
-  int32_t max_iters;
+  double* p;               // 5 x nc
+  double* r[2];            // 5 x nc each, by iteration parity
+  double* w[2];
+  double* s[2];
+  double* part[2];         // 5 x nbx x 3 block partials (r,u) (w,u) (r,r), by parity
+  double* pbb;             // 5 x nbx block partials of (b, b)
+  Ctl* ctl;
 };
 
 // ---------------------------------------------------------------------------
@@ -104,365 +136,444 @@ __global__ void k_relax_warm(const double* fields, const int32_t* rep, double* x
 }
 
 // ---------------------------------------------------------------------------
-// per element: stresses, k, <omega>, L^2 and the right-hand side of eq. (14)
+// per solve
 
-__global__ void k_relax_inputs(Args a) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= a.ne) return;
-  const double* f0 = a.fields + (size_t)a.tri[3 * e] * NFIELD;
-  const double* f1 = a.fields + (size_t)a.tri[3 * e + 1] * NFIELD;
-  const double* f2 = a.fields + (size_t)a.tri[3 * e + 2] * NFIELD;
-  auto cen = [&](int j) { return (f0[j] + f1[j] + f2[j]) / 3.0; };
-  const double* rec = a.stats + (size_t)e * a.nstat;
-  double r11, r22, r33, r12;
-  const bool est = rec[ST_N] >= (double)N_MIN;
-  if (est) {
-    // central second moments in pair order (uu uv uw up vv vw vp ww wp pp)
-    r11 = rec[ST_M2]; r12 = rec[ST_M2 + 1]; r22 = rec[ST_M2 + 4]; r33 = rec[ST_M2 + 7];
-  } else {
-    r11 = cen(F_R11); r22 = cen(F_R22); r33 = cen(F_R33); r12 = cen(F_R12);
+__global__ void k_relax_reset(Ctl* ctl, int max_iters, double tol2) {
+  if (threadIdx.x != 0) return;
+  ctl->tol2 = tol2;
+  ctl->iter = 0;
+  ctl->max_iters = max_iters;
+  ctl->done = 0;
+  ctl->converged = 0;
+  ctl->clamped = 0;
+  ctl->from_stats = 0;
+  for (int q = 0; q < 2; ++q) {
+    for (int c = 0; c < NC; ++c) ctl->sc[q].alpha[c] = ctl->sc[q].gamma[c] = 0.0;
+    ctl->sc[q].iter = 0;
+    ctl->sc[q].done = 0;
   }
-  const double tr = r11 + r22 + r33;
-  const double k = 0.5 * tr;
-  const double eps = cen(F_EPS);
-  const double om = 2.0 * eps / (k + sqrt(k * k + 4.0 * a.nu * CT * CT * eps));
-  // d<U_k>/dx_l for k, l in {x, y}
-  const double g00 = cen(F_DUDX), g01 = cen(F_DUDY), g10 = cen(F_DVDX), g11 = cen(F_DVDY);
-  // anisotropy (eq. 17) and A_v (eq. 16); R13 = R23 = 0
-  const double b00 = r11 / tr - 1.0 / 3.0, b11 = r22 / tr - 1.0 / 3.0, b01 = r12 / tr;
-  const double det = r33 * (r11 * r22 - r12 * r12);
-  const double k23 = 2.0 * k / 3.0;
-  const double Av = fmin(1.0, CV * det / (k23 * k23 * k23));
-  // H_ijkl g_kl (eq. 15) for the five components; b_ik g_kl sums over k, l
-  // in {x, y} (the spanwise row and column of the gradient vanish)
-  const double a1 = C2 * Av + GAMMA5 / 3.0;
-  const double g[2][2] = {{g00, g01}, {g10, g11}};
-  const double b[2][2] = {{b00, b01}, {b01, b11}};
-  auto hterm = [&](int i, int j) {
-    // (C2 Av + g5/3) g_ij - g5/3 g_ji + g5 sum_k b_ik g_kj - g5 sum_l b_il g_jl
-    double t = a1 * g[i][j] - GAMMA5 / 3.0 * g[j][i];
-    double s1 = 0.0, s2 = 0.0;
-    for (int m = 0; m < 2; ++m) {
-      s1 += b[i][m] * g[m][j];
-      s2 += b[i][m] * g[j][m];
-    }
-    return t + GAMMA5 * s1 - GAMMA5 * s2;
-  };
-  const double slow = 0.5 * (1.0 - C1) * k * om;
-  const int ne = a.ne;
-  a.S[0 * ne + e] = k * hterm(0, 0) + slow;
-  a.S[1 * ne + e] = k * hterm(0, 1);
-  a.S[2 * ne + e] = k * hterm(1, 0);
-  a.S[3 * ne + e] = k * hterm(1, 1) + slow;
-  a.S[4 * ne + e] = slow;   // H_33kl g_kl = 0: no spanwise gradient
-  const double L = CL * fmax(C_XI * k * sqrt(k) / eps, CETA * sqrt(sqrt(a.nu * a.nu * a.nu / eps)));
-  a.L2[e] = L * L;
-  a.Rk[0 * ne + e] = r11;
-  a.Rk[1 * ne + e] = r22;
-  a.Rk[2 * ne + e] = r33;
-  a.Rk[3 * ne + e] = r12;
-  a.Rk[4 * ne + e] = est ? rec[ST_N] : 0.0;
 }
 
-// ---------------------------------------------------------------------------
-// matrix entries per row (M + L^2 K gathered from the element contributions)
-// and its diagonal; the right-hand side and the first residual
+// per element: stresses, k, <omega>, L^2 and the right-hand side of eq. (14)
+__global__ __launch_bounds__(BLK) void k_relax_inputs(Args a) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  bool est = false;
+  if (e < a.ne) {
+    const double* f0 = a.fields + (size_t)a.tri[3 * e] * NFIELD;
+    const double* f1 = a.fields + (size_t)a.tri[3 * e + 1] * NFIELD;
+    const double* f2 = a.fields + (size_t)a.tri[3 * e + 2] * NFIELD;
+    auto cen = [&](int j) { return (f0[j] + f1[j] + f2[j]) / 3.0; };
+    const double* rec = a.stats + (size_t)e * a.nstat;
+    double r11, r22, r33, r12;
+    est = rec[ST_N] >= (double)N_MIN;
+    if (est) {
+      // central second moments in pair order (uu uv uw up vv vw vp ww wp pp)
+      r11 = rec[ST_M2]; r12 = rec[ST_M2 + 1]; r22 = rec[ST_M2 + 4]; r33 = rec[ST_M2 + 7];
+    } else {
+      r11 = cen(F_R11); r22 = cen(F_R22); r33 = cen(F_R33); r12 = cen(F_R12);
+    }
+    const double tr = r11 + r22 + r33;
+    const double k = 0.5 * tr;
+    const double eps = cen(F_EPS);
+    const double om = 2.0 * eps / (k + sqrt(k * k + 4.0 * a.nu * CT * CT * eps));
+    // d<U_k>/dx_l for k, l in {x, y}
+    const double g[2][2] = {{cen(F_DUDX), cen(F_DUDY)}, {cen(F_DVDX), cen(F_DVDY)}};
+    // anisotropy (eq. 17) and A_v (eq. 16); R13 = R23 = 0
+    const double b00 = r11 / tr - 1.0 / 3.0, b11 = r22 / tr - 1.0 / 3.0, b01 = r12 / tr;
+    const double det = r33 * (r11 * r22 - r12 * r12);
+    const double k23 = 2.0 * k / 3.0;
+    const double Av = fmin(1.0, CV * det / (k23 * k23 * k23));
+    // H_ijkl g_kl (eq. 15); b_ik g_kl sums over k, l in {x, y} (the spanwise
+    // row and column of the gradient vanish)
+    const double a1 = C2 * Av + GAMMA5 / 3.0;
+    const double b[2][2] = {{b00, b01}, {b01, b11}};
+    auto hterm = [&](int i, int j) {
+      // (C2 Av + g5/3) g_ij - g5/3 g_ji + g5 sum_m b_im g_mj - g5 sum_m b_im g_jm
+      double t = a1 * g[i][j] - GAMMA5 / 3.0 * g[j][i];
+      double s1 = 0.0, s2 = 0.0;
+      for (int m = 0; m < 2; ++m) {
+        s1 += b[i][m] * g[m][j];
+        s2 += b[i][m] * g[j][m];
+      }
+      return t + GAMMA5 * s1 - GAMMA5 * s2;
+    };
+    const double slow = 0.5 * (1.0 - C1) * k * om;
+    const int ne = a.ne;
+    a.S[0 * ne + e] = k * hterm(0, 0) + slow;
+    a.S[1 * ne + e] = k * hterm(0, 1);
+    a.S[2 * ne + e] = k * hterm(1, 0);
+    a.S[3 * ne + e] = k * hterm(1, 1) + slow;
+    a.S[4 * ne + e] = slow;   // H_33kl g_kl = 0: no spanwise gradient
+    const double L = CL * fmax(C_XI * k * sqrt(k) / eps, CETA * sqrt(sqrt(a.nu * a.nu * a.nu / eps)));
+    a.L2[e] = L * L;
+    a.Rk[0 * ne + e] = r11;
+    a.Rk[1 * ne + e] = r22;
+    a.Rk[2 * ne + e] = r33;
+    a.Rk[3 * ne + e] = r12;
+  }
+  const uint64_t m = __ballot(est);
+  if ((threadIdx.x & (WAVE - 1)) == 0 && m) atomicAdd(&a.ctl->from_stats, (int)__popcll(m));
+}
 
-__global__ void k_relax_matrix(Args a) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= a.nc) return;
-  for (int j = a.rowptr[i]; j < a.rowptr[i + 1]; ++j) {
-    double v = 0.0;
+// matrix entries (M + L^2 K gathered from the element contributions in
+// their fixed order), one thread per padded slot, and the inverse diagonal
+__global__ __launch_bounds__(BLK) void k_relax_matrix(Args a) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= a.ellw * a.nc) return;
+  const int j = a.enz[q];
+  double v = 0.0;
+  if (j >= 0) {
     for (int t = a.cptr[j]; t < a.cptr[j + 1]; ++t) {
       const int c = a.cidx[t];
       const int e = c / 9, ab = c - 9 * e, aa = ab / 3, bb = ab - 3 * aa;
       const double m = a.area[e] / 12.0 * (aa == bb ? 2.0 : 1.0);
       v += m + a.L2[e] * a.Ke[9 * e + ab];
     }
-    a.aval[j] = v;
-    if (a.col[j] == i) a.diag[i] = v;
   }
+  a.aval[q] = v;
+  const int i = q % a.nc;
+  if (j >= 0 && a.dpos[i] == j) a.dinv[i] = 1.0 / v;
 }
 
-// block sums of NV values per thread in a fixed tree; thread 0 holds the totals
-template <int NV> __device__ void block_sum(double (&v)[NV], double (*sh)[BLK]) {
-  const int t = threadIdx.x;
-  for (int c = 0; c < NV; ++c) sh[c][t] = v[c];
+// ---------------------------------------------------------------------------
+// reductions
+
+// One DPP move of a double (both halves with the same lane pattern).
+template <int CTRL> __device__ __forceinline__ double dpp_move(double v) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+
+__device__ __forceinline__ double read_lane(double v, int lane) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, lane);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), lane);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// The sum over the 64 lanes of a wavefront (every lane active), the same
+// value in every lane: within each row of 16 lanes, partners exchange by DPP
+// (lane ^ 1, lane ^ 2, then the mirrored half-row and row), so every lane of
+// a row holds the row sum; then the four row sums in order.  A fixed order,
+// and each pair of partners adds the same two numbers.
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_move<0xB1>(v);    // quad_perm [1, 0, 3, 2]
+  v += dpp_move<0x4E>(v);    // quad_perm [2, 3, 0, 1]
+  v += dpp_move<0x141>(v);   // row_half_mirror
+  v += dpp_move<0x140>(v);   // row_mirror
+  return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
+}
+
+// The block's sums of K values per thread (wavefront sums, then the
+// wavefronts in turn), valid in thread 0.
+template <int K> __device__ void block_sum(double (&v)[K]) {
+  __shared__ double sw[WPB][K];
+  const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+  double t[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) t[k] = wave_sum(v[k]);
+  if (lane == 0)
+    for (int k = 0; k < K; ++k) sw[wv][k] = t[k];
   __syncthreads();
-  for (int s = BLK / 2; s > 0; s >>= 1) {
-    if (t < s)
-      for (int c = 0; c < NV; ++c) sh[c][t] = sh[c][t] + sh[c][t + s];
-    __syncthreads();
-  }
-  for (int c = 0; c < NV; ++c) v[c] = sh[c][0];
-  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int k = 0; k < K; ++k) {
+      double u = sw[0][k];
+      for (int q = 1; q < WPB; ++q) u += sw[q][k];
+      v[k] = u;
+    }
 }
 
-// the global sums of one kind of partial (0 p.q, 1 r.z, 2 r.r), the same
-// fixed-order sum in every block
-__device__ void global_sum(const Args& a, int kind, double (&out)[NC], double (*sh)[BLK]) {
-  double v[NC];
-  for (int c = 0; c < NC; ++c) v[c] = 0.0;
-  for (int b = threadIdx.x; b < a.nblk; b += BLK)
-    for (int c = 0; c < NC; ++c) v[c] += a.part[(size_t)(b * 3 + kind) * NC + c];
-  block_sum<NC>(v, sh);
-  for (int c = 0; c < NC; ++c) out[c] = v[c];
+// Sums over the blocks of a launch of K partials per (component, block),
+// src[(c * nbx + bx) * K + k], into tot[c][k], computed by every wavefront
+// for itself (lane l adds blocks l, l + 64, ... in turn, then wave_sum): a
+// fixed order, the same in every block.
+template <int K> __device__ void total_partials(const Args& a, const double* src, double (&tot)[NC][K]) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  double t[NC][K];
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+#pragma unroll
+    for (int k = 0; k < K; ++k) t[c][k] = 0.0;
+  for (int bx = lane; bx < a.nbx; bx += WAVE)
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int k = 0; k < K; ++k) t[c][k] += src[((size_t)c * a.nbx + bx) * K + k];
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+#pragma unroll
+    for (int k = 0; k < K; ++k) tot[c][k] = wave_sum(t[c][k]);
 }
 
-// r = b - A x, z = r / diag, partials of r.z and r.r; b.b into hist[0]'s
-// neighbour slot (hist row 0 holds b.b, the iterations start at row 1)
-__global__ __launch_bounds__(BLK) void k_relax_start(Args a) {
-  __shared__ double sh[3 * NC][BLK];
-  const int i = blockIdx.x * BLK + threadIdx.x;
-  const int nc = a.nc;
-  double rz[NC], rr[NC], bb[NC];
-  for (int c = 0; c < NC; ++c) rz[c] = rr[c] = bb[c] = 0.0;
+// the recurrences of one unknown: s = w + beta s, r' = r - alpha s, u' = r' / d;
+// neighbours and owners evaluate them with the same operations
+__device__ __forceinline__ double s_next(double w, double s, double beta) { return __builtin_fma(beta, s, w); }
+__device__ __forceinline__ double r_next(double r, double s, double alpha) { return __builtin_fma(-alpha, s, r); }
+
+// ---------------------------------------------------------------------------
+// start: r0 = b - A x0 and (b, b) partials (first launch); w0 = A u0 and the
+// partials of iteration 0 (second launch); p and s start at zero
+
+__global__ __launch_bounds__(BLK) void k_relax_start1(Args a) {
+  const int i = blockIdx.x * BLK + threadIdx.x, c = blockIdx.y, nc = a.nc;
+  double bb[1] = {0.0};
   if (i < nc) {
-    double bv[NC];
-    for (int c = 0; c < NC; ++c) bv[c] = 0.0;
+    double bv = 0.0;
     for (int t = a.incptr[i]; t < a.incptr[i + 1]; ++t) {
       const int e = a.inc[t] / 3;
-      const double w = a.area[e] / 3.0;
-      for (int c = 0; c < NC; ++c) bv[c] += a.S[(size_t)c * a.ne + e] * w;
+      bv += a.S[(size_t)c * a.ne + e] * (a.area[e] / 3.0);
     }
-    double ax[NC];
-    for (int c = 0; c < NC; ++c) ax[c] = 0.0;
-    for (int j = a.rowptr[i]; j < a.rowptr[i + 1]; ++j) {
-      const double v = a.aval[j];
-      const int cj = a.col[j];
-      for (int c = 0; c < NC; ++c) ax[c] += v * a.x[(size_t)c * nc + cj];
-    }
-    const double dinv = 1.0 / a.diag[i];
-    for (int c = 0; c < NC; ++c) {
-      const double rv = bv[c] - ax[c];
-      const double zv = rv * dinv;
-      a.r[(size_t)c * nc + i] = rv;
-      a.z[(size_t)c * nc + i] = zv;
-      rz[c] = rv * zv;
-      rr[c] = rv * rv;
-      bb[c] = bv[c] * bv[c];
-    }
+    const double* xc = a.x + (size_t)c * nc;
+    double ax = 0.0;
+    for (int t = 0; t < a.ellw; ++t) ax = __builtin_fma(a.aval[t * nc + i], xc[a.ecol[t * nc + i]], ax);
+    const size_t o = (size_t)c * nc + i;
+    a.r[0][o] = bv - ax;
+    a.p[o] = 0.0;
+    a.s[1][o] = 0.0;
+    bb[0] = bv * bv;
   }
-  block_sum<NC>(rz, sh);
-  block_sum<NC>(rr, sh + NC);
-  block_sum<NC>(bb, sh + 2 * NC);
-  if (threadIdx.x == 0) {
-    for (int c = 0; c < NC; ++c) {
-      a.part[(size_t)(blockIdx.x * 3 + 1) * NC + c] = rz[c];
-      a.part[(size_t)(blockIdx.x * 3 + 2) * NC + c] = rr[c];
-      a.part[(size_t)(blockIdx.x * 3 + 0) * NC + c] = bb[c];   // b.b, summed once by the next kernel
-    }
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0)
-    for (int k = 0; k < 4; ++k) a.flag[k] = 0;
+  block_sum<1>(bb);
+  if (threadIdx.x == 0) a.pbb[(size_t)c * a.nbx + blockIdx.x] = bb[0];
 }
 
-// b.b from the start kernel's partials into hist[0] (one block)
-__global__ __launch_bounds__(BLK) void k_relax_norm(Args a) {
-  __shared__ double sh[NC][BLK];
-  double bb[NC];
-  global_sum(a, 0, bb, sh);
+__global__ __launch_bounds__(BLK) void k_relax_start2(Args a) {
+  const int i = blockIdx.x * BLK + threadIdx.x, c = blockIdx.y, nc = a.nc;
+  double v[3] = {0.0, 0.0, 0.0};
+  if (i < nc) {
+    const double* r0 = a.r[0] + (size_t)c * nc;
+    double acc = 0.0;
+    for (int t = 0; t < a.ellw; ++t) {
+      const int k = a.ecol[t * nc + i];
+      acc = __builtin_fma(a.aval[t * nc + i], r0[k] * a.dinv[k], acc);
+    }
+    const double ri = r0[i], ui = ri * a.dinv[i];
+    a.w[0][(size_t)c * nc + i] = acc;
+    v[0] = ri * ui;
+    v[1] = acc * ui;
+    v[2] = ri * ri;
+  }
+  block_sum<3>(v);
   if (threadIdx.x == 0)
-    for (int c = 0; c < NC; ++c) a.hist[c] = bb[c];
+    for (int k = 0; k < 3; ++k) a.part[0][((size_t)c * a.nbx + blockIdx.x) * 3 + k] = v[k];
+  if (blockIdx.x != 0 || blockIdx.y != 0) return;
+  double tot[NC][1];
+  total_partials<1>(a, a.pbb, tot);
+  if (threadIdx.x == 0)
+    for (int q = 0; q < NC; ++q) a.ctl->ref[q] = tot[q][0];   // (r0, r0) where b = 0: set by iteration 0
 }
 
-// the done flag as one value for the whole block (read by one thread)
-__device__ bool block_done(const Args& a) {
-  __shared__ int done;
-  if (threadIdx.x == 0) done = a.flag[0];
-  __syncthreads();
-  const bool d = done != 0;
-  __syncthreads();
-  return d;
-}
+// ---------------------------------------------------------------------------
+// iteration i (parity par): from the partials of the previous launch, gamma_i
+// = (r_i, u_i), delta_i = (w_i, u_i), rho_i = (r_i, r_i); stop when every
+// component has rho_i <= tol^2 ref or i reaches the limit; else beta_i =
+// gamma_i / gamma_{i-1}, alpha_i = gamma_i / (delta_i - beta_i gamma_i /
+// alpha_{i-1}), and p = u + beta p, s = w + beta s, x += alpha p,
+// r -= alpha s, u = M^-1 r, w = A u with the partials of iteration i + 1.
+// W: the padded row length.  Every load is issued before any decision (rows
+// past nc read the last row and store nothing): the row's entries, its own
+// values, the scalars and the partials in one round, then the neighbours'
+// values in a second.
 
-// converged when r.r <= tol2 b.b for every component (a zero right-hand side
-// converges at once)
-__device__ bool converged(const Args& a, double (*sh)[BLK]) {
-  double rr[NC];
-  global_sum(a, 2, rr, sh);
+template <int W> __global__ __launch_bounds__(BLK) void k_relax_iter(Args a, int par) {
+  const int c = blockIdx.y, nc = a.nc, lane = threadIdx.x & (WAVE - 1);
+  const int i = blockIdx.x * BLK + threadIdx.x;
+  const bool live = i < nc;
+  const int ii = live ? i : nc - 1;
+  const int ro = par, rn = par ^ 1;
+  const double* rold = a.r[ro] + (size_t)c * nc;
+  const double* wold = a.w[ro] + (size_t)c * nc;
+  const double* sold = a.s[rn] + (size_t)c * nc;   // s of the previous iteration
+  const size_t o = (size_t)c * nc + ii;
+  int cl[W];
+  double av[W];
+#pragma unroll
+  for (int t = 0; t < W; ++t) {
+    cl[t] = a.ecol[t * nc + ii];
+    av[t] = a.aval[t * nc + ii];
+  }
+  const double r_o = rold[ii], w_o = wold[ii], s_o = sold[ii], p_o = a.p[o], x_o = a.x[o], d_o = a.dinv[ii];
+  const Ctl* ctl = a.ctl;
+  const Scal& prev = ctl->sc[par ^ 1];
+  const int pdone = prev.done, it = prev.iter, max_iters = ctl->max_iters;
+  const double gold = prev.gamma[c], aold = prev.alpha[c], tol2 = ctl->tol2;
+  double ref[NC];
+#pragma unroll
+  for (int q = 0; q < NC; ++q) ref[q] = ctl->ref[q];
+  // partials of the blocks lane, lane + 64, ... (a fixed order per lane)
+  const double* src = a.part[par];
+  double tp[NC][3];
+  {
+    const int bx = lane < a.nbx ? lane : 0;
+    const double keep = lane < a.nbx ? 1.0 : 0.0;
+#pragma unroll
+    for (int q = 0; q < NC; ++q)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) tp[q][k] = keep * src[((size_t)q * a.nbx + bx) * 3 + k];
+  }
+  // the neighbours' values
+  double gr[W], gw[W], gs[W], gd[W];
+#pragma unroll
+  for (int t = 0; t < W; ++t) {
+    const int k = cl[t];
+    gr[t] = rold[k];
+    gw[t] = wold[k];
+    gs[t] = sold[k];
+    gd[t] = a.dinv[k];
+  }
+  for (int bx = lane + WAVE; bx < a.nbx; bx += WAVE)
+#pragma unroll
+    for (int q = 0; q < NC; ++q)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) tp[q][k] += src[((size_t)q * a.nbx + bx) * 3 + k];
+  if (pdone) return;
+  double tot[NC][3];
+#pragma unroll
+  for (int q = 0; q < NC; ++q)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) tot[q][k] = wave_sum(tp[q][k]);
   bool ok = true;
-  for (int c = 0; c < NC; ++c) ok = ok && rr[c] <= a.tol2 * a.hist[c];
-  return ok;
-}
-
-// iteration it, first half: beta from r.z, the new direction p (into the
-// other buffer), q = A p, partials of p.q
-__global__ __launch_bounds__(BLK) void k_relax_cg_a(Args a, int it) {
-  __shared__ double sh[NC][BLK];
-  if (block_done(a)) return;
-  if (converged(a, sh)) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      a.flag[0] = 1;
-      a.flag[1] = it;
-    }
-    return;
+#pragma unroll
+  for (int q = 0; q < NC; ++q) {
+    // where b = 0 the reference is (r0, r0), known from iteration 0 on
+    const double rq = ref[q] > 0.0 ? ref[q] : (it == 0 ? tot[q][2] : ref[q]);
+    ok = ok && tot[q][2] <= tol2 * rq;
   }
-  double rz[NC];
-  global_sum(a, 1, rz, sh);
-  if (blockIdx.x == 0 && threadIdx.x == 0)
-    for (int c = 0; c < NC; ++c) a.hist[(size_t)(it + 1) * NC + c] = rz[c];
-  double beta[NC];
-  for (int c = 0; c < NC; ++c) {
-    const double old = it == 0 ? 0.0 : a.hist[(size_t)it * NC + c];
-    beta[c] = old != 0.0 ? rz[c] / old : 0.0;   // a component already at r = 0 keeps p = z
-  }
-  const double* po = a.p[it & 1];
-  double* pn = a.p[(it + 1) & 1];
-  const int nc = a.nc;
-  const int i = blockIdx.x * BLK + threadIdx.x;
-  double pq[NC];
-  for (int c = 0; c < NC; ++c) pq[c] = 0.0;
-  if (i < nc) {
-    double qv[NC];
-    for (int c = 0; c < NC; ++c) qv[c] = 0.0;
-    for (int j = a.rowptr[i]; j < a.rowptr[i + 1]; ++j) {
-      const double v = a.aval[j];
-      const int cj = a.col[j];
-      for (int c = 0; c < NC; ++c) qv[c] += v * (a.z[(size_t)c * nc + cj] + beta[c] * po[(size_t)c * nc + cj]);
+  double g = 0.0, d = 0.0;
+#pragma unroll
+  for (int q = 0; q < NC; ++q)
+    if (q == c) {
+      g = tot[q][0];
+      d = tot[q][1];
     }
-    for (int c = 0; c < NC; ++c) {
-      const double pv = a.z[(size_t)c * nc + i] + beta[c] * po[(size_t)c * nc + i];
-      pn[(size_t)c * nc + i] = pv;
-      a.q[(size_t)c * nc + i] = qv[c];
-      pq[c] = pv * qv[c];
+  const double beta = gold != 0.0 ? g / gold : 0.0;
+  const double den = aold != 0.0 ? d - beta * g / aold : d;
+  const double alpha = den != 0.0 ? g / den : 0.0;
+  const bool stop = ok || it >= max_iters;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    Ctl* cw = a.ctl;
+    Scal& cur = cw->sc[par];
+    if (blockIdx.y == 0) {
+      cur.iter = it + 1;
+      cur.done = stop ? 1 : 0;
+      if (it == 0)
+        for (int q = 0; q < NC; ++q)
+          if (!(ref[q] > 0.0)) cw->ref[q] = tot[q][2];
+      if (stop) {
+        cw->iter = it;
+        cw->done = 1;
+        cw->converged = ok ? 1 : 0;
+        for (int q = 0; q < NC; ++q) cw->rho[q] = tot[q][2];
+      }
     }
+    cur.alpha[c] = alpha;
+    cur.gamma[c] = g;
   }
-  block_sum<NC>(pq, sh);
+  if (stop) return;
+  double acc = 0.0;
+#pragma unroll
+  for (int t = 0; t < W; ++t) {
+    const double un = r_next(gr[t], s_next(gw[t], gs[t], beta), alpha) * gd[t];
+    acc = __builtin_fma(av[t], un, acc);
+  }
+  const double sn = s_next(w_o, s_o, beta);
+  const double pn = __builtin_fma(beta, p_o, r_o * d_o);
+  const double rnw = r_next(r_o, sn, alpha);
+  const double un = rnw * d_o;
+  double v[3] = {0.0, 0.0, 0.0};
+  if (live) {
+    a.p[o] = pn;
+    a.x[o] = __builtin_fma(alpha, pn, x_o);
+    a.s[ro][o] = sn;
+    a.r[rn][o] = rnw;
+    a.w[rn][o] = acc;
+    v[0] = rnw * un;
+    v[1] = acc * un;
+    v[2] = rnw * rnw;
+  }
+  block_sum<3>(v);
   if (threadIdx.x == 0)
-    for (int c = 0; c < NC; ++c) a.part[(size_t)(blockIdx.x * 3 + 0) * NC + c] = pq[c];
+    for (int k = 0; k < 3; ++k) a.part[rn][((size_t)c * a.nbx + blockIdx.x) * 3 + k] = v[k];
 }
 
-// iteration it, second half: alpha, x += alpha p, r -= alpha q, z = r / diag,
-// partials of r.z and r.r
-__global__ __launch_bounds__(BLK) void k_relax_cg_b(Args a, int it) {
-  __shared__ double sh[NC][BLK];
-  if (block_done(a)) return;
-  double pq[NC];
-  global_sum(a, 0, pq, sh);
-  double alpha[NC];
-  for (int c = 0; c < NC; ++c) {
-    const double rz = a.hist[(size_t)(it + 1) * NC + c];
-    alpha[c] = pq[c] != 0.0 ? rz / pq[c] : 0.0;
-  }
-  const double* pn = a.p[(it + 1) & 1];
-  const int nc = a.nc;
-  const int i = blockIdx.x * BLK + threadIdx.x;
-  double rz[NC], rr[NC];
-  for (int c = 0; c < NC; ++c) rz[c] = rr[c] = 0.0;
-  if (i < nc) {
-    const double dinv = 1.0 / a.diag[i];
-    for (int c = 0; c < NC; ++c) {
-      const size_t o = (size_t)c * nc + i;
-      a.x[o] = a.x[o] + alpha[c] * pn[o];
-      const double rv = a.r[o] - alpha[c] * a.q[o];
-      const double zv = rv * dinv;
-      a.r[o] = rv;
-      a.z[o] = zv;
-      rz[c] = rv * zv;
-      rr[c] = rv * rv;
-    }
-  }
-  block_sum<NC>(rz, sh);
-  __shared__ double sh2[NC][BLK];
-  block_sum<NC>(rr, sh2);
-  if (threadIdx.x == 0) {
-    for (int c = 0; c < NC; ++c) {
-      a.part[(size_t)(blockIdx.x * 3 + 1) * NC + c] = rz[c];
-      a.part[(size_t)(blockIdx.x * 3 + 2) * NC + c] = rr[c];
-    }
-  }
-}
-
-// after the iterations the host enqueued (one block): r.r and b.b of every
-// component into res; convergence recorded if the loop ran out first
-__global__ __launch_bounds__(BLK) void k_relax_finish(Args a, int iters) {
-  __shared__ double sh[NC][BLK];
-  double rr[NC];
-  global_sum(a, 2, rr, sh);
-  if (threadIdx.x == 0) {
-    bool ok = true;
-    for (int c = 0; c < NC; ++c) {
-      a.res[c] = rr[c];
-      a.res[NC + c] = a.hist[c];
-      ok = ok && rr[c] <= a.tol2 * a.hist[c];
-    }
-    if (!a.flag[0]) {
-      a.flag[0] = ok ? 1 : 0;
-      a.flag[1] = iters;
-    }
+// the launch of the padded row length w (1..ELL_MAX)
+inline const void* relax_iter_kernel(int w) {
+  switch (w) {
+    case 1: return (const void*)k_relax_iter<1>;
+    case 2: return (const void*)k_relax_iter<2>;
+    case 3: return (const void*)k_relax_iter<3>;
+    case 4: return (const void*)k_relax_iter<4>;
+    case 5: return (const void*)k_relax_iter<5>;
+    case 6: return (const void*)k_relax_iter<6>;
+    case 7: return (const void*)k_relax_iter<7>;
+    case 8: return (const void*)k_relax_iter<8>;
+    case 9: return (const void*)k_relax_iter<9>;
+    case 10: return (const void*)k_relax_iter<10>;
+    case 11: return (const void*)k_relax_iter<11>;
+    case 12: return (const void*)k_relax_iter<12>;
+    case 13: return (const void*)k_relax_iter<13>;
+    case 14: return (const void*)k_relax_iter<14>;
+    case 15: return (const void*)k_relax_iter<15>;
+    case 16: return (const void*)k_relax_iter<16>;
+    default: return nullptr;
   }
 }
 
 // ---------------------------------------------------------------------------
-// G and C0 per vertex (eqs. 12-13) into the coefficient table
-
+// G and C0 per vertex (eqs. 12-13) into the coefficient table.
 // wp_out (V x 5, may be null): wp at every vertex; coef_out (V x 6, may be
 // null): G_11 G_12 G_21 G_22 G_33 C0 eps before rounding to the table's type
-template <typename T> __global__ void k_relax_coef(Args a, T* coef, double* wp_out, double* coef_out) {
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= a.nv) return;
-  const int c = a.canon[v];
-  const int ne = a.ne, nc = a.nc;
-  double ws = 0.0, r11 = 0.0, r22 = 0.0, r33 = 0.0, r12 = 0.0;
-  for (int t = a.incptr[c]; t < a.incptr[c + 1]; ++t) {
-    const int e = a.inc[t] / 3;
-    const double w = a.area[e];
-    ws += w;
-    r11 += w * a.Rk[0 * ne + e];
-    r22 += w * a.Rk[1 * ne + e];
-    r33 += w * a.Rk[2 * ne + e];
-    r12 += w * a.Rk[3 * ne + e];
-  }
-  r11 /= ws; r22 /= ws; r33 /= ws; r12 /= ws;
-  const double k = 0.5 * (r11 + r22 + r33);
-  const double eps = a.fields[(size_t)v * NFIELD + F_EPS];
-  const double w11 = a.x[0 * (size_t)nc + c], w12 = a.x[1 * (size_t)nc + c], w21 = a.x[2 * (size_t)nc + c];
-  const double w22 = a.x[3 * (size_t)nc + c], w33 = a.x[4 * (size_t)nc + c];
-  const double k2 = 2.0 * k;
-  T* q = coef + (size_t)v * NCOEF;
-  q[C_G11] = (T)((2.0 * w11 - eps) / k2);
-  q[C_G12] = (T)((2.0 * w12) / k2);
-  q[C_G21] = (T)((2.0 * w21) / k2);
-  q[C_G22] = (T)((2.0 * w22 - eps) / k2);
-  q[C_G33] = (T)((2.0 * w33 - eps) / k2);
-  const double wr = w11 * r11 + w12 * r12 + w21 * r12 + w22 * r22 + w33 * r33;
-  double C0 = -2.0 * wr / (3.0 * k * eps);
-  if (C0 < 0.0) {
-    C0 = 0.0;
-    atomicAdd(&a.flag[2], 1);
-  }
-  q[C_C0EPS] = (T)(C0 * eps);
-  if (coef_out) {
-    double* o = coef_out + 6 * (size_t)v;
-    o[0] = (2.0 * w11 - eps) / k2;
-    o[1] = (2.0 * w12) / k2;
-    o[2] = (2.0 * w21) / k2;
-    o[3] = (2.0 * w22 - eps) / k2;
-    o[4] = (2.0 * w33 - eps) / k2;
-    o[5] = C0 * eps;
-  }
-  if (wp_out) {
-    wp_out[5 * (size_t)v + 0] = w11;
-    wp_out[5 * (size_t)v + 1] = w12;
-    wp_out[5 * (size_t)v + 2] = w21;
-    wp_out[5 * (size_t)v + 3] = w22;
-    wp_out[5 * (size_t)v + 4] = w33;
-  }
-}
 
-// elements whose stresses came from the statistics (one block)
-__global__ __launch_bounds__(BLK) void k_relax_count(Args a) {
-  __shared__ int cnt[BLK];
-  int n = 0;
-  for (int e = threadIdx.x; e < a.ne; e += BLK) n += a.Rk[4 * a.ne + e] > 0.0 ? 1 : 0;
-  cnt[threadIdx.x] = n;
-  __syncthreads();
-  for (int s = BLK / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) cnt[threadIdx.x] += cnt[threadIdx.x + s];
-    __syncthreads();
+template <typename T>
+__global__ __launch_bounds__(BLK) void k_relax_coef(Args a, T* coef, double* wp_out, double* coef_out) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  bool neg = false;
+  if (v < a.nv) {
+    const int c = a.canon[v];
+    const int ne = a.ne, nc = a.nc;
+    double ws = 0.0, r11 = 0.0, r22 = 0.0, r33 = 0.0, r12 = 0.0;
+    for (int t = a.incptr[c]; t < a.incptr[c + 1]; ++t) {
+      const int e = a.inc[t] / 3;
+      const double w = a.area[e];
+      ws += w;
+      r11 += w * a.Rk[0 * ne + e];
+      r22 += w * a.Rk[1 * ne + e];
+      r33 += w * a.Rk[2 * ne + e];
+      r12 += w * a.Rk[3 * ne + e];
+    }
+    r11 /= ws; r22 /= ws; r33 /= ws; r12 /= ws;
+    const double k = 0.5 * (r11 + r22 + r33);
+    const double eps = a.fields[(size_t)v * NFIELD + F_EPS];
+    const double w11 = a.x[0 * (size_t)nc + c], w12 = a.x[1 * (size_t)nc + c], w21 = a.x[2 * (size_t)nc + c];
+    const double w22 = a.x[3 * (size_t)nc + c], w33 = a.x[4 * (size_t)nc + c];
+    const double k2 = 2.0 * k;
+    const double g11 = (2.0 * w11 - eps) / k2, g12 = (2.0 * w12) / k2, g21 = (2.0 * w21) / k2;
+    const double g22 = (2.0 * w22 - eps) / k2, g33 = (2.0 * w33 - eps) / k2;
+    const double wr = w11 * r11 + w12 * r12 + w21 * r12 + w22 * r22 + w33 * r33;
+    double C0 = -2.0 * wr / (3.0 * k * eps);
+    if (C0 < 0.0) {
+      C0 = 0.0;
+      neg = true;
+    }
+    T* q = coef + (size_t)v * NCOEF;
+    q[C_G11] = (T)g11;
+    q[C_G12] = (T)g12;
+    q[C_G21] = (T)g21;
+    q[C_G22] = (T)g22;
+    q[C_G33] = (T)g33;
+    q[C_C0EPS] = (T)(C0 * eps);
+    if (coef_out) {
+      double* o = coef_out + 6 * (size_t)v;
+      o[0] = g11; o[1] = g12; o[2] = g21; o[3] = g22; o[4] = g33; o[5] = C0 * eps;
+    }
+    if (wp_out) {
+      double* o = wp_out + 5 * (size_t)v;
+      o[0] = w11; o[1] = w12; o[2] = w21; o[3] = w22; o[4] = w33;
+    }
   }
-  if (threadIdx.x == 0) a.flag[3] = cnt[0];
+  const uint64_t m = __ballot(neg);
+  if ((threadIdx.x & (WAVE - 1)) == 0 && m) atomicAdd(&a.ctl->clamped, (int)__popcll(m));
 }
 
 }  // namespace relax
