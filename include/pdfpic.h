@@ -299,6 +299,14 @@ pdf_status pdf_estimate_statistics(pdf_ctx* ctx, double* out, int32_t out_on_hos
 pdf_status pdf_elliptic_relaxation(pdf_ctx* ctx, int32_t max_iters, double tol, double* wp, double* coef,
                                    int32_t* info, double* resid);
 
+/* Size of the relaxation system of the mesh (section 2.1, the Galerkin
+   system of eq. 14): out (host, 3 int64) = unknowns (vertices, periodic
+   copies joined), nonzeros of the matrix, and the padded row length the
+   solver stores (the longest row).  Errors: PDF_E_ARG, PDF_E_STATE (before
+   pdf_init_mesh, or model 0), PDF_E_MESH (a row longer than 16 entries: the
+   relaxation is unavailable on the mesh). */
+pdf_status pdf_relaxation_size(const pdf_ctx* ctx, int64_t* out);
+
 /* Run metrics from the device counters, into out (8 int64, host; waits):
    particles; arrivals written by the last step (particles now in another
    element than before it, 0 right after a repack, which folds them in);

@@ -27,7 +27,7 @@ NFIELD = 20
 # exported entry points (the declarations of include/pdfpic.h)
 ENTRY_POINTS = ("pdf_create", "pdf_query_sizes", "pdf_init_mesh", "pdf_seed_particles", "pdf_step",
                 "pdf_step_graph", "pdf_step_timed", "pdf_autotune", "pdf_set_launch", "pdf_repack", "pdf_repack_count",
-                "pdf_estimate_statistics", "pdf_elliptic_relaxation", "pdf_nstat", "pdf_sync", "pdf_metrics",
+                "pdf_estimate_statistics", "pdf_elliptic_relaxation", "pdf_relaxation_size", "pdf_nstat", "pdf_sync", "pdf_metrics",
                 "pdf_mlp_work_floats", "pdf_mlp_dataset", "pdf_mlp_forward", "pdf_mlp_grad", "pdf_mlp_grad_noalloc", "pdf_mlp_train",
                 "pdf_mlp_norm", "pdf_mlp_round", "pdf_mlp_infer", "pdf_mlp_attach",
                 "pdf_get_state", "pdf_set_state", "pdf_set_step", "pdf_get_omega", "pdf_omega_fields", "pdf_navg", "pdf_average_attach",
@@ -129,6 +129,8 @@ def load_library():
     L.pdf_estimate_statistics.argtypes = [vp, vp, i32]
     L.pdf_elliptic_relaxation.restype = i32
     L.pdf_elliptic_relaxation.argtypes = [vp, i32, ctypes.c_double, vp, vp, vp, vp]
+    L.pdf_relaxation_size.restype = i32
+    L.pdf_relaxation_size.argtypes = [vp, vp]
     L.pdf_nstat.restype = i32
     L.pdf_nstat.argtypes = [vp]
     L.pdf_sync.restype = i32
@@ -347,6 +349,12 @@ class Simulation:
             out["wp"] = wp.cpu().numpy()
             out["coef"] = coef.cpu().numpy()
         return out
+
+    def relaxation_size(self) -> dict:
+        """Unknowns, nonzeros and the padded row length of the relaxation system."""
+        out = np.zeros(3, np.int64)
+        self._check(load_library().pdf_relaxation_size(self.ctx, _ptr(out)), "pdf_relaxation_size")
+        return dict(unknowns=int(out[0]), nonzeros=int(out[1]), row_width=int(out[2]))
 
     def state_device(self, ens: int = 0):
         n = self.count(ens)

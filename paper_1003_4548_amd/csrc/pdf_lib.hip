@@ -36,7 +36,7 @@ struct Layout {
   int64_t vtx, tri, nbr, ekind, inv2a, alpha, wnorm, fields, coef, erec, om0, somega, omw;
   // elliptic relaxation (model 1 only): sparsity, element data, solver vectors
   int64_t rx_canon, rx_rep, rx_ecol, rx_enz, rx_dpos, rx_cptr, rx_cidx, rx_incptr, rx_inc, rx_Ke, rx_area;
-  int64_t rx_S, rx_L2, rx_Rk, rx_aval, rx_dinv, rx_x, rx_p, rx_r[2], rx_w[2], rx_s[2], rx_part[2], rx_pbb, rx_ctl;
+  int64_t rx_S, rx_L2, rx_Rk, rx_aval, rx_dinv, rx_x, rx_p, rx_rec[2], rx_part[2], rx_pbb, rx_ctl;
   int64_t start, cap, cap0, nstart, ncap, ns[3], nm[3], rate, idoff, order, seed, src;
   int64_t buf0, buf1, ovf, ovf_cell, stats, ctl, flag, metrics;
   int64_t total;
@@ -97,9 +97,7 @@ Layout make_layout(int32_t nv, int32_t ne, int32_t nens, int64_t slots, int32_t 
     L.rx_x = take(on * vec);
     L.rx_p = take(on * vec);
     for (int b = 0; b < 2; ++b) {
-      L.rx_r[b] = take(on * vec);
-      L.rx_w[b] = take(on * vec);
-      L.rx_s[b] = take(on * vec);
+      L.rx_rec[b] = take(on * relax::NC * nc * (int64_t)sizeof(relax::Rec));
       L.rx_part[b] = take(on * relax::NC * nbx * 3 * 8);
     }
     L.rx_pbb = take(on * relax::NC * nbx * 8);
@@ -1409,11 +1407,7 @@ static relax::Args relax_args(pdf_ctx* c) {
   a.dinv = (double*)(d + L.rx_dinv);
   a.x = (double*)(d + L.rx_x);
   a.p = (double*)(d + L.rx_p);
-  for (int b = 0; b < 2; ++b) {
-    a.r[b] = (double*)(d + L.rx_r[b]);
-    a.w[b] = (double*)(d + L.rx_w[b]);
-    a.s[b] = (double*)(d + L.rx_s[b]);
-  }
+  for (int b = 0; b < 2; ++b) a.rec[b] = (relax::Rec*)(d + L.rx_rec[b]);
   a.part[0] = (double*)(d + L.rx_part[0]);
   a.part[1] = (double*)(d + L.rx_part[1]);
   a.pbb = (double*)(d + L.rx_pbb);
@@ -1552,6 +1546,16 @@ pdf_status pdf_elliptic_relaxation(pdf_ctx* c, int32_t max_iters, double tol, do
   }
   if (resid)
     for (int q = 0; q < relax::NC; ++q) resid[q] = h.ref[q] > 0.0 ? std::sqrt(h.rho[q] / h.ref[q]) : 0.0;
+  return PDF_OK;
+}
+
+pdf_status pdf_relaxation_size(const pdf_ctx* c, int64_t* out) {
+  if (!c || !out) return PDF_E_ARG;
+  if (!c->mesh_ready || c->p.model != 1) return PDF_E_STATE;
+  if (c->rx_nc == 0) return PDF_E_MESH;
+  out[0] = c->rx_nc;
+  out[1] = c->rx_nnz;
+  out[2] = c->rx_ellw;
   return PDF_OK;
 }
 

@@ -18,9 +18,10 @@
 // does the vector updates, the product with the matrix and the partial inner
 // products.  The product needs the new preconditioned residual u = M^-1 r of
 // the neighbouring unknowns; each thread recomputes it from their values of
-// the previous iteration (r, w = A u, s = A p, kept in two buffers by
-// iteration parity), with the same operations as their owners, so the
-// product is exactly A u.  Every block sums the previous launch's block
+// the previous iteration (r, w = A u, s = A p and the inverse diagonal, one
+// 32-byte record per unknown and component, in two buffers by iteration
+// parity), with the same operations as their owners, so the product is
+// exactly A u.  Every block sums the previous launch's block
 // partials in the same fixed order and derives the iteration's scalars
 // itself, so a launch has two dependent rounds of memory accesses (its own
 // loads, then the gathers of the neighbours' values), no atomics, and every
@@ -66,6 +67,10 @@ struct Ctl {
   int32_t from_stats;           // elements whose stresses came from the particles
 };
 
+struct alignas(32) Rec {
+  double r, w, s, d;
+};
+
 struct Args {
   // mesh (device)
   int32_t ne, nv, nc, nbx, ellw;
@@ -95,9 +100,9 @@ struct Args {
   double* dinv;            // nc: 1 / diagonal
   double* x;               // 5 x nc (the solution; the previous one is the first guess)
   double* p;               // 5 x nc
-  double* r[2];            // 5 x nc each, by iteration parity
-  double* w[2];
-  double* s[2];
+  // per (component, unknown), by iteration parity: r_i, w_i, s_{i-1}, 1/diag
+  // of iteration i in buffer i & 1
+  Rec* rec[2];
   double* part[2];         // 5 x nbx x 3 block partials (r,u) (w,u) (r,r), by parity
   double* pbb;             // 5 x nbx block partials of (b, b)
   Ctl* ctl;
@@ -329,9 +334,11 @@ __global__ __launch_bounds__(BLK) void k_relax_start1(Args a) {
     double ax = 0.0;
     for (int t = 0; t < a.ellw; ++t) ax = __builtin_fma(a.aval[t * nc + i], xc[a.ecol[t * nc + i]], ax);
     const size_t o = (size_t)c * nc + i;
-    a.r[0][o] = bv - ax;
+    Rec& q = a.rec[0][o];
+    q.r = bv - ax;
+    q.s = 0.0;
+    q.d = a.dinv[i];
     a.p[o] = 0.0;
-    a.s[1][o] = 0.0;
     bb[0] = bv * bv;
   }
   block_sum<1>(bb);
@@ -342,14 +349,14 @@ __global__ __launch_bounds__(BLK) void k_relax_start2(Args a) {
   const int i = blockIdx.x * BLK + threadIdx.x, c = blockIdx.y, nc = a.nc;
   double v[3] = {0.0, 0.0, 0.0};
   if (i < nc) {
-    const double* r0 = a.r[0] + (size_t)c * nc;
+    Rec* r0 = a.rec[0] + (size_t)c * nc;
     double acc = 0.0;
     for (int t = 0; t < a.ellw; ++t) {
       const int k = a.ecol[t * nc + i];
-      acc = __builtin_fma(a.aval[t * nc + i], r0[k] * a.dinv[k], acc);
+      acc = __builtin_fma(a.aval[t * nc + i], r0[k].r * r0[k].d, acc);
     }
-    const double ri = r0[i], ui = ri * a.dinv[i];
-    a.w[0][(size_t)c * nc + i] = acc;
+    const double ri = r0[i].r, ui = ri * r0[i].d;
+    r0[i].w = acc;   // the neighbours read r and d of the record only
     v[0] = ri * ui;
     v[1] = acc * ui;
     v[2] = ri * ri;
@@ -381,10 +388,8 @@ template <int W> __global__ __launch_bounds__(BLK) void k_relax_iter(Args a, int
   const int i = blockIdx.x * BLK + threadIdx.x;
   const bool live = i < nc;
   const int ii = live ? i : nc - 1;
-  const int ro = par, rn = par ^ 1;
-  const double* rold = a.r[ro] + (size_t)c * nc;
-  const double* wold = a.w[ro] + (size_t)c * nc;
-  const double* sold = a.s[rn] + (size_t)c * nc;   // s of the previous iteration
+  const Rec* old = a.rec[par] + (size_t)c * nc;
+  Rec* nxt = a.rec[par ^ 1] + (size_t)c * nc;
   const size_t o = (size_t)c * nc + ii;
   int cl[W];
   double av[W];
@@ -393,7 +398,9 @@ template <int W> __global__ __launch_bounds__(BLK) void k_relax_iter(Args a, int
     cl[t] = a.ecol[t * nc + ii];
     av[t] = a.aval[t * nc + ii];
   }
-  const double r_o = rold[ii], w_o = wold[ii], s_o = sold[ii], p_o = a.p[o], x_o = a.x[o], d_o = a.dinv[ii];
+  const double2 rw_o = *reinterpret_cast<const double2*>(&old[ii].r);
+  const double2 sd_o = *reinterpret_cast<const double2*>(&old[ii].s);
+  const double r_o = rw_o.x, w_o = rw_o.y, s_o = sd_o.x, d_o = sd_o.y, p_o = a.p[o], x_o = a.x[o];
   const Ctl* ctl = a.ctl;
   const Scal& prev = ctl->sc[par ^ 1];
   const int pdone = prev.done, it = prev.iter, max_iters = ctl->max_iters;
@@ -413,14 +420,12 @@ template <int W> __global__ __launch_bounds__(BLK) void k_relax_iter(Args a, int
       for (int k = 0; k < 3; ++k) tp[q][k] = keep * src[((size_t)q * a.nbx + bx) * 3 + k];
   }
   // the neighbours' values
-  double gr[W], gw[W], gs[W], gd[W];
+  double2 grw[W], gsd[W];
 #pragma unroll
   for (int t = 0; t < W; ++t) {
     const int k = cl[t];
-    gr[t] = rold[k];
-    gw[t] = wold[k];
-    gs[t] = sold[k];
-    gd[t] = a.dinv[k];
+    grw[t] = *reinterpret_cast<const double2*>(&old[k].r);
+    gsd[t] = *reinterpret_cast<const double2*>(&old[k].s);
   }
   for (int bx = lane + WAVE; bx < a.nbx; bx += WAVE)
 #pragma unroll
@@ -474,7 +479,7 @@ template <int W> __global__ __launch_bounds__(BLK) void k_relax_iter(Args a, int
   double acc = 0.0;
 #pragma unroll
   for (int t = 0; t < W; ++t) {
-    const double un = r_next(gr[t], s_next(gw[t], gs[t], beta), alpha) * gd[t];
+    const double un = r_next(grw[t].x, s_next(grw[t].y, gsd[t].x, beta), alpha) * gsd[t].y;
     acc = __builtin_fma(av[t], un, acc);
   }
   const double sn = s_next(w_o, s_o, beta);
@@ -485,16 +490,15 @@ template <int W> __global__ __launch_bounds__(BLK) void k_relax_iter(Args a, int
   if (live) {
     a.p[o] = pn;
     a.x[o] = __builtin_fma(alpha, pn, x_o);
-    a.s[ro][o] = sn;
-    a.r[rn][o] = rnw;
-    a.w[rn][o] = acc;
+    *reinterpret_cast<double2*>(&nxt[ii].r) = make_double2(rnw, acc);
+    *reinterpret_cast<double2*>(&nxt[ii].s) = make_double2(sn, d_o);
     v[0] = rnw * un;
     v[1] = acc * un;
     v[2] = rnw * rnw;
   }
   block_sum<3>(v);
   if (threadIdx.x == 0)
-    for (int k = 0; k < 3; ++k) a.part[rn][((size_t)c * a.nbx + blockIdx.x) * 3 + k] = v[k];
+    for (int k = 0; k < 3; ++k) a.part[par ^ 1][((size_t)c * a.nbx + blockIdx.x) * 3 + k] = v[k];
 }
 
 // the launch of the padded row length w (1..ELL_MAX)
