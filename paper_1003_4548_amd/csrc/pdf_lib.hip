@@ -10,6 +10,7 @@
 #include <type_traits>
 #include <vector>
 
+#include "pdf_host.hpp"
 #include "pdf_kernels.hpp"
 #include "pdf_mlp.hpp"
 #include "pdf_relax.hpp"
@@ -250,112 +251,28 @@ pdf_status hip_check(pdf_ctx* c, hipError_t e, const char* what) {
   return fail(c, PDF_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-// The structure of the relaxation solve, from the mesh (host bookkeeping; the
-// numbers are computed on the device):
-// * unknowns: the vertices, with the copies of one point of the periodic
-//   domain joined (across a periodic edge, the partner element's vertex that
-//   equals an edge vertex shifted by the edge's period), numbered by their
-//   lowest vertex index;
-// * the matrix rows in CSR form, each nonzero with its element contributions
-//   (element, local row, local column) in increasing order, so that the
-//   device gathers every entry in a fixed order;
-// * the (element, local vertex) pairs of every unknown, in increasing order.
-// Then the element matrices and the first guess (the frozen wp at each
-// unknown's lowest vertex) on the device.  Waits for the stream.
+// The relaxation system's structure from the mesh (host::build_relax_structure:
+// joined seam vertices, CSR rows with their element contributions, padded
+// rows, incidence), copied to the arena; then the element matrices and the
+// first guess (the frozen wp at each unknown's lowest vertex) on the device.
+// Waits for the stream.
 pdf_status relax_setup(pdf_ctx* c, const pdf_mesh* m) {
   const int32_t nv = m->nvert, ne = m->nelem;
-  std::vector<int32_t> root(nv);
-  for (int32_t v = 0; v < nv; ++v) root[v] = v;
-  auto find = [&](int32_t v) {
-    while (root[v] != v) {
-      root[v] = root[root[v]];
-      v = root[v];
-    }
-    return v;
-  };
-  for (int32_t e = 0; e < ne; ++e) {
-    for (int k = 0; k < 3; ++k) {
-      const int32_t kind = m->ekind[3 * e + k];
-      if (kind < PDF_EDGE_PERIODIC_XP) continue;
-      const double sx = kind == PDF_EDGE_PERIODIC_XP ? c->p.Lx : (kind == PDF_EDGE_PERIODIC_XM ? -c->p.Lx : 0.0);
-      const double sy = kind == PDF_EDGE_PERIODIC_YP ? c->p.Ly : (kind == PDF_EDGE_PERIODIC_YM ? -c->p.Ly : 0.0);
-      const int32_t nb = m->nbr[3 * e + k];
-      for (int j = 0; j < 2; ++j) {
-        const int32_t v = m->tri[3 * e + (k + j) % 3];
-        const double px = m->vtx[2 * v] + sx, py = m->vtx[2 * v + 1] + sy;
-        for (int t = 0; t < 3; ++t) {
-          const int32_t w = m->tri[3 * nb + t];
-          if (m->vtx[2 * w] != px || m->vtx[2 * w + 1] != py) continue;
-          const int32_t a = find(v), b = find(w);
-          if (a != b) root[std::max(a, b)] = std::min(a, b);   // a class's root is its lowest vertex
-        }
-      }
-    }
-  }
-  std::vector<int32_t> canon(nv), rep, id_of(nv, -1);
-  for (int32_t v = 0; v < nv; ++v) {
-    const int32_t r = find(v);
-    if (r == v) {
-      id_of[v] = (int32_t)rep.size();
-      rep.push_back(v);
-    }
-    canon[v] = id_of[r];
-  }
-  const int32_t nc = (int32_t)rep.size();
-  struct Ent {
-    int32_t row, col, cid;
-  };
-  std::vector<Ent> ent((size_t)9 * ne);
-  for (int32_t e = 0; e < ne; ++e)
-    for (int a = 0; a < 3; ++a)
-      for (int b = 0; b < 3; ++b)
-        ent[(size_t)9 * e + 3 * a + b] = Ent{canon[m->tri[3 * e + a]], canon[m->tri[3 * e + b]], 9 * e + 3 * a + b};
-  std::sort(ent.begin(), ent.end(), [](const Ent& x, const Ent& y) {
-    if (x.row != y.row) return x.row < y.row;
-    if (x.col != y.col) return x.col < y.col;
-    return x.cid < y.cid;
-  });
-  std::vector<int32_t> rowptr((size_t)nc + 1, 0), col, cptr, cidx(ent.size());
-  for (size_t i = 0; i < ent.size(); ++i) {
-    cidx[i] = ent[i].cid;
-    if (i == 0 || ent[i].row != ent[i - 1].row || ent[i].col != ent[i - 1].col) {
-      col.push_back(ent[i].col);
-      cptr.push_back((int32_t)i);
-      ++rowptr[ent[i].row + 1];
-    }
-  }
-  cptr.push_back((int32_t)ent.size());
-  for (int32_t i = 0; i < nc; ++i) rowptr[i + 1] += rowptr[i];
-  const int64_t nnz = (int64_t)col.size();
-  // rows padded to the longest (padding: the row itself, no nonzero)
-  int32_t ellw = 0;
-  for (int32_t i = 0; i < nc; ++i) ellw = std::max(ellw, rowptr[i + 1] - rowptr[i]);
-  if (ellw > relax::ELL_MAX) {
+  host::RelaxStructure S;
+  const host::RelaxStatus hs =
+      host::build_relax_structure(nv, ne, m->vtx, m->tri, m->nbr, m->ekind, c->p.Lx, c->p.Ly, relax::ELL_MAX, S);
+  if (hs == host::RELAX_LONE_VERTEX) return fail(c, PDF_E_MESH, "relaxation: a vertex belongs to no element");
+  if (hs == host::RELAX_ROW_TOO_LONG) {
     c->rx_nc = 0;
     c->rx_err = "relaxation: a matrix row has more than " + std::to_string(relax::ELL_MAX) +
                 " entries (a vertex with more than " + std::to_string(relax::ELL_MAX - 1) + " neighbours)";
     return PDF_OK;
   }
-  std::vector<int32_t> dpos((size_t)nc, -1), ecol((size_t)ellw * nc), enz((size_t)ellw * nc);
-  for (int32_t i = 0; i < nc; ++i)
-    for (int32_t t = 0; t < ellw; ++t) {
-      const int32_t j = rowptr[i] + t;
-      const bool has = j < rowptr[i + 1];
-      ecol[(size_t)t * nc + i] = has ? col[j] : i;
-      enz[(size_t)t * nc + i] = has ? j : -1;
-      if (has && col[j] == i) dpos[i] = j;
-    }
-  if (nnz > relax_nnz_bound(nv, ne)) return fail(c, PDF_E_MESH, "relaxation: more nonzeros than the layout holds");
-  std::vector<int32_t> incptr((size_t)nc + 1, 0), inc((size_t)3 * ne), fill;
-  for (int32_t e = 0; e < ne; ++e)
-    for (int a = 0; a < 3; ++a) ++incptr[canon[m->tri[3 * e + a]] + 1];
-  for (int32_t i = 0; i < nc; ++i) {
-    if (incptr[i + 1] == 0) return fail(c, PDF_E_MESH, "relaxation: a vertex belongs to no element");
-    incptr[i + 1] += incptr[i];
-  }
-  fill.assign(incptr.begin(), incptr.end() - 1);
-  for (int32_t e = 0; e < ne; ++e)
-    for (int a = 0; a < 3; ++a) inc[fill[canon[m->tri[3 * e + a]]]++] = 3 * e + a;
+  if (S.nnz > relax_nnz_bound(nv, ne)) return fail(c, PDF_E_MESH, "relaxation: more nonzeros than the layout holds");
+  const int32_t nc = S.nc, ellw = S.ellw;
+  const int64_t nnz = S.nnz;
+  const std::vector<int32_t>&canon = S.canon, &rep = S.rep, &ecol = S.ecol, &enz = S.enz, &dpos = S.dpos,
+                             &cptr = S.cptr, &cidx = S.cidx, &incptr = S.incptr, &inc = S.inc;
   const Layout& L = c->L;
   char* d = c->arena;
   hipStream_t st = c->stream;

@@ -1,0 +1,196 @@
+"""Host code under the address and undefined-behaviour sanitizers (CPU only).
+
+* The oracle (oracle/orc.cpp) built with -fsanitize=address,undefined and
+  driven through its C interface on small workloads: float state with
+  moments to fourth order, histograms and the turbulent frequency on the
+  wall-function canyon, double state on the resolved canyon with three
+  ensembles, and the doubly periodic box.  The sanitizer build must run
+  clean (any report aborts it) and give the same statistics, states,
+  averages and point locations as the ordinary build, bit for bit.
+* The host bookkeeping of the relaxation system (pdf_host.hpp, the part of
+  the library's host layer that runs without a GPU), built with the same
+  sanitizers on the canyon meshes, the unit square periodic in x and the
+  doubly periodic box.  Its structure is checked against the oracle's
+  definitions: the joined unknowns (oracle.relax.canonical_vertices), the
+  sparsity of the assembled matrix, every nonzero's contributions decoding
+  to its own (row, column), the padded rows, the diagonal positions and the
+  incidence lists; and the error for a row longer than allowed.
+"""
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle as O
+import oracle.relax as R
+import workloads as W
+from workloads.mesh import doubly_periodic_box, unit_square_mesh
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SAN = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer", "-g", "-O1"]
+ENV = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0:halt_on_error=1",
+           UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1")
+
+
+def _build(tmp_path, name, sources, includes, extra=()):
+    exe = str(tmp_path / name)
+    cmd = ["g++", "-std=c++17", *SAN, "-ffp-contract=off", "-fno-fast-math", *extra,
+           *[f"-I{i}" for i in includes], *sources, "-o", exe]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-3000:]
+    return exe
+
+
+def _run(exe, inp, out):
+    r = subprocess.run([exe, inp, out], capture_output=True, text=True, env=ENV, timeout=600)
+    assert r.returncode == 0 and "runtime error" not in r.stderr and "Sanitizer" not in r.stderr, \
+        f"exit {r.returncode}\n{r.stderr[-4000:]}"
+
+
+@pytest.fixture(scope="module")
+def orc_exe(tmp_path_factory):
+    t = tmp_path_factory.mktemp("orc_san")
+    return _build(t, "orc_driver", [os.path.join(ROOT, "tests", "sanitize", "orc_driver.cpp"),
+                                    os.path.join(ROOT, "oracle", "orc.cpp")],
+                  [os.path.join(ROOT, "oracle")], extra=["-fopenmp"])
+
+
+@pytest.fixture(scope="module")
+def host_exe(tmp_path_factory):
+    t = tmp_path_factory.mktemp("host_san")
+    return _build(t, "host_driver", [os.path.join(ROOT, "tests", "sanitize", "host_driver.cpp")],
+                  [os.path.join(ROOT, "paper_1003_4548_amd", "csrc")])
+
+
+def _orc_cases():
+    wf = W.tiny_canyon(target=300, ppe=12, wallfn=True, moments=4, hist_bins=32, omega=True, steps=3)
+    dbl = W.tiny_canyon(target=300, ppe=10, precision="f64", nens=3, steps=3)
+    box = W.square_box(n=6, ppe=20, steps=3)
+    return {"wallfn_f32_m4_hist_omega": wf, "resolved_f64_3ens": dbl, "periodic_box": box}
+
+
+def _write_workload(path, wl, points):
+    m = wl.mesh
+    with open(path, "wb") as f:
+        f.write(bytes(O.params_of(wl)))
+        f.write(np.array([m.nvert, m.nelem], np.int32).tobytes())
+        for a, t in ((m.vtx, np.float64), (m.tri, np.int32), (m.nbr, np.int32), (m.ekind, np.int32),
+                     (wl.fields, np.float64)):
+            f.write(np.ascontiguousarray(a, t).tobytes())
+        f.write(np.array([wl.nens], np.int32).tobytes())
+        for en in wl.ensembles:
+            f.write(np.ascontiguousarray(en.counts, np.int64).tobytes())
+            f.write(np.array([en.seed], np.uint64).tobytes())
+            f.write(np.array([en.x0[0], en.x0[1], en.r0], np.float64).tobytes())
+        f.write(np.array([wl.steps, len(points)], np.int32).tobytes())
+        f.write(np.ascontiguousarray(points, np.float64).tobytes())
+
+
+@pytest.mark.parametrize("case", list(_orc_cases()))
+def test_oracle_runs_clean_under_sanitizers(orc_exe, tmp_path, case):
+    wl = _orc_cases()[case]
+    rng = np.random.default_rng(5)
+    lo, hi = wl.mesh.vtx.min(axis=0), wl.mesh.vtx.max(axis=0)
+    points = np.concatenate([rng.uniform(lo, hi, size=(20, 2)), wl.mesh.vtx[:5]])
+    inp, out = str(tmp_path / "in.bin"), str(tmp_path / "out.bin")
+    _write_workload(inp, wl, points)
+    _run(orc_exe, inp, out)
+    got = open(out, "rb").read()
+    # the same calls through the ordinary build
+    orc = O.Oracle(wl)
+    orc.average_start()
+    orc.step(wl.steps)
+    parts = []
+    for e in range(wl.nens):
+        st = orc.stats(e)
+        parts.append(st.tobytes())
+        s = orc.state(e)
+        for k in ("x", "y", "u", "v", "w", "psi"):
+            parts.append(s[k].tobytes())
+        parts.append(s["elem"].astype(np.int32).tobytes())
+        if getattr(wl, "omega", False):
+            parts.append(orc.omega(e).tobytes())
+        parts.append(orc.average(e).tobytes())
+        parts.append(st.tobytes())
+    parts.append(np.array([orc.locate(x, y) for x, y in points], np.int32).tobytes())
+    want = b"".join(parts)
+    assert len(got) == len(want)
+    assert got == want
+
+
+def _host_structure(host_exe, tmp_path, mesh, ell_max=16):
+    inp, out = str(tmp_path / "mesh.bin"), str(tmp_path / "rs.bin")
+    with open(inp, "wb") as f:
+        f.write(np.array([mesh.nvert, mesh.nelem], np.int32).tobytes())
+        f.write(np.array([mesh.Lx, mesh.Ly], np.float64).tobytes())
+        for a, t in ((mesh.vtx, np.float64), (mesh.tri, np.int32), (mesh.nbr, np.int32), (mesh.ekind, np.int32)):
+            f.write(np.ascontiguousarray(a, t).tobytes())
+        f.write(np.array([ell_max], np.int32).tobytes())
+    _run(host_exe, inp, out)
+    b = open(out, "rb").read()
+    status, nc, ellw = np.frombuffer(b[:12], np.int32)
+    nnz = int(np.frombuffer(b[12:20], np.int64)[0])
+    pos, arrs = 20, {}
+    for name in ("canon", "rep", "rowptr", "col", "cptr", "cidx", "ecol", "enz", "dpos", "incptr", "inc"):
+        n = int(np.frombuffer(b[pos:pos + 8], np.int64)[0])
+        pos += 8
+        arrs[name] = np.frombuffer(b[pos:pos + 4 * n], np.int32).copy()
+        pos += 4 * n
+    return int(status), int(nc), int(ellw), nnz, arrs
+
+
+def _meshes():
+    return {"canyon": W.tiny_canyon().mesh, "canyon_wallfn": W.tiny_canyon(wallfn=True).mesh,
+            "square_periodic_x": unit_square_mesh(7), "box_periodic_xy": doubly_periodic_box(6)}
+
+
+@pytest.mark.parametrize("name", list(_meshes()))
+def test_relaxation_structure_under_sanitizers(host_exe, tmp_path, name):
+    mesh = _meshes()[name]
+    status, nc, ellw, nnz, s = _host_structure(host_exe, tmp_path, mesh)
+    assert status == 0
+    canon, nco = R.canonical_vertices(mesh)
+    assert nc == nco
+    np.testing.assert_array_equal(s["canon"], canon)
+    # the representative of an unknown is its lowest vertex
+    for i, v in enumerate(s["rep"]):
+        assert canon[v] == i and v == np.flatnonzero(canon == i).min()
+    M, K, _, _, _ = R.assemble(mesh, np.ones(mesh.nelem))
+    A = (M + K).tocsr()
+    A.sum_duplicates()
+    A.sort_indices()
+    np.testing.assert_array_equal(s["rowptr"], A.indptr)
+    np.testing.assert_array_equal(s["col"], A.indices)
+    assert nnz == A.nnz
+    # every contribution of a nonzero is an (element, a, b) whose vertices
+    # map to the nonzero's row and column, in increasing order, all 9E once
+    assert len(s["cidx"]) == 9 * mesh.nelem and s["cptr"][-1] == 9 * mesh.nelem
+    assert sorted(s["cidx"].tolist()) == list(range(9 * mesh.nelem))
+    rows = np.repeat(np.arange(nc), np.diff(s["rowptr"]))
+    for j in range(nnz):
+        c = s["cidx"][s["cptr"][j]:s["cptr"][j + 1]]
+        assert len(c) > 0 and np.all(np.diff(c) > 0)
+        e, ab = c // 9, c % 9
+        assert np.all(canon[mesh.tri[e, ab // 3]] == rows[j])
+        assert np.all(canon[mesh.tri[e, ab % 3]] == s["col"][j])
+    # padded rows and diagonal positions
+    lens = np.diff(s["rowptr"])
+    assert ellw == lens.max()
+    ecol, enz = s["ecol"].reshape(ellw, nc), s["enz"].reshape(ellw, nc)
+    for i in range(nc):
+        L = lens[i]
+        np.testing.assert_array_equal(enz[:L, i], np.arange(s["rowptr"][i], s["rowptr"][i + 1]))
+        np.testing.assert_array_equal(ecol[:L, i], s["col"][s["rowptr"][i]:s["rowptr"][i + 1]])
+        assert np.all(enz[L:, i] == -1) and np.all(ecol[L:, i] == i)
+        assert s["col"][s["dpos"][i]] == i and s["rowptr"][i] <= s["dpos"][i] < s["rowptr"][i + 1]
+    # incidence: (element, local vertex) pairs of each unknown, increasing
+    assert s["incptr"][-1] == 3 * mesh.nelem
+    for i in range(nc):
+        t = s["inc"][s["incptr"][i]:s["incptr"][i + 1]]
+        assert np.all(np.diff(t) > 0) and np.all(canon[mesh.tri[t // 3, t % 3]] == i)
+
+
+def test_relaxation_structure_rejects_long_rows(host_exe, tmp_path):
+    status, *_ = _host_structure(host_exe, tmp_path, W.tiny_canyon().mesh, ell_max=5)
+    assert status == 1
