@@ -4,7 +4,8 @@ Each entry plants one plausible mistake in a copy of ``orc.cpp`` (a dropped
 term, a wrong sign, a swapped index, a transposed operand), builds that copy
 to a temporary library and runs the pin tests against it through the
 ORC_LIB override of ``oracle/__init__.py``; the entries for the Python
-oracle of the elliptic-relaxation solve replace ``relax.py`` for their run.  A pin set is adequate when every
+oracles of the elliptic-relaxation solve and of the mean-pressure projection
+replace ``relax.py`` or ``project.py`` for their run.  A pin set is adequate when every
 mutant fails at least one test.  Run: ``python oracle/mutation_sweep.py``
 (a few minutes; prints one line per mutant and exits 1 if any survives).
 """
@@ -23,6 +24,8 @@ from oracle import CFLAGS, SRC  # noqa: E402
 PINS = ["tests/test_oracle_pins.py", "tests/test_oracle_physics.py", "tests/test_oracle_geometry.py"]
 RELAX = os.path.join(HERE, "relax.py")
 RELAX_PINS = ["tests/test_oracle_relax.py"]
+PROJECT = os.path.join(HERE, "project.py")
+PROJECT_PINS = ["tests/test_oracle_project.py"]
 
 # (name, [(original text, planted text), ...])
 MUTANTS = [
@@ -76,20 +79,38 @@ RELAX_MUTANTS = [
 ]
 
 
-def run_relax_one(name, edits):
-    orig = open(RELAX).read()
+# the projection's Python oracle (project.py replaced in place for the run)
+PROJECT_MUTANTS = [
+    ("sign of the load", [("b, canon[mesh.tri[:, a]], area * (U[:, 0]", "b, canon[mesh.tri[:, a]], -area * (U[:, 0]")]),
+    ("x and y gradients swapped in the load",
+     [("(U[:, 0] * gx[:, a] + U[:, 1] * gy[:, a])", "(U[:, 0] * gy[:, a] + U[:, 1] * gx[:, a])")]),
+    ("element area dropped from the load",
+     [("b, canon[mesh.tri[:, a]], area * (U[:, 0]", "b, canon[mesh.tri[:, a]], (U[:, 0]")]),
+    ("dt dropped from the load", [("U[:, 1] * gy[:, a]) / dt)", "U[:, 1] * gy[:, a]))")]),
+    ("y gradient from the x weights", [("(p * gy).sum(axis=1)], axis=1)", "(p * gx).sum(axis=1)], axis=1)")]),
+    ("unweighted vertex average",
+     [("np.add.at(ws, canon[mesh.tri[:, a]], area)", "np.add.at(ws, canon[mesh.tri[:, a]], 1.0)"),
+      ("np.add.at(gs, canon[mesh.tri[:, a]], area[:, None] * ge)", "np.add.at(gs, canon[mesh.tri[:, a]], ge)")]),
+    ("sign of the velocity correction", [("- dt * ge[e, q]", "+ dt * ge[e, q]")]),
+    ("fallback below eleven particles", [("use = stats[:, ST_N] >= N_MIN", "use = stats[:, ST_N] > N_MIN")]),
+    ("frozen V in place of U", [("U = fc[:, F_U:F_U + 2].copy()", "U = fc[:, F_U + 1:F_U + 3].copy()")]),
+]
+
+
+def run_py_one(name, edits, path, pins):
+    orig = open(path).read()
     src = orig
     for old, new in edits:
         if src.count(old) != 1:
             raise RuntimeError(f"{name}: the text to mutate occurs {src.count(old)} times")
         src = src.replace(old, new)
     try:
-        with open(RELAX, "w") as f:
+        with open(path, "w") as f:
             f.write(src)
-        r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", *RELAX_PINS],
+        r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", *pins],
                            cwd=ROOT, capture_output=True, text=True)
     finally:
-        with open(RELAX, "w") as f:
+        with open(path, "w") as f:
             f.write(orig)
     failed = [ln.split(" ")[1] for ln in r.stdout.splitlines() if ln.startswith("FAILED")]
     return r.returncode != 0, failed
@@ -121,7 +142,11 @@ def main() -> int:
             survivors += 0 if caught else 1
             print(f"{'caught  ' if caught else 'SURVIVED'} {name}: {failed[0] if failed else '-'}", flush=True)
     for name, edits in RELAX_MUTANTS:
-        caught, failed = run_relax_one(name, edits)
+        caught, failed = run_py_one(name, edits, RELAX, RELAX_PINS)
+        survivors += 0 if caught else 1
+        print(f"{'caught  ' if caught else 'SURVIVED'} {name}: {failed[0] if failed else '-'}", flush=True)
+    for name, edits in PROJECT_MUTANTS:
+        caught, failed = run_py_one(name, edits, PROJECT, PROJECT_PINS)
         survivors += 0 if caught else 1
         print(f"{'caught  ' if caught else 'SURVIVED'} {name}: {failed[0] if failed else '-'}", flush=True)
     return 1 if survivors else 0
