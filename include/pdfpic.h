@@ -160,7 +160,10 @@ pdf_status pdf_query_sizes(const pdf_ctx* ctx, pdf_sizes* s);
    sized by pdf_query_sizes; the context keeps the pointer, the caller keeps
    ownership and must keep it alive) and precomputes, per vertex, the drift
    tensor G and C0 eps of eq. (6) from eq. (19) (SLM) or eqs. (12)-(13)
-   (from wp), and per wall-function edge alpha of eqs. (22)-(26).  Waits for
+   (from wp), and per wall-function edge alpha of eqs. (22)-(26), and the
+   structure of the Eulerian solves on the mesh (the P1 system of
+   pdf_elliptic_relaxation and pdf_pressure_projection: unknowns with the
+   periodic seam copies joined, sparsity, element matrices).  Waits for
    the stream.  Errors: PDF_E_ARG (null or empty input, unaligned arena),
    PDF_E_MESH (vertex id, neighbour or edge kind out of range; a degenerate or
    clockwise element), PDF_E_SIZE (arena too small for the mesh), PDF_E_HIP. */
@@ -299,12 +302,44 @@ pdf_status pdf_estimate_statistics(pdf_ctx* ctx, double* out, int32_t out_on_hos
 pdf_status pdf_elliptic_relaxation(pdf_ctx* ctx, int32_t max_iters, double tol, double* wp, double* coef,
                                    int32_t* info, double* resid);
 
+/* Mean-pressure projection (closing summary of section 2.2: the mean
+   pressure of eq. (6) by a projection scheme; section 3: the mean-pressure
+   Poisson equation solved on the grid by finite elements).  The scheme's
+   details are in a work that is not available; this is the reading taken:
+   the incremental projection of the particles' mean velocity onto weakly
+   divergence-free fields.  From the statistics of the current state (one
+   ensemble; per element the particles' mean velocity, the frozen mean
+   velocity at the centroid where the element holds fewer than 10
+   particles), the pressure increment phi solves lap(phi) = div<U> / dt with
+   d(phi)/dn = <U>.n / dt at walls, in the Galerkin P1 form
+     sum_e int_e grad(phi).grad(psi_i) = (1/dt) sum_e area_e <U>_e . grad(psi_i)|_e
+   on the unknowns of the relaxation system (its right-hand side sums to
+   zero: the system is singular and consistent, phi is defined up to a
+   constant).  Then grad(phi), constant per element, averaged by area to the
+   vertices, is added to the mean pressure gradient (the device copy of the
+   fields and the coefficient table the step reads), and every particle's
+   velocity (u, v) loses dt grad(phi) of its element (in double, rounded to
+   the state type).  The system is solved as in pdf_elliptic_relaxation
+   (Jacobi-preconditioned CG, one launch per iteration) from phi = 0 until
+   ||r|| <= tol ||b||, or max_iters iterations (1..20000; tol in (0, 1)).
+   Outputs, each may be NULL: phi (device, nvert doubles, up to a constant);
+   grad (device, nvert x 2 doubles: the vertex gradient added); info (host,
+   4 int32: iterations, 1 if converged, 1 if the update was applied,
+   elements whose velocity came from the particles); resid (host, 5 doubles:
+   ||r|| / ||b|| of the increment in the first, 0 in the others).  Waits for
+   the stream.  Errors: PDF_E_ARG, PDF_E_STATE (before seeding, or more than
+   one ensemble), PDF_E_MESH (the mesh cannot take the Eulerian solves, see
+   pdf_relaxation_size), PDF_E_HIP. */
+pdf_status pdf_pressure_projection(pdf_ctx* ctx, int32_t max_iters, double tol, double* phi, double* grad,
+                                   int32_t* info, double* resid);
+
 /* Size of the relaxation system of the mesh (section 2.1, the Galerkin
    system of eq. 14): out (host, 3 int64) = unknowns (vertices, periodic
    copies joined), nonzeros of the matrix, and the padded row length the
-   solver stores (the longest row).  Errors: PDF_E_ARG, PDF_E_STATE (before
-   pdf_init_mesh, or model 0), PDF_E_MESH (a row longer than 16 entries: the
-   relaxation is unavailable on the mesh). */
+   solver stores (the longest row); the mean-pressure projection solves on
+   the same unknowns.  Errors: PDF_E_ARG, PDF_E_STATE (before pdf_init_mesh),
+   PDF_E_MESH (a row longer than 16 entries, or a vertex in no element: the
+   Eulerian solves are unavailable on the mesh). */
 pdf_status pdf_relaxation_size(const pdf_ctx* ctx, int64_t* out);
 
 /* Run metrics from the device counters, into out (8 int64, host; waits):

@@ -99,6 +99,7 @@ def lib():
         L.orc_cbrt64.argtypes = [d]
         L.orc_coefficients.argtypes = [vp, vp]
         L.orc_set_drift.argtypes = [vp, vp]
+        L.orc_set_pressure_gradient.argtypes = [vp, vp]
         L.orc_mix_rate.argtypes = [vp, i32, vp]
         L.orc_wall_alpha.argtypes = [vp, vp]
         L.orc_exp64.restype = d
@@ -263,6 +264,11 @@ class Oracle:
         """Replace G_11 G_12 G_21 G_22 G_33 C0 eps of every vertex (nvert x 6)."""
         a = np.ascontiguousarray(g6, np.float64).reshape(self.wl.mesh.nvert, 6)
         lib().orc_set_drift(self.ctx, _ptr(a))
+
+    def set_pressure_gradient(self, g2) -> None:
+        """Replace d<P>/dx and d<P>/dy of every vertex (nvert x 2)."""
+        a = np.ascontiguousarray(g2, np.float64).reshape(self.wl.mesh.nvert, 2)
+        lib().orc_set_pressure_gradient(self.ctx, _ptr(a))
 
     def mix_rate(self, ens: int = 0) -> np.ndarray:
         out = np.zeros(self.wl.mesh.nelem)

@@ -1143,6 +1143,13 @@ void orc_coefficients(const orc_ctx* c, double* out) {
     out[i] = c->p.f32_state ? (double)(float)c->coef[i] : c->coef[i];
 }
 
+void orc_set_pressure_gradient(orc_ctx* c, const double* g2) {
+  for (int v = 0; v < c->nv; ++v) {
+    c->coef[(size_t)v * NC + C_DPDX] = g2[2 * (size_t)v];
+    c->coef[(size_t)v * NC + C_DPDY] = g2[2 * (size_t)v + 1];
+  }
+}
+
 void orc_set_drift(orc_ctx* c, const double* g6) {
   for (int v = 0; v < c->nv; ++v)
     for (int j = 0; j < 6; ++j) c->coef[(size_t)v * NC + C_G11 + j] = g6[(size_t)v * 6 + j];

@@ -146,6 +146,9 @@ void orc_coefficients(const orc_ctx* c, double* out);
 /* replace G11 G12 G21 G22 G33 C0eps of every vertex (g6: nvert x 6), e.g.
    with the result of the elliptic relaxation, eqs. (12)-(13) */
 void orc_set_drift(orc_ctx* c, const double* g6);
+/* replace the mean pressure gradient of every vertex (g2: nvert x 2), e.g.
+   after a mean-pressure projection */
+void orc_set_pressure_gradient(orc_ctx* c, const double* g2);
 /* IECM relaxation factor r = min(dt/t_m, 1) per element of one ensemble */
 void orc_mix_rate(const orc_ctx* c, int32_t ens, double* out);
 /* wall-function alpha per element edge (0 elsewhere): nelem x 3 */

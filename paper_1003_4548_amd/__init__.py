@@ -27,7 +27,7 @@ NFIELD = 20
 # exported entry points (the declarations of include/pdfpic.h)
 ENTRY_POINTS = ("pdf_create", "pdf_query_sizes", "pdf_init_mesh", "pdf_seed_particles", "pdf_step",
                 "pdf_step_graph", "pdf_step_timed", "pdf_autotune", "pdf_set_launch", "pdf_repack", "pdf_repack_count",
-                "pdf_estimate_statistics", "pdf_elliptic_relaxation", "pdf_relaxation_size", "pdf_nstat", "pdf_sync", "pdf_metrics",
+                "pdf_estimate_statistics", "pdf_elliptic_relaxation", "pdf_pressure_projection", "pdf_relaxation_size", "pdf_nstat", "pdf_sync", "pdf_metrics",
                 "pdf_mlp_work_floats", "pdf_mlp_dataset", "pdf_mlp_forward", "pdf_mlp_grad", "pdf_mlp_grad_noalloc", "pdf_mlp_train",
                 "pdf_mlp_norm", "pdf_mlp_round", "pdf_mlp_infer", "pdf_mlp_attach",
                 "pdf_get_state", "pdf_set_state", "pdf_set_step", "pdf_get_omega", "pdf_omega_fields", "pdf_navg", "pdf_average_attach",
@@ -129,6 +129,8 @@ def load_library():
     L.pdf_estimate_statistics.argtypes = [vp, vp, i32]
     L.pdf_elliptic_relaxation.restype = i32
     L.pdf_elliptic_relaxation.argtypes = [vp, i32, ctypes.c_double, vp, vp, vp, vp]
+    L.pdf_pressure_projection.restype = i32
+    L.pdf_pressure_projection.argtypes = [vp, i32, ctypes.c_double, vp, vp, vp, vp]
     L.pdf_relaxation_size.restype = i32
     L.pdf_relaxation_size.argtypes = [vp, vp]
     L.pdf_nstat.restype = i32
@@ -348,6 +350,28 @@ class Simulation:
         if outputs:
             out["wp"] = wp.cpu().numpy()
             out["coef"] = coef.cpu().numpy()
+        return out
+
+    def pressure_projection(self, max_iters: int = 20000, tol: float = 1e-10, outputs: bool = True) -> dict:
+        """Project the particles' mean velocity (one ensemble): solve for the
+        pressure increment, add its gradient to the mean pressure gradient and
+        correct every particle's velocity (waits).  Returns iterations,
+        converged, applied, from_stats, resid and, with outputs, phi (nvert,
+        up to a constant) and grad (nvert x 2) as numpy arrays."""
+        info = np.zeros(4, np.int32)
+        resid = np.zeros(5)
+        phi = grad = None
+        if outputs:
+            phi = self.torch.empty((self.nvert,), dtype=self.torch.float64, device=self.device)
+            grad = self.torch.empty((self.nvert, 2), dtype=self.torch.float64, device=self.device)
+        self._check(load_library().pdf_pressure_projection(
+            self.ctx, int(max_iters), float(tol), ctypes.c_void_p(phi.data_ptr() if outputs else 0),
+            ctypes.c_void_p(grad.data_ptr() if outputs else 0), _ptr(info), _ptr(resid)), "pdf_pressure_projection")
+        out = dict(iterations=int(info[0]), converged=bool(info[1]), applied=bool(info[2]), from_stats=int(info[3]),
+                   resid=resid)
+        if outputs:
+            out["phi"] = phi.cpu().numpy()
+            out["grad"] = grad.cpu().numpy()
         return out
 
     def relaxation_size(self) -> dict:

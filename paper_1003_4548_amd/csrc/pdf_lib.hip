@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <mutex>
 #include <string>
 #include <type_traits>
@@ -35,9 +36,9 @@ int64_t align_up(int64_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 // Byte offsets of the arena sections.
 struct Layout {
   int64_t vtx, tri, nbr, ekind, inv2a, alpha, wnorm, fields, coef, erec, om0, somega, omw;
-  // elliptic relaxation (model 1 only): sparsity, element data, solver vectors
+  // the Eulerian solves (elliptic relaxation, mean-pressure projection): sparsity, element data, solver vectors
   int64_t rx_canon, rx_rep, rx_ecol, rx_enz, rx_dpos, rx_cptr, rx_cidx, rx_incptr, rx_inc, rx_Ke, rx_area;
-  int64_t rx_S, rx_L2, rx_Rk, rx_aval, rx_dinv, rx_x, rx_p, rx_rec[2], rx_part[2], rx_pbb, rx_ctl;
+  int64_t rx_S, rx_L2, rx_Rk, rx_aval, rx_dinv, rx_x, rx_px, rx_p, rx_rec[2], rx_part[2], rx_pbb, rx_ctl;
   int64_t start, cap, cap0, nstart, ncap, ns[3], nm[3], rate, idoff, order, seed, src;
   int64_t buf0, buf1, ovf, ovf_cell, stats, ctl, flag, metrics;
   int64_t total;
@@ -56,8 +57,7 @@ constexpr int32_t RELAX_LONG = 32, RELAX_SHORT = 8;
 int64_t relax_nnz_bound(int32_t nv, int32_t ne) { return (int64_t)nv + 6 * (int64_t)ne; }
 int32_t relax_blocks(int32_t nv) { return std::max(1, (nv + relax::BLK - 1) / relax::BLK); }
 
-Layout make_layout(int32_t nv, int32_t ne, int32_t nens, int64_t slots, int32_t nstat, int tsize, bool omega,
-                   bool relaxation) {
+Layout make_layout(int32_t nv, int32_t ne, int32_t nens, int64_t slots, int32_t nstat, int tsize, bool omega) {
   Layout L{};
   int64_t o = 0;
   auto take = [&](int64_t bytes) { int64_t r = o; o = align_up(o + bytes); return r; };
@@ -76,33 +76,33 @@ Layout make_layout(int32_t nv, int32_t ne, int32_t nens, int64_t slots, int32_t 
   L.somega = take(omega ? (int64_t)ne * 8 : 0);
   L.omw = take(omega ? (int64_t)ne * 3 * 8 : 0);
   {
-    const int64_t on = relaxation ? 1 : 0;
     const int64_t nnz = relax_nnz_bound(nv, ne), nc = nv, E = ne, vec = relax::NC * nc * 8;
     const int64_t ell = (int64_t)relax::ELL_MAX * nc, nbx = relax_blocks(nv);
-    L.rx_canon = take(on * nv * 4);
-    L.rx_rep = take(on * nc * 4);
-    L.rx_ecol = take(on * ell * 4);
-    L.rx_enz = take(on * ell * 4);
-    L.rx_dpos = take(on * nc * 4);
-    L.rx_cptr = take(on * (nnz + 1) * 4);
-    L.rx_cidx = take(on * 9 * E * 4);
-    L.rx_incptr = take(on * (nc + 1) * 4);
-    L.rx_inc = take(on * 3 * E * 4);
-    L.rx_Ke = take(on * 9 * E * 8);
-    L.rx_area = take(on * E * 8);
-    L.rx_S = take(on * relax::NC * E * 8);
-    L.rx_L2 = take(on * E * 8);
-    L.rx_Rk = take(on * 4 * E * 8);
-    L.rx_aval = take(on * ell * 8);
-    L.rx_dinv = take(on * nc * 8);
-    L.rx_x = take(on * vec);
-    L.rx_p = take(on * vec);
+    L.rx_canon = take(nv * 4);
+    L.rx_rep = take(nc * 4);
+    L.rx_ecol = take(ell * 4);
+    L.rx_enz = take(ell * 4);
+    L.rx_dpos = take(nc * 4);
+    L.rx_cptr = take((nnz + 1) * 4);
+    L.rx_cidx = take(9 * E * 4);
+    L.rx_incptr = take((nc + 1) * 4);
+    L.rx_inc = take(3 * E * 4);
+    L.rx_Ke = take(9 * E * 8);
+    L.rx_area = take(E * 8);
+    L.rx_S = take(relax::NC * E * 8);
+    L.rx_L2 = take(E * 8);
+    L.rx_Rk = take(4 * E * 8);
+    L.rx_aval = take(ell * 8);
+    L.rx_dinv = take(nc * 8);
+    L.rx_x = take(vec);
+    L.rx_px = take(vec);
+    L.rx_p = take(vec);
     for (int b = 0; b < 2; ++b) {
-      L.rx_rec[b] = take(on * relax::NC * nc * (int64_t)sizeof(relax::Rec));
-      L.rx_part[b] = take(on * relax::NC * nbx * 3 * 8);
+      L.rx_rec[b] = take(relax::NC * nc * (int64_t)sizeof(relax::Rec));
+      L.rx_part[b] = take(relax::NC * nbx * 3 * 8);
     }
-    L.rx_pbb = take(on * relax::NC * nbx * 8);
-    L.rx_ctl = take(on * (int64_t)sizeof(relax::Ctl));
+    L.rx_pbb = take(relax::NC * nbx * 8);
+    L.rx_ctl = take((int64_t)sizeof(relax::Ctl));
   }
   L.start = take(ncell * 4);
   L.cap = take(ncell * 4);
@@ -151,6 +151,25 @@ template <typename T> StateDev<T> state_at(char* base, int64_t off, int64_t slot
 }
 
 }  // namespace
+
+// Replayable graphs of RELAX_LONG and RELAX_SHORT iteration launches of one
+// solve (built for its kernel arguments: pointers of the mesh part of the
+// arena), and the iteration count of its last run.
+struct SolveGraphs {
+  hipGraph_t g[2] = {nullptr, nullptr};
+  hipGraphExec_t ex[2] = {nullptr, nullptr};
+  bool ok = false;
+  int32_t last_iters = 0;
+  void release() {
+    for (int i = 0; i < 2; ++i) {
+      if (ex[i]) (void)hipGraphExecDestroy(ex[i]);
+      if (g[i]) (void)hipGraphDestroy(g[i]);
+      ex[i] = nullptr;
+      g[i] = nullptr;
+    }
+    ok = false;
+  }
+};
 
 struct pdf_ctx {
   pdf_params p{};
@@ -207,12 +226,8 @@ struct pdf_ctx {
   // memory behind it
   relax::Ctl* rx_pin = nullptr;
   hipEvent_t rx_ev[2] = {nullptr, nullptr};
-  // replayable graphs of RELAX_LONG and RELAX_SHORT iterations (pointers of
-  // the mesh part)
-  hipGraph_t rx_graph[2] = {nullptr, nullptr};
-  hipGraphExec_t rx_graph_exec[2] = {nullptr, nullptr};
-  bool rx_graph_ok = false;
-  int32_t rx_last_iters = 0;   // iterations of the last solve
+  // the iteration graphs of the relaxation and of the projection solves
+  SolveGraphs rx_sg, px_sg;
   std::string err;
   pdf_status last = PDF_OK;
 };
@@ -261,11 +276,13 @@ pdf_status relax_setup(pdf_ctx* c, const pdf_mesh* m) {
   host::RelaxStructure S;
   const host::RelaxStatus hs =
       host::build_relax_structure(nv, ne, m->vtx, m->tri, m->nbr, m->ekind, c->p.Lx, c->p.Ly, relax::ELL_MAX, S);
-  if (hs == host::RELAX_LONE_VERTEX) return fail(c, PDF_E_MESH, "relaxation: a vertex belongs to no element");
-  if (hs == host::RELAX_ROW_TOO_LONG) {
+  // a mesh the Eulerian solves cannot take still steps particles
+  if (hs != host::RELAX_OK) {
     c->rx_nc = 0;
-    c->rx_err = "relaxation: a matrix row has more than " + std::to_string(relax::ELL_MAX) +
-                " entries (a vertex with more than " + std::to_string(relax::ELL_MAX - 1) + " neighbours)";
+    c->rx_err = hs == host::RELAX_LONE_VERTEX
+                    ? std::string("Eulerian solves: a vertex belongs to no element")
+                    : "Eulerian solves: a matrix row has more than " + std::to_string(relax::ELL_MAX) +
+                          " entries (a vertex with more than " + std::to_string(relax::ELL_MAX - 1) + " neighbours)";
     return PDF_OK;
   }
   if (S.nnz > relax_nnz_bound(nv, ne)) return fail(c, PDF_E_MESH, "relaxation: more nonzeros than the layout holds");
@@ -301,8 +318,8 @@ pdf_status relax_setup(pdf_ctx* c, const pdf_mesh* m) {
   c->rx_nnz = nnz;
   c->rx_ellw = ellw;
   c->rx_err.clear();
-  c->rx_graph_ok = false;
-  c->rx_last_iters = 0;
+  c->rx_sg.ok = c->px_sg.ok = false;
+  c->rx_sg.last_iters = c->px_sg.last_iters = 0;
   return PDF_OK;
 }
 
@@ -886,8 +903,7 @@ pdf_status pdf_query_sizes(const pdf_ctx* c, pdf_sizes* s) {
   const int64_t ncell = (int64_t)s->nelem * s->nens;
   const int64_t slots = slots_bound(s->nparticles, ncell, c->p.slack);
   if (slots >= (int64_t)1 << 31) return PDF_E_SIZE;
-  const Layout L = make_layout(s->nvert, s->nelem, s->nens, slots, nstat_of(c->p), tsize_of(c->p), c->p.omega != 0,
-                                 c->p.model == 1);
+  const Layout L = make_layout(s->nvert, s->nelem, s->nens, slots, nstat_of(c->p), tsize_of(c->p), c->p.omega != 0);
   s->arena_bytes = L.total;
   s->slots = slots;
   return PDF_OK;
@@ -909,7 +925,7 @@ pdf_status pdf_init_mesh(pdf_ctx* c, const pdf_mesh* m, void* arena, int64_t are
   c->arena = (char*)arena;
   c->arena_bytes = arena_bytes;
   // the mesh part of the layout does not depend on the ensembles
-  Layout L = make_layout(c->nv, c->ne, 1, 1, nstat_of(c->p), tsize_of(c->p), c->p.omega != 0, c->p.model == 1);
+  Layout L = make_layout(c->nv, c->ne, 1, 1, nstat_of(c->p), tsize_of(c->p), c->p.omega != 0);
   if (L.start > arena_bytes) return fail(c, PDF_E_SIZE, "arena too small for the mesh");
   c->L = L;
   hipStream_t st = c->stream;
@@ -947,7 +963,7 @@ pdf_status pdf_init_mesh(pdf_ctx* c, const pdf_mesh* m, void* arena, int64_t are
                        (double*)(c->arena + L.om0), (double*)(c->arena + L.somega), (double*)(c->arena + L.omw), c->ne,
                        c->p.nu, c->p.CT, c->p.Cw1, c->p.Cw2);
   if ((r = hip_check(c, hipGetLastError(), "init kernels"))) return r;
-  if (c->p.model == 1 && (r = relax_setup(c, m))) return r;
+  if ((r = relax_setup(c, m))) return r;
   int32_t bad = 0;
   if ((r = hip_check(c, hipMemcpyAsync(&bad, flag, 4, hipMemcpyDeviceToHost, st), "read mesh flag"))) return r;
   if ((r = hip_check(c, hipStreamSynchronize(st), "sync init"))) return r;
@@ -1050,8 +1066,7 @@ pdf_status pdf_seed_particles(pdf_ctx* c, int32_t nens, const int64_t* counts, c
   c->nsplit = split ? ncell - nsmall : 0;
   for (int gi = 0; gi < 5; ++gi) c->xcd_n[gi][0] = c->xcd_n[gi][1] = -1;
   const int64_t slots = slot + growth_reserve(total, ncell, slack);
-  const Layout L = make_layout(c->nv, c->ne, nens, slots, nstat_of(c->p), tsize_of(c->p), c->p.omega != 0,
-                               c->p.model == 1);
+  const Layout L = make_layout(c->nv, c->ne, nens, slots, nstat_of(c->p), tsize_of(c->p), c->p.omega != 0);
   if (L.total > c->arena_bytes)
     return fail(c, PDF_E_SIZE, "arena too small for the particle layout (query with slack >= 2)");
   c->L = L;
@@ -1303,7 +1318,9 @@ static relax::Args relax_args(pdf_ctx* c) {
   a.nbx = relax_blocks(c->rx_nc);
   a.ellw = c->rx_ellw;
   a.tri = (const int32_t*)(d + L.tri);
+  a.vtx = (const double*)(d + L.vtx);
   a.fields = (const double*)(d + L.fields);
+  a.fields_rw = (double*)(d + L.fields);
   a.canon = (const int32_t*)(d + L.rx_canon);
   a.ecol = (const int32_t*)(d + L.rx_ecol);
   a.enz = (const int32_t*)(d + L.rx_enz);
@@ -1317,6 +1334,9 @@ static relax::Args relax_args(pdf_ctx* c) {
   a.stats = (const double*)(d + L.stats);
   a.nstat = nstat_of(c->p);
   a.nu = c->p.nu;
+  a.mass = 1.0;
+  a.rhs_mode = 0;
+  a.dt = c->p.dt;
   a.S = (double*)(d + L.rx_S);
   a.L2 = (double*)(d + L.rx_L2);
   a.Rk = (double*)(d + L.rx_Rk);
@@ -1332,19 +1352,16 @@ static relax::Args relax_args(pdf_ctx* c) {
   return a;
 }
 
-// The graphs of RELAX_LONG and RELAX_SHORT iteration launches (kernel nodes
-// only; every launch after the stop returns at once).
-static pdf_status relax_graph(pdf_ctx* c, const relax::Args& a) {
-  if (c->rx_graph_ok) return PDF_OK;
+// The graphs of RELAX_LONG and RELAX_SHORT iteration launches of a solve
+// (kernel nodes only; every launch after the stop returns at once).
+static pdf_status build_solve_graphs(pdf_ctx* c, const relax::Args& a, SolveGraphs& sg) {
+  if (sg.ok) return PDF_OK;
   static_assert(RELAX_LONG % 2 == 0 && RELAX_SHORT % 2 == 0, "iteration parity continues across replays");
+  sg.release();
   pdf_status r;
   for (int gi = 0; gi < 2; ++gi) {
-    if (c->rx_graph_exec[gi]) (void)hipGraphExecDestroy(c->rx_graph_exec[gi]);
-    if (c->rx_graph[gi]) (void)hipGraphDestroy(c->rx_graph[gi]);
-    c->rx_graph_exec[gi] = nullptr;
-    c->rx_graph[gi] = nullptr;
     hipGraph_t g = nullptr;
-    if ((r = hip_check(c, hipGraphCreate(&g, 0), "relaxation graph create"))) return r;
+    if ((r = hip_check(c, hipGraphCreate(&g, 0), "solver graph create"))) return r;
     relax::Args store = a;   // kernel parameters are copied into the nodes at creation
     int32_t pars[2] = {0, 1};
     hipGraphNode_t prev = nullptr;
@@ -1360,22 +1377,88 @@ static pdf_status relax_graph(pdf_ctx* c, const relax::Args& a) {
       kp.extra = nullptr;
       hipGraphNode_t node;
       if ((r = hip_check(c, hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &kp),
-                         "relaxation graph node"))) {
+                         "solver graph node"))) {
         (void)hipGraphDestroy(g);
         return r;
       }
       prev = node;
     }
     hipGraphExec_t ex = nullptr;
-    if ((r = hip_check(c, hipGraphInstantiate(&ex, g, nullptr, nullptr, 0), "relaxation graph instantiate"))) {
+    if ((r = hip_check(c, hipGraphInstantiate(&ex, g, nullptr, nullptr, 0), "solver graph instantiate"))) {
       (void)hipGraphDestroy(g);
       return r;
     }
-    c->rx_graph[gi] = g;
-    c->rx_graph_exec[gi] = ex;
+    sg.g[gi] = g;
+    sg.ex[gi] = ex;
   }
-  c->rx_graph_ok = true;
+  sg.ok = true;
   return PDF_OK;
+}
+
+// The iterations of a solve whose start kernels are enqueued, in graph
+// replays until the device reports the stop (launch i checks the stop after
+// i iterations, so up to max_iters + 1 launches run; launches after the stop
+// return at once).  The first batch covers the iteration count of the last
+// run; finish(again) enqueues the kernels that use the solution, then a copy
+// of the solver control into pinned host memory follows, and the host waits
+// once.  If the solve has not stopped, batches of RELAX_SHORT follow, each
+// with its control copy and event, the next one enqueued before the host
+// waits for the previous one, and finish(true) runs again.  *out: the
+// control at the end (pinned host memory of the context).
+static pdf_status run_solve(pdf_ctx* c, const relax::Args& a, SolveGraphs& sg, int32_t max_iters,
+                            const std::function<pdf_status(bool)>& finish, const relax::Ctl** out) {
+  pdf_status r;
+  if ((r = build_solve_graphs(c, a, sg))) return r;
+  hipStream_t st = c->stream;
+  if (!c->rx_pin) {
+    if ((r = hip_check(c, hipHostMalloc((void**)&c->rx_pin, 2 * sizeof(relax::Ctl), hipHostMallocDefault), "pinned control"))) return r;
+    for (auto& e : c->rx_ev)
+      if ((r = hip_check(c, hipEventCreateWithFlags(&e, hipEventDisableTiming), "solver event"))) return r;
+  }
+  int32_t launched = 0;
+  auto replay = [&](int gi) -> pdf_status {
+    launched += gi == 0 ? RELAX_LONG : RELAX_SHORT;
+    return hip_check(c, hipGraphLaunch(sg.ex[gi], st), "solver graph launch");
+  };
+  auto mark = [&](int slot) -> pdf_status {
+    pdf_status q;
+    if ((q = hip_check(c, hipMemcpyAsync(c->rx_pin + slot, a.ctl, sizeof(relax::Ctl), hipMemcpyDeviceToHost, st), "read solver control"))) return q;
+    return hip_check(c, hipEventRecord(c->rx_ev[slot], st), "solver event");
+  };
+  const int32_t first = std::max(1, std::min(sg.last_iters, max_iters) + 1);
+  while (launched + RELAX_LONG <= first)
+    if ((r = replay(0))) return r;
+  while (launched < first)
+    if ((r = replay(1))) return r;
+  int slot = 0;
+  if ((r = finish(false)) || (r = mark(slot))) return r;
+  if ((r = hip_check(c, hipEventSynchronize(c->rx_ev[slot]), "sync solver"))) return r;
+  if (!c->rx_pin[slot].done && launched <= max_iters) {
+    if ((r = replay(1)) || (r = mark(slot))) return r;
+    for (;;) {
+      const bool more = launched <= max_iters;
+      if (more && ((r = replay(1)) || (r = mark(slot ^ 1)))) return r;
+      if ((r = hip_check(c, hipEventSynchronize(c->rx_ev[slot]), "sync solver"))) return r;
+      if (c->rx_pin[slot].done || !more) break;
+      slot ^= 1;
+    }
+    if ((r = finish(true)) || (r = mark(slot))) return r;
+    if ((r = hip_check(c, hipEventSynchronize(c->rx_ev[slot]), "sync solver"))) return r;
+  }
+  sg.last_iters = c->rx_pin[slot].iter;
+  *out = c->rx_pin + slot;
+  return PDF_OK;
+}
+
+static void report_solve(const relax::Ctl& h, int32_t* info, double* resid, int32_t extra) {
+  if (info) {
+    info[0] = h.iter;
+    info[1] = h.converged;
+    info[2] = extra;
+    info[3] = h.from_stats;
+  }
+  if (resid)
+    for (int q = 0; q < relax::NC; ++q) resid[q] = h.ref[q] > 0.0 ? std::sqrt(h.rho[q] / h.ref[q]) : 0.0;
 }
 
 pdf_status pdf_elliptic_relaxation(pdf_ctx* c, int32_t max_iters, double tol, double* wp, double* coef,
@@ -1389,7 +1472,6 @@ pdf_status pdf_elliptic_relaxation(pdf_ctx* c, int32_t max_iters, double tol, do
   pdf_status r = dispatch_step<false>(c, StepIndex{0, c->parity, c->rot, 0});
   if (r) return r;
   const relax::Args a = relax_args(c);
-  if ((r = relax_graph(c, a))) return r;
   hipStream_t st = c->stream;
   const int tb = relax::BLK;
   const unsigned eb = (unsigned)((c->ne + tb - 1) / tb), vb = (unsigned)((c->nv + tb - 1) / tb);
@@ -1401,74 +1483,84 @@ pdf_status pdf_elliptic_relaxation(pdf_ctx* c, int32_t max_iters, double tol, do
   hipLaunchKernelGGL(relax::k_relax_start1, grid, dim3(tb), 0, st, a);
   hipLaunchKernelGGL(relax::k_relax_start2, grid, dim3(tb), 0, st, a);
   if ((r = hip_check(c, hipGetLastError(), "relaxation launch"))) return r;
-  // Iterations in graph replays until the device reports the stop (launch i
-  // checks the stop after i iterations, so up to max_iters + 1 launches run;
-  // launches after the stop return at once).  The first batch covers the
-  // iteration count of the last solve; the coefficient update and a copy of
-  // the solver control into pinned host memory follow it, and the host waits
-  // once.  If the solve has not stopped, batches of RELAX_SHORT follow, each
-  // with its control copy and event, the next one enqueued before the host
-  // waits for the previous one, and the coefficients are updated again.
-  if (!c->rx_pin) {
-    if ((r = hip_check(c, hipHostMalloc((void**)&c->rx_pin, 2 * sizeof(relax::Ctl), hipHostMallocDefault), "pinned control"))) return r;
-    for (auto& e : c->rx_ev)
-      if ((r = hip_check(c, hipEventCreateWithFlags(&e, hipEventDisableTiming), "relaxation event"))) return r;
-  }
-  int32_t launched = 0;
-  auto replay = [&](int gi) -> pdf_status {
-    launched += gi == 0 ? RELAX_LONG : RELAX_SHORT;
-    return hip_check(c, hipGraphLaunch(c->rx_graph_exec[gi], st), "relaxation graph launch");
-  };
-  auto mark = [&](int slot) -> pdf_status {
-    pdf_status q;
-    if ((q = hip_check(c, hipMemcpyAsync(c->rx_pin + slot, a.ctl, sizeof(relax::Ctl), hipMemcpyDeviceToHost, st), "read relaxation control"))) return q;
-    return hip_check(c, hipEventRecord(c->rx_ev[slot], st), "relaxation event");
-  };
-  auto update = [&]() -> pdf_status {
+  // G and C0 from the solution; run again after further iterations (the
+  // count of clamped C0 anew)
+  auto update = [&](bool again) -> pdf_status {
+    if (again) hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, &a.ctl->clamped, 0, (int64_t)1);
     if (c->p.f32_state)
       hipLaunchKernelGGL(relax::k_relax_coef<float>, dim3(vb), dim3(tb), 0, st, a, (float*)(c->arena + c->L.coef), wp, coef);
     else
       hipLaunchKernelGGL(relax::k_relax_coef<double>, dim3(vb), dim3(tb), 0, st, a, (double*)(c->arena + c->L.coef), wp, coef);
     return hip_check(c, hipGetLastError(), "relaxation launch");
   };
-  const int32_t first = std::max(1, std::min(c->rx_last_iters, max_iters) + 1);
-  while (launched + RELAX_LONG <= first)
-    if ((r = replay(0))) return r;
-  while (launched < first)
-    if ((r = replay(1))) return r;
-  int slot = 0;
-  if ((r = update()) || (r = mark(slot))) return r;
-  if ((r = hip_check(c, hipEventSynchronize(c->rx_ev[slot]), "sync relaxation"))) return r;
-  if (!c->rx_pin[slot].done && launched <= max_iters) {
-    if ((r = replay(1)) || (r = mark(slot))) return r;
-    for (;;) {
-      const bool more = launched <= max_iters;
-      if (more && ((r = replay(1)) || (r = mark(slot ^ 1)))) return r;
-      if ((r = hip_check(c, hipEventSynchronize(c->rx_ev[slot]), "sync relaxation"))) return r;
-      if (c->rx_pin[slot].done || !more) break;
-      slot ^= 1;
+  const relax::Ctl* h = nullptr;
+  if ((r = run_solve(c, a, c->rx_sg, max_iters, update, &h))) return r;
+  report_solve(*h, info, resid, h->clamped);
+  return PDF_OK;
+}
+
+pdf_status pdf_pressure_projection(pdf_ctx* c, int32_t max_iters, double tol, double* phi, double* grad,
+                                   int32_t* info, double* resid) {
+  if (!c || max_iters < 1 || max_iters > RELAX_MAX_ITERS || !(tol > 0.0) || !(tol < 1.0))
+    return fail(c, PDF_E_ARG, "pdf_pressure_projection: bad argument");
+  if (!c->seeded) return fail(c, PDF_E_STATE, "pdf_pressure_projection before pdf_seed_particles");
+  if (c->nens != 1) return fail(c, PDF_E_STATE, "pdf_pressure_projection: one ensemble only");
+  if (c->rx_nc == 0) return fail(c, PDF_E_MESH, c->rx_err);
+  pdf_status r = dispatch_step<false>(c, StepIndex{0, c->parity, c->rot, 0});
+  if (r) return r;
+  relax::Args a = relax_args(c);
+  a.x = (double*)(c->arena + c->L.rx_px);
+  a.mass = 0.0;
+  a.rhs_mode = 1;
+  hipStream_t st = c->stream;
+  const int tb = relax::BLK;
+  const unsigned eb = (unsigned)((c->ne + tb - 1) / tb), vb = (unsigned)((c->nv + tb - 1) / tb);
+  const unsigned zb = (unsigned)(((int64_t)c->rx_ellw * c->rx_nc + tb - 1) / tb);
+  const dim3 grid((unsigned)a.nbx, relax::NC);
+  const int64_t xwords = 2 * (int64_t)relax::NC * c->rx_nc;
+  hipLaunchKernelGGL(relax::k_relax_reset, dim3(1), dim3(64), 0, st, a.ctl, max_iters, tol * tol);
+  hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((xwords + 255) / 256)), dim3(256), 0, st, (int32_t*)a.x, 0, xwords);
+  hipLaunchKernelGGL(relax::k_proj_inputs, dim3(eb), dim3(tb), 0, st, a);
+  hipLaunchKernelGGL(relax::k_relax_matrix, dim3(zb), dim3(tb), 0, st, a);
+  hipLaunchKernelGGL(relax::k_relax_start1, grid, dim3(tb), 0, st, a);
+  hipLaunchKernelGGL(relax::k_relax_start2, grid, dim3(tb), 0, st, a);
+  if ((r = hip_check(c, hipGetLastError(), "projection launch"))) return r;
+  // the update, once the solve has stopped (the kernels check the device's
+  // stop and applied flags, so a launch behind an unfinished batch does nothing)
+  char* d = c->arena;
+  const Layout& L = c->L;
+  CounterSets cs;
+  for (int q = 0; q < 3; ++q) {
+    cs.ns[q] = (int32_t*)(d + L.ns[q]);
+    cs.nm[q] = (int32_t*)(d + L.nm[q]);
+  }
+  const StepIndex si{0, c->parity, c->rot, 0};
+  const unsigned pb = (unsigned)((c->ne + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK);
+  auto apply = [&](bool) -> pdf_status {
+    hipLaunchKernelGGL(relax::k_proj_grad, dim3(eb), dim3(tb), 0, st, a);
+    if (c->p.f32_state) {
+      hipLaunchKernelGGL(relax::k_proj_apply<float>, dim3(vb), dim3(tb), 0, st, a, (float*)(d + L.coef), phi, grad);
+      hipLaunchKernelGGL(relax::k_proj_particles<float>, dim3(pb), dim3(BLOCK), 0, st, a,
+                         state_at<float>(d, L.buf0, L.slots, L.omega), state_at<float>(d, L.buf1, L.slots, L.omega), cs,
+                         (const int32_t*)(d + L.start), (const int32_t*)(d + L.cap), (const Ctl*)(d + L.ctl), si);
+    } else {
+      hipLaunchKernelGGL(relax::k_proj_apply<double>, dim3(vb), dim3(tb), 0, st, a, (double*)(d + L.coef), phi, grad);
+      hipLaunchKernelGGL(relax::k_proj_particles<double>, dim3(pb), dim3(BLOCK), 0, st, a,
+                         state_at<double>(d, L.buf0, L.slots, L.omega), state_at<double>(d, L.buf1, L.slots, L.omega), cs,
+                         (const int32_t*)(d + L.start), (const int32_t*)(d + L.cap), (const Ctl*)(d + L.ctl), si);
     }
-    // the coefficients of the final solution (the count of clamped C0 anew)
-    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, &a.ctl->clamped, 0, (int64_t)1);
-    if ((r = update()) || (r = mark(slot))) return r;
-    if ((r = hip_check(c, hipEventSynchronize(c->rx_ev[slot]), "sync relaxation"))) return r;
-  }
-  const relax::Ctl& h = c->rx_pin[slot];
-  c->rx_last_iters = h.iter;
-  if (info) {
-    info[0] = h.iter;
-    info[1] = h.converged;
-    info[2] = h.clamped;
-    info[3] = h.from_stats;
-  }
-  if (resid)
-    for (int q = 0; q < relax::NC; ++q) resid[q] = h.ref[q] > 0.0 ? std::sqrt(h.rho[q] / h.ref[q]) : 0.0;
+    hipLaunchKernelGGL(relax::k_proj_done, dim3(1), dim3(64), 0, st, a.ctl);
+    return hip_check(c, hipGetLastError(), "projection launch");
+  };
+  const relax::Ctl* h = nullptr;
+  if ((r = run_solve(c, a, c->px_sg, max_iters, apply, &h))) return r;
+  report_solve(*h, info, resid, h->applied);
   return PDF_OK;
 }
 
 pdf_status pdf_relaxation_size(const pdf_ctx* c, int64_t* out) {
   if (!c || !out) return PDF_E_ARG;
-  if (!c->mesh_ready || c->p.model != 1) return PDF_E_STATE;
+  if (!c->mesh_ready) return PDF_E_STATE;
   if (c->rx_nc == 0) return PDF_E_MESH;
   out[0] = c->rx_nc;
   out[1] = c->rx_nnz;
@@ -1678,10 +1770,8 @@ void pdf_destroy(pdf_ctx* c) {
   if (c->stream || c->seeded) (void)hipStreamSynchronize(c->stream);
   if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
   if (c->graph) (void)hipGraphDestroy(c->graph);
-  for (int gi = 0; gi < 2; ++gi) {
-    if (c->rx_graph_exec[gi]) (void)hipGraphExecDestroy(c->rx_graph_exec[gi]);
-    if (c->rx_graph[gi]) (void)hipGraphDestroy(c->rx_graph[gi]);
-  }
+  c->rx_sg.release();
+  c->px_sg.release();
   for (auto& e : c->rx_ev)
     if (e) (void)hipEventDestroy(e);
   if (c->rx_pin) (void)hipHostFree(c->rx_pin);

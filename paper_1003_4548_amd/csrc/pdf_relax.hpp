@@ -65,6 +65,8 @@ struct Ctl {
   int32_t converged;
   int32_t clamped;              // vertices whose C0 was negative
   int32_t from_stats;           // elements whose stresses came from the particles
+  int32_t applied;              // the projection's update has been applied
+  int32_t pad_;
 };
 
 struct alignas(32) Rec {
@@ -75,7 +77,9 @@ struct Args {
   // mesh (device)
   int32_t ne, nv, nc, nbx, ellw;
   const int32_t* tri;      // ne x 3
-  const double* fields;    // nv x NFIELD (frozen)
+  const double* vtx;       // nv x 2
+  const double* fields;    // nv x NFIELD (frozen; the projection updates the mean pressure gradient)
+  double* fields_rw;       // the same array, written by the projection
   const int32_t* canon;    // nv: unknown of each vertex
   // matrix rows padded to ellw entries, slot t of row i at t * nc + i;
   // padding points at the row itself with a zero entry
@@ -92,6 +96,12 @@ struct Args {
   const double* stats;
   int32_t nstat;
   double nu;
+  // the system: mass * M + L^2 K; right-hand side 0: relaxation (S per
+  // element and component, times a third of the area), 1: projection (S per
+  // element and local vertex, component 0 only)
+  double mass;
+  int32_t rhs_mode;
+  double dt;
   // work (device)
   double* S;               // 5 x ne right-hand side per element
   double* L2;              // ne
@@ -152,6 +162,7 @@ __global__ void k_relax_reset(Ctl* ctl, int max_iters, double tol2) {
   ctl->converged = 0;
   ctl->clamped = 0;
   ctl->from_stats = 0;
+  ctl->applied = 0;
   for (int q = 0; q < 2; ++q) {
     for (int c = 0; c < NC; ++c) ctl->sc[q].alpha[c] = ctl->sc[q].gamma[c] = 0.0;
     ctl->sc[q].iter = 0;
@@ -232,7 +243,7 @@ __global__ __launch_bounds__(BLK) void k_relax_matrix(Args a) {
       const int c = a.cidx[t];
       const int e = c / 9, ab = c - 9 * e, aa = ab / 3, bb = ab - 3 * aa;
       const double m = a.area[e] / 12.0 * (aa == bb ? 2.0 : 1.0);
-      v += m + a.L2[e] * a.Ke[9 * e + ab];
+      v += a.mass * m + a.L2[e] * a.Ke[9 * e + ab];
     }
   }
   a.aval[q] = v;
@@ -326,9 +337,16 @@ __global__ __launch_bounds__(BLK) void k_relax_start1(Args a) {
   double bb[1] = {0.0};
   if (i < nc) {
     double bv = 0.0;
-    for (int t = a.incptr[i]; t < a.incptr[i + 1]; ++t) {
-      const int e = a.inc[t] / 3;
-      bv += a.S[(size_t)c * a.ne + e] * (a.area[e] / 3.0);
+    if (a.rhs_mode == 0) {
+      for (int t = a.incptr[i]; t < a.incptr[i + 1]; ++t) {
+        const int e = a.inc[t] / 3;
+        bv += a.S[(size_t)c * a.ne + e] * (a.area[e] / 3.0);
+      }
+    } else if (c == 0) {
+      for (int t = a.incptr[i]; t < a.incptr[i + 1]; ++t) {
+        const int e = a.inc[t] / 3, l = a.inc[t] - 3 * e;
+        bv += a.S[(size_t)l * a.ne + e];
+      }
     }
     const double* xc = a.x + (size_t)c * nc;
     double ax = 0.0;
@@ -522,6 +540,138 @@ inline const void* relax_iter_kernel(int w) {
     case 16: return (const void*)k_relax_iter<16>;
     default: return nullptr;
   }
+}
+
+// ---------------------------------------------------------------------------
+// Mean-pressure projection (closing summary of section 2.2; section 3: the
+// mean-pressure Poisson equation on the grid by finite elements).  The
+// pressure increment phi solves lap(phi) = div<U> / dt with d(phi)/dn =
+// <U>.n / dt at walls, in the Galerkin form K phi = (1/dt) sum_e area_e
+// <U>_e . grad(psi_i)|_e (the same unknowns, seams and solver as the
+// relaxation, no mass term; the load sums to zero, so the singular system
+// is consistent); the mean pressure gradient gains grad(phi) averaged to the
+// vertices by area, and every particle's velocity loses dt grad(phi) of its
+// element.
+
+// the P1 shape-function gradients of element e (2A grad(psi_k) = (y_{k+1} -
+// y_{k+2}, x_{k+2} - x_{k+1})) and its area
+__device__ __forceinline__ double shape_grads(const Args& a, int e, double (&gx)[3], double (&gy)[3]) {
+  double x[3], y[3];
+  for (int k = 0; k < 3; ++k) {
+    x[k] = a.vtx[2 * a.tri[3 * e + k]];
+    y[k] = a.vtx[2 * a.tri[3 * e + k] + 1];
+  }
+  const double a2 = (x[1] - x[0]) * (y[2] - y[0]) - (x[2] - x[0]) * (y[1] - y[0]);
+  for (int k = 0; k < 3; ++k) {
+    gx[k] = (y[(k + 1) % 3] - y[(k + 2) % 3]) / a2;
+    gy[k] = (x[(k + 2) % 3] - x[(k + 1) % 3]) / a2;
+  }
+  return 0.5 * a2;
+}
+
+// per element: the mean velocity (the particles', the frozen one at the
+// centroid under N_MIN particles) and its load on the element's three
+// vertices; L^2 = 1
+__global__ __launch_bounds__(BLK) void k_proj_inputs(Args a) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  bool est = false;
+  if (e < a.ne) {
+    const double* rec = a.stats + (size_t)e * a.nstat;
+    est = rec[ST_N] >= (double)N_MIN;
+    double U, V;
+    if (est) {
+      U = rec[ST_MEAN];
+      V = rec[ST_MEAN + 1];
+    } else {
+      const double* f0 = a.fields + (size_t)a.tri[3 * e] * NFIELD;
+      const double* f1 = a.fields + (size_t)a.tri[3 * e + 1] * NFIELD;
+      const double* f2 = a.fields + (size_t)a.tri[3 * e + 2] * NFIELD;
+      U = (f0[F_U] + f1[F_U] + f2[F_U]) / 3.0;
+      V = (f0[F_V] + f1[F_V] + f2[F_V]) / 3.0;
+    }
+    double gx[3], gy[3];
+    const double area = shape_grads(a, e, gx, gy);
+    for (int k = 0; k < 3; ++k) a.S[(size_t)k * a.ne + e] = area * (U * gx[k] + V * gy[k]) / a.dt;
+    a.L2[e] = 1.0;
+  }
+  const uint64_t m = __ballot(est);
+  if ((threadIdx.x & (WAVE - 1)) == 0 && m) atomicAdd(&a.ctl->from_stats, (int)__popcll(m));
+}
+
+// The kernels below do nothing before the stop or after k_proj_done has
+// marked the update applied, so the host may enqueue them behind any batch
+// of iterations and they act once per solve.
+
+// grad(phi) per element into Rk rows 0 and 1
+__global__ __launch_bounds__(BLK) void k_proj_grad(Args a) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= a.ne || !a.ctl->done || a.ctl->applied) return;
+  double gx[3], gy[3];
+  (void)shape_grads(a, e, gx, gy);
+  double px = 0.0, py = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    const double ph = a.x[a.canon[a.tri[3 * e + k]]];
+    px += ph * gx[k];
+    py += ph * gy[k];
+  }
+  a.Rk[e] = px;
+  a.Rk[(size_t)a.ne + e] = py;
+}
+
+// per vertex: grad(phi) averaged by area over the unknown's elements, added
+// to the mean pressure gradient (fields and the coefficient table);
+// phi_out (V, may be null): phi (up to a constant); grad_out (V x 2, may be
+// null): the vertex gradient
+template <typename T>
+__global__ __launch_bounds__(BLK) void k_proj_apply(Args a, T* coef, double* phi_out, double* grad_out) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= a.nv || !a.ctl->done || a.ctl->applied) return;
+  const int c = a.canon[v];
+  double ws = 0.0, gx = 0.0, gy = 0.0;
+  for (int t = a.incptr[c]; t < a.incptr[c + 1]; ++t) {
+    const int e = a.inc[t] / 3;
+    const double w = a.area[e];
+    ws += w;
+    gx += w * a.Rk[e];
+    gy += w * a.Rk[(size_t)a.ne + e];
+  }
+  gx /= ws;
+  gy /= ws;
+  double* f = a.fields_rw + (size_t)v * NFIELD;
+  f[F_DPDX] += gx;
+  f[F_DPDY] += gy;
+  coef[(size_t)v * NCOEF + C_DPDX] = (T)f[F_DPDX];
+  coef[(size_t)v * NCOEF + C_DPDY] = (T)f[F_DPDY];
+  if (phi_out) phi_out[v] = a.x[c];
+  if (grad_out) {
+    grad_out[2 * (size_t)v] = gx;
+    grad_out[2 * (size_t)v + 1] = gy;
+  }
+}
+
+// every particle of ensemble 0 (one wavefront per element): velocity less
+// dt grad(phi) of its element, in double, rounded to the state type
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_proj_particles(Args a, StateDev<T> b0, StateDev<T> b1, CounterSets cs,
+                                                          const int32_t* start, const int32_t* cap,
+                                                          const pdf::Ctl* sctl, StepIndex si) {
+  const int e = blockIdx.x * WAVES_PER_BLOCK + (int)(threadIdx.x / WAVE);
+  if (e >= a.ne || !a.ctl->done || a.ctl->applied) return;
+  const StateDev<T> st = (si.parity ^ (sctl->flip & 1u)) ? b1 : b0;
+  const int capc = cap[e], s0 = start[e];
+  const int ns = min(cs.ns[si.rot][e], capc);
+  const int nm = min(cs.nm[si.rot][e], capc - ns);
+  const double du = a.dt * a.Rk[e], dv = a.dt * a.Rk[(size_t)a.ne + e];
+  for (int j = lane_id(); j < ns + nm; j += WAVE) {
+    const int s = slot_of(j, s0, ns, nm, capc);
+    st.u[s] = (T)((double)st.u[s] - du);
+    st.v[s] = (T)((double)st.v[s] - dv);
+  }
+}
+
+// marks the projection's update applied once the solve has stopped
+__global__ void k_proj_done(Ctl* ctl) {
+  if (threadIdx.x == 0 && ctl->done) ctl->applied = 1;
 }
 
 // ---------------------------------------------------------------------------

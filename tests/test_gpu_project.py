@@ -1,0 +1,164 @@
+"""Parity of the mean-pressure projection on the GPU against the oracle
+(oracle/project.py: the same weak pressure-Poisson system solved directly
+with a zero-mean constraint, the same gradient averaging and correction).
+
+Both sides start from bit-identical particles (the step parity tests) and
+take the statistics of their own state.  The GPU solves by conjugate
+gradients to a relative residual tol = 1e-12, so
+* the increment is compared after removing its mean: |phi_gpu - phi| <=
+  10 kappa tol |phi|, kappa = lambda_max / lambda_2 of the stiffness matrix
+  (lambda_2: its smallest nonzero eigenvalue);
+* the vertex gradients within the largest gradient that difference can
+  make: max_e sum_a |grad(psi_a)| times it (averaging cannot enlarge it);
+* the particles' velocities after the correction within dt times that bound
+  plus one rounding to the state type; positions and elements bit for bit.
+Then: a second projection right after the first finds almost nothing left
+where every element holds ten particles or more (the particle means now are
+the corrected field, up to the rounding of the velocities); and the step after a projection uses the new mean pressure
+gradient (against the oracle stepping with it, and far from the oracle
+stepping with the old one).  Cases: the 2k-element canyon (resolved walls,
+float and double state), its wall-function variant, the doubly periodic box
+and the 1M-particle, 10k-element canyon.
+"""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+import oracle as O
+import oracle.project as P
+import oracle.relax as R
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1003_4548_amd as PK
+    PK.load_library()
+    return PK
+
+
+def _cases():
+    return {
+        "canyon_f32": lambda: W.small_canyon(target=2000, ppe=40, steps=5),
+        "canyon_f64": lambda: W.small_canyon(target=2000, ppe=40, steps=5, precision="f64"),
+        "canyon_wallfn_f32": lambda: W.small_canyon(target=2000, ppe=40, steps=5, wallfn=True),
+        "periodic_box_f32": lambda: W.square_box(n=12, ppe=30, periodic_y=True, precision="f32", dt=1e-3, steps=5),
+        "canyon_1M_f32": lambda: W.config2(steps=3),
+    }
+
+
+def _bounds(mesh, phi_ref):
+    M, K, canon, nc, area = R.assemble(mesh, np.ones(mesh.nelem))
+    lmax = spla.eigsh(K, k=1, which="LA", return_eigenvectors=False)[0]
+    lam = np.sort(spla.eigsh(K, k=2, sigma=-1e-6 * lmax, which="LM", return_eigenvectors=False))
+    kappa = lmax / lam[1]
+    _, gx, gy = R.element_geometry(mesh)
+    gnorm = (np.abs(gx) + np.abs(gy)).sum(axis=1).max()
+    err_phi = 10 * kappa * TOL * np.linalg.norm(phi_ref)
+    return kappa, err_phi, gnorm * err_phi
+
+
+@pytest.mark.parametrize("case", list(_cases()))
+def test_projection_matches_the_oracle(gpu, case):
+    wl = _cases()[case]()
+    print(f"[case] projection {case}: {wl.name} n={wl.n_total} elements={wl.mesh.nelem} steps={wl.steps}",
+          flush=True)
+    sim = gpu.Simulation.from_workload(wl)
+    sim.step(wl.steps)
+    sim.sync()
+    res = sim.pressure_projection(max_iters=20000, tol=TOL)
+    g = sim.state()
+    sim.close()
+    orc = O.Oracle(wl)
+    orc.step(wl.steps)
+    st = orc.stats()
+    ref = P.project(wl.mesh, wl.fields, st, wl.dt)
+    o = P.correct_state(orc.state(), ref["grad_elem"], wl.dt, wl.precision == "f32")
+    kappa, err_phi, err_g = _bounds(wl.mesh, ref["phi"])
+    phi = res["phi"] - res["phi"].mean()
+    dphi = np.abs(phi - (ref["phi"] - ref["phi"].mean())).max()
+    dg = np.abs(res["grad"] - ref["grad_vertex"]).max()
+    print(f"[project] {case}: kappa {kappa:.3g}, iterations {res['iterations']}, resid {res['resid'][0]:.2e}, "
+          f"|dphi| {dphi:.2e} (bound {err_phi:.2e}), |dgrad| {dg:.2e} (bound {err_g:.2e}), "
+          f"max |grad| {np.abs(ref['grad_vertex']).max():.3g}", flush=True)
+    assert res["converged"] and res["applied"]
+    assert res["resid"][0] <= TOL
+    assert res["from_stats"] == int((st[:, O.ST_N] >= P.N_MIN).sum())
+    assert dphi <= err_phi
+    assert dg <= err_g
+    for q in ("x", "y", "w", "psi", "elem"):
+        np.testing.assert_array_equal(g[q], o[q], err_msg=q)
+    ulp = 2.4e-7 if wl.precision == "f32" else 4.5e-16
+    for q in ("u", "v"):
+        lim = wl.dt * err_g + ulp * np.abs(o[q]).max()
+        assert np.abs(g[q] - o[q]).max() <= lim, (q, np.abs(g[q] - o[q]).max(), lim)
+
+
+@pytest.mark.parametrize("case", ["canyon_200ppe_f64", "periodic_box_f64"])
+def test_second_projection_finds_little(gpu, case):
+    # every element holds ten particles or more, so both projections take
+    # the particles' mean velocity everywhere (an element under ten takes the
+    # frozen velocity, which the correction of its particles does not change)
+    wl = (W.small_canyon(target=600, ppe=200, steps=5, precision="f64") if case == "canyon_200ppe_f64" else
+          W.square_box(n=12, ppe=30, periodic_y=True, precision="f64", dt=1e-3, steps=5))
+    print(f"[case] projection twice: {wl.name}", flush=True)
+    sim = gpu.Simulation.from_workload(wl)
+    sim.step(wl.steps)
+    first = sim.pressure_projection(tol=TOL)
+    second = sim.pressure_projection(tol=TOL)
+    sim.close()
+    assert first["from_stats"] == second["from_stats"] == wl.mesh.nelem
+    r = np.abs(second["grad"]).max() / np.abs(first["grad"]).max()
+    print(f"[project] second / first gradient {r:.2e}", flush=True)
+    assert r < 1e-9
+
+
+def test_step_after_projection_uses_the_new_pressure_gradient(gpu):
+    wl = W.small_canyon(target=2000, ppe=40, steps=5)
+    print(f"[case] step after projection: {wl.name}", flush=True)
+    sim = gpu.Simulation.from_workload(wl)
+    sim.step(wl.steps)
+    res = sim.pressure_projection(tol=TOL)
+    assert res["applied"]
+    sim.step(1)
+    sim.sync()
+    g = sim.state()
+    sim.close()
+    orc = O.Oracle(wl)
+    orc.step(wl.steps)
+    ref = P.project(wl.mesh, wl.fields, orc.stats(), wl.dt)
+    old = O.Oracle(wl)
+    old.step(wl.steps)
+    corrected = P.correct_state(orc.state(), ref["grad_elem"], wl.dt, True)
+    for x in (orc, old):
+        x.set_state(corrected)
+        x.step_index = wl.steps
+    f = wl.fields
+    orc.set_pressure_gradient(np.stack([f[:, 8] + ref["grad_vertex"][:, 0], f[:, 9] + ref["grad_vertex"][:, 1]], 1))
+    orc.step(1)
+    old.step(1)
+    o, b = orc.state(), old.state()
+    d_new = max(np.abs(g[q] - o[q]).max() for q in ("u", "v"))
+    d_old = max(np.abs(g[q] - b[q]).max() for q in ("u", "v"))
+    moved = int((g["elem"] != o["elem"]).sum())
+    print(f"[project] after one step: new gradient {d_new:.2e}, old gradient {d_old:.2e}, elements differing "
+          f"{moved}", flush=True)
+    assert d_new <= 1e-5
+    assert d_old > 100 * max(d_new, 1e-9)
+    assert moved <= 1e-4 * len(g["elem"]) + 1
+
+
+def test_projection_needs_one_ensemble(gpu):
+    wl = W.small_canyon(target=600, ppe=10, nens=2, steps=1)
+    sim = gpu.Simulation.from_workload(wl)
+    with pytest.raises(gpu.PdfError) as ei:
+        sim.pressure_projection()
+    assert ei.value.code == -8
+    sim.close()
