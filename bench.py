@@ -327,30 +327,34 @@ def learned_leg(torch, W, Simulation) -> dict:
     return res
 
 
-def relaxation_leg(torch, W, Simulation, cycles: int = 5, between: int = 6) -> dict:
-    """The elliptic relaxation (eqs. 12-18) on the 1M-particle, 10k-element
-    canyon: a first solve from the frozen wp fields, then solves every
-    `between` steps, each warm-started from the last, at four tolerances.
-    GPU time per solve from HIP events on the simulation's stream around the
-    call (statistics pass, assembly, iterations, coefficient update).  The
-    per-iteration cost and the per-solve set-up are the slope and intercept
-    of a least-squares line through (iterations, solve time) of the warm
-    solves.  Bytes per iteration (algorithmic): per unknown and component,
-    r w s p x read and p x s r w written (80 B), and per unknown the inverse
-    diagonal and its padded row (8 + 12 W B)."""
+def eulerian_leg(torch, W, Simulation, solve: str, cycles: int = 5, between: int = 6) -> dict:
+    """An Eulerian solve on the 1M-particle, 10k-element canyon: the elliptic
+    relaxation (eqs. 12-18; five components, warm-started from the last
+    solution) or the mean-pressure projection (one component, from zero).
+    A first solve, then solves every `between` steps at four tolerances.  GPU
+    time per solve from HIP events on the simulation's stream around the call
+    (statistics pass, assembly, iterations, the update that uses the
+    solution).  The per-iteration cost and the per-solve set-up are the slope
+    and intercept of a least-squares line through (iterations, solve time)
+    of the solves after the first at each tolerance.  Bytes per iteration
+    (algorithmic): per unknown and solved component, r w s p x read and
+    p x s r w written (80 B), and per unknown the inverse diagonal and its
+    padded row (8 + 12 W B)."""
     wl = W.config2(steps=10)
     sim = Simulation.from_workload(wl, device="cuda:0")
     size = sim.relaxation_size()
     sim.step_graph(30)
     sim.sync()
     stream = sim.stream
+    call = sim.elliptic_relaxation if solve == "relaxation" else sim.pressure_projection
+    ncomp = 5 if solve == "relaxation" else 1
 
     def timed(tol):
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         e0.record(stream)
-        r = sim.elliptic_relaxation(max_iters=20000, tol=tol, outputs=False)
+        r = call(max_iters=20000, tol=tol, outputs=False)
         e1.record(stream)
         torch.cuda.synchronize()
         return r, e0.elapsed_time(e1)
@@ -377,13 +381,13 @@ def relaxation_leg(torch, W, Simulation, cycles: int = 5, between: int = 6) -> d
     slope = sum((p[0] - mx) * (p[1] - my) for p in pts) / sum((p[0] - mx) ** 2 for p in pts)
     icpt = my - slope * mx
     nc, w = size["unknowns"], size["row_width"]
-    bytes_iter = nc * (5 * 80 + 8 + 12 * w)
+    bytes_iter = nc * (ncomp * 80 + 8 + 12 * w)
     achieved = bytes_iter / (slope * 1e-3) / 1e9
     res = {
-        "workload": f"{wl.name}: the relaxation system of its mesh, statistics of its 1M particles",
-        "unknowns": nc, "nonzeros": size["nonzeros"], "row_width": w, "components": 5,
+        "workload": f"{wl.name}: the P1 system of its mesh, statistics of its 1M particles",
+        "unknowns": nc, "nonzeros": size["nonzeros"], "row_width": w, "components": ncomp,
         "first_solve": {"tol": 1e-8, "iterations": cold["iterations"], "ms": round(cold_ms, 4)},
-        "warm_every_steps": between, "warm": warm,
+        "every_steps": between, "by_tol": warm,
         "per_iteration_us": round(1e3 * slope, 3), "per_solve_setup_us": round(1e3 * icpt, 1),
         "roofline": {"bound": "hbm", "kernel": "k_relax_iter", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -392,7 +396,10 @@ def relaxation_leg(torch, W, Simulation, cycles: int = 5, between: int = 6) -> d
                      "note": "the system is L2-resident (a few MB) and each iteration is one launch with two "
                              "dependent rounds of loads: launch latency and load latency bound it, not HBM"},
     }
-    print(f"[bench] relaxation: {res}", file=sys.stderr, flush=True)
+    if solve == "projection":
+        res["note"] = ("the iteration kernel runs all five component slots; the projection's load is in the "
+                       "first and the other four stop at once, so its bytes count one component")
+    print(f"[bench] {solve}: {res}", file=sys.stderr, flush=True)
     return res
 
 
@@ -419,7 +426,8 @@ def main() -> int:
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned conditional-mean leg (training, error, in-step throughput)")
     ap.add_argument("--no-relaxation", action="store_true",
-                    help="skip the elliptic-relaxation leg (solve time and per-iteration cost)")
+                    help="skip the Eulerian legs (elliptic relaxation and mean-pressure projection: solve time "
+                         "and per-iteration cost)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -587,7 +595,8 @@ def main() -> int:
     if not args.no_learned:
         out["learned_phi_given_v"] = learned_leg(torch, W, Simulation)
     if not args.no_relaxation:
-        out["elliptic_relaxation"] = relaxation_leg(torch, W, Simulation)
+        out["elliptic_relaxation"] = eulerian_leg(torch, W, Simulation, "relaxation")
+        out["pressure_projection"] = eulerian_leg(torch, W, Simulation, "projection")
     if args.calibrate_copy:
         nbytes = 1 << 30
         a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda:0").fill_(1.0)
