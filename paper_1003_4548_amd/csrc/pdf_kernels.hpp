@@ -4,7 +4,9 @@
 //   particles  x y u v w psi (state type T), id (u32) and, with the
 //              stochastic turbulent frequency, omega (T), in two buffers.
 //              Each (ensemble, element) pair -- a "cell" -- owns a segment of
-//              fixed capacity; its particles sit densely at the front.  A
+//              fixed capacity (resized by the device-side repack): the
+//              particles that stayed in the element sit densely at its
+//              bottom, those that arrived in the last step at its top.  A
 //              particle's element is implied by the segment that holds it.
 //   cells      segment start, capacity, particle count per buffer, IECM rate.
 //   mesh       vertex coordinates (f64), element vertices / neighbours / edge
