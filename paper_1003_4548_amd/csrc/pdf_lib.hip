@@ -226,6 +226,10 @@ struct pdf_ctx {
   // memory behind it
   relax::Ctl* rx_pin = nullptr;
   hipEvent_t rx_ev[2] = {nullptr, nullptr};
+  // a split order's small cells run on a second stream beside the other
+  // cells' launch (fork and join by events; created at the first such step)
+  hipStream_t side = nullptr;
+  hipEvent_t side_ev[2] = {nullptr, nullptr};
   // the iteration graphs of the relaxation and of the projection solves
   SolveGraphs rx_sg, px_sg;
   std::string err;
@@ -537,6 +541,16 @@ void launch_ext(pdf_ctx* c, const StepArgs<T>& s, StepIndex si) {
 // network attached (its means inside the step need 16 or more lanes per cell).
 bool split_launch(const pdf_ctx* c) { return c->nsplit > 0 && !c->mlp_w && c->p.f32_state; }
 
+// The side stream of a split order and its fork and join events.
+pdf_status side_stream(pdf_ctx* c) {
+  pdf_status r = PDF_OK;
+  if (!c->side && (r = hip_check(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking), "side stream")))
+    return r;
+  for (auto& e : c->side_ev)
+    if (!e && (r = hip_check(c, hipEventCreateWithFlags(&e, hipEventDisableTiming), "side event"))) return r;
+  return r;
+}
+
 template <bool ADV> pdf_status dispatch_step(pdf_ctx* c, StepIndex si) {
   if (c->p.f32_state) {
     StepArgs<float> s = step_args<float>(c);
@@ -544,20 +558,35 @@ template <bool ADV> pdf_status dispatch_step(pdf_ctx* c, StepIndex si) {
     if (!ADV) s.mlp_w = nullptr;
     const bool split = split_launch(c);
     const int32_t ncell = s.ncell;
-    if (split) s.ncell = (int32_t)c->nsplit;
+    pdf_status r;
+    if (split) {
+      // the small cells (at the end of the order) on the side stream, at the
+      // same time as the others: the two launches touch disjoint cells, as
+      // the wavefronts of one launch do
+      if ((r = side_stream(c))) return r;
+      if ((r = hip_check(c, hipEventRecord(c->side_ev[0], c->stream), "fork"))) return r;
+      if ((r = hip_check(c, hipStreamWaitEvent(c->side, c->side_ev[0], 0), "fork"))) return r;
+      StepArgs<float> sm = s;
+      sm.order = s.order + c->nsplit;
+      sm.ncell = ncell - (int32_t)c->nsplit;
+      const int32_t g = c->group, pe = c->persist;
+      hipStream_t main = c->stream;
+      c->group = SMALL_GROUP;
+      c->persist = 0;
+      c->stream = c->side;
+      if (c->p.moments == 2) launch_ext<float, 2, 0, ADV>(c, sm, si);
+      else launch_ext<float, 4, 32, ADV>(c, sm, si);
+      c->group = g;
+      c->persist = pe;
+      c->stream = main;
+      if ((r = hip_check(c, hipGetLastError(), "step launch"))) return r;
+      s.ncell = (int32_t)c->nsplit;
+    }
     if (c->p.moments == 2) launch_ext<float, 2, 0, ADV>(c, s, si);
     else launch_ext<float, 4, 32, ADV>(c, s, si);
     if (split) {
-      // the small cells at the end of the order
-      s.order = s.order + c->nsplit;
-      s.ncell = ncell - (int32_t)c->nsplit;
-      const int32_t g = c->group, pe = c->persist;
-      c->group = SMALL_GROUP;
-      c->persist = 0;
-      if (c->p.moments == 2) launch_ext<float, 2, 0, ADV>(c, s, si);
-      else launch_ext<float, 4, 32, ADV>(c, s, si);
-      c->group = g;
-      c->persist = pe;
+      if ((r = hip_check(c, hipEventRecord(c->side_ev[1], c->side), "join"))) return r;
+      if ((r = hip_check(c, hipStreamWaitEvent(c->stream, c->side_ev[1], 0), "join"))) return r;
     }
   } else {
     StepArgs<double> s = step_args<double>(c);
@@ -771,7 +800,9 @@ template <typename T> pdf_status build_graph_t(pdf_ctx* c) {
   pdf_status r;
   hipGraph_t g = nullptr;
   if ((r = hip_check(c, hipGraphCreate(&g, 0), "graph create"))) return r;
-  hipGraphNode_t prev = nullptr;
+  // the nodes the next one depends on (none before the first step)
+  hipGraphNode_t deps[2] = {nullptr, nullptr};
+  size_t ndep = 0;
   StepIndex sis[GRAPH_STEPS];
   void* params[GRAPH_STEPS][2];
   void* params_small[GRAPH_STEPS][2];
@@ -790,9 +821,10 @@ template <typename T> pdf_status build_graph_t(pdf_ctx* c) {
     kp.kernelParams = params[i];
     kp.extra = nullptr;
     hipGraphNode_t node;
-    if ((r = hip_check(c, hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &kp), "graph node"))) return r;
-    prev = node;
+    if ((r = hip_check(c, hipGraphAddKernelNode(&node, g, deps, ndep, &kp), "graph node"))) return r;
     if (split) {
+      // the small cells' launch is a parallel branch of the same step: the two
+      // launches touch disjoint cells, as the wavefronts of one launch do
       params_small[i][0] = &args_small;
       params_small[i][1] = &sis[i];
       hipKernelNodeParams ks = kp;
@@ -801,9 +833,13 @@ template <typename T> pdf_status build_graph_t(pdf_ctx* c) {
       ks.blockDim = dim3(ls.threads);
       ks.kernelParams = params_small[i];
       hipGraphNode_t sn;
-      if ((r = hip_check(c, hipGraphAddKernelNode(&sn, g, &prev, 1, &ks), "graph node"))) return r;
-      prev = sn;
+      if ((r = hip_check(c, hipGraphAddKernelNode(&sn, g, deps, ndep, &ks), "graph node"))) return r;
+      deps[1] = sn;
+      ndep = 2;
+    } else {
+      ndep = 1;
     }
+    deps[0] = node;
     if (c->avg) {
       hipKernelNodeParams km{};
       km.func = reinterpret_cast<void*>(&k_average_merge);
@@ -811,8 +847,9 @@ template <typename T> pdf_status build_graph_t(pdf_ctx* c) {
       km.blockDim = dim3(BLOCK);
       km.kernelParams = mparams8;
       hipGraphNode_t mn;
-      if ((r = hip_check(c, hipGraphAddKernelNode(&mn, g, &prev, 1, &km), "graph node"))) return r;
-      prev = mn;
+      if ((r = hip_check(c, hipGraphAddKernelNode(&mn, g, deps, ndep, &km), "graph node"))) return r;
+      deps[0] = mn;
+      ndep = 1;
     }
   }
   // capacity check at the end of the cycle (parity 0, counter set 0); the
@@ -826,7 +863,7 @@ template <typename T> pdf_status build_graph_t(pdf_ctx* c) {
   kpl.blockDim = dim3(PLAN_THREADS);
   kpl.kernelParams = pparams;
   hipGraphNode_t pnode;
-  if ((r = hip_check(c, hipGraphAddKernelNode(&pnode, g, &prev, 1, &kpl), "graph node"))) return r;
+  if ((r = hip_check(c, hipGraphAddKernelNode(&pnode, g, deps, ndep, &kpl), "graph node"))) return r;
   RepackMove<T> mv = repack_move_args<T>(c, 0);
   StepIndex si0{0, 0, 0, 0};
   void* mparams[2] = {&mv, &si0};
@@ -1773,6 +1810,12 @@ void pdf_destroy(pdf_ctx* c) {
   c->rx_sg.release();
   c->px_sg.release();
   for (auto& e : c->rx_ev)
+    if (e) (void)hipEventDestroy(e);
+  if (c->side) {
+    (void)hipStreamSynchronize(c->side);
+    (void)hipStreamDestroy(c->side);
+  }
+  for (auto& e : c->side_ev)
     if (e) (void)hipEventDestroy(e);
   if (c->rx_pin) (void)hipHostFree(c->rx_pin);
   delete c;
