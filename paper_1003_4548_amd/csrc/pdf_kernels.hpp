@@ -499,27 +499,11 @@ __device__ __forceinline__ void lds_sync_wave() {
   __builtin_amdgcn_wave_barrier();
 }
 
-// XV, an extension of the model: XV_OMEGA, the particles carry the stochastic
-// turbulent frequency of eq. (9) and the record gains its mean, variance and
-// the dissipation estimate of eq. (8); XV_BINS5, <phi|V> on 5 x 5 x 5
-// velocity bins (the record gains their counts and means).
-enum { XV_NONE = 0, XV_OMEGA = 1, XV_BINS5 = 2 };
-
-// Per-cell constants that only an extension reads (none for the plain model,
-// so its LDS holds nothing unused).
-template <int XV> struct CellExt {};
-template <> struct CellExt<XV_OMEGA> {
-  double om_mean, sw;  // the element's frozen <omega> and S_omega
-};
-template <> struct CellExt<XV_BINS5> {
-  double fsd[3];       // standard deviations of u, v, w
-};
-
 // Per-cell constants of the advance, kept in LDS rather than in registers
 // across the particle loop: the element's vertices, the interpolation
 // coefficients of its three vertices, the velocity means that define the
 // bins and the conditional means IECM relaxes toward.
-template <typename T, int XV> struct CellConst : CellExt<XV> {
+template <typename T> struct CellConst {
   T coef[3 * NCOEF];
   // edge k (vertex k -> k+1) from its lexicographically smaller endpoint:
   // origin, and direction times the sign that turns the result into the
@@ -528,18 +512,25 @@ template <typename T, int XV> struct CellConst : CellExt<XV> {
   double ox[3], oy[3], dx[3], dy[3];
   double mean[3];
   double cm[8];
+  double om_mean, sw;  // turbulent frequency: the element's frozen <omega> and S_omega
+  double fsd[3];       // 5 x 5 x 5 bins: standard deviations of u, v, w
 };
 
 // orient_edge of (px, py) against edge k of a cell, from its CellConst data:
 // the sign carried by the direction flips the result exactly (the rounding
 // of a fused multiply-add is symmetric), so it is orient_edge's number.
-template <typename CC>
-__device__ __forceinline__ double orient_cc(const CC& C, int k, double px, double py) {
+template <typename T>
+__device__ __forceinline__ double orient_cc(const CellConst<T>& C, int k, double px, double py) {
   return __builtin_fma(C.dx[k], py - C.oy[k], -(C.dy[k] * (px - C.ox[k])));
 }
 
 // SCHED: 0 one work item per wavefront; 1 persistent grid; 2 one item per
 // wavefront with the learned conditional means computed inside the step.
+// XV, an extension of the model: XV_OMEGA, the particles carry the stochastic
+// turbulent frequency of eq. (9) and the record gains its mean, variance and
+// the dissipation estimate of eq. (8); XV_BINS5, <phi|V> on 5 x 5 x 5
+// velocity bins (the record gains their counts and means).
+enum { XV_NONE = 0, XV_OMEGA = 1, XV_BINS5 = 2 };
 
 // Five bins per velocity component: widths 1.2 sigma on [-3 sigma, 3 sigma]
 // about the element mean, the outermost bins open; sigma = 0: the middle bin.
@@ -580,16 +571,13 @@ void k_step(StepArgs<T> a, StepIndex si) {
   // already set the blocks per CU and the deeper tile still fits their LDS
   // (it saves re-reads of larger cells in each pass): five for the
   // fourth-order float kernels of 32 or 64 lanes per cell (three blocks),
-  // six at 8 lanes per cell (two blocks); two at 4 lanes per cell, the
-  // launch of cells seeded with at most 8 particles, whose LDS then allows
-  // the three blocks per SIMD its registers allow
-  constexpr int TILEN = ((MOM >= 4 && XV == XV_NONE && sizeof(T) == 4 && G >= 32) ? 5 :
-                         (G == 8 ? 6 : (G == 4 ? 2 : 4))) * G;
+  // six at 8 lanes per cell (two blocks)
+  constexpr int TILEN = ((MOM >= 4 && XV == XV_NONE && sizeof(T) == 4 && G >= 32) ? 5 : (G == 8 ? 6 : 4)) * G;
   constexpr int SWPB = step_block<SCHED>() / WAVE;  // wavefronts per block
   constexpr int CPB = SWPB * GPW;
   __shared__ Tile<T, TILEN> tiles[CPB];
   __shared__ int hist_lds[HIST > 0 ? CPB : 1][HIST > 0 ? HIST : 1];
-  __shared__ CellConst<T, XV> ccs[ADVANCE ? CPB : 1];
+  __shared__ CellConst<T> ccs[ADVANCE ? CPB : 1];
   __shared__ T otile[OMG ? CPB : 1][OMG ? TILEN : 1];
   __shared__ double fsum[VB5 ? CPB : 1][VB5 ? 125 : 1];
   __shared__ int fcnt[VB5 ? CPB : 1][VB5 ? 125 : 1];
@@ -1075,7 +1063,7 @@ void k_step(StepArgs<T> a, StepIndex si) {
 
     if (ADVANCE) {
       // ---- C: advance ----
-      CellConst<T, XV>& CC = ccs[ADVANCE ? slot_id : 0];
+      CellConst<T>& CC = ccs[ADVANCE ? slot_id : 0];
       {
         if constexpr (PRE_SC) {
 #pragma unroll
