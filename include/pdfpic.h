@@ -319,9 +319,13 @@ pdf_status pdf_elliptic_relaxation(pdf_ctx* ctx, int32_t max_iters, double tol, 
    vertices, is added to the mean pressure gradient (the device copy of the
    fields and the coefficient table the step reads), and every particle's
    velocity (u, v) loses dt grad(phi) of its element (in double, rounded to
-   the state type).  The system is solved as in pdf_elliptic_relaxation
-   (Jacobi-preconditioned CG, one launch per iteration) from phi = 0 until
-   ||r|| <= tol ||b||, or max_iters iterations (1..20000; tol in (0, 1)).
+   the state type).  The system is solved by conjugate gradients in the
+   form of pdf_elliptic_relaxation (one launch per iteration), preconditioned
+   by the inverse diagonal plus a coarse correction on aggregates of 32
+   unknowns (the pseudo-inverse of the stiffness matrix projected on them;
+   the diagonal alone where pdf_relaxation_size reports no aggregates),
+   from phi = 0 until ||r|| <= tol ||b||, or max_iters iterations
+   (1..20000; tol in (0, 1)).
    Outputs, each may be NULL: phi (device, nvert doubles, up to a constant);
    grad (device, nvert x 2 doubles: the vertex gradient added); info (host,
    4 int32: iterations, 1 if converged, 1 if the update was applied,
@@ -334,10 +338,13 @@ pdf_status pdf_pressure_projection(pdf_ctx* ctx, int32_t max_iters, double tol, 
                                    int32_t* info, double* resid);
 
 /* Size of the relaxation system of the mesh (section 2.1, the Galerkin
-   system of eq. 14): out (host, 3 int64) = unknowns (vertices, periodic
-   copies joined), nonzeros of the matrix, and the padded row length the
-   solver stores (the longest row); the mean-pressure projection solves on
-   the same unknowns.  Errors: PDF_E_ARG, PDF_E_STATE (before pdf_init_mesh),
+   system of eq. 14): out (host, 4 int64) = unknowns (vertices, periodic
+   copies joined), nonzeros of the matrix, the padded row length the solver
+   stores (the longest row), and the aggregates of the coarse space of the
+   mean-pressure projection's preconditioner (32 consecutive unknowns each;
+   0: the mesh has more than 192 of them, or a solver block's rows touch
+   more than 32, and the projection is preconditioned by the diagonal
+   alone); the projection solves on the same unknowns.  Errors: PDF_E_ARG, PDF_E_STATE (before pdf_init_mesh),
    PDF_E_MESH (a row longer than 16 entries, or a vertex in no element: the
    Eulerian solves are unavailable on the mesh). */
 pdf_status pdf_relaxation_size(const pdf_ctx* ctx, int64_t* out);

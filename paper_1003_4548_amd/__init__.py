@@ -375,10 +375,11 @@ class Simulation:
         return out
 
     def relaxation_size(self) -> dict:
-        """Unknowns, nonzeros and the padded row length of the relaxation system."""
-        out = np.zeros(3, np.int64)
+        """Unknowns, nonzeros and the padded row length of the relaxation
+        system, and the aggregates of the projection's coarse space."""
+        out = np.zeros(4, np.int64)
         self._check(load_library().pdf_relaxation_size(self.ctx, _ptr(out)), "pdf_relaxation_size")
-        return dict(unknowns=int(out[0]), nonzeros=int(out[1]), row_width=int(out[2]))
+        return dict(unknowns=int(out[0]), nonzeros=int(out[1]), row_width=int(out[2]), aggregates=int(out[3]))
 
     def state_device(self, ens: int = 0):
         n = self.count(ens)

@@ -39,6 +39,7 @@ struct Layout {
   // the Eulerian solves (elliptic relaxation, mean-pressure projection): sparsity, element data, solver vectors
   int64_t rx_canon, rx_rep, rx_ecol, rx_enz, rx_dpos, rx_cptr, rx_cidx, rx_incptr, rx_inc, rx_Ke, rx_area;
   int64_t rx_S, rx_L2, rx_Rk, rx_aval, rx_dinv, rx_x, rx_px, rx_p, rx_rec[2], rx_part[2], rx_pbb, rx_ctl;
+  int64_t rx_ep, rx_need, rx_eneed, rx_agp[2], rx_cglob[2];   // the projection's coarse space
   int64_t start, cap, cap0, nstart, ncap, ns[3], nm[3], rate, idoff, order, seed, src;
   int64_t buf0, buf1, ovf, ovf_cell, stats, ctl, flag, metrics;
   int64_t total;
@@ -103,6 +104,14 @@ Layout make_layout(int32_t nv, int32_t ne, int32_t nens, int64_t slots, int32_t 
     }
     L.rx_pbb = take(relax::NC * nbx * 8);
     L.rx_ctl = take((int64_t)sizeof(relax::Ctl));
+    const int64_t na = std::min<int64_t>((nc + relax::AGG - 1) / relax::AGG, relax::NA_MAX);
+    L.rx_ep = take(na * na * 8);
+    L.rx_need = take(nbx * relax::NEED * 4);
+    L.rx_eneed = take(ell * 4);
+    for (int b = 0; b < 2; ++b) {
+      L.rx_agp[b] = take(relax::NA_MAX * 3 * 8);
+      L.rx_cglob[b] = take(relax::NA_MAX * 8);
+    }
   }
   L.start = take(ncell * 4);
   L.cap = take(ncell * 4);
@@ -220,6 +229,7 @@ struct pdf_ctx {
   std::vector<uint8_t> restore_pending;
   // elliptic relaxation (model 1): unknowns and nonzeros of its matrix
   int32_t rx_nc = 0, rx_ellw = 0;
+  int32_t rx_na = 0;           // aggregates of the projection's coarse space (0: none)
   int64_t rx_nnz = 0;
   std::string rx_err;          // why the relaxation is unavailable on this mesh
   // the solver control after each batch of replays, copied to pinned host
@@ -279,7 +289,8 @@ pdf_status relax_setup(pdf_ctx* c, const pdf_mesh* m) {
   const int32_t nv = m->nvert, ne = m->nelem;
   host::RelaxStructure S;
   const host::RelaxStatus hs =
-      host::build_relax_structure(nv, ne, m->vtx, m->tri, m->nbr, m->ekind, c->p.Lx, c->p.Ly, relax::ELL_MAX, S);
+      host::build_relax_structure(nv, ne, m->vtx, m->tri, m->nbr, m->ekind, c->p.Lx, c->p.Ly, relax::ELL_MAX,
+                                  relax::AGG, S);
   // a mesh the Eulerian solves cannot take still steps particles
   if (hs != host::RELAX_OK) {
     c->rx_nc = 0;
@@ -310,6 +321,17 @@ pdf_status relax_setup(pdf_ctx* c, const pdf_mesh* m) {
   if ((r = put(L.rx_cidx, cidx, "copy relaxation contributions"))) return r;
   if ((r = put(L.rx_incptr, incptr, "copy relaxation incidence"))) return r;
   if ((r = put(L.rx_inc, inc, "copy relaxation incidence"))) return r;
+  // the projection's coarse space, where the mesh allows one (else its
+  // preconditioner is the diagonal alone)
+  host::CoarseStructure CS;
+  const bool coarse = host::build_coarse(S, ne, m->vtx, m->tri, relax::AGG, relax::BLK, relax::NEED, relax::NA_MAX,
+                                         CS) == host::COARSE_OK;
+  if (coarse) {
+    if ((r = hip_check(c, hipMemcpyAsync(d + L.rx_ep, CS.ep.data(), CS.ep.size() * 8, hipMemcpyHostToDevice, st),
+                       "copy coarse operator"))) return r;
+    if ((r = put(L.rx_need, CS.need, "copy coarse need lists"))) return r;
+    if ((r = put(L.rx_eneed, CS.eneed, "copy coarse need lists"))) return r;
+  }
   const int tb = 256;
   hipLaunchKernelGGL(relax::k_relax_geom, dim3((ne + tb - 1) / tb), dim3(tb), 0, st, (const double*)(d + L.vtx),
                      (const int32_t*)(d + L.tri), (double*)(d + L.rx_Ke), (double*)(d + L.rx_area), ne);
@@ -321,6 +343,7 @@ pdf_status relax_setup(pdf_ctx* c, const pdf_mesh* m) {
   c->rx_nc = nc;
   c->rx_nnz = nnz;
   c->rx_ellw = ellw;
+  c->rx_na = coarse ? CS.na : 0;
   c->rx_err.clear();
   c->rx_sg.ok = c->px_sg.ok = false;
   c->rx_sg.last_iters = c->px_sg.last_iters = 0;
@@ -1386,12 +1409,21 @@ static relax::Args relax_args(pdf_ctx* c) {
   a.part[1] = (double*)(d + L.rx_part[1]);
   a.pbb = (double*)(d + L.rx_pbb);
   a.ctl = (relax::Ctl*)(d + L.rx_ctl);
+  a.na = 0;   // the projection sets its coarse space
+  a.ep = (const double*)(d + L.rx_ep);
+  a.need = (const int32_t*)(d + L.rx_need);
+  a.eneed = (const int32_t*)(d + L.rx_eneed);
+  for (int b = 0; b < 2; ++b) {
+    a.agp[b] = (double*)(d + L.rx_agp[b]);
+    a.cglob[b] = (double*)(d + L.rx_cglob[b]);
+  }
   return a;
 }
 
 // The graphs of RELAX_LONG and RELAX_SHORT iteration launches of a solve
-// (kernel nodes only; every launch after the stop returns at once).
-static pdf_status build_solve_graphs(pdf_ctx* c, const relax::Args& a, SolveGraphs& sg) {
+// (kernel nodes only; every launch after the stop returns at once): the
+// relaxation's five components, or the projection's one.
+static pdf_status build_solve_graphs(pdf_ctx* c, const relax::Args& a, SolveGraphs& sg, bool proj) {
   if (sg.ok) return PDF_OK;
   static_assert(RELAX_LONG % 2 == 0 && RELAX_SHORT % 2 == 0, "iteration parity continues across replays");
   sg.release();
@@ -1406,8 +1438,8 @@ static pdf_status build_solve_graphs(pdf_ctx* c, const relax::Args& a, SolveGrap
     for (int i = 0; i < n; ++i) {
       void* params[2] = {&store, &pars[i & 1]};
       hipKernelNodeParams kp{};
-      kp.func = const_cast<void*>(relax::relax_iter_kernel(a.ellw));
-      kp.gridDim = dim3((unsigned)a.nbx, relax::NC);
+      kp.func = const_cast<void*>(proj ? relax::proj_iter_kernel(a.ellw) : relax::relax_iter_kernel(a.ellw));
+      kp.gridDim = dim3((unsigned)a.nbx, proj ? 1 : relax::NC);
       kp.blockDim = dim3(relax::BLK);
       kp.sharedMemBytes = 0;
       kp.kernelParams = params;
@@ -1442,10 +1474,10 @@ static pdf_status build_solve_graphs(pdf_ctx* c, const relax::Args& a, SolveGrap
 // with its control copy and event, the next one enqueued before the host
 // waits for the previous one, and finish(true) runs again.  *out: the
 // control at the end (pinned host memory of the context).
-static pdf_status run_solve(pdf_ctx* c, const relax::Args& a, SolveGraphs& sg, int32_t max_iters,
+static pdf_status run_solve(pdf_ctx* c, const relax::Args& a, SolveGraphs& sg, bool proj, int32_t max_iters,
                             const std::function<pdf_status(bool)>& finish, const relax::Ctl** out) {
   pdf_status r;
-  if ((r = build_solve_graphs(c, a, sg))) return r;
+  if ((r = build_solve_graphs(c, a, sg, proj))) return r;
   hipStream_t st = c->stream;
   if (!c->rx_pin) {
     if ((r = hip_check(c, hipHostMalloc((void**)&c->rx_pin, 2 * sizeof(relax::Ctl), hipHostMallocDefault), "pinned control"))) return r;
@@ -1531,7 +1563,7 @@ pdf_status pdf_elliptic_relaxation(pdf_ctx* c, int32_t max_iters, double tol, do
     return hip_check(c, hipGetLastError(), "relaxation launch");
   };
   const relax::Ctl* h = nullptr;
-  if ((r = run_solve(c, a, c->rx_sg, max_iters, update, &h))) return r;
+  if ((r = run_solve(c, a, c->rx_sg, false, max_iters, update, &h))) return r;
   report_solve(*h, info, resid, h->clamped);
   return PDF_OK;
 }
@@ -1549,18 +1581,18 @@ pdf_status pdf_pressure_projection(pdf_ctx* c, int32_t max_iters, double tol, do
   a.x = (double*)(c->arena + c->L.rx_px);
   a.mass = 0.0;
   a.rhs_mode = 1;
+  a.na = c->rx_na;
   hipStream_t st = c->stream;
   const int tb = relax::BLK;
   const unsigned eb = (unsigned)((c->ne + tb - 1) / tb), vb = (unsigned)((c->nv + tb - 1) / tb);
   const unsigned zb = (unsigned)(((int64_t)c->rx_ellw * c->rx_nc + tb - 1) / tb);
-  const dim3 grid((unsigned)a.nbx, relax::NC);
   const int64_t xwords = 2 * (int64_t)relax::NC * c->rx_nc;
   hipLaunchKernelGGL(relax::k_relax_reset, dim3(1), dim3(64), 0, st, a.ctl, max_iters, tol * tol);
   hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((xwords + 255) / 256)), dim3(256), 0, st, (int32_t*)a.x, 0, xwords);
   hipLaunchKernelGGL(relax::k_proj_inputs, dim3(eb), dim3(tb), 0, st, a);
   hipLaunchKernelGGL(relax::k_relax_matrix, dim3(zb), dim3(tb), 0, st, a);
-  hipLaunchKernelGGL(relax::k_relax_start1, grid, dim3(tb), 0, st, a);
-  hipLaunchKernelGGL(relax::k_relax_start2, grid, dim3(tb), 0, st, a);
+  hipLaunchKernelGGL(relax::k_proj_start1, dim3((unsigned)a.nbx), dim3(tb), 0, st, a);
+  hipLaunchKernelGGL(relax::k_proj_start2, dim3((unsigned)a.nbx), dim3(tb), 0, st, a);
   if ((r = hip_check(c, hipGetLastError(), "projection launch"))) return r;
   // the update, once the solve has stopped (the kernels check the device's
   // stop and applied flags, so a launch behind an unfinished batch does nothing)
@@ -1590,7 +1622,7 @@ pdf_status pdf_pressure_projection(pdf_ctx* c, int32_t max_iters, double tol, do
     return hip_check(c, hipGetLastError(), "projection launch");
   };
   const relax::Ctl* h = nullptr;
-  if ((r = run_solve(c, a, c->px_sg, max_iters, apply, &h))) return r;
+  if ((r = run_solve(c, a, c->px_sg, true, max_iters, apply, &h))) return r;
   report_solve(*h, info, resid, h->applied);
   return PDF_OK;
 }
@@ -1602,6 +1634,7 @@ pdf_status pdf_relaxation_size(const pdf_ctx* c, int64_t* out) {
   out[0] = c->rx_nc;
   out[1] = c->rx_nnz;
   out[2] = c->rx_ellw;
+  out[3] = c->rx_na;
   return PDF_OK;
 }
 

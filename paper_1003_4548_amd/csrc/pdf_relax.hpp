@@ -1,7 +1,9 @@
 // Elliptic relaxation (section 2.1): the tensor wp of eq. (14) from the
 // particle statistics, by Galerkin P1 finite elements on the mesh and a
 // Jacobi-preconditioned conjugate-gradient solve, then G and C0 of eqs.
-// (12)-(13) per vertex into the coefficient table the step reads.
+// (12)-(13) per vertex into the coefficient table the step reads.  The
+// mean-pressure projection further down solves its Poisson system with the
+// same iteration and a two-level preconditioner.
 //
 //   wp_ij - L^2 lap wp_ij = 1/2 (1 - C1) k <omega> delta_ij + k H_ijkl d<U_k>/dx_l
 //
@@ -116,7 +118,27 @@ struct Args {
   double* part[2];         // 5 x nbx x 3 block partials (r,u) (w,u) (r,r), by parity
   double* pbb;             // 5 x nbx block partials of (b, b)
   Ctl* ctl;
+  // the projection's coarse space (na = 0: none, the preconditioner is D^-1)
+  int32_t na;
+  const double* ep;        // na x na: E^+
+  const int32_t* need;     // nbx x NEED: aggregates whose correction a block reads
+  const int32_t* eneed;    // ellw x nc: position of each row slot's column aggregate in that list
+  double* agp[2];          // na x 3 aggregate sums of r_i, w_i, s_{i-1}, by parity
+  double* cglob[2];        // na: the coarse correction of r_i, by parity
 };
+
+// the projection's coarse space: aggregates of AGG consecutive unknowns (the
+// numbering is a recursive bisection, so they are compact patches); a block
+// of BLK unknowns owns APB of them and reads the correction of at most NEED
+// (its own and those its rows touch), TPE threads per entry of that list,
+// each summing JMAX terms of a row of E^+
+constexpr int AGG = 32;
+constexpr int APB = BLK / AGG;
+constexpr int NEED = 32;
+constexpr int TPE = BLK / NEED;
+constexpr int NA_MAX = 192;
+constexpr int JMAX = NA_MAX / TPE;
+static_assert(BLK % AGG == 0 && BLK % NEED == 0 && NA_MAX % TPE == 0 && NA_MAX <= 3 * WAVE, "coarse layout");
 
 // ---------------------------------------------------------------------------
 // set-up with the mesh: per element the area and area grad(phi_a).grad(phi_b)
@@ -538,6 +560,320 @@ inline const void* relax_iter_kernel(int w) {
     case 14: return (const void*)k_relax_iter<14>;
     case 15: return (const void*)k_relax_iter<15>;
     case 16: return (const void*)k_relax_iter<16>;
+    default: return nullptr;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The projection's solve: the same iteration for one component, with the
+// two-level preconditioner M^-1 = D^-1 + Z E^+ Z^T (Z: the aggregates'
+// indicator vectors, E = Z^T K Z; host::build_coarse), so u = D^-1 r + c with
+// c = E^+ Z^T r constant on each aggregate.  The aggregate sums of r_{i+1}
+// follow the recurrences of the unknowns, Z^T r_{i+1} = Z^T r_i - alpha (Z^T
+// w_i + beta Z^T s_{i-1}), from aggregate partials of the previous launch,
+// so every block forms them and the correction of the aggregates it needs
+// (the same products in the same order in every block, so a neighbour's
+// value is exactly its owner's) without another synchronisation; the owner
+// keeps its aggregates' correction for the next launch (cglob).
+
+// Sums over the 32-lane halves of a wavefront, in lanes 0 and 32 of the
+// result pair (every lane active): DPP within rows of 16, then the two rows.
+__device__ __forceinline__ void half_sums(double v, double& lo, double& hi) {
+  v += dpp_move<0xB1>(v);
+  v += dpp_move<0x4E>(v);
+  v += dpp_move<0x141>(v);
+  v += dpp_move<0x140>(v);
+  lo = read_lane(v, 0) + read_lane(v, 16);
+  hi = read_lane(v, 32) + read_lane(v, 48);
+}
+
+// This thread's share of the E^+ rows of its block's need list (entry
+// threadIdx / TPE, columns threadIdx % TPE + TPE j), zero past the list or na.
+__device__ __forceinline__ void coarse_rows(const Args& a, double (&ev)[JMAX]) {
+  const int e = threadIdx.x / TPE, q = threadIdx.x % TPE;
+  const int row = a.na > 0 ? a.need[blockIdx.x * NEED + e] : -1;
+  const double* er = a.ep + (size_t)(row >= 0 ? row : 0) * a.na;
+#pragma unroll
+  for (int j = 0; j < JMAX; ++j) {
+    const int col = q + TPE * j;
+    ev[j] = (row >= 0 && col < a.na) ? er[col] : 0.0;
+  }
+}
+
+// c = E^+ v on the need list into csh[NEED] (vsh: v for every aggregate, zero
+// past na); the TPE partial sums of an entry meet by DPP within a quad, so
+// all of its threads hold the same sum.  Every thread of the block calls it.
+__device__ __forceinline__ void coarse_product(const double (&ev)[JMAX], const double* vsh, double* csh) {
+  const int q = threadIdx.x % TPE;
+  double acc = 0.0;
+#pragma unroll
+  for (int j = 0; j < JMAX; ++j) acc = __builtin_fma(ev[j], vsh[q + TPE * j], acc);
+  static_assert(TPE == 4, "the quad exchange sums four threads");
+  acc += dpp_move<0xB1>(acc);
+  acc += dpp_move<0x4E>(acc);
+  if (q == 0) csh[threadIdx.x / TPE] = acc;
+}
+
+// The aggregate sums of three values per unknown (zero past nc) into dst
+// (na x 3), by lane 0 of each wavefront for its two aggregates.
+__device__ __forceinline__ void aggregate_sums(const Args& a, const double (&v)[3], double* dst) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int g0 = (blockIdx.x * BLK + (threadIdx.x - lane)) / AGG;
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    double lo, hi;
+    half_sums(v[m], lo, hi);
+    if (lane == 0) {
+      if (g0 < a.na) dst[(size_t)g0 * 3 + m] = lo;
+      if (g0 + 1 < a.na) dst[(size_t)(g0 + 1) * 3 + m] = hi;
+    }
+  }
+}
+
+// start: r0 = b - A x0 (component 0), p = 0, s = 0, the (b, b) partials and
+// the aggregate sums of r0 (and of s_{-1} = 0)
+__global__ __launch_bounds__(BLK) void k_proj_start1(Args a) {
+  const int i = blockIdx.x * BLK + threadIdx.x, nc = a.nc;
+  double bb[1] = {0.0};
+  double g[3] = {0.0, 0.0, 0.0};
+  if (i < nc) {
+    double bv = 0.0;
+    for (int t = a.incptr[i]; t < a.incptr[i + 1]; ++t) {
+      const int e = a.inc[t] / 3, l = a.inc[t] - 3 * e;
+      bv += a.S[(size_t)l * a.ne + e];
+    }
+    double ax = 0.0;
+    for (int t = 0; t < a.ellw; ++t) ax = __builtin_fma(a.aval[t * nc + i], a.x[a.ecol[t * nc + i]], ax);
+    Rec& q = a.rec[0][i];
+    q.r = bv - ax;
+    q.s = 0.0;
+    q.d = a.dinv[i];
+    a.p[i] = 0.0;
+    bb[0] = bv * bv;
+    g[0] = bv - ax;
+  }
+  if (a.na > 0) aggregate_sums(a, g, a.agp[0]);   // r0, (w0 from the second launch), s_{-1} = 0
+  block_sum<1>(bb);
+  if (threadIdx.x == 0) a.pbb[blockIdx.x] = bb[0];
+}
+
+// start: the coarse correction c0 of r0, u0 = D^-1 r0 + c0, w0 = A u0, the
+// partials of iteration 0 and the aggregate sums of w0
+__global__ __launch_bounds__(BLK) void k_proj_start2(Args a) {
+  __shared__ double vsh[NA_MAX];
+  __shared__ double csh[NEED];
+  const int i = blockIdx.x * BLK + threadIdx.x, nc = a.nc, lane = threadIdx.x & (WAVE - 1);
+  const bool live = i < nc;
+  const int ii = live ? i : nc - 1;
+  Rec* r0 = a.rec[0];
+  const int own = ii / AGG - blockIdx.x * APB;
+  double c0 = 0.0;
+  if (a.na > 0) {
+    double ev[JMAX];
+    coarse_rows(a, ev);
+    if (threadIdx.x < WAVE)
+      for (int k = 0; k < NA_MAX / WAVE; ++k) {
+        const int g = lane + WAVE * k;
+        vsh[g] = g < a.na ? a.agp[0][(size_t)g * 3] : 0.0;
+      }
+    __syncthreads();
+    coarse_product(ev, vsh, csh);
+    __syncthreads();
+    c0 = csh[own];
+  }
+  double acc = 0.0;
+  for (int t = 0; t < a.ellw; ++t) {
+    const int k = a.ecol[t * nc + ii];
+    const double ck = a.na > 0 ? csh[a.eneed[t * nc + ii]] : 0.0;
+    acc = __builtin_fma(a.aval[t * nc + ii], __builtin_fma(r0[k].r, r0[k].d, ck), acc);
+  }
+  const double ri = r0[ii].r, ui = __builtin_fma(ri, r0[ii].d, c0);
+  double v[3] = {0.0, 0.0, 0.0};
+  double g[3] = {0.0, 0.0, 0.0};
+  if (live) {
+    r0[ii].w = acc;
+    v[0] = ri * ui;
+    v[1] = acc * ui;
+    v[2] = ri * ri;
+    g[1] = acc;
+    if (a.na > 0 && ii % AGG == 0) a.cglob[0][ii / AGG] = c0;
+  }
+  if (a.na > 0) {
+    const int lane0 = threadIdx.x - lane;
+    const int g0 = (blockIdx.x * BLK + lane0) / AGG;
+    double lo, hi;
+    half_sums(g[1], lo, hi);
+    if (lane == 0) {
+      if (g0 < a.na) a.agp[0][(size_t)g0 * 3 + 1] = lo;
+      if (g0 + 1 < a.na) a.agp[0][(size_t)(g0 + 1) * 3 + 1] = hi;
+    }
+  }
+  block_sum<3>(v);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 3; ++k) a.part[0][(size_t)blockIdx.x * 3 + k] = v[k];
+  if (blockIdx.x != 0) return;
+  double tot[NC][1];
+  total_partials<1>(a, a.pbb, tot);
+  if (threadIdx.x == 0) {
+    a.ctl->ref[0] = tot[0][0];   // (r0, r0) where b = 0: set by iteration 0
+    for (int q = 1; q < NC; ++q) a.ctl->ref[q] = 0.0;
+  }
+}
+
+// iteration i of the projection's solve (parity par): as k_relax_iter for
+// component 0, with u = D^-1 r + c
+template <int W> __global__ __launch_bounds__(BLK) void k_proj_iter(Args a, int par) {
+  __shared__ double vsh[NA_MAX];
+  __shared__ double csh[NEED];
+  const int nc = a.nc, lane = threadIdx.x & (WAVE - 1);
+  const int i = blockIdx.x * BLK + threadIdx.x;
+  const bool live = i < nc;
+  const int ii = live ? i : nc - 1;
+  const bool co = a.na > 0;
+  const Rec* old = a.rec[par];
+  Rec* nxt = a.rec[par ^ 1];
+  int cl[W], en[W];
+  double av[W];
+#pragma unroll
+  for (int t = 0; t < W; ++t) {
+    cl[t] = a.ecol[t * nc + ii];
+    av[t] = a.aval[t * nc + ii];
+    en[t] = co ? a.eneed[t * nc + ii] : 0;
+  }
+  const double2 rw_o = *reinterpret_cast<const double2*>(&old[ii].r);
+  const double2 sd_o = *reinterpret_cast<const double2*>(&old[ii].s);
+  const double r_o = rw_o.x, w_o = rw_o.y, s_o = sd_o.x, d_o = sd_o.y, p_o = a.p[ii], x_o = a.x[ii];
+  const int own = ii / AGG - blockIdx.x * APB;
+  const double c_o = co ? a.cglob[par][ii / AGG] : 0.0;
+  const Ctl* ctl = a.ctl;
+  const Scal& prev = ctl->sc[par ^ 1];
+  const int pdone = prev.done, it = prev.iter, max_iters = ctl->max_iters;
+  const double gold = prev.gamma[0], aold = prev.alpha[0], tol2 = ctl->tol2, ref = ctl->ref[0];
+  // partials of the blocks lane, lane + 64, ... (a fixed order per lane)
+  const double* src = a.part[par];
+  double tp[3];
+  {
+    const int bx = lane < a.nbx ? lane : 0;
+    const double keep = lane < a.nbx ? 1.0 : 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) tp[k] = keep * src[(size_t)bx * 3 + k];
+  }
+  // aggregate sums of r_i, w_i, s_{i-1} (aggregates lane + 64 k) and this
+  // thread's share of the E^+ rows
+  double ag[NA_MAX / WAVE][3];
+  double ev[JMAX];
+  if (co) {
+#pragma unroll
+    for (int k = 0; k < NA_MAX / WAVE; ++k) {
+      const int g = lane + WAVE * k;
+      const bool in = g < a.na;
+#pragma unroll
+      for (int m = 0; m < 3; ++m) ag[k][m] = in ? a.agp[par][(size_t)g * 3 + m] : 0.0;
+    }
+    coarse_rows(a, ev);
+  }
+  // the neighbours' values
+  double2 grw[W], gsd[W];
+#pragma unroll
+  for (int t = 0; t < W; ++t) {
+    const int k = cl[t];
+    grw[t] = *reinterpret_cast<const double2*>(&old[k].r);
+    gsd[t] = *reinterpret_cast<const double2*>(&old[k].s);
+  }
+  for (int bx = lane + WAVE; bx < a.nbx; bx += WAVE)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) tp[k] += src[(size_t)bx * 3 + k];
+  if (pdone) return;
+  double tot[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) tot[k] = wave_sum(tp[k]);
+  // where b = 0 the reference is (r0, r0), known from iteration 0 on
+  const double rq = ref > 0.0 ? ref : (it == 0 ? tot[2] : ref);
+  const bool ok = tot[2] <= tol2 * rq;
+  const double g = tot[0], d = tot[1];
+  const double beta = gold != 0.0 ? g / gold : 0.0;
+  const double den = aold != 0.0 ? d - beta * g / aold : d;
+  const double alpha = den != 0.0 ? g / den : 0.0;
+  const bool stop = ok || it >= max_iters;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    Ctl* cw = a.ctl;
+    Scal& cur = cw->sc[par];
+    cur.iter = it + 1;
+    cur.done = stop ? 1 : 0;
+    if (it == 0 && !(ref > 0.0)) cw->ref[0] = tot[2];
+    if (stop) {
+      cw->iter = it;
+      cw->done = 1;
+      cw->converged = ok ? 1 : 0;
+      cw->rho[0] = tot[2];
+      for (int q = 1; q < NC; ++q) cw->rho[q] = 0.0;
+    }
+    cur.alpha[0] = alpha;
+    cur.gamma[0] = g;
+  }
+  if (stop) return;
+  // the coarse correction of r_{i+1} on the need list
+  double c_n = 0.0;
+  if (co) {
+    if (threadIdx.x < WAVE)
+#pragma unroll
+      for (int k = 0; k < NA_MAX / WAVE; ++k) vsh[lane + WAVE * k] = r_next(ag[k][0], s_next(ag[k][1], ag[k][2], beta), alpha);
+    __syncthreads();
+    coarse_product(ev, vsh, csh);
+    __syncthreads();
+    c_n = csh[own];
+  }
+  double acc = 0.0;
+#pragma unroll
+  for (int t = 0; t < W; ++t) {
+    const double ck = co ? csh[en[t]] : 0.0;
+    const double un = __builtin_fma(r_next(grw[t].x, s_next(grw[t].y, gsd[t].x, beta), alpha), gsd[t].y, ck);
+    acc = __builtin_fma(av[t], un, acc);
+  }
+  const double sn = s_next(w_o, s_o, beta);
+  const double pn = __builtin_fma(beta, p_o, __builtin_fma(r_o, d_o, c_o));
+  const double rnw = r_next(r_o, sn, alpha);
+  const double un = __builtin_fma(rnw, d_o, c_n);
+  double v[3] = {0.0, 0.0, 0.0};
+  double gsum[3] = {0.0, 0.0, 0.0};
+  if (live) {
+    a.p[ii] = pn;
+    a.x[ii] = __builtin_fma(alpha, pn, x_o);
+    *reinterpret_cast<double2*>(&nxt[ii].r) = make_double2(rnw, acc);
+    *reinterpret_cast<double2*>(&nxt[ii].s) = make_double2(sn, d_o);
+    v[0] = rnw * un;
+    v[1] = acc * un;
+    v[2] = rnw * rnw;
+    gsum[0] = rnw;
+    gsum[1] = acc;
+    gsum[2] = sn;
+    if (co && ii % AGG == 0) a.cglob[par ^ 1][ii / AGG] = c_n;
+  }
+  if (co) aggregate_sums(a, gsum, a.agp[par ^ 1]);
+  block_sum<3>(v);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 3; ++k) a.part[par ^ 1][(size_t)blockIdx.x * 3 + k] = v[k];
+}
+
+// the projection's launch of the padded row length w (1..ELL_MAX)
+inline const void* proj_iter_kernel(int w) {
+  switch (w) {
+    case 1: return (const void*)k_proj_iter<1>;
+    case 2: return (const void*)k_proj_iter<2>;
+    case 3: return (const void*)k_proj_iter<3>;
+    case 4: return (const void*)k_proj_iter<4>;
+    case 5: return (const void*)k_proj_iter<5>;
+    case 6: return (const void*)k_proj_iter<6>;
+    case 7: return (const void*)k_proj_iter<7>;
+    case 8: return (const void*)k_proj_iter<8>;
+    case 9: return (const void*)k_proj_iter<9>;
+    case 10: return (const void*)k_proj_iter<10>;
+    case 11: return (const void*)k_proj_iter<11>;
+    case 12: return (const void*)k_proj_iter<12>;
+    case 13: return (const void*)k_proj_iter<13>;
+    case 14: return (const void*)k_proj_iter<14>;
+    case 15: return (const void*)k_proj_iter<15>;
+    case 16: return (const void*)k_proj_iter<16>;
     default: return nullptr;
   }
 }

@@ -18,7 +18,10 @@ the corrected field, up to the rounding of the velocities); and the step after a
 gradient (against the oracle stepping with it, and far from the oracle
 stepping with the old one).  Cases: the 2k-element canyon (resolved walls,
 float and double state), its wall-function variant, the doubly periodic box
-and the 1M-particle, 10k-element canyon.
+and the 1M-particle, 10k-element canyon, all with the coarse space of the
+preconditioner (aggregates of 32 unknowns), and a 16k-element canyon whose
+unknowns make more aggregates than the coarse space takes (the diagonal
+preconditioner alone).
 """
 import numpy as np
 import pytest
@@ -51,6 +54,8 @@ def _cases():
         "canyon_wallfn_f32": lambda: W.small_canyon(target=2000, ppe=40, steps=5, wallfn=True),
         "periodic_box_f32": lambda: W.square_box(n=12, ppe=30, periodic_y=True, precision="f32", dt=1e-3, steps=5),
         "canyon_1M_f32": lambda: W.config2(steps=3),
+        # more than 192 aggregates: the preconditioner is the diagonal alone
+        "canyon_16k_no_coarse_f32": lambda: W.small_canyon(target=16000, ppe=12, steps=3),
     }
 
 
@@ -71,6 +76,10 @@ def test_projection_matches_the_oracle(gpu, case):
     print(f"[case] projection {case}: {wl.name} n={wl.n_total} elements={wl.mesh.nelem} steps={wl.steps}",
           flush=True)
     sim = gpu.Simulation.from_workload(wl)
+    size = sim.relaxation_size()
+    assert (size["aggregates"] == 0) == ("no_coarse" in case), size
+    if size["aggregates"]:
+        assert size["aggregates"] == -(-size["unknowns"] // 32)
     sim.step(wl.steps)
     sim.sync()
     res = sim.pressure_projection(max_iters=20000, tol=TOL)
@@ -85,7 +94,8 @@ def test_projection_matches_the_oracle(gpu, case):
     phi = res["phi"] - res["phi"].mean()
     dphi = np.abs(phi - (ref["phi"] - ref["phi"].mean())).max()
     dg = np.abs(res["grad"] - ref["grad_vertex"]).max()
-    print(f"[project] {case}: kappa {kappa:.3g}, iterations {res['iterations']}, resid {res['resid'][0]:.2e}, "
+    print(f"[project] {case}: aggregates {size['aggregates']}, kappa {kappa:.3g}, iterations {res['iterations']}, "
+          f"resid {res['resid'][0]:.2e}, "
           f"|dphi| {dphi:.2e} (bound {err_phi:.2e}), |dgrad| {dg:.2e} (bound {err_g:.2e}), "
           f"max |grad| {np.abs(ref['grad_vertex']).max():.3g}", flush=True)
     assert res["converged"] and res["applied"]

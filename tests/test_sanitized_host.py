@@ -11,10 +11,15 @@
   the library's host layer that runs without a GPU), built with the same
   sanitizers on the canyon meshes, the unit square periodic in x and the
   doubly periodic box.  Its structure is checked against the oracle's
-  definitions: the joined unknowns (oracle.relax.canonical_vertices), the
-  sparsity of the assembled matrix, every nonzero's contributions decoding
-  to its own (row, column), the padded rows, the diagonal positions and the
-  incidence lists; and the error for a row longer than allowed.
+  definitions: the joined unknowns (oracle.relax.canonical_vertices, up to
+  the numbering), the numbering itself against a plain recursive bisection
+  written here, the sparsity of the assembled matrix, every nonzero's
+  contributions decoding to its own (row, column), the padded rows, the
+  diagonal positions and the incidence lists; and the error for a row longer
+  than allowed.  The projection's coarse space: E^+ times E + sigma 1 1^T is
+  the identity, with E = Z^T K Z from the oracle's stiffness matrix; the need
+  lists and every row slot's position in them; the refusal of a coarse space
+  larger than allowed.
 """
 import os
 import subprocess
@@ -119,14 +124,17 @@ def test_oracle_runs_clean_under_sanitizers(orc_exe, tmp_path, case):
     assert got == want
 
 
-def _host_structure(host_exe, tmp_path, mesh, ell_max=16):
+AGG, BLK, NEED, NA_MAX = 32, 128, 32, 192
+
+
+def _host_structure(host_exe, tmp_path, mesh, ell_max=16, agg=AGG, na_max=NA_MAX):
     inp, out = str(tmp_path / "mesh.bin"), str(tmp_path / "rs.bin")
     with open(inp, "wb") as f:
         f.write(np.array([mesh.nvert, mesh.nelem], np.int32).tobytes())
         f.write(np.array([mesh.Lx, mesh.Ly], np.float64).tobytes())
         for a, t in ((mesh.vtx, np.float64), (mesh.tri, np.int32), (mesh.nbr, np.int32), (mesh.ekind, np.int32)):
             f.write(np.ascontiguousarray(a, t).tobytes())
-        f.write(np.array([ell_max], np.int32).tobytes())
+        f.write(np.array([ell_max, agg, BLK, NEED, na_max], np.int32).tobytes())
     _run(host_exe, inp, out)
     b = open(out, "rb").read()
     status, nc, ellw = np.frombuffer(b[:12], np.int32)
@@ -137,7 +145,28 @@ def _host_structure(host_exe, tmp_path, mesh, ell_max=16):
         pos += 8
         arrs[name] = np.frombuffer(b[pos:pos + 4 * n], np.int32).copy()
         pos += 4 * n
+    arrs["coarse_status"], arrs["na"] = (int(v) for v in np.frombuffer(b[pos:pos + 8], np.int32))
+    pos += 8
+    for name, t, w in (("ep", np.float64, 8), ("need", np.int32, 4), ("eneed", np.int32, 4)):
+        n = int(np.frombuffer(b[pos:pos + 8], np.int64)[0])
+        pos += 8
+        arrs[name] = np.frombuffer(b[pos:pos + w * n], t).copy()
+        pos += w * n
+    assert pos == len(b)
     return int(status), int(nc), int(ellw), nnz, arrs
+
+
+def _bisection(vtx, ids, agg):
+    """Recursive coordinate bisection of the vertices ids: the longer side
+    of their bounding box (x on a tie), sorted by that coordinate then by
+    vertex index, halved at half the runs of agg (rounded down)."""
+    if len(ids) <= agg:
+        return list(ids)
+    c = vtx[ids]
+    ax = 0 if np.ptp(c[:, 0]) >= np.ptp(c[:, 1]) else 1
+    o = ids[np.lexsort((ids, c[:, ax]))]
+    half = (-(-len(ids) // agg) // 2) * agg
+    return _bisection(vtx, o[:half], agg) + _bisection(vtx, o[half:], agg)
 
 
 def _meshes():
@@ -148,16 +177,25 @@ def _meshes():
 @pytest.mark.parametrize("name", list(_meshes()))
 def test_relaxation_structure_under_sanitizers(host_exe, tmp_path, name):
     mesh = _meshes()[name]
-    status, nc, ellw, nnz, s = _host_structure(host_exe, tmp_path, mesh)
+    status, nc, ellw, nnz, s = _host_structure(host_exe, tmp_path, mesh, agg=4)
     assert status == 0
-    canon, nco = R.canonical_vertices(mesh)
+    ocanon, nco = R.canonical_vertices(mesh)
     assert nc == nco
-    np.testing.assert_array_equal(s["canon"], canon)
-    # the representative of an unknown is its lowest vertex
+    # the same classes of vertices, renumbered: our id of each oracle unknown
+    canon = s["canon"]
+    ours = np.full(nc, -1)
+    ours[ocanon] = canon
+    np.testing.assert_array_equal(ours[ocanon], canon)
+    assert sorted(ours.tolist()) == list(range(nc))
+    # the representative of an unknown is its lowest vertex, and the
+    # numbering is the bisection of the representatives
     for i, v in enumerate(s["rep"]):
         assert canon[v] == i and v == np.flatnonzero(canon == i).min()
+    lowest = np.array(sorted(np.flatnonzero(canon == i).min() for i in range(nc)))
+    assert _bisection(mesh.vtx, lowest, 4) == s["rep"].tolist()
     M, K, _, _, _ = R.assemble(mesh, np.ones(mesh.nelem))
-    A = (M + K).tocsr()
+    inv = np.argsort(ours)   # oracle unknown of each of ours
+    A = (M + K).tocsr()[inv][:, inv].tocsr()
     A.sum_duplicates()
     A.sort_indices()
     np.testing.assert_array_equal(s["rowptr"], A.indptr)
@@ -189,6 +227,46 @@ def test_relaxation_structure_under_sanitizers(host_exe, tmp_path, name):
     for i in range(nc):
         t = s["inc"][s["incptr"][i]:s["incptr"][i + 1]]
         assert np.all(np.diff(t) > 0) and np.all(canon[mesh.tri[t // 3, t % 3]] == i)
+
+
+@pytest.mark.parametrize("name", list(_meshes()) + ["canyon_2k"])
+def test_coarse_space_under_sanitizers(host_exe, tmp_path, name):
+    mesh = W.small_canyon(target=2000, ppe=1, steps=1).mesh if name == "canyon_2k" else _meshes()[name]
+    status, nc, ellw, nnz, s = _host_structure(host_exe, tmp_path, mesh)
+    assert status == 0 and s["coarse_status"] == 0
+    na = s["na"]
+    assert na == -(-nc // AGG)
+    canon, ocanon = s["canon"], R.canonical_vertices(mesh)[0]
+    ours = np.full(nc, -1)
+    ours[ocanon] = canon
+    inv = np.argsort(ours)
+    _, K, _, _, _ = R.assemble(mesh, np.ones(mesh.nelem))
+    K = K.tocsr()[inv][:, inv].toarray()
+    Z = np.zeros((nc, na))
+    Z[np.arange(nc), np.arange(nc) // AGG] = 1.0
+    E = Z.T @ K @ Z
+    assert np.abs(E.sum(axis=1)).max() <= 1e-9 * np.abs(E).max()   # constants are its null space
+    Et = E + np.trace(E) / na ** 2
+    ep = s["ep"].reshape(na, na)
+    np.testing.assert_allclose(ep @ Et, np.eye(na), atol=1e-9 * np.linalg.cond(Et))
+    # need lists: own aggregates first, then the others the block's rows
+    # touch, in increasing order; every row slot's position names its column's
+    nbx = -(-nc // BLK)
+    need = s["need"].reshape(nbx, NEED)
+    ecol, eneed = s["ecol"].reshape(ellw, nc), s["eneed"].reshape(ellw, nc)
+    apb = BLK // AGG
+    for b in range(nbx):
+        rows = np.arange(b * BLK, min(nc, (b + 1) * BLK))
+        own = [g for g in range(b * apb, (b + 1) * apb) if g < na]
+        other = sorted(set((ecol[:, rows] // AGG).ravel().tolist()) - set(own))
+        lst = own + other
+        assert need[b, :len(lst)].tolist() == lst and np.all(need[b, len(lst):] == -1)
+        np.testing.assert_array_equal(need[b][eneed[:, rows]], ecol[:, rows] // AGG)
+
+
+def test_coarse_space_refuses_too_many_aggregates(host_exe, tmp_path):
+    _, nc, _, _, s = _host_structure(host_exe, tmp_path, W.tiny_canyon().mesh, agg=4, na_max=3)
+    assert s["coarse_status"] == 1 and s["na"] == 0 and len(s["ep"]) == 0
 
 
 def test_relaxation_structure_rejects_long_rows(host_exe, tmp_path):
