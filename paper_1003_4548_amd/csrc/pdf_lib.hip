@@ -105,7 +105,7 @@ Layout make_layout(int32_t nv, int32_t ne, int32_t nens, int64_t slots, int32_t 
     L.rx_pbb = take(relax::NC * nbx * 8);
     L.rx_ctl = take((int64_t)sizeof(relax::Ctl));
     const int64_t na = std::min<int64_t>((nc + relax::AGG - 1) / relax::AGG, relax::NA_MAX);
-    L.rx_ep = take(na * na * 8);
+    L.rx_ep = take(na * relax::NA_MAX * 4);
     L.rx_need = take(nbx * relax::NEED * 4);
     L.rx_eneed = take(ell * 4);
     for (int b = 0; b < 2; ++b) {
@@ -326,8 +326,15 @@ pdf_status relax_setup(pdf_ctx* c, const pdf_mesh* m) {
   host::CoarseStructure CS;
   const bool coarse = host::build_coarse(S, ne, m->vtx, m->tri, relax::AGG, relax::BLK, relax::NEED, relax::NA_MAX,
                                          CS) == host::COARSE_OK;
+  // E^+ on the device: symmetric in float, rows NA_MAX wide (zero past na)
+  std::vector<float> epf;
   if (coarse) {
-    if ((r = hip_check(c, hipMemcpyAsync(d + L.rx_ep, CS.ep.data(), CS.ep.size() * 8, hipMemcpyHostToDevice, st),
+    const int32_t na = CS.na;
+    epf.assign((size_t)na * relax::NA_MAX, 0.0f);
+    for (int32_t i = 0; i < na; ++i)
+      for (int32_t j = 0; j < na; ++j)
+        epf[(size_t)i * relax::NA_MAX + j] = (float)(0.5 * (CS.ep[(size_t)i * na + j] + CS.ep[(size_t)j * na + i]));
+    if ((r = hip_check(c, hipMemcpyAsync(d + L.rx_ep, epf.data(), epf.size() * 4, hipMemcpyHostToDevice, st),
                        "copy coarse operator"))) return r;
     if ((r = put(L.rx_need, CS.need, "copy coarse need lists"))) return r;
     if ((r = put(L.rx_eneed, CS.eneed, "copy coarse need lists"))) return r;
@@ -1410,7 +1417,7 @@ static relax::Args relax_args(pdf_ctx* c) {
   a.pbb = (double*)(d + L.rx_pbb);
   a.ctl = (relax::Ctl*)(d + L.rx_ctl);
   a.na = 0;   // the projection sets its coarse space
-  a.ep = (const double*)(d + L.rx_ep);
+  a.ep = (const float*)(d + L.rx_ep);
   a.need = (const int32_t*)(d + L.rx_need);
   a.eneed = (const int32_t*)(d + L.rx_eneed);
   for (int b = 0; b < 2; ++b) {

@@ -120,7 +120,7 @@ struct Args {
   Ctl* ctl;
   // the projection's coarse space (na = 0: none, the preconditioner is D^-1)
   int32_t na;
-  const double* ep;        // na x na: E^+
+  const float* ep;         // na x NA_MAX: E^+ (symmetric, in float; zero past column na)
   const int32_t* need;     // nbx x NEED: aggregates whose correction a block reads
   const int32_t* eneed;    // ellw x nc: position of each row slot's column aggregate in that list
   double* agp[2];          // na x 3 aggregate sums of r_i, w_i, s_{i-1}, by parity
@@ -138,7 +138,7 @@ constexpr int NEED = 32;
 constexpr int TPE = BLK / NEED;
 constexpr int NA_MAX = 192;
 constexpr int JMAX = NA_MAX / TPE;
-static_assert(BLK % AGG == 0 && BLK % NEED == 0 && NA_MAX % TPE == 0 && NA_MAX <= 3 * WAVE, "coarse layout");
+static_assert(BLK % AGG == 0 && BLK % NEED == 0 && NA_MAX % (4 * TPE) == 0 && NA_MAX == 3 * WAVE, "coarse layout");
 
 // ---------------------------------------------------------------------------
 // set-up with the mesh: per element the area and area grad(phi_a).grad(phi_b)
@@ -587,31 +587,41 @@ __device__ __forceinline__ void half_sums(double v, double& lo, double& hi) {
   hi = read_lane(v, 32) + read_lane(v, 48);
 }
 
-// This thread's share of the E^+ rows of its block's need list (entry
-// threadIdx / TPE, columns threadIdx % TPE + TPE j), zero past the list or na.
-__device__ __forceinline__ void coarse_rows(const Args& a, double (&ev)[JMAX]) {
+// This thread's share of the E^+ rows of its block's need list: entry
+// threadIdx / TPE, the JMAX columns from JMAX (threadIdx % TPE) on, in
+// 16-byte loads (zero past the list; the rows are zero past na).
+constexpr int JV = JMAX / 4;
+__device__ __forceinline__ void coarse_rows(const Args& a, float4 (&ev)[JV]) {
   const int e = threadIdx.x / TPE, q = threadIdx.x % TPE;
   const int row = a.na > 0 ? a.need[blockIdx.x * NEED + e] : -1;
-  const double* er = a.ep + (size_t)(row >= 0 ? row : 0) * a.na;
+  const float4* er = reinterpret_cast<const float4*>(a.ep + (size_t)(row >= 0 ? row : 0) * NA_MAX + JMAX * q);
 #pragma unroll
-  for (int j = 0; j < JMAX; ++j) {
-    const int col = q + TPE * j;
-    ev[j] = (row >= 0 && col < a.na) ? er[col] : 0.0;
-  }
+  for (int j = 0; j < JV; ++j) ev[j] = row >= 0 ? er[j] : make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
-// c = E^+ v on the need list into csh[NEED] (vsh: v for every aggregate, zero
-// past na); the TPE partial sums of an entry meet by DPP within a quad, so
-// all of its threads hold the same sum.  Every thread of the block calls it.
-__device__ __forceinline__ void coarse_product(const double (&ev)[JMAX], const double* vsh, double* csh) {
+// c = E^+ v on the need list into csh[NEED] (vw: the wavefront's copy of v
+// for every aggregate, zero past na): four running sums per thread, then the
+// TPE threads of an entry meet by DPP within a quad, so all of them hold the
+// same sum; a fixed order, the same in every block.  Every thread of the
+// block calls it; csh is complete after the next block barrier.
+__device__ __forceinline__ void coarse_product(const float4 (&ev)[JV], const double* vw, double* csh) {
   const int q = threadIdx.x % TPE;
-  double acc = 0.0;
+  const double* v = vw + JMAX * q;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-  for (int j = 0; j < JMAX; ++j) acc = __builtin_fma(ev[j], vsh[q + TPE * j], acc);
+  for (int j = 0; j < JV; ++j) {
+    const double2 v01 = *reinterpret_cast<const double2*>(v + 4 * j);
+    const double2 v23 = *reinterpret_cast<const double2*>(v + 4 * j + 2);
+    acc[0] = __builtin_fma((double)ev[j].x, v01.x, acc[0]);
+    acc[1] = __builtin_fma((double)ev[j].y, v01.y, acc[1]);
+    acc[2] = __builtin_fma((double)ev[j].z, v23.x, acc[2]);
+    acc[3] = __builtin_fma((double)ev[j].w, v23.y, acc[3]);
+  }
+  double t = (acc[0] + acc[1]) + (acc[2] + acc[3]);
   static_assert(TPE == 4, "the quad exchange sums four threads");
-  acc += dpp_move<0xB1>(acc);
-  acc += dpp_move<0x4E>(acc);
-  if (q == 0) csh[threadIdx.x / TPE] = acc;
+  t += dpp_move<0xB1>(t);
+  t += dpp_move<0x4E>(t);
+  if (q == 0) csh[threadIdx.x / TPE] = t;
 }
 
 // The aggregate sums of three values per unknown (zero past nc) into dst
@@ -660,7 +670,7 @@ __global__ __launch_bounds__(BLK) void k_proj_start1(Args a) {
 // start: the coarse correction c0 of r0, u0 = D^-1 r0 + c0, w0 = A u0, the
 // partials of iteration 0 and the aggregate sums of w0
 __global__ __launch_bounds__(BLK) void k_proj_start2(Args a) {
-  __shared__ double vsh[NA_MAX];
+  __shared__ double vsh[WPB][NA_MAX];
   __shared__ double csh[NEED];
   const int i = blockIdx.x * BLK + threadIdx.x, nc = a.nc, lane = threadIdx.x & (WAVE - 1);
   const bool live = i < nc;
@@ -669,15 +679,15 @@ __global__ __launch_bounds__(BLK) void k_proj_start2(Args a) {
   const int own = ii / AGG - blockIdx.x * APB;
   double c0 = 0.0;
   if (a.na > 0) {
-    double ev[JMAX];
+    float4 ev[JV];
     coarse_rows(a, ev);
-    if (threadIdx.x < WAVE)
-      for (int k = 0; k < NA_MAX / WAVE; ++k) {
-        const int g = lane + WAVE * k;
-        vsh[g] = g < a.na ? a.agp[0][(size_t)g * 3] : 0.0;
-      }
-    __syncthreads();
-    coarse_product(ev, vsh, csh);
+    double* vw = vsh[threadIdx.x / WAVE];
+    for (int k = 0; k < NA_MAX / WAVE; ++k) {
+      const int g = lane + WAVE * k;
+      vw[g] = g < a.na ? a.agp[0][(size_t)g * 3] : 0.0;
+    }
+    lds_sync_wave();
+    coarse_product(ev, vw, csh);
     __syncthreads();
     c0 = csh[own];
   }
@@ -723,7 +733,7 @@ __global__ __launch_bounds__(BLK) void k_proj_start2(Args a) {
 // iteration i of the projection's solve (parity par): as k_relax_iter for
 // component 0, with u = D^-1 r + c
 template <int W> __global__ __launch_bounds__(BLK) void k_proj_iter(Args a, int par) {
-  __shared__ double vsh[NA_MAX];
+  __shared__ double vsh[WPB][NA_MAX];
   __shared__ double csh[NEED];
   const int nc = a.nc, lane = threadIdx.x & (WAVE - 1);
   const int i = blockIdx.x * BLK + threadIdx.x;
@@ -761,7 +771,7 @@ template <int W> __global__ __launch_bounds__(BLK) void k_proj_iter(Args a, int 
   // aggregate sums of r_i, w_i, s_{i-1} (aggregates lane + 64 k) and this
   // thread's share of the E^+ rows
   double ag[NA_MAX / WAVE][3];
-  double ev[JMAX];
+  float4 ev[JV];
   if (co) {
 #pragma unroll
     for (int k = 0; k < NA_MAX / WAVE; ++k) {
@@ -815,11 +825,12 @@ template <int W> __global__ __launch_bounds__(BLK) void k_proj_iter(Args a, int 
   // the coarse correction of r_{i+1} on the need list
   double c_n = 0.0;
   if (co) {
-    if (threadIdx.x < WAVE)
+    // every wavefront forms Z^T r_{i+1} in its own copy
+    double* vw = vsh[threadIdx.x / WAVE];
 #pragma unroll
-      for (int k = 0; k < NA_MAX / WAVE; ++k) vsh[lane + WAVE * k] = r_next(ag[k][0], s_next(ag[k][1], ag[k][2], beta), alpha);
-    __syncthreads();
-    coarse_product(ev, vsh, csh);
+    for (int k = 0; k < NA_MAX / WAVE; ++k) vw[lane + WAVE * k] = r_next(ag[k][0], s_next(ag[k][1], ag[k][2], beta), alpha);
+    lds_sync_wave();
+    coarse_product(ev, vw, csh);
     __syncthreads();
     c_n = csh[own];
   }
