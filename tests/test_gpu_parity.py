@@ -265,6 +265,36 @@ def test_graph_replay_matches_eager(gpu, shape):
         _ = graph.statistics()          # eager work between replays
 
 
+def test_split_launch_graph_and_eager(gpu):
+    """Batched ensembles whose cells of at most eight particles and the others
+    each make up an eighth of the cells or more: their steps take two launches
+    that run side by side (a parallel graph branch; a second stream when
+    stepping eagerly).  Graph replays and eager steps, each against the
+    oracle, bit for bit in every ensemble."""
+    wl = W.config4(steps=0, nens=8, target=2000)
+    counts = np.concatenate([e.counts for e in wl.ensembles])
+    small = int((counts <= 8).sum())
+    assert 8 * small >= len(counts) and 8 * (len(counts) - small) >= len(counts)
+    _label(wl, "split launch")
+    eager = gpu.Simulation.from_workload(wl)
+    graph = gpu.Simulation.from_workload(wl)
+    for s in (eager, graph):
+        s.set_launch(16, 0)
+    orc = O.Oracle(wl)
+    for rep, n in enumerate([6, 7, 5]):
+        graph.step_graph(n)
+        eager.step(n)
+        orc.step(n)
+        graph.sync()
+        eager.sync()
+        for en in range(wl.nens):
+            o = orc.state(en)
+            assert_state_parity(graph.state(en), o, what=f"graph {rep} ens {en}")
+            assert_state_parity(eager.state(en), o, what=f"eager {rep} ens {en}")
+    eager.close()
+    graph.close()
+
+
 @pytest.mark.parametrize("graph", [False, True])
 def test_repack_keeps_parity(gpu, graph):
     """Segments sized with no slack run short of room within a few steps, so
