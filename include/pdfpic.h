@@ -194,7 +194,11 @@ pdf_status pdf_seed_particles(pdf_ctx* ctx, int32_t nens, const int64_t* counts,
    tracking through the grid with the wall and periodic conditions; the
    source of section 3.  The sub-steps taken are pdf_params.flags, fixed at
    pdf_create.  Enqueues nsteps steps of every ensemble on the context's
-   stream and returns without waiting (nsteps = 0: nothing).  After a device
+   stream and returns without waiting (nsteps = 0: nothing); where the order
+   is split (cells of at most eight particles taking a launch of their own),
+   that launch runs on a second stream of the context, forked from and
+   joined back to the context's stream by events within each step, so work
+   enqueued on the context's stream afterwards sees whole steps.  After a device
    error the remaining steps do nothing and pdf_sync reports it.  Errors:
    PDF_E_ARG (nsteps < 0), PDF_E_STATE (before pdf_seed_particles),
    PDF_E_HIP (launch failure). */
