@@ -72,7 +72,7 @@ def algorithmic_bytes(wl) -> dict:
     return dict(per_particle=per_particle, per_cell=per_cell, per_step=total, particles=n)
 
 
-def survey_bytes(wl) -> dict:
+def scope_bytes(wl) -> dict:
     """The scope table's algorithmic bytes per particle-step: one read of the
     particle state (x y u v w psi, element, id, and omega when carried), one write of
     its mutable part (x y u v w psi, element, and omega), one re-read of the
@@ -143,8 +143,8 @@ def cpu_baseline(wl_fn, seconds: float = 15.0) -> dict:
     """The oracle on the host cores, on a bounded sample of the same workload:
     the full particle set, as many whole steps as fit in about `seconds`."""
     import oracle as O
-    # the GPU box allots 16 host CPUs to a one-GPU job, whatever os.cpu_count()
-    # reports there; on a smaller host all of its cores
+    # a one-GPU job is allotted 16 host CPUs, whatever os.cpu_count() reports;
+    # on a smaller host all of its cores
     threads = min(16, os.cpu_count() or 1)
     wl = wl_fn()
     orc = O.Oracle(wl, threads=threads)
@@ -439,7 +439,7 @@ def main() -> int:
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs on one GPU only; the batched-ensemble and mesh-partition "
+        print("bench.py: the library runs on one GPU; the batched-ensemble and mesh-partition "
               "designs for several GPUs are documented with the library but not launched", file=sys.stderr)
         return 2
 
@@ -521,7 +521,7 @@ def main() -> int:
         wall = t1 - t0
         graph_ms = e0.elapsed_time(e1) / steps
         ab = algorithmic_bytes(wl)
-        sb = survey_bytes(wl)
+        sb = scope_bytes(wl)
         achieved = sb["per_step"] / (kern_ms * 1e-3) / 1e9
         achieved_design = ab["per_step"] / (kern_ms * 1e-3) / 1e9
         traffic = read_traffic(name, src_hash)
