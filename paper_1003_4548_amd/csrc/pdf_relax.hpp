@@ -448,16 +448,17 @@ template <int W> __global__ __launch_bounds__(BLK) void k_relax_iter(Args a, int
   double ref[NC];
 #pragma unroll
   for (int q = 0; q < NC; ++q) ref[q] = ctl->ref[q];
-  // partials of the blocks lane, lane + 64, ... (a fixed order per lane)
+  // partials of the blocks lane, lane + 64, ... (a fixed order per lane):
+  // (r, u) and (w, u) of this block's component, (r, r) of every component
   const double* src = a.part[par];
-  double tp[NC][3];
+  double tg[2], tr[NC];
   {
     const int bx = lane < a.nbx ? lane : 0;
     const double keep = lane < a.nbx ? 1.0 : 0.0;
 #pragma unroll
-    for (int q = 0; q < NC; ++q)
+    for (int k = 0; k < 2; ++k) tg[k] = keep * src[((size_t)c * a.nbx + bx) * 3 + k];
 #pragma unroll
-      for (int k = 0; k < 3; ++k) tp[q][k] = keep * src[((size_t)q * a.nbx + bx) * 3 + k];
+    for (int q = 0; q < NC; ++q) tr[q] = keep * src[((size_t)q * a.nbx + bx) * 3 + 2];
   }
   // the neighbours' values
   double2 grw[W], gsd[W];
@@ -467,31 +468,24 @@ template <int W> __global__ __launch_bounds__(BLK) void k_relax_iter(Args a, int
     grw[t] = *reinterpret_cast<const double2*>(&old[k].r);
     gsd[t] = *reinterpret_cast<const double2*>(&old[k].s);
   }
-  for (int bx = lane + WAVE; bx < a.nbx; bx += WAVE)
+  for (int bx = lane + WAVE; bx < a.nbx; bx += WAVE) {
 #pragma unroll
-    for (int q = 0; q < NC; ++q)
+    for (int k = 0; k < 2; ++k) tg[k] += src[((size_t)c * a.nbx + bx) * 3 + k];
 #pragma unroll
-      for (int k = 0; k < 3; ++k) tp[q][k] += src[((size_t)q * a.nbx + bx) * 3 + k];
+    for (int q = 0; q < NC; ++q) tr[q] += src[((size_t)q * a.nbx + bx) * 3 + 2];
+  }
   if (pdone) return;
-  double tot[NC][3];
+  double rho[NC];
 #pragma unroll
-  for (int q = 0; q < NC; ++q)
-#pragma unroll
-    for (int k = 0; k < 3; ++k) tot[q][k] = wave_sum(tp[q][k]);
+  for (int q = 0; q < NC; ++q) rho[q] = wave_sum(tr[q]);
   bool ok = true;
 #pragma unroll
   for (int q = 0; q < NC; ++q) {
     // where b = 0 the reference is (r0, r0), known from iteration 0 on
-    const double rq = ref[q] > 0.0 ? ref[q] : (it == 0 ? tot[q][2] : ref[q]);
-    ok = ok && tot[q][2] <= tol2 * rq;
+    const double rq = ref[q] > 0.0 ? ref[q] : (it == 0 ? rho[q] : ref[q]);
+    ok = ok && rho[q] <= tol2 * rq;
   }
-  double g = 0.0, d = 0.0;
-#pragma unroll
-  for (int q = 0; q < NC; ++q)
-    if (q == c) {
-      g = tot[q][0];
-      d = tot[q][1];
-    }
+  const double g = wave_sum(tg[0]), d = wave_sum(tg[1]);
   const double beta = gold != 0.0 ? g / gold : 0.0;
   const double den = aold != 0.0 ? d - beta * g / aold : d;
   const double alpha = den != 0.0 ? g / den : 0.0;
@@ -504,12 +498,12 @@ template <int W> __global__ __launch_bounds__(BLK) void k_relax_iter(Args a, int
       cur.done = stop ? 1 : 0;
       if (it == 0)
         for (int q = 0; q < NC; ++q)
-          if (!(ref[q] > 0.0)) cw->ref[q] = tot[q][2];
+          if (!(ref[q] > 0.0)) cw->ref[q] = rho[q];
       if (stop) {
         cw->iter = it;
         cw->done = 1;
         cw->converged = ok ? 1 : 0;
-        for (int q = 0; q < NC; ++q) cw->rho[q] = tot[q][2];
+        for (int q = 0; q < NC; ++q) cw->rho[q] = rho[q];
       }
     }
     cur.alpha[c] = alpha;
@@ -768,20 +762,6 @@ template <int W> __global__ __launch_bounds__(BLK) void k_proj_iter(Args a, int 
 #pragma unroll
     for (int k = 0; k < 3; ++k) tp[k] = keep * src[(size_t)bx * 3 + k];
   }
-  // aggregate sums of r_i, w_i, s_{i-1} (aggregates lane + 64 k) and this
-  // thread's share of the E^+ rows
-  double ag[NA_MAX / WAVE][3];
-  float4 ev[JV];
-  if (co) {
-#pragma unroll
-    for (int k = 0; k < NA_MAX / WAVE; ++k) {
-      const int g = lane + WAVE * k;
-      const bool in = g < a.na;
-#pragma unroll
-      for (int m = 0; m < 3; ++m) ag[k][m] = in ? a.agp[par][(size_t)g * 3 + m] : 0.0;
-    }
-    coarse_rows(a, ev);
-  }
   // the neighbours' values
   double2 grw[W], gsd[W];
 #pragma unroll
@@ -794,6 +774,22 @@ template <int W> __global__ __launch_bounds__(BLK) void k_proj_iter(Args a, int 
 #pragma unroll
     for (int k = 0; k < 3; ++k) tp[k] += src[(size_t)bx * 3 + k];
   if (pdone) return;
+  // aggregate sums of r_i, w_i, s_{i-1} (aggregates lane + 64 k) and this
+  // thread's share of the E^+ rows: issued behind the stop test, so in the
+  // second round with the neighbours' values (a wavefront keeps at most 63
+  // loads in flight, and the first round is near that already)
+  double ag[NA_MAX / WAVE][3];
+  float4 ev[JV];
+  if (co) {
+#pragma unroll
+    for (int k = 0; k < NA_MAX / WAVE; ++k) {
+      const int g = lane + WAVE * k;
+      const bool in = g < a.na;
+#pragma unroll
+      for (int m = 0; m < 3; ++m) ag[k][m] = in ? a.agp[par][(size_t)g * 3 + m] : 0.0;
+    }
+    coarse_rows(a, ev);
+  }
   double tot[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) tot[k] = wave_sum(tp[k]);
