@@ -23,9 +23,10 @@
 // the previous iteration (r, w = A u, s = A p and the inverse diagonal, one
 // 32-byte record per unknown and component, in two buffers by iteration
 // parity), with the same operations as their owners, so the product is
-// exactly A u.  Every block sums the previous launch's block
-// partials in the same fixed order and derives the iteration's scalars
-// itself, so a launch has two dependent rounds of memory accesses (its own
+// exactly A u.  Every block sums the previous launch's block partials it
+// needs (its component's two inner products, every component's residual
+// norm) in the same fixed order and derives the iteration's scalars itself,
+// so a launch has two dependent rounds of memory accesses (its own
 // loads, then the gathers of the neighbours' values), no atomics, and every
 // result is reproducible.
 #pragma once
@@ -570,8 +571,9 @@ inline const void* relax_iter_kernel(int w) {
 // value is exactly its owner's) without another synchronisation; the owner
 // keeps its aggregates' correction for the next launch (cglob).
 
-// Sums over the 32-lane halves of a wavefront, in lanes 0 and 32 of the
-// result pair (every lane active): DPP within rows of 16, then the two rows.
+// The sums over the two 32-lane halves of a wavefront (every lane active;
+// the same two values in every lane): DPP within rows of 16, then the two
+// rows of each half.
 __device__ __forceinline__ void half_sums(double v, double& lo, double& hi) {
   v += dpp_move<0xB1>(v);
   v += dpp_move<0x4E>(v);
