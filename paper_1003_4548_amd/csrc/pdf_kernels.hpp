@@ -1838,9 +1838,14 @@ __device__ __forceinline__ int64_t plan_cap(const RepackPlan& p, int c, bool fal
   return max((int64_t)p.cap0[c], (int64_t)floor(p.grow * (n + (double)nm)) + p.pad);
 }
 
-// One block: capacities, then an exclusive scan over the cells.
+// One block: capacities, then an exclusive scan over the cells.  Each
+// wavefront owns a contiguous range of cells and reads it in runs of 64
+// consecutive cells (coalesced, one cell per lane): first the range's sum,
+// then, after a block scan of the wavefronts' sums, the offsets, by a
+// wavefront scan of each run carried from run to run.
 __global__ __launch_bounds__(PLAN_THREADS) void k_repack_plan(RepackPlan p) {
-  __shared__ int64_t wsum[PLAN_THREADS / WAVE];
+  constexpr int NW = PLAN_THREADS / WAVE;
+  __shared__ int64_t wsum[NW];
   __shared__ int64_t total_s;
   Ctl* ctl = p.ctl;
   // a graph cycle ends here: its steps join the step base (no other thread
@@ -1852,24 +1857,22 @@ __global__ __launch_bounds__(PLAN_THREADS) void k_repack_plan(RepackPlan p) {
   }
   const int t = threadIdx.x;
   const int lane = lane_id(), wv = t / WAVE;
-  const int per = (p.ncell + PLAN_THREADS - 1) / PLAN_THREADS;
-  const int c0 = min(p.ncell, t * per), c1 = min(p.ncell, c0 + per);
+  // the wavefront's cells [c0, c1), a whole number of runs of 64
+  const int per = (p.ncell + NW * WAVE - 1) / (NW * WAVE) * WAVE;
+  const int c0 = min(p.ncell, wv * per), c1 = min(p.ncell, c0 + per);
   bool fallback = false;
-  int64_t excl = 0;
+  int64_t woff = 0;
   for (int pass = 0; pass < 2; ++pass) {
     int64_t mine = 0;
-    for (int c = c0; c < c1; ++c) mine += plan_cap(p, c, fallback);
-    // block exclusive scan of the per-thread sums
-    int64_t incl = mine;
-    for (int off = 1; off < WAVE; off <<= 1) {
-      const int64_t o = __shfl_up(incl, off, WAVE);
-      if (lane >= off) incl += o;
-    }
-    if (lane == WAVE - 1) wsum[wv] = incl;
+#pragma unroll 4
+    for (int c = c0 + lane; c < c1; c += WAVE) mine += plan_cap(p, c, fallback);
+    // the wavefront's sum, then the block's exclusive scan of those sums
+    for (int off = WAVE / 2; off > 0; off >>= 1) mine += __shfl_xor(mine, off, WAVE);
+    if (lane == 0) wsum[wv] = mine;
     __syncthreads();
     if (t == 0) {
       int64_t acc = 0;
-      for (int w = 0; w < PLAN_THREADS / WAVE; ++w) {
+      for (int w = 0; w < NW; ++w) {
         const int64_t v = wsum[w];
         wsum[w] = acc;
         acc += v;
@@ -1877,7 +1880,7 @@ __global__ __launch_bounds__(PLAN_THREADS) void k_repack_plan(RepackPlan p) {
       total_s = acc;
     }
     __syncthreads();
-    excl = wsum[wv] + incl - mine;
+    woff = wsum[wv];
     const int64_t total = total_s;
     __syncthreads();
     if (total <= p.slots) break;
@@ -1892,12 +1895,21 @@ __global__ __launch_bounds__(PLAN_THREADS) void k_repack_plan(RepackPlan p) {
     }
     fallback = true;
   }
-  int64_t o = excl;
-  for (int c = c0; c < c1; ++c) {
-    const int64_t cp = plan_cap(p, c, fallback);
-    p.nstart[c] = (int32_t)o;
-    p.ncap[c] = (int32_t)cp;
-    o += cp;
+  // offsets: an inclusive scan of each run of 64 cells, carried over the runs
+  int64_t run = woff;
+  for (int b = c0; b < c1; b += WAVE) {
+    const int c = b + lane;
+    const int64_t cp = c < c1 ? plan_cap(p, c, fallback) : 0;
+    int64_t incl = cp;
+    for (int off = 1; off < WAVE; off <<= 1) {
+      const int64_t o = __shfl_up(incl, off, WAVE);
+      if (lane >= off) incl += o;
+    }
+    if (c < c1) {
+      p.nstart[c] = (int32_t)(run + incl - cp);
+      p.ncap[c] = (int32_t)cp;
+    }
+    run += __shfl(incl, WAVE - 1, WAVE);
   }
   if (t == 0) {
     ctl->active = 1u;
