@@ -30,17 +30,17 @@ PROJECT_PINS = ["tests/test_oracle_project.py"]
 # (name, [(original text, planted text), ...])
 MUTANTS = [
     ("sign of the mean pressure gradient (eq. 6)",
-     [("T au = (-f[C_DPDX] + nu2 * f[C_LAPU])", "T au = (f[C_DPDX] + nu2 * f[C_LAPU])")]),
+     [("std::fma(nu2, f[C_LAPU], -f[C_DPDX])", "std::fma(nu2, f[C_LAPU], f[C_DPDX])")]),
     ("swapped barycentric weights",
      [("lam[0] = orient_edge(c, e, 1, px, py) * ia;\n  lam[1] = orient_edge(c, e, 2, px, py) * ia;",
        "lam[0] = orient_edge(c, e, 2, px, py) * ia;\n  lam[1] = orient_edge(c, e, 1, px, py) * ia;")]),
     ("nu in place of 2 nu in the viscous drift",
-     [("T au = (-f[C_DPDX] + nu2 * f[C_LAPU])", "T au = (-f[C_DPDX] + (T)p.nu * f[C_LAPU])")]),
+     [("std::fma(nu2, f[C_LAPU], -f[C_DPDX])", "std::fma((T)p.nu, f[C_LAPU], -f[C_DPDX])")]),
     ("transposed velocity gradient in the laminar noise",
-     [("s2nu * (f[C_DUDX] * dW1 + f[C_DUDY] * dW2)", "s2nu * (f[C_DUDX] * dW1 + f[C_DVDX] * dW2)"),
-      ("s2nu * (f[C_DVDX] * dW1 + f[C_DVDY] * dW2)", "s2nu * (f[C_DUDY] * dW1 + f[C_DVDY] * dW2)")]),
+     [("T gu = std::fma(f[C_DUDY], dW2, f[C_DUDX] * dW1), gv = std::fma(f[C_DVDY], dW2, f[C_DVDX] * dW1);",
+       "T gu = std::fma(f[C_DVDX], dW2, f[C_DUDX] * dW1), gv = std::fma(f[C_DVDY], dW2, f[C_DUDY] * dW1);")]),
     ("position and velocity with independent molecular increments",
-     [("T xn = (x + u * dt) + s2nu * dW1;", "T xn = (x + u * dt) + s2nu * dWp1;")]),
+     [("T xn = std::fma(s2nu, dW1, std::fma(u, dt, x));", "T xn = std::fma(s2nu, dWp1, std::fma(u, dt, x));")]),
     ("r0 in place of r0^2 in eq. (11)",
      [("newton_cbrt(r0 * r0 / eps)", "newton_cbrt(r0 / eps)")]),
     ("dropped C_t in eq. (11)",
