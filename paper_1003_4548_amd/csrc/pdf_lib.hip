@@ -39,7 +39,7 @@ struct Layout {
   // the Eulerian solves (elliptic relaxation, mean-pressure projection): sparsity, element data, solver vectors
   int64_t rx_canon, rx_rep, rx_ecol, rx_enz, rx_dpos, rx_cptr, rx_cidx, rx_incptr, rx_inc, rx_Ke, rx_area;
   int64_t rx_S, rx_L2, rx_Rk, rx_aval, rx_dinv, rx_x, rx_px, rx_p, rx_rec[2], rx_part[2], rx_pbb, rx_ctl;
-  int64_t rx_ep, rx_need, rx_eneed, rx_agp[2], rx_cglob[2];   // the projection's coarse space
+  int64_t rx_ep, rx_eneed, rx_agp[2], rx_cglob[2];   // the projection's coarse space
   int64_t start, cap, cap0, nstart, ncap, ns[3], nm[3], rate, idoff, order, seed, src;
   int64_t buf0, buf1, ovf, ovf_cell, stats, ctl, flag, metrics;
   int64_t total;
@@ -105,8 +105,8 @@ Layout make_layout(int32_t nv, int32_t ne, int32_t nens, int64_t slots, int32_t 
     L.rx_pbb = take(relax::NC * nbx * 8);
     L.rx_ctl = take((int64_t)sizeof(relax::Ctl));
     const int64_t na = std::min<int64_t>((nc + relax::AGG - 1) / relax::AGG, relax::NA_MAX);
-    L.rx_ep = take(na * relax::NA_MAX * 4);
-    L.rx_need = take(nbx * relax::NEED * 4);
+    const int64_t nbc = (na + relax::APB - 1) / relax::APB;   // blocks that can hold a coarse space
+    L.rx_ep = take(nbc * relax::NEED * relax::NA_MAX * 4);
     L.rx_eneed = take(ell * 4);
     for (int b = 0; b < 2; ++b) {
       L.rx_agp[b] = take(relax::NA_MAX * 3 * 8);
@@ -326,17 +326,23 @@ pdf_status relax_setup(pdf_ctx* c, const pdf_mesh* m) {
   host::CoarseStructure CS;
   const bool coarse = host::build_coarse(S, ne, m->vtx, m->tri, relax::AGG, relax::BLK, relax::NEED, relax::NA_MAX,
                                          CS) == host::COARSE_OK;
-  // E^+ on the device: symmetric in float, rows NA_MAX wide (zero past na)
+  // E^+ on the device, symmetric in float: per block, the rows of its need
+  // list, NA_MAX wide (zero past na and past the end of the list)
   std::vector<float> epf;
   if (coarse) {
     const int32_t na = CS.na;
-    epf.assign((size_t)na * relax::NA_MAX, 0.0f);
-    for (int32_t i = 0; i < na; ++i)
+    const size_t nk = CS.need.size();   // blocks x NEED
+    if ((int64_t)(nk * relax::NA_MAX * 4) > L.rx_eneed - L.rx_ep)   // the layout's bound on the blocks
+      return fail(c, PDF_E_SIZE, "relaxation: coarse rows exceed their layout");
+    epf.assign(nk * relax::NA_MAX, 0.0f);
+    for (size_t k = 0; k < nk; ++k) {
+      const int32_t i = CS.need[k];
+      if (i < 0) continue;
       for (int32_t j = 0; j < na; ++j)
-        epf[(size_t)i * relax::NA_MAX + j] = (float)(0.5 * (CS.ep[(size_t)i * na + j] + CS.ep[(size_t)j * na + i]));
+        epf[(size_t)k * relax::NA_MAX + j] = (float)(0.5 * (CS.ep[(size_t)i * na + j] + CS.ep[(size_t)j * na + i]));
+    }
     if ((r = hip_check(c, hipMemcpyAsync(d + L.rx_ep, epf.data(), epf.size() * 4, hipMemcpyHostToDevice, st),
                        "copy coarse operator"))) return r;
-    if ((r = put(L.rx_need, CS.need, "copy coarse need lists"))) return r;
     if ((r = put(L.rx_eneed, CS.eneed, "copy coarse need lists"))) return r;
   }
   const int tb = 256;
@@ -1418,7 +1424,6 @@ static relax::Args relax_args(pdf_ctx* c) {
   a.ctl = (relax::Ctl*)(d + L.rx_ctl);
   a.na = 0;   // the projection sets its coarse space
   a.ep = (const float*)(d + L.rx_ep);
-  a.need = (const int32_t*)(d + L.rx_need);
   a.eneed = (const int32_t*)(d + L.rx_eneed);
   for (int b = 0; b < 2; ++b) {
     a.agp[b] = (double*)(d + L.rx_agp[b]);

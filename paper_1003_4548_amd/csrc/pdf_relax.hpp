@@ -121,8 +121,9 @@ struct Args {
   Ctl* ctl;
   // the projection's coarse space (na = 0: none, the preconditioner is D^-1)
   int32_t na;
-  const float* ep;         // na x NA_MAX: E^+ (symmetric, in float; zero past column na)
-  const int32_t* need;     // nbx x NEED: aggregates whose correction a block reads
+  const float* ep;         // nbx x NEED x NA_MAX: per block, the E^+ rows of the aggregates
+                           // whose correction it reads (symmetric, in float; zero past
+                           // column na and past the end of its list)
   const int32_t* eneed;    // ellw x nc: position of each row slot's column aggregate in that list
   double* agp[2];          // na x 3 aggregate sums of r_i, w_i, s_{i-1}, by parity
   double* cglob[2];        // na: the coarse correction of r_i, by parity
@@ -292,17 +293,26 @@ __device__ __forceinline__ double read_lane(double v, int lane) {
   return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
-// The sum over the 64 lanes of a wavefront (every lane active), the same
-// value in every lane: within each row of 16 lanes, partners exchange by DPP
-// (lane ^ 1, lane ^ 2, then the mirrored half-row and row), so every lane of
-// a row holds the row sum; then the four row sums in order.  A fixed order,
-// and each pair of partners adds the same two numbers.
-__device__ __forceinline__ double wave_sum(double v) {
-  v += dpp_move<0xB1>(v);    // quad_perm [1, 0, 3, 2]
-  v += dpp_move<0x4E>(v);    // quad_perm [2, 3, 0, 1]
-  v += dpp_move<0x141>(v);   // row_half_mirror
-  v += dpp_move<0x140>(v);   // row_mirror
-  return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
+// The sums over the 64 lanes of a wavefront of K values per lane (every lane
+// active), the same in every lane: within each row of 16 lanes, partners
+// exchange by DPP (lane ^ 1, lane ^ 2, then the mirrored half-row and row),
+// so every lane of a row holds the row sum; then the four row sums in order.
+// A fixed order, and each pair of partners adds the same two numbers.  The K
+// exchanges go step by step side by side, so that they overlap instead of
+// waiting on one another.
+template <int K> __device__ __forceinline__ void wave_sums(const double (&v)[K], double (&out)[K]) {
+  double t[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) t[k] = v[k] + dpp_move<0xB1>(v[k]);
+#pragma unroll
+  for (int k = 0; k < K; ++k) t[k] += dpp_move<0x4E>(t[k]);
+#pragma unroll
+  for (int k = 0; k < K; ++k) t[k] += dpp_move<0x141>(t[k]);
+#pragma unroll
+  for (int k = 0; k < K; ++k) t[k] += dpp_move<0x140>(t[k]);
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+    out[k] = (read_lane(t[k], 0) + read_lane(t[k], 16)) + (read_lane(t[k], 32) + read_lane(t[k], 48));
 }
 
 // The block's sums of K values per thread (wavefront sums, then the
@@ -311,8 +321,7 @@ template <int K> __device__ void block_sum(double (&v)[K]) {
   __shared__ double sw[WPB][K];
   const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
   double t[K];
-#pragma unroll
-  for (int k = 0; k < K; ++k) t[k] = wave_sum(v[k]);
+  wave_sums<K>(v, t);
   if (lane == 0)
     for (int k = 0; k < K; ++k) sw[wv][k] = t[k];
   __syncthreads();
@@ -326,7 +335,7 @@ template <int K> __device__ void block_sum(double (&v)[K]) {
 
 // Sums over the blocks of a launch of K partials per (component, block),
 // src[(c * nbx + bx) * K + k], into tot[c][k], computed by every wavefront
-// for itself (lane l adds blocks l, l + 64, ... in turn, then wave_sum): a
+// for itself (lane l adds blocks l, l + 64, ... in turn, then wave_sums): a
 // fixed order, the same in every block.
 template <int K> __device__ void total_partials(const Args& a, const double* src, double (&tot)[NC][K]) {
   const int lane = threadIdx.x & (WAVE - 1);
@@ -341,9 +350,7 @@ template <int K> __device__ void total_partials(const Args& a, const double* src
 #pragma unroll
       for (int k = 0; k < K; ++k) t[c][k] += src[((size_t)c * a.nbx + bx) * K + k];
 #pragma unroll
-  for (int c = 0; c < NC; ++c)
-#pragma unroll
-    for (int k = 0; k < K; ++k) tot[c][k] = wave_sum(t[c][k]);
+  for (int c = 0; c < NC; ++c) wave_sums<K>(t[c], tot[c]);
 }
 
 // the recurrences of one unknown: s = w + beta s, r' = r - alpha s, u' = r' / d;
@@ -476,9 +483,16 @@ template <int W> __global__ __launch_bounds__(BLK) void k_relax_iter(Args a, int
     for (int q = 0; q < NC; ++q) tr[q] += src[((size_t)q * a.nbx + bx) * 3 + 2];
   }
   if (pdone) return;
+  // the two inner products of this component and every component's (r, r)
+  double sv[2 + NC], sm[2 + NC];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) sv[k] = tg[k];
+#pragma unroll
+  for (int q = 0; q < NC; ++q) sv[2 + q] = tr[q];
+  wave_sums<2 + NC>(sv, sm);
   double rho[NC];
 #pragma unroll
-  for (int q = 0; q < NC; ++q) rho[q] = wave_sum(tr[q]);
+  for (int q = 0; q < NC; ++q) rho[q] = sm[2 + q];
   bool ok = true;
 #pragma unroll
   for (int q = 0; q < NC; ++q) {
@@ -486,7 +500,7 @@ template <int W> __global__ __launch_bounds__(BLK) void k_relax_iter(Args a, int
     const double rq = ref[q] > 0.0 ? ref[q] : (it == 0 ? rho[q] : ref[q]);
     ok = ok && rho[q] <= tol2 * rq;
   }
-  const double g = wave_sum(tg[0]), d = wave_sum(tg[1]);
+  const double g = sm[0], d = sm[1];
   const double beta = gold != 0.0 ? g / gold : 0.0;
   const double den = aold != 0.0 ? d - beta * g / aold : d;
   const double alpha = den != 0.0 ? g / den : 0.0;
@@ -585,14 +599,14 @@ __device__ __forceinline__ void half_sums(double v, double& lo, double& hi) {
 
 // This thread's share of the E^+ rows of its block's need list: entry
 // threadIdx / TPE, the JMAX columns from JMAX (threadIdx % TPE) on, in
-// 16-byte loads (zero past the list; the rows are zero past na).
+// 16-byte loads.  The rows sit in a copy per block, so the addresses need no
+// index load first.
 constexpr int JV = JMAX / 4;
 __device__ __forceinline__ void coarse_rows(const Args& a, float4 (&ev)[JV]) {
   const int e = threadIdx.x / TPE, q = threadIdx.x % TPE;
-  const int row = a.na > 0 ? a.need[blockIdx.x * NEED + e] : -1;
-  const float4* er = reinterpret_cast<const float4*>(a.ep + (size_t)(row >= 0 ? row : 0) * NA_MAX + JMAX * q);
+  const float4* er = reinterpret_cast<const float4*>(a.ep + ((size_t)blockIdx.x * NEED + e) * NA_MAX + JMAX * q);
 #pragma unroll
-  for (int j = 0; j < JV; ++j) ev[j] = row >= 0 ? er[j] : make_float4(0.f, 0.f, 0.f, 0.f);
+  for (int j = 0; j < JV; ++j) ev[j] = er[j];
 }
 
 // c = E^+ v on the need list into csh[NEED] (vw: the wavefront's copy of v
@@ -625,14 +639,26 @@ __device__ __forceinline__ void coarse_product(const float4 (&ev)[JV], const dou
 __device__ __forceinline__ void aggregate_sums(const Args& a, const double (&v)[3], double* dst) {
   const int lane = threadIdx.x & (WAVE - 1);
   const int g0 = (blockIdx.x * BLK + (threadIdx.x - lane)) / AGG;
+  // the three exchanges step by step side by side, then the stores
+  double t[3], lo[3], hi[3];
+#pragma unroll
+  for (int m = 0; m < 3; ++m) t[m] = v[m] + dpp_move<0xB1>(v[m]);
+#pragma unroll
+  for (int m = 0; m < 3; ++m) t[m] += dpp_move<0x4E>(t[m]);
+#pragma unroll
+  for (int m = 0; m < 3; ++m) t[m] += dpp_move<0x141>(t[m]);
+#pragma unroll
+  for (int m = 0; m < 3; ++m) t[m] += dpp_move<0x140>(t[m]);
 #pragma unroll
   for (int m = 0; m < 3; ++m) {
-    double lo, hi;
-    half_sums(v[m], lo, hi);
-    if (lane == 0) {
-      if (g0 < a.na) dst[(size_t)g0 * 3 + m] = lo;
-      if (g0 + 1 < a.na) dst[(size_t)(g0 + 1) * 3 + m] = hi;
-    }
+    lo[m] = read_lane(t[m], 0) + read_lane(t[m], 16);
+    hi[m] = read_lane(t[m], 32) + read_lane(t[m], 48);
+  }
+  if (lane == 0) {
+    if (g0 < a.na)
+      for (int m = 0; m < 3; ++m) dst[(size_t)g0 * 3 + m] = lo[m];
+    if (g0 + 1 < a.na)
+      for (int m = 0; m < 3; ++m) dst[(size_t)(g0 + 1) * 3 + m] = hi[m];
   }
 }
 
@@ -690,7 +716,8 @@ __global__ __launch_bounds__(BLK) void k_proj_start2(Args a) {
   double acc = 0.0;
   for (int t = 0; t < a.ellw; ++t) {
     const int k = a.ecol[t * nc + ii];
-    const double ck = a.na > 0 ? csh[a.eneed[t * nc + ii]] : 0.0;
+    const int e = a.eneed[t * nc + ii] & (NEED - 1);
+    const double ck = a.na > 0 ? csh[e] : 0.0;
     acc = __builtin_fma(a.aval[t * nc + ii], __builtin_fma(r0[k].r, r0[k].d, ck), acc);
   }
   const double ri = r0[ii].r, ui = __builtin_fma(ri, r0[ii].d, c0);
@@ -744,13 +771,19 @@ template <int W> __global__ __launch_bounds__(BLK) void k_proj_iter(Args a, int 
   for (int t = 0; t < W; ++t) {
     cl[t] = a.ecol[t * nc + ii];
     av[t] = a.aval[t * nc + ii];
-    en[t] = co ? a.eneed[t * nc + ii] : 0;
+    // loaded whether or not co: the compiler ends a load under a branch with
+    // a wait for every load in flight
+    en[t] = a.eneed[t * nc + ii] & (NEED - 1);
   }
   const double2 rw_o = *reinterpret_cast<const double2*>(&old[ii].r);
   const double2 sd_o = *reinterpret_cast<const double2*>(&old[ii].s);
   const double r_o = rw_o.x, w_o = rw_o.y, s_o = sd_o.x, d_o = sd_o.y, p_o = a.p[ii], x_o = a.x[ii];
   const int own = ii / AGG - blockIdx.x * APB;
   const double c_o = co ? a.cglob[par][ii / AGG] : 0.0;
+  // this thread's share of the E^+ rows: no index load before them, so they
+  // go out with the first round
+  float4 ev[JV];
+  if (co) coarse_rows(a, ev);
   const Ctl* ctl = a.ctl;
   const Scal& prev = ctl->sc[par ^ 1];
   const int pdone = prev.done, it = prev.iter, max_iters = ctl->max_iters;
@@ -776,12 +809,10 @@ template <int W> __global__ __launch_bounds__(BLK) void k_proj_iter(Args a, int 
 #pragma unroll
     for (int k = 0; k < 3; ++k) tp[k] += src[(size_t)bx * 3 + k];
   if (pdone) return;
-  // aggregate sums of r_i, w_i, s_{i-1} (aggregates lane + 64 k) and this
-  // thread's share of the E^+ rows: issued behind the stop test, so in the
-  // second round with the neighbours' values (a wavefront keeps at most 63
-  // loads in flight, and the first round is near that already)
+  // aggregate sums of r_i, w_i, s_{i-1} (aggregates lane + 64 k): issued
+  // behind the stop test, so in the second round with the neighbours' values
+  // (a wavefront keeps at most 63 loads in flight)
   double ag[NA_MAX / WAVE][3];
-  float4 ev[JV];
   if (co) {
 #pragma unroll
     for (int k = 0; k < NA_MAX / WAVE; ++k) {
@@ -790,11 +821,9 @@ template <int W> __global__ __launch_bounds__(BLK) void k_proj_iter(Args a, int 
 #pragma unroll
       for (int m = 0; m < 3; ++m) ag[k][m] = in ? a.agp[par][(size_t)g * 3 + m] : 0.0;
     }
-    coarse_rows(a, ev);
   }
   double tot[3];
-#pragma unroll
-  for (int k = 0; k < 3; ++k) tot[k] = wave_sum(tp[k]);
+  wave_sums<3>(tp, tot);
   // where b = 0 the reference is (r0, r0), known from iteration 0 on
   const double rq = ref > 0.0 ? ref : (it == 0 ? tot[2] : ref);
   const bool ok = tot[2] <= tol2 * rq;
