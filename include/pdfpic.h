@@ -314,16 +314,21 @@ pdf_status pdf_elliptic_relaxation(pdf_ctx* ctx, int32_t max_iters, double tol, 
    divergence-free fields.  From the statistics of the current state (one
    ensemble; per element the particles' mean velocity, the frozen mean
    velocity at the centroid where the element holds fewer than 10
-   particles), the pressure increment phi solves lap(phi) = div<U> / dt with
-   d(phi)/dn = <U>.n / dt at walls, in the Galerkin P1 form
-     sum_e int_e grad(phi).grad(psi_i) = (1/dt) sum_e area_e <U>_e . grad(psi_i)|_e
+   particles), the pressure increment phi solves lap(phi) = div<U> / T with
+   d(phi)/dn = <U>.n / T at walls, in the Galerkin P1 form
+     sum_e int_e grad(phi).grad(psi_i) = (1/T) sum_e area_e <U>_e . grad(psi_i)|_e
    on the unknowns of the relaxation system (its right-hand side sums to
    zero: the system is singular and consistent, phi is defined up to a
    constant).  Then grad(phi), constant per element, averaged by area to the
    vertices, is added to the mean pressure gradient (the device copy of the
    fields and the coefficient table the step reads), and every particle's
-   velocity (u, v) loses dt grad(phi) of its element (in double, rounded to
-   the state type).  The system is solved by conjugate gradients in the
+   velocity (u, v) loses T grad(phi) of its element (in double, rounded to
+   the state type).  T = n dt covers the n steps since the previous applied
+   projection (since seeding for the first; n >= 1): grad(phi) is then the
+   mean pressure gradient those n steps lacked, so a caller that projects
+   every n steps sees the gradient settle (with T = dt at every n > 2 the
+   increments would grow about (n - 1)-fold per call, alternating in sign).
+   The system is solved by conjugate gradients in the
    form of pdf_elliptic_relaxation (one launch per iteration), preconditioned
    by the inverse diagonal plus a coarse correction on aggregates of 32
    unknowns (the pseudo-inverse of the stiffness matrix projected on them;

@@ -355,7 +355,9 @@ class Simulation:
     def pressure_projection(self, max_iters: int = 20000, tol: float = 1e-10, outputs: bool = True) -> dict:
         """Project the particles' mean velocity (one ensemble): solve for the
         pressure increment, add its gradient to the mean pressure gradient and
-        correct every particle's velocity (waits).  Returns iterations,
+        correct every particle's velocity (waits).  The correction covers the
+        steps since the previous applied projection (since seeding for the
+        first), so it may be called every n steps.  Returns iterations,
         converged, applied, from_stats, resid and, with outputs, phi (nvert,
         up to a constant) and grad (nvert x 2) as numpy arrays."""
         info = np.zeros(4, np.int32)

@@ -197,6 +197,7 @@ struct pdf_ctx {
   std::vector<int32_t> h_start, h_cap, h_cnt, h_idoff, h_zero, h_order;
   // host-side step state: the launch arguments of the next step
   int64_t steps_done = 0;
+  int64_t proj_mark = 0;   // steps_done at the last applied projection
   uint32_t parity = 0, rot = 0;
   // launch configuration (set by pdf_autotune; defaults below)
   int32_t group = 64;     // lanes per cell
@@ -1192,6 +1193,7 @@ pdf_status pdf_seed_particles(pdf_ctx* c, int32_t nens, const int64_t* counts, c
   c->restore_pending.clear();
   c->graph_group = 0;  // a graph built for an earlier layout is stale
   c->steps_done = 0;
+  c->proj_mark = 0;
   c->parity = 0;
   c->rot = 0;
   c->last = PDF_OK;
@@ -1594,6 +1596,10 @@ pdf_status pdf_pressure_projection(pdf_ctx* c, int32_t max_iters, double tol, do
   a.mass = 0.0;
   a.rhs_mode = 1;
   a.na = c->rx_na;
+  // the span the correction covers: the steps since the last applied
+  // projection (at least one)
+  const int64_t span = std::max<int64_t>(1, c->steps_done - c->proj_mark);
+  a.dt = (double)span * c->p.dt;
   hipStream_t st = c->stream;
   const int tb = relax::BLK;
   const unsigned eb = (unsigned)((c->ne + tb - 1) / tb), vb = (unsigned)((c->nv + tb - 1) / tb);
@@ -1635,6 +1641,7 @@ pdf_status pdf_pressure_projection(pdf_ctx* c, int32_t max_iters, double tol, do
   };
   const relax::Ctl* h = nullptr;
   if ((r = run_solve(c, a, c->px_sg, true, max_iters, apply, &h))) return r;
+  if (h->applied) c->proj_mark = c->steps_done;
   report_solve(*h, info, resid, h->applied);
   return PDF_OK;
 }
