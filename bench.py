@@ -341,7 +341,7 @@ def eulerian_leg(torch, W, Simulation, solve: str, cycles: int = 5, between: int
     p x s r w written (80 B), and per unknown the inverse diagonal and its
     padded row (8 + 12 W B); with the projection's coarse space, per
     aggregate its three sums and correction read and written (64 B) and per
-    block the rows of E^+ its need list reads (32 na 8 B)."""
+    block the rows of E^+ its need list reads (32 na 4 B: float)."""
     wl = W.config2(steps=10)
     sim = Simulation.from_workload(wl, device="cuda:0")
     size = sim.relaxation_size()
@@ -385,7 +385,7 @@ def eulerian_leg(torch, W, Simulation, solve: str, cycles: int = 5, between: int
     nc, w = size["unknowns"], size["row_width"]
     na = size["aggregates"] if solve == "projection" else 0
     nbx = -(-nc // 128)
-    bytes_iter = nc * (ncomp * 80 + 8 + 12 * w) + (na * 64 + nbx * 32 * na * 8 if na else 0)
+    bytes_iter = nc * (ncomp * 80 + 8 + 12 * w) + (na * 64 + nbx * 32 * na * 4 if na else 0)
     achieved = bytes_iter / (slope * 1e-3) / 1e9
     res = {
         "workload": f"{wl.name}: the P1 system of its mesh, statistics of its 1M particles",
