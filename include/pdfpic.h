@@ -319,7 +319,8 @@ pdf_status pdf_elliptic_relaxation(pdf_ctx* ctx, int32_t max_iters, double tol, 
      sum_e int_e grad(phi).grad(psi_i) = (1/T) sum_e area_e <U>_e . grad(psi_i)|_e
    on the unknowns of the relaxation system (its right-hand side sums to
    zero: the system is singular and consistent, phi is defined up to a
-   constant).  Then grad(phi), constant per element, averaged by area to the
+   constant; the mean the load keeps from rounding is taken off before the
+   solve, as the bordered system that fixes phi's mean does).  Then grad(phi), constant per element, averaged by area to the
    vertices, is added to the mean pressure gradient (the device copy of the
    fields and the coefficient table the step reads), and every particle's
    velocity (u, v) loses T grad(phi) of its element (in double, rounded to

@@ -1610,6 +1610,7 @@ pdf_status pdf_pressure_projection(pdf_ctx* c, int32_t max_iters, double tol, do
   hipLaunchKernelGGL(relax::k_proj_inputs, dim3(eb), dim3(tb), 0, st, a);
   hipLaunchKernelGGL(relax::k_relax_matrix, dim3(zb), dim3(tb), 0, st, a);
   hipLaunchKernelGGL(relax::k_proj_start1, dim3((unsigned)a.nbx), dim3(tb), 0, st, a);
+  hipLaunchKernelGGL(relax::k_proj_center, dim3((unsigned)a.nbx), dim3(tb), 0, st, a);
   hipLaunchKernelGGL(relax::k_proj_start2, dim3((unsigned)a.nbx), dim3(tb), 0, st, a);
   if ((r = hip_check(c, hipGetLastError(), "projection launch"))) return r;
   // the update, once the solve has stopped (the kernels check the device's

@@ -662,12 +662,11 @@ __device__ __forceinline__ void aggregate_sums(const Args& a, const double (&v)[
   }
 }
 
-// start: r0 = b - A x0 (component 0), p = 0, s = 0, the (b, b) partials and
-// the aggregate sums of r0 (and of s_{-1} = 0)
+// start: r0 = b - A x0 (component 0), p = 0, s = 0, and the block partials
+// of the sum of r0 (in the second component's slots of pbb)
 __global__ __launch_bounds__(BLK) void k_proj_start1(Args a) {
   const int i = blockIdx.x * BLK + threadIdx.x, nc = a.nc;
-  double bb[1] = {0.0};
-  double g[3] = {0.0, 0.0, 0.0};
+  double sr[1] = {0.0};
   if (i < nc) {
     double bv = 0.0;
     for (int t = a.incptr[i]; t < a.incptr[i + 1]; ++t) {
@@ -681,10 +680,35 @@ __global__ __launch_bounds__(BLK) void k_proj_start1(Args a) {
     q.s = 0.0;
     q.d = a.dinv[i];
     a.p[i] = 0.0;
-    bb[0] = bv * bv;
-    g[0] = bv - ax;
+    sr[0] = bv - ax;
   }
-  if (a.na > 0) aggregate_sums(a, g, a.agp[0]);   // r0, (w0 from the second launch), s_{-1} = 0
+  block_sum<1>(sr);
+  if (threadIdx.x == 0) a.pbb[(size_t)a.nbx + blockIdx.x] = sr[0];
+}
+
+// start: the mean of r0 taken off.  The system is singular (pure Neumann and
+// periodic sides: the constants span its null space) and its range is the
+// vectors of zero sum; the load sums to zero only up to rounding, and the
+// bordered form that fixes the mean of phi solves with the load's mean
+// removed, which is what this does (every block totals the partials in the
+// same order, so all take the same mean).  Then the (r0, r0) partials, the
+// solve's reference, and the aggregate sums of r0 (and of s_{-1} = 0).
+__global__ __launch_bounds__(BLK) void k_proj_center(Args a) {
+  const int i = blockIdx.x * BLK + threadIdx.x, nc = a.nc, lane = threadIdx.x & (WAVE - 1);
+  double ts[1] = {0.0}, tot[1];
+  for (int bx = lane; bx < a.nbx; bx += WAVE) ts[0] += a.pbb[(size_t)a.nbx + bx];
+  wave_sums<1>(ts, tot);
+  const double mean = tot[0] / nc;
+  double bb[1] = {0.0};
+  double g[3] = {0.0, 0.0, 0.0};
+  if (i < nc) {
+    Rec& q = a.rec[0][i];
+    const double r = q.r - mean;
+    q.r = r;
+    bb[0] = r * r;
+    g[0] = r;
+  }
+  if (a.na > 0) aggregate_sums(a, g, a.agp[0]);   // r0, (w0 from the next launch), s_{-1} = 0
   block_sum<1>(bb);
   if (threadIdx.x == 0) a.pbb[blockIdx.x] = bb[0];
 }

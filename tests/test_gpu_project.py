@@ -16,7 +16,8 @@ T is the span the correction covers: the steps since seeding (the first
 projection) or since the previous applied projection, times dt.
 Then: a second projection right after the first finds almost nothing left
 where every element holds ten particles or more (the particle means now are
-the corrected field, up to the rounding of the velocities); the step after a projection uses the new mean pressure
+the corrected field, up to the rounding of the velocities), and converges
+although its load is rounding noise; the step after a projection uses the new mean pressure
 gradient (against the oracle stepping with it, and far from the oracle
 stepping with the old one); and projections every six steps settle (their
 increments do not grow from one to the next, the particles' velocities stay
@@ -133,8 +134,14 @@ def test_second_projection_finds_little(gpu, case):
     # the velocity corrections: the first covers wl.steps steps, the second
     # (no step between) one
     r = np.abs(second["grad"]).max() / (wl.steps * np.abs(first["grad"]).max())
-    print(f"[project] second / first velocity correction {r:.2e}", flush=True)
+    print(f"[project] second / first velocity correction {r:.2e}, iterations {first['iterations']} then "
+          f"{second['iterations']}", flush=True)
     assert r < 1e-9
+    # its load is rounding noise; with the load's mean taken off (the part
+    # outside the singular system's range) it still converges, in about as
+    # many iterations as the first (measured 93 then 94 on the canyon;
+    # without it 5000 to 20000, some never)
+    assert second["converged"] and second["iterations"] <= 2 * first["iterations"]
 
 
 def test_step_after_projection_uses_the_new_pressure_gradient(gpu):
