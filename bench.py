@@ -403,7 +403,8 @@ def eulerian_leg(torch, W, Simulation, solve: str, cycles: int = 5, between: int
     }
     if solve == "projection":
         res["note"] = ("conjugate gradients preconditioned by the diagonal plus a coarse correction on "
-                       f"{na} aggregates of 32 unknowns (one launch per iteration)")
+                       f"{na} aggregates of 32 unknowns (one launch per iteration); each projection covers "
+                       f"the {between} steps since the one before")
     print(f"[bench] {solve}: {res}", file=sys.stderr, flush=True)
     return res
 
